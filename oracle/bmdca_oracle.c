@@ -1,0 +1,530 @@
+/*
+ * bmdca_oracle.c -- plain, slow, FP64 CPU oracle for the bmDCA training hot
+ * path (adabmDCA 2.0, arXiv:2501.18456).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library; both implement the
+ * same written definitions independently.
+ *
+ * Every routine is the textbook definition written out in double precision:
+ * no blocking, no incremental updates, no reordering of any sum beyond the
+ * ascending index order stated at each routine.  Build with contraction off
+ * (-ffp-contract=off) so that every a*b+c is two roundings.
+ *
+ * Conventions (shared definitions, restated here):
+ *   tokens      int8 0..q-1, token 0 = gap (Table 1 lists the gap first)
+ *   flat index  r = i*q + a for site i, state a
+ *   h           float32 [L*q]
+ *   J           float32 [L*q][L*q], full-symmetric, zero diagonal blocks
+ *   energy      E(s) = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i, s_j)   (Eq. 1)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX2(r1, r2, Lq) ((size_t)(r1) * (size_t)(Lq) + (size_t)(r2))
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 counter-based generator, as defined by Salmon, Moraes, Dror  */
+/* and Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten       */
+/* rounds of two 32x32->64 multiplies with the round function                 */
+/*   (c0,c1,c2,c3) -> (hi(M1*c2)^c1^k0, lo(M1*c2), hi(M0*c0)^c3^k1, lo(M0*c0)) */
+/* and a Weyl-sequence key bump between rounds.                               */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* One 32-bit word of the stream: key = seed, counter = (ctr0, ctr1, ctr2,
+ * stream), word = output[word_index]. */
+static uint32_t philox_word(uint64_t seed, uint32_t ctr0, uint32_t ctr1,
+                            uint32_t ctr2, uint32_t stream, int word_index)
+{
+    uint32_t ctr[4] = {ctr0, ctr1, ctr2, stream};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[word_index];
+}
+
+/* Uniform used by the Gibbs draw of chain c at site i in global sweep sg:
+ * counter (i/4, sg, c, 0), word i%4, u = (word >> 8) * 2^-24 in [0, 1). */
+double orc_gibbs_uniform(uint64_t seed, uint64_t c, uint64_t sg, int32_t i)
+{
+    uint32_t w = philox_word(seed, (uint32_t)i >> 2, (uint32_t)sg, (uint32_t)c,
+                             0u, i & 3);
+    return (double)(w >> 8) * (1.0 / 16777216.0);
+}
+
+/* Uniform random initial chains (the "chosen uniformly at random" start of
+ * Sec. 2.1): counter (i/4, 0, c, 1), word i%4, token = (word * q) >> 32. */
+void orc_init_chains(int8_t* chains, int64_t N, int32_t L, int32_t q,
+                     uint64_t seed)
+{
+    for (int64_t c = 0; c < N; ++c)
+        for (int32_t i = 0; i < L; ++i) {
+            uint32_t w = philox_word(seed, (uint32_t)i >> 2, 0u, (uint32_t)c, 1u,
+                                     i & 3);
+            chains[c * L + i] = (int8_t)(((uint64_t)w * (uint64_t)q) >> 32);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pre-processing step p.2: importance weights, Eq. (7).                      */
+/* ------------------------------------------------------------------------ */
+
+/* Integer identity threshold: number of identical positions >= theta*L,
+ * read as T = ceil(theta*L - 1e-6) so that products such as 0.8*35 that
+ * round just above an integer do not raise the threshold by one. */
+int32_t orc_identity_threshold(double theta, int32_t L)
+{
+    return (int32_t)ceil(theta * (double)L - 1e-6);
+}
+
+/* N^(m) = #{n : sum_i [a_i^(m) == a_i^(n)] >= T}, self included (Eq. 7);
+ * w^(m) = 1 / N^(m); M_eff = sum_m w^(m) in ascending m (the M_eff of the
+ * pseudocount paragraph). Gaps count as ordinary symbols. */
+void orc_reweight(const int8_t* msa, int64_t M, int32_t L, double theta,
+                  int32_t* n_sim, double* w, double* meff)
+{
+    int32_t T = orc_identity_threshold(theta, L);
+    for (int64_t m = 0; m < M; ++m) {
+        int32_t count = 0;
+        for (int64_t n = 0; n < M; ++n) {
+            int32_t same = 0;
+            for (int32_t i = 0; i < L; ++i)
+                same += (msa[m * L + i] == msa[n * L + i]);
+            if (same >= T) count += 1;
+        }
+        n_sim[m] = count;
+    }
+    double s = 0.0;
+    for (int64_t m = 0; m < M; ++m) {
+        w[m] = 1.0 / (double)n_sim[m];
+        s += w[m];
+    }
+    *meff = s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pre-processing step p.3: reweighted frequencies Eq. (3) and pseudocount    */
+/* Eqs. (8)-(9).                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* f1[i,a] = sum_m w_m [a_i^m == a] / M_eff,
+ * f2[(i,a),(j,b)] = sum_m w_m [a_i^m == a][a_j^m == b] / M_eff   (i != j),
+ * each sum taken in ascending m.  w == NULL means unit weights (M_eff = M).
+ * Pseudocount alpha: alpha < 0 selects alpha = 1/M_eff.
+ *   f1' = (1 - alpha) f1 + alpha / q
+ *   f2' = (1 - alpha) f2 + alpha / q^2              (i != j)
+ *   f2'[(i,a),(i,b)] = delta_ab f1'[i,a]            (diagonal blocks)
+ * Outputs f1 [L*q], f2 [Lq*Lq], *meff_out. */
+void orc_stats(const int8_t* X, const double* w, int64_t M, int32_t L, int32_t q,
+               double pseudocount, double* f1, double* f2, double* meff_out)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double meff = 0.0;
+    for (int64_t m = 0; m < M; ++m) meff += (w ? w[m] : 1.0);
+    memset(f1, 0, sizeof(double) * (size_t)Lq);
+    memset(f2, 0, sizeof(double) * (size_t)Lq * (size_t)Lq);
+    /* Accumulate weighted counts; every entry receives its terms in
+     * ascending m because m is the outer loop. */
+    for (int64_t m = 0; m < M; ++m) {
+        const double wm = w ? w[m] : 1.0;
+        const int8_t* s = X + m * L;
+        for (int32_t i = 0; i < L; ++i) {
+            f1[i * q + s[i]] += wm;
+            for (int32_t j = 0; j < L; ++j) {
+                if (j == i) continue;
+                f2[IDX2(i * q + s[i], j * q + s[j], Lq)] += wm;
+            }
+        }
+    }
+    double alpha = pseudocount < 0.0 ? 1.0 / meff : pseudocount;
+    for (int64_t r = 0; r < Lq; ++r) {
+        double f = f1[r] / meff;
+        double t1 = (1.0 - alpha) * f;
+        double t2 = alpha / (double)q;
+        f1[r] = t1 + t2;
+    }
+    const double qq = (double)q * (double)q;
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t a = 0; a < q; ++a)
+            for (int32_t j = 0; j < L; ++j)
+                for (int32_t b = 0; b < q; ++b) {
+                    size_t k = IDX2(i * q + a, j * q + b, Lq);
+                    if (i == j) {
+                        f2[k] = (a == b) ? f1[i * q + a] : 0.0;
+                    } else {
+                        double f = f2[k] / meff;
+                        double t1 = (1.0 - alpha) * f;
+                        double t2 = alpha / qq;
+                        f2[k] = t1 + t2;
+                    }
+                }
+    *meff_out = meff;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy of Eq. (1).                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* E(s) = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i,s_j), accumulated in double,
+ * fields first (ascending i), then pairs in (i, j) lexicographic order. */
+double orc_energy_one(const float* h, const float* J, const int8_t* s, int32_t L,
+                      int32_t q)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double e = 0.0;
+    for (int32_t i = 0; i < L; ++i) e -= (double)h[i * q + s[i]];
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t j = i + 1; j < L; ++j)
+            e -= (double)J[IDX2(i * q + s[i], j * q + s[j], Lq)];
+    return e;
+}
+
+void orc_energy(const float* h, const float* J, const int8_t* seqs, int64_t B,
+                int32_t L, int32_t q, double* E)
+{
+    for (int64_t b = 0; b < B; ++b) E[b] = orc_energy_one(h, J, seqs + b * L, L, q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local field: the log of the conditional of Eq. (1) at site i, up to a     */
+/* constant: H_i(a) = h_i(a) + sum_{j != i} J_ij(a, s_j).  From scratch.      */
+/* ------------------------------------------------------------------------ */
+void orc_local_field(const float* h, const float* J, const int8_t* s, int32_t L,
+                     int32_t q, int32_t i, double* Hi)
+{
+    const int64_t Lq = (int64_t)L * q;
+    for (int32_t a = 0; a < q; ++a) {
+        double v = (double)h[i * q + a];
+        for (int32_t j = 0; j < L; ++j) {
+            if (j == i) continue;
+            v += (double)J[IDX2(i * q + a, j * q + s[j], Lq)];
+        }
+        Hi[a] = v;
+    }
+}
+
+/* All L*q local fields of one configuration (H[i*q + a]). */
+void orc_local_fields_all(const float* h, const float* J, const int8_t* s,
+                          int32_t L, int32_t q, double* H)
+{
+    for (int32_t i = 0; i < L; ++i) orc_local_field(h, J, s, L, q, i, H + i * q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gibbs sampling (Sec. 2.1, Monte Carlo estimation of the gradient): one     */
+/* sweep proposes a new state at every site; sites are visited in the order  */
+/* i = 0..L-1, and site i is redrawn from its exact conditional               */
+/* P(a) ~ exp(beta * H_i(a)).                                                 */
+/* Draw rule (inverse CDF): e_a = exp(l_a - max l), S_a = sum_{b<=a} e_b in   */
+/* ascending b, CDF_a = S_a / S_{q-1}, a_new = #{a in 0..q-2 : CDF_a <= u}.   */
+/* The distance from u to the nearest CDF_a (a <= q-2) is the "margin" of the */
+/* visit; it is recorded per (chain, sweep, site) when margins != NULL.       */
+/* ------------------------------------------------------------------------ */
+void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
+               int32_t L, int32_t q, int32_t sweeps, uint64_t seed,
+               uint64_t sweep_offset, double beta, double* margins,
+               int64_t* flips)
+{
+    double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
+    double* e = (double*)malloc(sizeof(double) * (size_t)q);
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)q);
+    int64_t nflip = 0;
+    for (int64_t c = 0; c < N; ++c) {
+        int8_t* s = chains + c * L;
+        for (int32_t sw = 0; sw < sweeps; ++sw) {
+            uint64_t sg = sweep_offset + (uint64_t)sw;
+            for (int32_t i = 0; i < L; ++i) {
+                orc_local_field(h, J, s, L, q, i, Hi);
+                double mx = -INFINITY;
+                for (int32_t a = 0; a < q; ++a) {
+                    double l = beta * Hi[a];
+                    if (l > mx) mx = l;
+                }
+                double S = 0.0;
+                for (int32_t a = 0; a < q; ++a) {
+                    e[a] = exp(beta * Hi[a] - mx);
+                    S += e[a];
+                    cdf[a] = S; /* running sum, normalised below */
+                }
+                for (int32_t a = 0; a < q; ++a) cdf[a] = cdf[a] / S;
+                double u = orc_gibbs_uniform(seed, (uint64_t)c, sg, i);
+                int32_t anew = 0;
+                double margin = INFINITY;
+                for (int32_t a = 0; a < q - 1; ++a) {
+                    if (cdf[a] <= u) anew += 1;
+                    double d = fabs(u - cdf[a]);
+                    if (d < margin) margin = d;
+                }
+                if (margins) margins[((size_t)c * sweeps + sw) * L + i] = margin;
+                if (anew != s[i]) nflip += 1;
+                s[i] = (int8_t)anew;
+            }
+        }
+    }
+    if (flips) *flips = nflip;
+    free(Hi);
+    free(e);
+    free(cdf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model marginals estimated from N chains (unit weights): p = count / N.     */
+/* Diagonal blocks hold delta_ab p_i(a) by the same definition.               */
+/* ------------------------------------------------------------------------ */
+void orc_chain_freqs(const int8_t* chains, int64_t N, int32_t L, int32_t q,
+                     double* p1, double* p2)
+{
+    const int64_t Lq = (int64_t)L * q;
+    memset(p1, 0, sizeof(double) * (size_t)Lq);
+    memset(p2, 0, sizeof(double) * (size_t)Lq * (size_t)Lq);
+    for (int64_t c = 0; c < N; ++c) {
+        const int8_t* s = chains + c * L;
+        for (int32_t i = 0; i < L; ++i) {
+            p1[i * q + s[i]] += 1.0;
+            for (int32_t j = 0; j < L; ++j)
+                p2[IDX2(i * q + s[i], j * q + s[j], Lq)] += 1.0;
+        }
+    }
+    for (int64_t r = 0; r < Lq; ++r) p1[r] = p1[r] / (double)N;
+    for (int64_t k = 0; k < Lq * Lq; ++k) p2[k] = p2[k] / (double)N;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Convergence check of Sec. 2.1: Pearson correlation between the connected  */
+/* correlations (Eq. 6) C^data = f_ij - f_i f_j and C^model = p_ij - p_i p_j */
+/* over all i<j and all a, b, in (i, j, a, b) lexicographic order; two-pass. */
+/* ------------------------------------------------------------------------ */
+double orc_pearson(const double* f1, const double* f2, const double* p1,
+                   const double* p2, int32_t L, int32_t q)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double sx = 0.0, sy = 0.0;
+    int64_t n = 0;
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t j = i + 1; j < L; ++j)
+            for (int32_t a = 0; a < q; ++a)
+                for (int32_t b = 0; b < q; ++b) {
+                    size_t k = IDX2(i * q + a, j * q + b, Lq);
+                    sx += f2[k] - f1[i * q + a] * f1[j * q + b];
+                    sy += p2[k] - p1[i * q + a] * p1[j * q + b];
+                    n += 1;
+                }
+    double mx = sx / (double)n, my = sy / (double)n;
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t j = i + 1; j < L; ++j)
+            for (int32_t a = 0; a < q; ++a)
+                for (int32_t b = 0; b < q; ++b) {
+                    size_t k = IDX2(i * q + a, j * q + b, Lq);
+                    double x = f2[k] - f1[i * q + a] * f1[j * q + b] - mx;
+                    double y = p2[k] - p1[i * q + a] * p1[j * q + b] - my;
+                    sxx += x * x;
+                    syy += y * y;
+                    sxy += x * y;
+                }
+    return sxy / sqrt(sxx * syy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boltzmann-learning update, Eq. (5):                                        */
+/*   h_i(a)    <- h_i(a)    + lr (f_i(a)    - p_i(a))                         */
+/*   J_ij(a,b) <- J_ij(a,b) + lr (f_ij(a,b) - p_ij(a,b))      (i != j)        */
+/* in double, rounded once to float; diagonal blocks J_ii stay 0 (Sec. 2.1). */
+/* ------------------------------------------------------------------------ */
+void orc_update(float* h, float* J, const double* f1, const double* f2,
+                const double* p1, const double* p2, int32_t L, int32_t q,
+                double lr)
+{
+    const int64_t Lq = (int64_t)L * q;
+    for (int64_t r = 0; r < Lq; ++r) {
+        double d = f1[r] - p1[r];
+        double t = lr * d;
+        h[r] = (float)((double)h[r] + t);
+    }
+    for (int64_t r1 = 0; r1 < Lq; ++r1)
+        for (int64_t r2 = 0; r2 < Lq; ++r2) {
+            size_t k = IDX2(r1, r2, Lq);
+            if (r1 / q == r2 / q) {
+                J[k] = 0.0f;
+                continue;
+            }
+            double d = f2[k] - p2[k];
+            double t = lr * d;
+            J[k] = (float)((double)J[k] + t);
+        }
+}
+
+/* One epoch of persistent-chain Boltzmann learning (Sec. 2.1): `sweeps`
+ * Gibbs sweeps at beta = 1 with global sweep index epoch*sweeps + s, model
+ * marginals from the final chain state, the Pearson check of (f, p), then the
+ * update of Eq. (5).  Returns the Pearson coefficient. */
+double orc_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L,
+                      int32_t q, const double* f1, const double* f2, double lr,
+                      int32_t sweeps, uint64_t seed, uint64_t epoch,
+                      double* margins, int64_t* flips)
+{
+    const int64_t Lq = (int64_t)L * q;
+    orc_gibbs(h, J, chains, N, L, q, sweeps, seed, epoch * (uint64_t)sweeps, 1.0,
+              margins, flips);
+    double* p1 = (double*)malloc(sizeof(double) * (size_t)Lq);
+    double* p2 = (double*)malloc(sizeof(double) * (size_t)Lq * (size_t)Lq);
+    orc_chain_freqs(chains, N, L, q, p1, p2);
+    double r = orc_pearson(f1, f2, p1, p2, L, q);
+    orc_update(h, J, f1, f2, p1, p2, L, q, lr);
+    free(p1);
+    free(p2);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-mutant library (Sec. 4.4): dE[i*q+b] = E(mutant) - E(wild type),   */
+/* the mutant being the wild type with site i set to b; two brute-force       */
+/* energies per entry (dE = 0 where b is the wild-type state).                */
+/* ------------------------------------------------------------------------ */
+void orc_mutant_scan(const float* h, const float* J, const int8_t* wt, int32_t L,
+                     int32_t q, double* dE)
+{
+    int8_t* s = (int8_t*)malloc((size_t)L);
+    memcpy(s, wt, (size_t)L);
+    double e0 = orc_energy_one(h, J, wt, L, q);
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t b = 0; b < q; ++b) {
+            s[i] = (int8_t)b;
+            dE[i * q + b] = orc_energy_one(h, J, s, L, q) - e0;
+            s[i] = wt[i];
+        }
+    free(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contact score, Eq. (13) and Sec. 4.2: each coupling block J_ij (i != j)   */
+/* is moved to the zero-sum gauge over all q states,                          */
+/*   J0(a,b) = J(a,b) - mean_b' J(a,b') - mean_a' J(a',b) + mean_a'b' J,      */
+/* then F_ij = sqrt(sum_{a,b != gap} J0(a,b)^2), F_ii = 0, and                */
+/* F^APC_ij = F_ij - (sum_k F_ik)(sum_k F_kj) / sum_kl F_kl (diagonal = 0).   */
+/* gap < 0 keeps every state in the norm.                                     */
+/* ------------------------------------------------------------------------ */
+void orc_apc_frobenius(const float* J, int32_t L, int32_t q, int32_t gap,
+                       double* F, double* Fapc)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double* B = (double*)malloc(sizeof(double) * (size_t)q * (size_t)q);
+    double* rm = (double*)malloc(sizeof(double) * (size_t)q);
+    double* cm = (double*)malloc(sizeof(double) * (size_t)q);
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t j = 0; j < L; ++j) {
+            if (i == j) {
+                F[(size_t)i * L + j] = 0.0;
+                continue;
+            }
+            double all = 0.0;
+            for (int32_t a = 0; a < q; ++a)
+                for (int32_t b = 0; b < q; ++b) {
+                    B[a * q + b] = (double)J[IDX2(i * q + a, j * q + b, Lq)];
+                    all += B[a * q + b];
+                }
+            all /= (double)q * (double)q;
+            for (int32_t a = 0; a < q; ++a) {
+                double s = 0.0;
+                for (int32_t b = 0; b < q; ++b) s += B[a * q + b];
+                rm[a] = s / (double)q;
+            }
+            for (int32_t b = 0; b < q; ++b) {
+                double s = 0.0;
+                for (int32_t a = 0; a < q; ++a) s += B[a * q + b];
+                cm[b] = s / (double)q;
+            }
+            double ss = 0.0;
+            for (int32_t a = 0; a < q; ++a)
+                for (int32_t b = 0; b < q; ++b) {
+                    if (a == gap || b == gap) continue;
+                    double z = B[a * q + b] - rm[a] - cm[b] + all;
+                    ss += z * z;
+                }
+            F[(size_t)i * L + j] = sqrt(ss);
+        }
+    double* S = (double*)malloc(sizeof(double) * (size_t)L);
+    double tot = 0.0;
+    for (int32_t i = 0; i < L; ++i) {
+        double s = 0.0;
+        for (int32_t k = 0; k < L; ++k) s += F[(size_t)i * L + k];
+        S[i] = s;
+        tot += s;
+    }
+    for (int32_t i = 0; i < L; ++i)
+        for (int32_t j = 0; j < L; ++j)
+            Fapc[(size_t)i * L + j] =
+                (i == j) ? 0.0 : F[(size_t)i * L + j] - S[i] * S[j] / tot;
+    free(S);
+    free(B);
+    free(rm);
+    free(cm);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact enumeration of all q^L states of a tiny model at inverse            */
+/* temperature beta: log Z = log sum_s exp(-beta E(s)) (log-sum-exp), exact  */
+/* marginals p1 [L*q] and p2 [Lq*Lq] (diagonal blocks delta_ab p_i(a)).       */
+/* Returns 0, or -1 if q^L exceeds 2^24.                                       */
+/* ------------------------------------------------------------------------ */
+int orc_enumerate(const float* h, const float* J, int32_t L, int32_t q,
+                  double beta, double* p1, double* p2, double* logZ)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double nstates_d = pow((double)q, (double)L);
+    if (nstates_d > 16777216.0) return -1;
+    int64_t nstates = (int64_t)nstates_d;
+    int8_t* s = (int8_t*)malloc((size_t)L);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)nstates);
+    double mx = -INFINITY;
+    for (int64_t k = 0; k < nstates; ++k) {
+        int64_t t = k;
+        for (int32_t i = L - 1; i >= 0; --i) { s[i] = (int8_t)(t % q); t /= q; }
+        lw[k] = -beta * orc_energy_one(h, J, s, L, q);
+        if (lw[k] > mx) mx = lw[k];
+    }
+    double Z = 0.0;
+    for (int64_t k = 0; k < nstates; ++k) Z += exp(lw[k] - mx);
+    *logZ = mx + log(Z);
+    memset(p1, 0, sizeof(double) * (size_t)Lq);
+    memset(p2, 0, sizeof(double) * (size_t)Lq * (size_t)Lq);
+    for (int64_t k = 0; k < nstates; ++k) {
+        int64_t t = k;
+        for (int32_t i = L - 1; i >= 0; --i) { s[i] = (int8_t)(t % q); t /= q; }
+        double p = exp(lw[k] - *logZ);
+        for (int32_t i = 0; i < L; ++i) {
+            p1[i * q + s[i]] += p;
+            for (int32_t j = 0; j < L; ++j) p2[IDX2(i * q + s[i], j * q + s[j], Lq)] += p;
+        }
+    }
+    free(s);
+    free(lw);
+    return 0;
+}

@@ -1,0 +1,243 @@
+"""Python view of the FP64 CPU oracle (bmdca_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product path. It shares no
+code with the HIP library; it implements the same written definitions of the
+method (adabmDCA 2.0, arXiv:2501.18456) independently, in double precision.
+
+Every function takes and returns numpy arrays. Parameters follow the storage
+conventions of the library: h float32 [L, q] (or flat L*q), J float32
+[L*q, L*q] full-symmetric with zero diagonal blocks, tokens int8 0..q-1.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bmdca_oracle.c")
+_LIB = os.path.join(_HERE, "libbmdca_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, contraction off) into oracle/."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+_p = C.c_void_p
+_i32, _i64, _u64, _f64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+
+
+def _declare(L):
+    sig = {
+        "orc_philox4x32_10": (None, [_p, _p, _p]),
+        "orc_gibbs_uniform": (_f64, [_u64, _u64, _u64, _i32]),
+        "orc_init_chains": (None, [_p, _i64, _i32, _i32, _u64]),
+        "orc_identity_threshold": (_i32, [_f64, _i32]),
+        "orc_reweight": (None, [_p, _i64, _i32, _f64, _p, _p, _p]),
+        "orc_stats": (None, [_p, _p, _i64, _i32, _i32, _f64, _p, _p, _p]),
+        "orc_energy_one": (_f64, [_p, _p, _p, _i32, _i32]),
+        "orc_energy": (None, [_p, _p, _p, _i64, _i32, _i32, _p]),
+        "orc_local_field": (None, [_p, _p, _p, _i32, _i32, _i32, _p]),
+        "orc_local_fields_all": (None, [_p, _p, _p, _i32, _i32, _p]),
+        "orc_gibbs": (None, [_p, _p, _p, _i64, _i32, _i32, _i32, _u64, _u64, _f64, _p, _p]),
+        "orc_chain_freqs": (None, [_p, _i64, _i32, _i32, _p, _p]),
+        "orc_pearson": (_f64, [_p, _p, _p, _p, _i32, _i32]),
+        "orc_update": (None, [_p, _p, _p, _p, _p, _p, _i32, _i32, _f64]),
+        "orc_train_step": (_f64, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32, _u64,
+                                  _u64, _p, _p]),
+        "orc_mutant_scan": (None, [_p, _p, _p, _i32, _i32, _p]),
+        "orc_apc_frobenius": (None, [_p, _i32, _i32, _i32, _p, _p]),
+        "orc_enumerate": (C.c_int, [_p, _p, _i32, _i32, _f64, _p, _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i8(a):
+    return np.ascontiguousarray(a, dtype=np.int8)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (Salmon et al., SC'11)
+# --------------------------------------------------------------------------
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def gibbs_uniform(seed: int, c: int, sg: int, i: int) -> float:
+    return lib().orc_gibbs_uniform(seed, c, sg, i)
+
+
+def init_chains(N: int, L: int, q: int, seed: int) -> np.ndarray:
+    ch = np.zeros((N, L), dtype=np.int8)
+    lib().orc_init_chains(_ptr(ch), N, L, q, seed)
+    return ch
+
+
+# --------------------------------------------------------------------------
+# Pre-processing (Sec. 2.3)
+# --------------------------------------------------------------------------
+def identity_threshold(theta: float, L: int) -> int:
+    return lib().orc_identity_threshold(theta, L)
+
+
+def reweight(msa, theta: float = 0.8):
+    msa = _i8(msa)
+    M, L = msa.shape
+    n = np.zeros(M, dtype=np.int32)
+    w = np.zeros(M, dtype=np.float64)
+    meff = np.zeros(1, dtype=np.float64)
+    lib().orc_reweight(_ptr(msa), M, L, theta, _ptr(n), _ptr(w), _ptr(meff))
+    return n, w, float(meff[0])
+
+
+def stats(X, q: int, w=None, pseudocount: float = -1.0):
+    """Returns (f1 [L*q], f2 [Lq, Lq], meff)."""
+    X = _i8(X)
+    M, L = X.shape
+    Lq = L * q
+    f1 = np.zeros(Lq, dtype=np.float64)
+    f2 = np.zeros((Lq, Lq), dtype=np.float64)
+    meff = np.zeros(1, dtype=np.float64)
+    wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    lib().orc_stats(_ptr(X), _ptr(wv), M, L, q, pseudocount, _ptr(f1), _ptr(f2), _ptr(meff))
+    return f1, f2, float(meff[0])
+
+
+# --------------------------------------------------------------------------
+# Energies and fields (Eq. 1)
+# --------------------------------------------------------------------------
+def energy(h, J, seqs, q: int):
+    h, J, seqs = _f32(h), _f32(J), _i8(seqs)
+    B, L = seqs.shape
+    E = np.zeros(B, dtype=np.float64)
+    lib().orc_energy(_ptr(h), _ptr(J), _ptr(seqs), B, L, q, _ptr(E))
+    return E
+
+
+def local_fields(h, J, s, q: int):
+    h, J, s = _f32(h), _f32(J), _i8(s)
+    L = s.shape[0]
+    H = np.zeros(L * q, dtype=np.float64)
+    lib().orc_local_fields_all(_ptr(h), _ptr(J), _ptr(s), L, q, _ptr(H))
+    return H
+
+
+# --------------------------------------------------------------------------
+# Sampling and learning (Sec. 2.1)
+# --------------------------------------------------------------------------
+def gibbs(h, J, chains, q: int, sweeps: int, seed: int, sweep_offset: int = 0,
+          beta: float = 1.0, want_margins: bool = False):
+    """Returns (new chains, margins [N, sweeps, L] or None, flips)."""
+    h, J = _f32(h), _f32(J)
+    ch = _i8(chains).copy()
+    N, L = ch.shape
+    mg = np.zeros((N, sweeps, L), dtype=np.float64) if want_margins else None
+    flips = np.zeros(1, dtype=np.int64)
+    lib().orc_gibbs(_ptr(h), _ptr(J), _ptr(ch), N, L, q, sweeps, seed, sweep_offset,
+                    float(beta), _ptr(mg), _ptr(flips))
+    return ch, mg, int(flips[0])
+
+
+def chain_freqs(chains, q: int):
+    ch = _i8(chains)
+    N, L = ch.shape
+    p1 = np.zeros(L * q, dtype=np.float64)
+    p2 = np.zeros((L * q, L * q), dtype=np.float64)
+    lib().orc_chain_freqs(_ptr(ch), N, L, q, _ptr(p1), _ptr(p2))
+    return p1, p2
+
+
+def pearson(f1, f2, p1, p2, L: int, q: int) -> float:
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (f1, f2, p1, p2)]
+    return lib().orc_pearson(*[_ptr(x) for x in a], L, q)
+
+
+def update(h, J, f1, f2, p1, p2, L: int, q: int, lr: float):
+    """Eq. (5) update; returns new (h, J) as float32 copies."""
+    h = _f32(h).copy()
+    J = _f32(J).copy()
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (f1, f2, p1, p2)]
+    lib().orc_update(_ptr(h), _ptr(J), *[_ptr(x) for x in a], L, q, lr)
+    return h, J
+
+
+def train_step(h, J, chains, f1, f2, q: int, lr: float, sweeps: int, seed: int,
+               epoch: int, want_margins: bool = False):
+    """One epoch. Returns (h', J', chains', pearson, margins, flips)."""
+    h = _f32(h).copy()
+    J = _f32(J).copy()
+    ch = _i8(chains).copy()
+    N, L = ch.shape
+    f1 = np.ascontiguousarray(f1, dtype=np.float64)
+    f2 = np.ascontiguousarray(f2, dtype=np.float64)
+    mg = np.zeros((N, sweeps, L), dtype=np.float64) if want_margins else None
+    flips = np.zeros(1, dtype=np.int64)
+    r = lib().orc_train_step(_ptr(h), _ptr(J), _ptr(ch), N, L, q, _ptr(f1), _ptr(f2), lr,
+                             sweeps, seed, epoch, _ptr(mg), _ptr(flips))
+    return h, J, ch, r, mg, int(flips[0])
+
+
+# --------------------------------------------------------------------------
+# Applications (Sec. 4)
+# --------------------------------------------------------------------------
+def mutant_scan(h, J, wt, q: int):
+    h, J, wt = _f32(h), _f32(J), _i8(wt)
+    L = wt.shape[0]
+    dE = np.zeros(L * q, dtype=np.float64)
+    lib().orc_mutant_scan(_ptr(h), _ptr(J), _ptr(wt), L, q, _ptr(dE))
+    return dE
+
+
+def apc_frobenius(J, L: int, q: int, gap: int = 0):
+    J = _f32(J)
+    F = np.zeros((L, L), dtype=np.float64)
+    Fa = np.zeros((L, L), dtype=np.float64)
+    lib().orc_apc_frobenius(_ptr(J), L, q, gap, _ptr(F), _ptr(Fa))
+    return F, Fa
+
+
+def enumerate_exact(h, J, L: int, q: int, beta: float = 1.0):
+    """Exact marginals by enumeration of all q^L states: (p1, p2, logZ)."""
+    h, J = _f32(h), _f32(J)
+    p1 = np.zeros(L * q, dtype=np.float64)
+    p2 = np.zeros((L * q, L * q), dtype=np.float64)
+    lz = np.zeros(1, dtype=np.float64)
+    rc = lib().orc_enumerate(_ptr(h), _ptr(J), L, q, beta, _ptr(p1), _ptr(p2), _ptr(lz))
+    if rc != 0:
+        raise ValueError("q^L too large for enumeration")
+    return p1, p2, float(lz[0])

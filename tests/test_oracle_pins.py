@@ -1,0 +1,440 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself:
+published known-answer vectors, closed forms, invariants of the definitions,
+library routines that compute a special case, and exact enumeration written
+independently with numpy. Each test names the passage of the paper it pins.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+from scipy.special import logsumexp
+
+from oracle import oracle as O
+from paper_2501_18456_amd import synth
+from tests.conftest import GOLDEN
+
+
+# ---------------------------------------------------------------- helpers
+def onehot(X, q):
+    M, L = X.shape
+    Y = np.zeros((M, L * q))
+    Y[np.arange(M)[:, None], np.arange(L)[None, :] * q + X] = 1.0
+    return Y
+
+
+def energy_quadratic(h, J, s, q):
+    """Eq. (1) as a quadratic form of the one-hot vector x:
+    E = -h.x - x^T J x / 2 (J full-symmetric with zero diagonal blocks)."""
+    x = onehot(s[None, :], q)[0]
+    hd = h.reshape(-1).astype(np.float64)
+    Jd = J.astype(np.float64)
+    return -(hd @ x) - 0.5 * (x @ Jd @ x)
+
+
+def enumerate_numpy(h, J, L, q, beta=1.0):
+    states = np.array(list(itertools.product(range(q), repeat=L)), dtype=np.int8)
+    E = np.array([energy_quadratic(h, J, s, q) for s in states])
+    lz = logsumexp(-beta * E)
+    p = np.exp(-beta * E - lz)
+    X = onehot(states, q)
+    p1 = X.T @ p
+    p2 = (X * p[:, None]).T @ X
+    return p1, p2, lz, states, p
+
+
+def tiny_model(seed, L=4, q=3, sJ=0.1):
+    return synth.planted_dense(L, q, seed, sigma_h=1.0, sigma_J=sJ)
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    path = os.path.join(GOLDEN, "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = O.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_gibbs_uniform_is_24bit_and_uniform():
+    u = np.array([O.gibbs_uniform(7, c, 3, i) for c in range(200) for i in range(50)])
+    assert np.all(u >= 0) and np.all(u < 1)
+    assert np.all((u * 2 ** 24) == np.floor(u * 2 ** 24))
+    # uniformity: 10 bins, chi-square at a loose level
+    cnt, _ = np.histogram(u, bins=10, range=(0, 1))
+    chi2 = ((cnt - len(u) / 10) ** 2 / (len(u) / 10)).sum()
+    assert chi2 < 40.0  # 9 dof; p < 1e-5
+
+
+def test_init_chains_uniform_tokens():
+    q = 21
+    ch = O.init_chains(4000, 30, q, seed=11)
+    assert ch.min() == 0 and ch.max() == q - 1
+    cnt = np.bincount(ch.reshape(-1), minlength=q)
+    exp = ch.size / q
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < 60.0  # 20 dof
+    # chains and sites get different draws
+    assert not np.array_equal(ch[0], ch[1])
+    assert np.array_equal(ch, O.init_chains(4000, 30, q, seed=11))
+
+
+# ---------------------------------------------------------------- reweighting (Eq. 7)
+def test_identity_threshold_reading():
+    assert O.identity_threshold(0.8, 35) == 28  # 0.8*35 rounds above 28 in FP64
+    assert O.identity_threshold(0.8, 20) == 16
+    assert O.identity_threshold(0.8, 10) == 8
+    assert O.identity_threshold(0.8, 11) == 9
+    assert O.identity_threshold(1.0, 17) == 17
+    assert O.identity_threshold(0.0, 17) == 0
+
+
+def test_reweight_identical_and_random():
+    X = np.tile(synth.random_sequences(1, 30, 21, 1), (50, 1))
+    n, w, meff = O.reweight(X, 0.8)
+    assert np.all(n == 50) and np.allclose(w, 1 / 50) and abs(meff - 1.0) < 1e-14
+    X = synth.random_sequences(300, 100, 21, 2)
+    n, w, meff = O.reweight(X, 0.8)
+    assert np.all(n == 1) and meff == 300.0
+
+
+def test_reweight_threshold_boundary():
+    L, q, theta = 35, 21, 0.8
+    T = 28
+    g = np.random.default_rng(3)
+    A = g.integers(0, q, L).astype(np.int8)
+    B = A.copy()
+    pos = g.choice(L, L - T, replace=False)  # exactly T matches
+    B[pos] = (B[pos] + 1) % q
+    C = A.copy()
+    pos = g.choice(L, L - T + 1, replace=False)  # T - 1 matches
+    C[pos] = (C[pos] + 1) % q
+    n, w, _ = O.reweight(np.stack([A, B]), theta)
+    assert list(n) == [2, 2]
+    n, w, _ = O.reweight(np.stack([A, C]), theta)
+    assert list(n) == [1, 1]
+
+
+def test_reweight_matches_scipy_hamming():
+    X = synth.clustered_msa(400, 40, 21, seed=4)
+    n, w, meff = O.reweight(X, 0.8)
+    ident = (1.0 - cdist(X, X, metric="hamming")) * 40
+    n_ref = (np.rint(ident) >= 32).sum(axis=1)
+    assert np.array_equal(n, n_ref)
+    assert n.max() > 1  # the clustered alignment is redundant
+    assert np.array_equal(w, 1.0 / n_ref)
+    assert abs(meff - (1.0 / n_ref).sum()) < 1e-12 * meff
+
+
+# ---------------------------------------------------------------- statistics (Eqs. 3, 8, 9)
+@pytest.mark.parametrize("weighted", [False, True])
+def test_stats_against_onehot_products(weighted):
+    L, q, M = 12, 5, 300
+    X = synth.clustered_msa(M, L, q, seed=5)
+    w = synth.weights_open_unit(M, 6) if weighted else None
+    f1, f2, meff = O.stats(X, q, w, pseudocount=0.0)
+    Y = onehot(X, q)
+    ww = np.ones(M) if w is None else w
+    assert abs(meff - ww.sum()) < 1e-12 * meff
+    ref1 = (ww @ Y) / ww.sum()
+    ref2 = (Y * ww[:, None]).T @ Y / ww.sum()
+    assert np.allclose(f1, ref1, rtol=0, atol=1e-14)
+    off = np.kron(1 - np.eye(L), np.ones((q, q))).astype(bool)
+    assert np.allclose(f2[off], ref2[off], rtol=0, atol=1e-14)
+    assert np.allclose(f2[~off], ref2[~off], rtol=0, atol=1e-14)  # diag blocks = diag(f1)
+    if not weighted:
+        # unit weights: the single rounding of the exact integer count / M
+        assert np.array_equal(f1, Y.sum(0) / M)
+
+
+def test_stats_invariants_with_pseudocount():
+    L, q, M = 10, 21, 200
+    X = synth.clustered_msa(M, L, q, seed=7)
+    w = synth.weights_open_unit(M, 8)
+    f1, f2, meff = O.stats(X, q, w, pseudocount=-1.0)
+    alpha = 1.0 / meff
+    F1 = f1.reshape(L, q)
+    assert np.allclose(F1.sum(1), 1.0, atol=1e-13)
+    F2 = f2.reshape(L, q, L, q)
+    for i in range(L):
+        for j in range(L):
+            if i == j:
+                assert np.allclose(F2[i, :, i, :], np.diag(F1[i]), atol=0)
+                continue
+            assert np.allclose(F2[i, :, j, :].sum(1), F1[i], atol=1e-13)  # marginalisation
+            assert np.allclose(F2[i, :, j, :].sum(0), F1[j], atol=1e-13)
+    assert np.array_equal(f2, f2.T)
+    off = np.kron(1 - np.eye(L), np.ones((q, q))).astype(bool)
+    assert f2[off].min() >= alpha / q ** 2 * (1 - 1e-12)  # pseudocount floor
+    f1a, f2a, _ = O.stats(X, q, w, pseudocount=1.0)
+    assert np.allclose(f1a, 1 / q, atol=1e-15)
+    assert np.allclose(f2a[off], 1 / q ** 2, atol=1e-15)
+
+
+# ---------------------------------------------------------------- energy (Eq. 1)
+def test_energy_matches_quadratic_form_and_field_only():
+    L, q = 9, 21
+    h, J = synth.planted_dense(L, q, seed=9, sigma_J=0.3)
+    S = synth.random_sequences(40, L, q, 10)
+    E = O.energy(h, J, S, q)
+    ref = np.array([energy_quadratic(h, J, s, q) for s in S])
+    assert np.allclose(E, ref, rtol=0, atol=1e-11)
+    E0 = O.energy(h, np.zeros_like(J), S, q)
+    hd = h.astype(np.float64)
+    assert np.allclose(E0, [-hd[np.arange(L), s].sum() for s in S], atol=1e-12)
+
+
+def test_energy_gauge_invariance():
+    L, q = 6, 5
+    h, J = synth.planted_dense(L, q, seed=12, sigma_J=0.5)
+    S = synth.random_sequences(30, L, q, 13)
+    E = O.energy(h, J, S, q)
+    g = np.random.default_rng(14)
+    J4 = J.reshape(L, q, L, q).astype(np.float64).copy()
+    h2 = h.astype(np.float64).copy()
+    # J_ij(a,b) += u(a) on block (i<j) and its transpose; h_i(a) -= u(a)
+    for i in range(L):
+        for j in range(i + 1, L):
+            u = g.normal(size=q) * 0.25
+            J4[i, :, j, :] += u[:, None]
+            J4[j, :, i, :] += u[None, :]
+            h2[i] -= u
+    E2 = O.energy(h2.astype(np.float32), J4.reshape(L * q, L * q).astype(np.float32), S, q)
+    assert np.allclose(E, E2, atol=1e-5)
+
+
+def test_local_field_is_energy_difference():
+    L, q = 8, 7
+    h, J = synth.planted_dense(L, q, seed=15, sigma_J=0.4)
+    s = synth.random_sequences(1, L, q, 16)[0]
+    H = O.local_fields(h, J, s, q).reshape(L, q)
+    e0 = energy_quadratic(h, J, s, q)
+    for i in range(L):
+        for a in range(q):
+            t = s.copy()
+            t[i] = a
+            assert abs((energy_quadratic(h, J, t, q) - e0) + (H[i, a] - H[i, s[i]])) < 1e-11
+
+
+# ---------------------------------------------------------------- enumeration
+def test_enumeration_matches_numpy():
+    h, J = tiny_model(17, sJ=0.5)
+    p1, p2, lz = O.enumerate_exact(h, J, 4, 3)
+    r1, r2, rz, _, _ = enumerate_numpy(h, J, 4, 3)
+    assert abs(lz - rz) < 1e-12
+    assert np.allclose(p1, r1, atol=1e-14) and np.allclose(p2, r2, atol=1e-14)
+
+
+# ---------------------------------------------------------------- Gibbs sampler (Sec. 2.1)
+def _sidak_z(n_tests, alpha=0.01):
+    from scipy.stats import norm
+    a1 = 1 - (1 - alpha) ** (1.0 / n_tests)
+    return norm.ppf(1 - a1 / 2)
+
+
+def _marginal_check(chains, q, p1, p2):
+    """Max standardized deviation of sampled p_i, p_ij from exact values."""
+    N = chains.shape[0]
+    Y = onehot(chains, q)
+    s1 = Y.mean(0)
+    s2 = Y.T @ Y / N
+    z1 = np.abs(s1 - p1) / np.sqrt(np.maximum(p1 * (1 - p1), 1e-12) / N)
+    z2 = np.abs(s2 - p2) / np.sqrt(np.maximum(p2 * (1 - p2), 1e-12) / N)
+    return max(z1.max(), z2.max()), len(p1) + p2.size
+
+
+def test_gibbs_conditional_matches_enumeration():
+    L, q = 4, 3
+    h, J = tiny_model(18, sJ=1.0)
+    _, _, _, states, p = enumerate_numpy(h, J, L, q)
+    idx = {tuple(s): k for k, s in enumerate(states)}
+    s = np.array([2, 0, 1, 1], dtype=np.int8)
+    H = O.local_fields(h, J, s, q).reshape(L, q)
+    for i in range(L):
+        pr = []
+        for a in range(q):
+            t = s.copy()
+            t[i] = a
+            pr.append(p[idx[tuple(t)]])
+        pr = np.array(pr) / np.sum(pr)
+        cond = np.exp(H[i] - H[i].max())
+        cond /= cond.sum()
+        assert np.allclose(pr, cond, atol=1e-13)
+
+
+@pytest.mark.parametrize("sJ", [0.1, 1.0])
+def test_gibbs_stationary_marginals(sJ):
+    L, q = 4, 3
+    h, J = tiny_model(19, sJ=sJ)
+    p1, p2, _, _, _ = enumerate_numpy(h, J, L, q)
+    ch0 = O.init_chains(20000, L, q, seed=21)
+    ch, _, flips = O.gibbs(h, J, ch0, q, sweeps=30, seed=22)
+    zmax, ntest = _marginal_check(ch, q, p1, p2)
+    assert zmax < _sidak_z(ntest), zmax
+    assert flips > 0
+
+
+def test_gibbs_power_ignoring_couplings_fails():
+    L, q = 4, 3
+    h, J = tiny_model(19, sJ=1.0)
+    p1, p2, _, _, _ = enumerate_numpy(h, J, L, q)
+    ch0 = O.init_chains(20000, L, q, seed=21)
+    ch, _, _ = O.gibbs(h, np.zeros_like(J), ch0, q, sweeps=30, seed=22)
+    zmax, ntest = _marginal_check(ch, q, p1, p2)
+    assert zmax > _sidak_z(ntest)
+
+
+def test_gibbs_two_state_and_beta():
+    h = np.array([[0.3, -0.9]], dtype=np.float32)
+    J = np.zeros((2, 2), dtype=np.float32)
+    ch, _, _ = O.gibbs(h, J, np.zeros((40000, 1), np.int8), 2, sweeps=1, seed=5)
+    p = np.exp(-0.9) / (np.exp(0.3) + np.exp(-0.9))
+    f = ch.mean()
+    assert abs(f - p) < 5 * np.sqrt(p * (1 - p) / 40000)
+    ch, _, _ = O.gibbs(h, J, np.zeros((40000, 1), np.int8), 2, sweeps=1, seed=5, beta=0.0)
+    assert abs(ch.mean() - 0.5) < 5 * np.sqrt(0.25 / 40000)
+
+
+def test_gibbs_margins_and_determinism():
+    L, q = 6, 5
+    h, J = synth.planted_dense(L, q, seed=23, sigma_J=0.3)
+    ch0 = O.init_chains(50, L, q, seed=24)
+    a, mg, fa = O.gibbs(h, J, ch0, q, sweeps=3, seed=25, want_margins=True)
+    b, _, fb = O.gibbs(h, J, ch0, q, sweeps=3, seed=25)
+    assert np.array_equal(a, b) and fa == fb
+    assert mg.shape == (50, 3, L) and np.all(mg >= 0) and np.all(mg < 1)
+    # sweep offsets compose: 3 sweeps == 1 + 2 with offset
+    c, _, _ = O.gibbs(h, J, ch0, q, sweeps=1, seed=25)
+    c, _, _ = O.gibbs(h, J, c, q, sweeps=2, seed=25, sweep_offset=1)
+    assert np.array_equal(a, c)
+
+
+# ---------------------------------------------------------------- Pearson (Eq. 6)
+def test_pearson_matches_corrcoef():
+    L, q = 7, 4
+    X = synth.clustered_msa(200, L, q, seed=26)
+    f1, f2, _ = O.stats(X, q, None, -1.0)
+    ch = synth.random_sequences(150, L, q, 27)
+    p1, p2 = O.chain_freqs(ch, q)
+    r = O.pearson(f1, f2, p1, p2, L, q)
+    iu = [(i, j) for i in range(L) for j in range(i + 1, L)]
+    F1, F2 = f1.reshape(L, q), f2.reshape(L, q, L, q)
+    P1, P2 = p1.reshape(L, q), p2.reshape(L, q, L, q)
+    x = np.concatenate([(F2[i, :, j, :] - np.outer(F1[i], F1[j])).ravel() for i, j in iu])
+    y = np.concatenate([(P2[i, :, j, :] - np.outer(P1[i], P1[j])).ravel() for i, j in iu])
+    assert abs(r - np.corrcoef(x, y)[0, 1]) < 1e-12
+    assert abs(O.pearson(f1, f2, f1, f2, L, q) - 1.0) < 1e-12
+
+
+def test_chain_freqs_unit_weight_stats_agree():
+    L, q = 6, 5
+    ch = synth.random_sequences(100, L, q, 28)
+    p1, p2 = O.chain_freqs(ch, q)
+    f1, f2, _ = O.stats(ch, q, None, 0.0)
+    assert np.array_equal(p1, f1) and np.array_equal(p2, f2)
+
+
+# ---------------------------------------------------------------- update (Eq. 5)
+def test_update_converges_to_max_entropy_fixed_point():
+    """Iterating Eq. (5) with exact model marginals moves p towards f: the
+    update direction is the likelihood gradient, so the moment mismatch falls."""
+    L, q = 3, 3
+    ht, Jt = synth.planted_dense(L, q, seed=29, sigma_J=0.8)
+    f1, f2, _ = O.enumerate_exact(ht, Jt, L, q)
+    h = np.zeros((L, q), np.float32)
+    J = np.zeros((L * q, L * q), np.float32)
+    off = np.kron(1 - np.eye(L), np.ones((q, q))).astype(bool)
+    errs = []
+    for it in range(400):
+        p1, p2, _ = O.enumerate_exact(h, J, L, q)
+        errs.append(max(np.abs(f1 - p1).max(), np.abs(f2 - p2)[off].max()))
+        h, J = O.update(h, J, f1, f2, p1, p2, L, q, lr=0.5)
+    assert errs[-1] < 5e-3 * errs[0] and errs[-1] < errs[len(errs) // 2] < errs[0]
+    J4 = J.reshape(L, q, L, q)
+    for i in range(L):
+        assert np.all(J4[i, :, i, :] == 0)
+    assert np.array_equal(J, J.T)
+
+
+def test_update_rounding_and_diagonal():
+    L, q = 3, 2
+    h = np.zeros((L, q), np.float32)
+    J = np.ones((L * q, L * q), np.float32)
+    f1 = np.full(L * q, 0.5)
+    f2 = np.full((L * q, L * q), 0.25)
+    p1 = np.zeros(L * q)
+    p2 = np.zeros((L * q, L * q))
+    h2, J2 = O.update(h, J, f1, f2, p1, p2, L, q, lr=0.1)
+    assert np.all(h2 == np.float32(0.05))
+    assert np.all(J2[0, 2:] == np.float32(1.025)) and np.all(J2[0, :2] == 0)
+
+
+def test_train_step_composition():
+    L, q, N = 5, 4, 60
+    h, J = synth.planted_dense(L, q, seed=30, sigma_J=0.3)
+    f1, f2, _ = O.stats(synth.clustered_msa(100, L, q, seed=31), q, None, -1.0)
+    ch0 = O.init_chains(N, L, q, seed=32)
+    h1, J1, ch1, r, _, _ = O.train_step(h, J, ch0, f1, f2, q, 0.05, 4, seed=33, epoch=2)
+    ch_ref, _, _ = O.gibbs(h, J, ch0, q, 4, 33, sweep_offset=8)
+    p1, p2 = O.chain_freqs(ch_ref, q)
+    h_ref, J_ref = O.update(h, J, f1, f2, p1, p2, L, q, 0.05)
+    assert np.array_equal(ch1, ch_ref) and np.array_equal(h1, h_ref) and np.array_equal(J1, J_ref)
+    assert r == O.pearson(f1, f2, p1, p2, L, q)
+
+
+# ---------------------------------------------------------------- mutant scan (Sec. 4.4)
+def test_mutant_scan_against_quadratic_energies():
+    L, q = 10, 21
+    h, J = synth.planted_dense(L, q, seed=34, sigma_J=0.2)
+    wt = synth.random_sequences(1, L, q, 35)[0]
+    dE = O.mutant_scan(h, J, wt, q).reshape(L, q)
+    e0 = energy_quadratic(h, J, wt, q)
+    for i in range(L):
+        assert dE[i, wt[i]] == 0.0
+        for b in range(q):
+            t = wt.copy()
+            t[i] = b
+            assert abs(dE[i, b] - (energy_quadratic(h, J, t, q) - e0)) < 1e-11
+
+
+# ---------------------------------------------------------------- APC Frobenius (Eq. 13)
+def test_apc_closed_form_uniform_norms():
+    """Every block equal to the same zero-sum rank-1 pattern u v^T: F_ij is
+    |u_{-gap}| |v_{-gap}| for all i != j, and APC leaves F_ij / L."""
+    L, q = 6, 5
+    g = np.random.default_rng(36)
+    u = g.normal(size=q); u -= u.mean()
+    v = g.normal(size=q); v -= v.mean()
+    B = np.outer(u, v).astype(np.float32)
+    blocks = {(i, j): B for i in range(L) for j in range(i + 1, L)}
+    # symmetric storage needs J_ji = J_ij^T, and F_ji uses the transposed block:
+    J = synth.symmetric_couplings(blocks, L, q)
+    F, Fa = O.apc_frobenius(J, L, q, gap=0)
+    c = np.linalg.norm(u[1:]) * np.linalg.norm(v[1:])
+    off = ~np.eye(L, dtype=bool)
+    assert np.allclose(F[off], c, rtol=1e-6)
+    assert np.allclose(Fa[off], c / L, rtol=1e-5)
+    assert np.all(np.diag(F) == 0) and np.all(np.diag(Fa) == 0)
+
+
+def test_apc_gauge_invariance_and_symmetry():
+    L, q = 7, 5
+    _, J = synth.planted_dense(L, q, seed=37, sigma_J=0.5)
+    F, Fa = O.apc_frobenius(J, L, q, gap=0)
+    g = np.random.default_rng(38)
+    J4 = J.reshape(L, q, L, q).astype(np.float64).copy()
+    for i in range(L):
+        for j in range(i + 1, L):
+            u, v = g.normal(size=q), g.normal(size=q)
+            J4[i, :, j, :] += u[:, None] + v[None, :]
+            J4[j, :, i, :] += u[None, :] + v[:, None]
+    F2, Fa2 = O.apc_frobenius(J4.reshape(L * q, L * q).astype(np.float32), L, q, gap=0)
+    assert np.allclose(F, F2, atol=2e-5) and np.allclose(Fa, Fa2, atol=2e-5)
+    assert np.allclose(F, F.T, atol=1e-12) and np.allclose(Fa, Fa.T, atol=1e-12)
+    # the gap-excluded norm of a zero-sum block, by numpy
+    Bz = J.reshape(L, q, L, q)[1, :, 4, :].astype(np.float64)
+    Bz = Bz - Bz.mean(1, keepdims=True) - Bz.mean(0, keepdims=True) + Bz.mean()
+    assert abs(F[1, 4] - np.linalg.norm(Bz[1:, 1:])) < 1e-12
