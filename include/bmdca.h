@@ -1,0 +1,225 @@
+/*
+ * bmdca.h -- C ABI of libbmdca, the MI355X (gfx950) implementation of the
+ * Boltzmann-machine DCA training hot path of adabmDCA 2.0 (arXiv:2501.18456).
+ *
+ * Storage conventions (every call):
+ *   - Tokens are int8 in 0..q-1; token 0 is the alignment gap (Table 1 lists
+ *     the gap first).  Alignments and chains are row-major [rows][L].
+ *   - The one-hot vertex (i, a) of Sec. 2.1 has flat index r = i*q + a;
+ *     Lq = L*q.
+ *   - Fields h: float32 [Lq].  Couplings J: float32 [Lq][Lq], full-symmetric
+ *     (J[(i,a),(j,b)] == J[(j,b),(i,a)]) with all-zero diagonal blocks J_ii,
+ *     the two constraints stated with Eq. (1).  Every kernel skips j == i, so
+ *     a non-zero diagonal block is ignored, never used.
+ *   - Energy (Eq. 1): E(s) = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i, s_j);
+ *     each unordered pair is counted once.
+ *
+ * Memory and streams:
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless
+ *     its comment says otherwise.  The library allocates nothing: scratch
+ *     memory comes in through `ws` (size from bmdca_workspace_bytes).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call only enqueues work on it and returns; results are ready once the
+ *     stream has been synchronised.
+ *   - The library keeps no hidden state between calls.  Calls on different
+ *     streams do not share memory unless the caller passes the same buffers.
+ *
+ * Errors:
+ *   - Host-side validation (null pointers, sizes, q outside 2..32, theta
+ *     outside [0,1], non-finite lr, workspace too small) returns a negative
+ *     status at once, before anything is enqueued.
+ *   - Conditions only the device can see are OR-ed into *dev_err (a device
+ *     int32 that the caller zeroes and reads after synchronising):
+ *     BMDCA_DEVERR_TOKEN for a token outside 0..q-1 (the caller's duty under
+ *     pre-processing step p.1, Sec. 2.3), BMDCA_DEVERR_NONFINITE for a
+ *     non-finite parameter or Pearson value.  dev_err may be NULL where noted.
+ *   - A failed kernel launch returns BMDCA_EHIP; bmdca_last_error() then
+ *     gives the text.  The library never aborts the process.
+ */
+#ifndef BMDCA_H
+#define BMDCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BMDCA_OK = 0,
+    BMDCA_EINVAL = -1,     /* bad argument (null pointer, size, range) */
+    BMDCA_ETOKEN = -2,     /* reserved for host-checked token errors */
+    BMDCA_EWORKSPACE = -3, /* ws_bytes smaller than bmdca_workspace_bytes() */
+    BMDCA_EHIP = -4,       /* a HIP call or kernel launch failed */
+    BMDCA_ENONFINITE = -5  /* non-finite learning rate or beta */
+} bmdca_status;
+
+/* Arithmetic of the two-site statistics product (Eq. 3). */
+typedef enum {
+    BMDCA_PREC_FP32 = 0,  /* FP32 matrix cores, FP32 weights */
+    BMDCA_PREC_BF16X2 = 1 /* BF16 matrix cores; one-hot operands are exact in
+                             BF16, each weight is split w = hi + lo into two
+                             BF16 parts (two products), FP32 accumulation over
+                             chunks of at most 512 rows flushed into FP64 */
+} bmdca_prec;
+
+/* Bits OR-ed into *dev_err. */
+#define BMDCA_DEVERR_TOKEN 1
+#define BMDCA_DEVERR_NONFINITE 2
+
+/* Workspace kinds for bmdca_workspace_bytes. */
+typedef enum {
+    BMDCA_WS_REWEIGHT = 0,   /* MN = M (alignment rows) */
+    BMDCA_WS_STATS = 1,      /* MN = M */
+    BMDCA_WS_GIBBS = 2,      /* MN = N (chains) */
+    BMDCA_WS_TRAIN_STEP = 3, /* MN = N */
+    BMDCA_WS_APC = 4,        /* MN ignored */
+    BMDCA_WS_MUTANT = 5,     /* MN = B (wild types) */
+    BMDCA_WS_ENERGY = 6      /* MN = B (sequences) */
+} bmdca_ws_kind;
+
+/* Bytes of device scratch memory the call `kind` needs for these sizes
+ * (0 for an invalid request).  Any buffer at least this large, 256-byte
+ * aligned, may be passed as `ws`. */
+size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q,
+                             int32_t prec);
+
+/* Text of the last non-OK status returned on this host thread. */
+const char* bmdca_last_error(void);
+
+/* Integer identity threshold used by bmdca_reweight (host function):
+ * T = ceil(theta*L - 1e-6), the number of identical positions at and above
+ * which two sequences count as similar (Eq. 7 uses identity >= 0.8 L). */
+int32_t bmdca_identity_threshold(double theta, int32_t L);
+
+/* Uniform random chain initialisation, the "chosen uniformly at random"
+ * start of the persistent chains (Sec. 2.1).  Token of chain c at site i:
+ * (w * q) >> 32 for the Philox4x32-10 word w = out[i % 4] with key = seed
+ * (low, high 32 bits) and counter (i / 4, 0, c, 1).
+ * chains: int8 [N][L], written. */
+int bmdca_init_chains(int8_t* chains, int64_t N, int32_t L, int32_t q,
+                      uint64_t seed, void* stream);
+
+/* Importance weights, Eq. (7) (pre-processing step p.2, Sec. 2.3).
+ * msa   int8 [M][L] (read)
+ * theta identity fraction (0.8 by default in the paper)
+ * n_sim int32 [M]  out: N^(m) = #{n : identical positions >= T}, self
+ *                  included, T = bmdca_identity_threshold(theta, L);
+ *                  bit-exact integer counts, gaps count as symbols
+ * w     double [M] out: 1.0 / N^(m) (one IEEE division)
+ * meff  double [1] out: sum_m w^(m) (fixed-order reduction)
+ * ws    scratch, bmdca_workspace_bytes(BMDCA_WS_REWEIGHT, M, L, q, 0)
+ * dev_err optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1. */
+int bmdca_reweight(const int8_t* msa, int64_t M, int32_t L, int32_t q,
+                   double theta, int32_t* n_sim, double* w, double* meff,
+                   void* ws, size_t ws_bytes, int32_t* dev_err, void* stream);
+
+/* Reweighted one- and two-site frequencies, Eq. (3), with the pseudocount
+ * of Eqs. (8)-(9) (pre-processing step p.3, Sec. 2.3).
+ * X      int8 [M][L] (read)
+ * w      double [M] weights, or NULL for unit weights (M_eff = M)
+ * pseudocount  alpha; a negative value selects alpha = 1 / M_eff (the
+ *        paper's default), 0 gives the raw frequencies
+ * prec   bmdca_prec of the product; with w == NULL both forms are exact
+ * f1     double [Lq] out: (1-alpha) f_i(a) + alpha/q
+ * f2     double [Lq][Lq] out: (1-alpha) f_ij(a,b) + alpha/q^2 for i != j;
+ *        the diagonal blocks hold delta_ab f1[(i,a)]
+ * meff_out double [1] out: M_eff = sum_m w_m (fixed-order reduction)
+ * ws     scratch, bmdca_workspace_bytes(BMDCA_WS_STATS, M, L, q, prec)
+ * dev_err optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1.
+ * With w == NULL the result is the single rounding of count / M, bit-exact. */
+int bmdca_stats(const int8_t* X, const double* w, int64_t M, int32_t L,
+                int32_t q, double pseudocount, int32_t prec, double* f1,
+                double* f2, double* meff_out, void* ws, size_t ws_bytes,
+                int32_t* dev_err, void* stream);
+
+/* Gibbs sampling of the persistent chains (Sec. 2.1, "Monte Carlo
+ * estimation of the gradient"); one sweep redraws every site once, sites in
+ * the order i = 0..L-1, from the conditional P(a) ~ exp(beta * H_i(a)),
+ * H_i(a) = h_i(a) + sum_{j != i} J_ij(a, s_j).
+ * Draw: l_a = beta*H_i(a); e_a = exp(l_a - max l); S_a = sum_{b<=a} e_b;
+ * CDF_a = S_a / S_{q-1}; a_new = #{a in 0..q-2 : CDF_a <= u}, with the
+ * uniform u = (w >> 8) * 2^-24 from the Philox4x32-10 word w = out[i % 4],
+ * key = seed, counter (i / 4, sweep_offset + s, c, 0) for chain c and sweep s.
+ * The local fields are kept per chain in H_ws (float32 [N][Lq], HBM) and
+ * updated incrementally on every accepted change:
+ * H += J[(i,new),:] - J[(i,old),:].
+ * chains  int8 [N][L] in/out
+ * H_ws    float32 [N][Lq] scratch, at least
+ *         bmdca_workspace_bytes(BMDCA_WS_GIBBS, N, L, q, 0) bytes
+ * keep_fields 0: rebuild H_ws from h, J and the chains first (always valid);
+ *         1: H_ws already holds the local fields of these chains under these
+ *         h and J (left by the previous call on the same buffers), so the
+ *         rebuild is skipped -- for sampling in several slices of sweeps.
+ * flips_out optional device uint64: the number of accepted changes is added.
+ * Arithmetic is FP32; the state is integer. */
+int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
+                int32_t L, int32_t q, int32_t sweeps, uint64_t seed,
+                uint64_t sweep_offset, float beta, float* H_ws,
+                size_t H_ws_bytes, int32_t keep_fields,
+                unsigned long long* flips_out, void* stream);
+
+/* DCA energies of a batch of sequences, Eq. (1) (Sec. 4.3, "Scoring a
+ * sequence set"): E[b] = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i, s_j), FP32
+ * terms summed in FP64, rounded once to float32.
+ * seqs int8 [B][L]; E float32 [B] out.
+ * ws   scratch, bmdca_workspace_bytes(BMDCA_WS_ENERGY, B, L, q, 0)
+ * dev_err optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1. */
+int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B,
+                 int32_t L, int32_t q, float* E, void* ws, size_t ws_bytes,
+                 int32_t* dev_err, void* stream);
+
+/* One epoch of persistent-chain Boltzmann learning (Sec. 2.1):
+ *   1. `sweeps` Gibbs sweeps of the chains at beta = 1, global sweep index
+ *      epoch*sweeps + s (as bmdca_gibbs);
+ *   2. model marginals from the final chains, p = count / N, with the counts
+ *      from the one-hot product of `prec` (exact integers in both forms);
+ *   3. *pearson = Pearson correlation of C^data = f_ij - f_i f_j and
+ *      C^model = p_ij - p_i p_j (Eq. 6) over i < j and all a, b, FP64,
+ *      two-pass;
+ *   4. the update of Eq. (5) in FP64, rounded once to float32:
+ *      J_ij(a,b) += lr (f_ij(a,b) - p_ij(a,b)) for i != j, J_ii stays 0;
+ *      h_i(a)    += lr (f_i(a) - p_i(a)).
+ * h, J     float32, updated in place
+ * chains   int8 [N][L] in/out
+ * f1, f2   double data frequencies as produced by bmdca_stats
+ * pearson  double [1] out (device)
+ * flips_out optional device uint64, accepted changes added
+ * ws       scratch, bmdca_workspace_bytes(BMDCA_WS_TRAIN_STEP, N, L, q, prec)
+ * dev_err  optional; BMDCA_DEVERR_NONFINITE if an updated parameter or the
+ *          Pearson value is not finite. */
+int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L,
+                     int32_t q, const double* f1, const double* f2, double lr,
+                     int32_t sweeps, uint64_t seed, uint64_t epoch,
+                     int32_t prec, double* pearson,
+                     unsigned long long* flips_out, void* ws, size_t ws_bytes,
+                     int32_t* dev_err, void* stream);
+
+/* Single-mutant library (Sec. 4.4): for each of B wild types,
+ * dE[b][i*q + a] = E(wild type with site i set to a) - E(wild type)
+ *               = -(H_i(a) - H_i(wt_i)),  H_i(a) = h_i(a) + sum_{j!=i} J_ij(a, wt_j);
+ * dE is exactly 0 at a = wt_i.
+ * wt int8 [B][L]; dE float32 [B][Lq] out.
+ * ws scratch, bmdca_workspace_bytes(BMDCA_WS_MUTANT, B, L, q, 0). */
+int bmdca_single_mutant_scan(const float* h, const float* J, const int8_t* wt,
+                             int64_t B, int32_t L, int32_t q, float* dE,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Contact scores, Eq. (13) and Sec. 4.2: every block J_ij (i != j) is moved
+ * to the zero-sum gauge over all q states, F_ij = sqrt(sum over a, b != gap of
+ * the gauged block squared), F_ii = 0, and
+ * F_apc[i][j] = F_ij - (sum_k F_ik)(sum_k F_kj) / sum_kl F_kl (0 on the
+ * diagonal).  FP64 inside, float32 out.
+ * gap  state excluded from the norm (0 for the default alphabets), -1 = none
+ * F    float32 [L][L] out (may be NULL); F_apc float32 [L][L] out
+ * ws   scratch, bmdca_workspace_bytes(BMDCA_WS_APC, 0, L, q, 0). */
+int bmdca_apc_frobenius(const float* J, int32_t L, int32_t q, int32_t gap,
+                        float* F, float* F_apc, void* ws, size_t ws_bytes,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMDCA_H */

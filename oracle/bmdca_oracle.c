@@ -247,10 +247,13 @@ void orc_local_fields_all(const float* h, const float* J, const int8_t* s,
 /* The distance from u to the nearest CDF_a (a <= q-2) is the "margin" of the */
 /* visit; it is recorded per (chain, sweep, site) when margins != NULL.       */
 /* ------------------------------------------------------------------------ */
-void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
-               int32_t L, int32_t q, int32_t sweeps, uint64_t seed,
-               uint64_t sweep_offset, double beta, double* margins,
-               int64_t* flips)
+/* Chains chains[0..N) carry the global chain indices c0 .. c0+N-1 (the
+ * chain index is part of the Philox counter), so any contiguous slice of a
+ * large set of chains can be advanced on its own. */
+void orc_gibbs_range(const float* h, const float* J, int8_t* chains, int64_t N,
+                     int64_t c0, int32_t L, int32_t q, int32_t sweeps,
+                     uint64_t seed, uint64_t sweep_offset, double beta,
+                     double* margins, int64_t* flips)
 {
     double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
     double* e = (double*)malloc(sizeof(double) * (size_t)q);
@@ -274,7 +277,7 @@ void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
                     cdf[a] = S; /* running sum, normalised below */
                 }
                 for (int32_t a = 0; a < q; ++a) cdf[a] = cdf[a] / S;
-                double u = orc_gibbs_uniform(seed, (uint64_t)c, sg, i);
+                double u = orc_gibbs_uniform(seed, (uint64_t)(c0 + c), sg, i);
                 int32_t anew = 0;
                 double margin = INFINITY;
                 for (int32_t a = 0; a < q - 1; ++a) {
@@ -292,6 +295,15 @@ void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
     free(Hi);
     free(e);
     free(cdf);
+}
+
+void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
+               int32_t L, int32_t q, int32_t sweeps, uint64_t seed,
+               uint64_t sweep_offset, double beta, double* margins,
+               int64_t* flips)
+{
+    orc_gibbs_range(h, J, chains, N, 0, L, q, sweeps, seed, sweep_offset, beta,
+                    margins, flips);
 }
 
 /* ------------------------------------------------------------------------ */

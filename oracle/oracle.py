@@ -60,6 +60,8 @@ def _declare(L):
         "orc_local_field": (None, [_p, _p, _p, _i32, _i32, _i32, _p]),
         "orc_local_fields_all": (None, [_p, _p, _p, _i32, _i32, _p]),
         "orc_gibbs": (None, [_p, _p, _p, _i64, _i32, _i32, _i32, _u64, _u64, _f64, _p, _p]),
+        "orc_gibbs_range": (None, [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _u64, _u64, _f64, _p,
+                                   _p]),
         "orc_chain_freqs": (None, [_p, _i64, _i32, _i32, _p, _p]),
         "orc_pearson": (_f64, [_p, _p, _p, _p, _i32, _i32]),
         "orc_update": (None, [_p, _p, _p, _p, _p, _p, _i32, _i32, _f64]),
@@ -170,6 +172,19 @@ def gibbs(h, J, chains, q: int, sweeps: int, seed: int, sweep_offset: int = 0,
     flips = np.zeros(1, dtype=np.int64)
     lib().orc_gibbs(_ptr(h), _ptr(J), _ptr(ch), N, L, q, sweeps, seed, sweep_offset,
                     float(beta), _ptr(mg), _ptr(flips))
+    return ch, mg, int(flips[0])
+
+
+def gibbs_range(h, J, chains, c0: int, q: int, sweeps: int, seed: int, sweep_offset: int = 0,
+                beta: float = 1.0, want_margins: bool = False):
+    """As gibbs(), for chains whose global indices are c0, c0+1, ..."""
+    h, J = _f32(h), _f32(J)
+    ch = _i8(chains).copy()
+    N, L = ch.shape
+    mg = np.zeros((N, sweeps, L), dtype=np.float64) if want_margins else None
+    flips = np.zeros(1, dtype=np.int64)
+    lib().orc_gibbs_range(_ptr(h), _ptr(J), _ptr(ch), N, c0, L, q, sweeps, seed, sweep_offset,
+                          float(beta), _ptr(mg), _ptr(flips))
     return ch, mg, int(flips[0])
 
 

@@ -1,0 +1,67 @@
+"""ctypes view of libbmdca.so (include/bmdca.h).
+
+The library must have been built in-tree (`python -m paper_2501_18456_amd.build`);
+if it is missing, loading fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbmdca.so")
+
+# status codes (bmdca_status)
+OK, EINVAL, ETOKEN, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
+PREC_FP32, PREC_BF16X2 = 0, 1
+DEVERR_TOKEN, DEVERR_NONFINITE = 1, 2
+WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY = range(7)
+
+_p, _i32, _i64, _u64, _f64, _f32, _sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,
+                                          C.c_double, C.c_float, C.c_size_t)
+
+SIGNATURES = {
+    "bmdca_workspace_bytes": (_sz, [_i32, _i64, _i32, _i32, _i32]),
+    "bmdca_last_error": (C.c_char_p, []),
+    "bmdca_identity_threshold": (_i32, [_f64, _i32]),
+    "bmdca_init_chains": (C.c_int, [_p, _i64, _i32, _i32, _u64, _p]),
+    "bmdca_reweight": (C.c_int, [_p, _i64, _i32, _i32, _f64, _p, _p, _p, _p, _sz, _p, _p]),
+    "bmdca_stats": (C.c_int, [_p, _p, _i64, _i32, _i32, _f64, _i32, _p, _p, _p, _p, _sz, _p,
+                              _p]),
+    "bmdca_gibbs": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _i32, _u64, _u64, _f32, _p, _sz,
+                              _i32, _p, _p]),
+    "bmdca_energy": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p, _p]),
+    "bmdca_train_step": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32, _u64, _u64,
+                                   _i32, _p, _p, _p, _sz, _p, _p]),
+    "bmdca_single_mutant_scan": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p]),
+    "bmdca_apc_frobenius": (C.c_int, [_p, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+}
+
+_lib = None
+
+
+class BmdcaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bmdca status {code}: {msg}")
+        self.code = code
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2501_18456_amd.build` "
+                "(the HIP library is the only implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise BmdcaError(rc, lib().bmdca_last_error().decode(errors="replace"))

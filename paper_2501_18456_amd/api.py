@@ -1,0 +1,197 @@
+"""Python calls with the names of the C ABI (include/bmdca.h).
+
+Argument marshalling only: tensors are checked for device, dtype and layout,
+workspaces are allocated with torch (device memory is plumbing here), and the
+C entry point is called on the current stream. Every step of the computation
+runs in the HIP library.
+
+Shapes: h float32 [L, q]; J float32 [L*q, L*q]; tokens int8 [rows, L].
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as B
+from ._lib import check
+
+PREC = {"fp32": B.PREC_FP32, "bf16x2": B.PREC_BF16X2}
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str, ndim: int | None = None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims")
+    return t
+
+
+def _model(h, J):
+    _dev(h, torch.float32, "h", 2)
+    _dev(J, torch.float32, "J", 2)
+    L, q = h.shape
+    if J.shape != (L * q, L * q):
+        raise ValueError(f"J must be [{L * q}, {L * q}], got {tuple(J.shape)}")
+    return L, q
+
+
+def _prec(prec) -> int:
+    return PREC[prec] if isinstance(prec, str) else int(prec)
+
+
+def workspace_bytes(kind: int, MN: int, L: int, q: int, prec=B.PREC_BF16X2) -> int:
+    n = B.lib().bmdca_workspace_bytes(kind, MN, L, q, _prec(prec))
+    if n == 0:
+        raise ValueError(f"no workspace size for kind={kind}, MN={MN}, L={L}, q={q}")
+    return n
+
+
+def workspace(kind: int, MN: int, L: int, q: int, prec=B.PREC_BF16X2, device=None):
+    n = workspace_bytes(kind, MN, L, q, prec)
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+def identity_threshold(theta: float, L: int) -> int:
+    return B.lib().bmdca_identity_threshold(theta, L)
+
+
+def init_chains(N: int, L: int, q: int, seed: int, out=None, device=None):
+    if out is None:
+        out = torch.empty((N, L), dtype=torch.int8, device=device or "cuda")
+    _dev(out, torch.int8, "chains", 2)
+    check(B.lib().bmdca_init_chains(_ptr(out), N, L, q, seed, _stream()))
+    return out
+
+
+def reweight(msa, q: int, theta: float = 0.8, ws=None, dev_err=None):
+    """Eq. (7) weights: returns (n_sim int32 [M], w float64 [M], meff float64 [1])."""
+    _dev(msa, torch.int8, "msa", 2)
+    M, L = msa.shape
+    dev = msa.device
+    n = torch.empty(M, dtype=torch.int32, device=dev)
+    w = torch.empty(M, dtype=torch.float64, device=dev)
+    meff = torch.empty(1, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = workspace(B.WS_REWEIGHT, M, L, q, 0, dev)
+    check(B.lib().bmdca_reweight(_ptr(msa), M, L, q, theta, _ptr(n), _ptr(w), _ptr(meff),
+                                 _ptr(ws), _nbytes(ws), _ptr(dev_err), _stream()))
+    return n, w, meff
+
+
+def stats(X, q: int, w=None, pseudocount: float = -1.0, prec="bf16x2", ws=None, dev_err=None,
+          out=None):
+    """Eqs. (3), (8)-(9): returns (f1 float64 [L*q], f2 float64 [Lq, Lq], meff [1])."""
+    _dev(X, torch.int8, "X", 2)
+    M, L = X.shape
+    dev = X.device
+    if w is not None:
+        _dev(w, torch.float64, "w", 1)
+        if w.numel() != M:
+            raise ValueError("w must have one entry per row")
+    if out is None:
+        f1 = torch.empty(L * q, dtype=torch.float64, device=dev)
+        f2 = torch.empty((L * q, L * q), dtype=torch.float64, device=dev)
+        meff = torch.empty(1, dtype=torch.float64, device=dev)
+    else:
+        f1, f2, meff = out
+    p = _prec(prec)
+    if ws is None:
+        ws = workspace(B.WS_STATS, M, L, q, p, dev)
+    check(B.lib().bmdca_stats(_ptr(X), _ptr(w), M, L, q, pseudocount, p, _ptr(f1), _ptr(f2),
+                              _ptr(meff), _ptr(ws), _nbytes(ws), _ptr(dev_err), _stream()))
+    return f1, f2, meff
+
+
+def gibbs(h, J, chains, sweeps: int, seed: int, sweep_offset: int = 0, beta: float = 1.0,
+          H_ws=None, flips=None, keep_fields: bool = False):
+    """Sweeps the chains in place (Sec. 2.1). Returns the chains tensor.
+    keep_fields=True continues from the local fields a previous call left in
+    H_ws for the same h, J and chains."""
+    L, q = _model(h, J)
+    _dev(chains, torch.int8, "chains", 2)
+    N = chains.shape[0]
+    if chains.shape[1] != L:
+        raise ValueError("chains must be [N, L]")
+    if H_ws is None:
+        if keep_fields:
+            raise ValueError("keep_fields needs the H_ws of the previous call")
+        H_ws = workspace(B.WS_GIBBS, N, L, q, 0, chains.device)
+    check(B.lib().bmdca_gibbs(_ptr(h), _ptr(J), _ptr(chains), N, L, q, sweeps, seed, sweep_offset,
+                              beta, _ptr(H_ws), _nbytes(H_ws), int(keep_fields), _ptr(flips),
+                              _stream()))
+    return chains
+
+
+def energy(h, J, seqs, dev_err=None, out=None):
+    """Eq. (1) energies: float32 [B]."""
+    L, q = _model(h, J)
+    _dev(seqs, torch.int8, "seqs", 2)
+    Bn = seqs.shape[0]
+    if out is None:
+        out = torch.empty(Bn, dtype=torch.float32, device=seqs.device)
+    check(B.lib().bmdca_energy(_ptr(h), _ptr(J), _ptr(seqs), Bn, L, q, _ptr(out), None, 0,
+                               _ptr(dev_err), _stream()))
+    return out
+
+
+def train_step(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: int,
+               prec="bf16x2", ws=None, pearson=None, flips=None, dev_err=None):
+    """One epoch (Sec. 2.1); h, J and chains are updated in place.
+    Returns the device scalar holding the Pearson coefficient."""
+    L, q = _model(h, J)
+    _dev(chains, torch.int8, "chains", 2)
+    _dev(f1, torch.float64, "f1")
+    _dev(f2, torch.float64, "f2")
+    N = chains.shape[0]
+    p = _prec(prec)
+    if ws is None:
+        ws = workspace(B.WS_TRAIN_STEP, N, L, q, p, chains.device)
+    if pearson is None:
+        pearson = torch.empty(1, dtype=torch.float64, device=chains.device)
+    check(B.lib().bmdca_train_step(_ptr(h), _ptr(J), _ptr(chains), N, L, q, _ptr(f1), _ptr(f2),
+                                   lr, sweeps, seed, epoch, p, _ptr(pearson), _ptr(flips),
+                                   _ptr(ws), _nbytes(ws), _ptr(dev_err), _stream()))
+    return pearson
+
+
+def single_mutant_scan(h, J, wt, ws=None, out=None):
+    """Sec. 4.4: dE float32 [B, L*q] for wild types wt int8 [B, L]."""
+    L, q = _model(h, J)
+    _dev(wt, torch.int8, "wt", 2)
+    Bn = wt.shape[0]
+    if ws is None:
+        ws = workspace(B.WS_MUTANT, Bn, L, q, 0, wt.device)
+    if out is None:
+        out = torch.empty((Bn, L * q), dtype=torch.float32, device=wt.device)
+    check(B.lib().bmdca_single_mutant_scan(_ptr(h), _ptr(J), _ptr(wt), Bn, L, q, _ptr(out),
+                                           _ptr(ws), _nbytes(ws), _stream()))
+    return out
+
+
+def apc_frobenius(J, L: int, q: int, gap: int = 0, ws=None):
+    """Eq. (13): returns (F, F_apc), float32 [L, L]."""
+    _dev(J, torch.float32, "J", 2)
+    if J.shape != (L * q, L * q):
+        raise ValueError("J must be [L*q, L*q]")
+    F = torch.empty((L, L), dtype=torch.float32, device=J.device)
+    Fa = torch.empty((L, L), dtype=torch.float32, device=J.device)
+    if ws is None:
+        ws = workspace(B.WS_APC, 0, L, q, 0, J.device)
+    check(B.lib().bmdca_apc_frobenius(_ptr(J), L, q, gap, _ptr(F), _ptr(Fa), _ptr(ws), _nbytes(ws),
+                                      _stream()))
+    return F, Fa

@@ -1,0 +1,252 @@
+// C-ABI entry points of libbmdca (declared in include/bmdca.h): host-side
+// validation, workspace carve-up, and the kernel sequence of each call.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/bmdca.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace bmdca;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return BMDCA_OK;
+  return fail(BMDCA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kMaxL = 1024;
+constexpr int kMaxQ = 32;
+
+int check_model(int32_t L, int32_t q) {
+  if (L < 1 || L > kMaxL) return fail(BMDCA_EINVAL, "L=%d outside 1..%d", L, kMaxL);
+  if (q < 2 || q > kMaxQ) return fail(BMDCA_EINVAL, "q=%d outside 2..%d", q, kMaxQ);
+  return BMDCA_OK;
+}
+
+#define BMDCA_REQUIRE(cond, ...) \
+  do {                           \
+    if (!(cond)) return fail(BMDCA_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+#define BMDCA_TRY(expr)               \
+  do {                                \
+    int _rc = (expr);                 \
+    if (_rc != BMDCA_OK) return _rc;  \
+  } while (0)
+
+// Train-step workspace: H, chain-count planes (via the stats plan over N
+// rows), full count matrix C, Pearson reductions.
+struct TrainPlan {
+  StatsPlan sp;
+  size_t off_H, off_stats, off_C, off_red, total;
+};
+
+TrainPlan plan_train(int64_t N, int L, int q, int prec) {
+  TrainPlan t{};
+  const size_t Lq = (size_t)L * q;
+  t.sp = plan_stats(N, L, q, prec);
+  size_t o = 0;
+  t.off_H = o;     o = align256(o + sizeof(float) * (size_t)N * Lq);
+  t.off_stats = o; o = align256(o + t.sp.total);
+  t.off_C = o;     o = align256(o + sizeof(double) * Lq * Lq);
+  t.off_red = o;   o = align256(o + pearson_red_bytes());
+  t.total = o;
+  return t;
+}
+
+size_t gibbs_bytes(int64_t N, int L, int q) { return align256(sizeof(float) * (size_t)N * L * q); }
+
+}  // namespace
+
+extern "C" {
+
+const char* bmdca_last_error(void) { return g_err.c_str(); }
+
+int32_t bmdca_identity_threshold(double theta, int32_t L) {
+  return (int32_t)std::ceil(theta * (double)L - 1e-6);
+}
+
+size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q, int32_t prec) {
+  if (L < 1 || L > kMaxL || q < 2 || q > kMaxQ) return 0;
+  switch (kind) {
+    case BMDCA_WS_REWEIGHT:
+      if (MN < 1 || L > 512) return 0;
+      return plan_reweight(MN, L, q).total;
+    case BMDCA_WS_STATS:
+      if (MN < 1) return 0;
+      return plan_stats(MN, L, q, prec).total;
+    case BMDCA_WS_GIBBS:
+      if (MN < 1) return 0;
+      return gibbs_bytes(MN, L, q);
+    case BMDCA_WS_TRAIN_STEP:
+      if (MN < 1) return 0;
+      return plan_train(MN, L, q, prec).total;
+    case BMDCA_WS_APC:
+      return apc_ws_bytes(L);
+    case BMDCA_WS_MUTANT:
+      if (MN < 1) return 0;
+      return gibbs_bytes(MN, L, q);
+    case BMDCA_WS_ENERGY:
+      return 256;
+    default:
+      return 0;
+  }
+}
+
+int bmdca_init_chains(int8_t* chains, int64_t N, int32_t L, int32_t q, uint64_t seed,
+                      void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(chains, "chains is NULL");
+  BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
+  return hip_status(launch_init_chains(chains, N, L, q, seed, (hipStream_t)stream), "init_chains");
+}
+
+int bmdca_reweight(const int8_t* msa, int64_t M, int32_t L, int32_t q, double theta,
+                   int32_t* n_sim, double* w, double* meff, void* ws, size_t ws_bytes,
+                   int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(L <= 512, "reweight supports L <= 512 (got %d)", L);
+  BMDCA_REQUIRE(msa && n_sim && w && meff && ws, "null pointer argument");
+  BMDCA_REQUIRE(M >= 1 && M <= (int64_t)1 << 31, "M=%lld outside 1..2^31", (long long)M);
+  BMDCA_REQUIRE(theta >= 0.0 && theta <= 1.0, "theta=%g outside [0,1]", theta);
+  const ReweightPlan plan = plan_reweight(M, L, q);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "reweight workspace %zu < %zu bytes", ws_bytes, plan.total);
+  const int32_t T = bmdca_identity_threshold(theta, L);
+  return hip_status(launch_reweight(msa, M, L, q, T, plan, ws, n_sim, w, meff, dev_err,
+                                    (hipStream_t)stream),
+                    "reweight");
+}
+
+int bmdca_stats(const int8_t* X, const double* w, int64_t M, int32_t L, int32_t q,
+                double pseudocount, int32_t prec, double* f1, double* f2, double* meff_out,
+                void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(X && f1 && f2 && meff_out && ws, "null pointer argument");
+  BMDCA_REQUIRE(M >= 1 && M < ((int64_t)1 << 24), "M=%lld outside 1..2^24-1", (long long)M);
+  BMDCA_REQUIRE(prec == BMDCA_PREC_FP32 || prec == BMDCA_PREC_BF16X2, "prec=%d unknown", prec);
+  BMDCA_REQUIRE(std::isfinite(pseudocount) && pseudocount <= 1.0, "pseudocount=%g invalid",
+                pseudocount);
+  const StatsPlan plan = plan_stats(M, L, q, prec);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "stats workspace %zu < %zu bytes", ws_bytes, plan.total);
+  hipStream_t s = (hipStream_t)stream;
+  BMDCA_TRY(hip_status(launch_meff(w, M, meff_out, s), "stats/meff"));
+  BMDCA_TRY(hip_status(launch_onehot_products(X, w, M, L, q, prec, plan, ws, dev_err, s),
+                       "stats/product"));
+  return hip_status(launch_stats_epilogue(plan, ws, L, q, meff_out, pseudocount, f1, f2, s),
+                    "stats/epilogue");
+}
+
+int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,
+                int32_t sweeps, uint64_t seed, uint64_t sweep_offset, float beta, float* H_ws,
+                size_t H_ws_bytes, int32_t keep_fields, unsigned long long* flips_out,
+                void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(h && J && chains && H_ws, "null pointer argument");
+  BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
+  BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
+  if (!std::isfinite(beta)) return fail(BMDCA_ENONFINITE, "beta is not finite");
+  if (H_ws_bytes < gibbs_bytes(N, L, q))
+    return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
+                gibbs_bytes(N, L, q));
+  hipStream_t s = (hipStream_t)stream;
+  if (!keep_fields)
+    BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H_ws, nullptr, s),
+                         "gibbs/fields"));
+  if (sweeps == 0) return BMDCA_OK;
+  return hip_status(launch_gibbs_sweeps(J, chains, H_ws, N, L, q, sweeps, seed, sweep_offset, beta,
+                                        flips_out, s),
+                    "gibbs/sweeps");
+}
+
+int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int32_t L,
+                 int32_t q, float* E, void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(h && J && seqs && E, "null pointer argument");
+  BMDCA_REQUIRE(B >= 0 && B <= (int64_t)1 << 31, "B=%lld outside 0..2^31", (long long)B);
+  if (B == 0) return BMDCA_OK;
+  return hip_status(launch_energy(h, J, seqs, B, L, q, E, dev_err, (hipStream_t)stream), "energy");
+}
+
+int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,
+                     const double* f1, const double* f2, double lr, int32_t sweeps, uint64_t seed,
+                     uint64_t epoch, int32_t prec, double* pearson, unsigned long long* flips_out,
+                     void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(h && J && chains && f1 && f2 && pearson && ws, "null pointer argument");
+  BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)N);
+  BMDCA_REQUIRE(L >= 2, "train_step needs L >= 2 (got %d)", L);
+  BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
+  BMDCA_REQUIRE(prec == BMDCA_PREC_FP32 || prec == BMDCA_PREC_BF16X2, "prec=%d unknown", prec);
+  if (!std::isfinite(lr)) return fail(BMDCA_ENONFINITE, "lr is not finite");
+  const TrainPlan plan = plan_train(N, L, q, prec);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "train_step workspace %zu < %zu bytes", ws_bytes, plan.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = static_cast<char*>(ws);
+  float* H = reinterpret_cast<float*>(base + plan.off_H);
+  void* sws = base + plan.off_stats;
+  double* C = reinterpret_cast<double*>(base + plan.off_C);
+  double* red = reinterpret_cast<double*>(base + plan.off_red);
+  const int Lq = L * q;
+  BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H, dev_err, s),
+                       "train_step/fields"));
+  if (sweeps > 0)
+    BMDCA_TRY(hip_status(launch_gibbs_sweeps(J, chains, H, N, L, q, sweeps, seed,
+                                             epoch * (uint64_t)sweeps, 1.0f, flips_out, s),
+                         "train_step/sweeps"));
+  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, prec, plan.sp, sws,
+                                              dev_err, s),
+                       "train_step/counts"));
+  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));
+  BMDCA_TRY(hip_status(launch_pearson(f1, f2, C, N, L, q, red, pearson, dev_err, s),
+                       "train_step/pearson"));
+  return hip_status(launch_update(h, J, f1, f2, C, N, L, q, lr, dev_err, s), "train_step/update");
+}
+
+int bmdca_single_mutant_scan(const float* h, const float* J, const int8_t* wt, int64_t B,
+                             int32_t L, int32_t q, float* dE, void* ws, size_t ws_bytes,
+                             void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(h && J && wt && dE && ws, "null pointer argument");
+  BMDCA_REQUIRE(B >= 1 && B <= (int64_t)1 << 31, "B=%lld outside 1..2^31", (long long)B);
+  if (ws_bytes < gibbs_bytes(B, L, q))
+    return fail(BMDCA_EWORKSPACE, "mutant workspace %zu < %zu bytes", ws_bytes,
+                gibbs_bytes(B, L, q));
+  hipStream_t s = (hipStream_t)stream;
+  float* H = static_cast<float*>(ws);
+  BMDCA_TRY(hip_status(launch_local_fields(h, J, wt, B, L, q, H, nullptr, s), "mutant/fields"));
+  return hip_status(launch_mutant_delta(H, wt, B, L, q, dE, s), "mutant/delta");
+}
+
+int bmdca_apc_frobenius(const float* J, int32_t L, int32_t q, int32_t gap, float* F,
+                        float* F_apc, void* ws, size_t ws_bytes, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(L >= 2, "apc_frobenius needs L >= 2 (got %d)", L);
+  BMDCA_REQUIRE(J && F_apc && ws, "null pointer argument");
+  BMDCA_REQUIRE(gap >= -1 && gap < q, "gap=%d outside -1..q-1", gap);
+  if (ws_bytes < apc_ws_bytes(L))
+    return fail(BMDCA_EWORKSPACE, "apc workspace %zu < %zu bytes", ws_bytes, apc_ws_bytes(L));
+  return hip_status(launch_apc(J, L, q, gap, F, F_apc, ws, (hipStream_t)stream), "apc_frobenius");
+}
+
+}  // extern "C"

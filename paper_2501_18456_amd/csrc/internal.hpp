@@ -1,0 +1,77 @@
+// Launchers shared between the kernel sources and the C-ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bmdca {
+
+// ----- sampler.hip
+hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t seed,
+                              hipStream_t s);
+// H[c][r] = h[r] + sum_{k != r/q} J[(k, chains[c][k])][r] for c < N.
+hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
+                               int L, int q, float* H, int32_t* dev_err, hipStream_t s);
+hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
+                               int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
+                               unsigned long long* flips_out, hipStream_t s);
+
+// ----- stats.hip
+// Workspace carve-up of the one-hot statistics product for M rows.
+struct StatsPlan {
+  int64_t Mpad;     // rows padded to the K stage
+  int ntile;        // output tiles per side
+  int nupper;       // upper-triangle tiles
+  int splits;       // K splits (FP64 partial planes)
+  int64_t kchunk;   // rows per split (multiple of the K stage)
+  size_t off_xt, off_whi, off_wlo, off_wf, off_part, off_red, total;
+};
+StatsPlan plan_stats(int64_t M, int L, int q, int prec);
+
+// Statistics product: partial planes P[s][Lq][Lq] (upper tiles only) of
+// sum_m w_m [x_mi == a][x_mj == b].  w == nullptr: unit weights.
+hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
+                                  int prec, const StatsPlan& plan, void* ws, int32_t* dev_err,
+                                  hipStream_t s);
+// Sum of the partial planes into the full symmetric matrix C (FP64).
+hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq, double* C,
+                                  hipStream_t s);
+// M_eff = sum_m w_m (fixed order) into *meff; unit weights give M exactly.
+hipError_t launch_meff(const double* w, int64_t M, double* meff, hipStream_t s);
+// f1, f2 with pseudocount from the partial planes.
+hipError_t launch_stats_epilogue(const StatsPlan& plan, const void* ws, int L, int q,
+                                 const double* meff, double pseudocount, double* f1, double* f2,
+                                 hipStream_t s);
+
+// ----- learn.hip
+// Pearson coefficient of the connected correlations (Eq. 6); `red` needs
+// pearson_red_bytes().
+size_t pearson_red_bytes();
+hipError_t launch_pearson(const double* f1, const double* f2, const double* C, int64_t N, int L,
+                          int q, double* red, double* out, int32_t* dev_err, hipStream_t s);
+hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
+                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s);
+
+// ----- reweight.hip
+struct ReweightPlan {
+  int planes, words;
+  int64_t Mpad;
+  size_t off_planes, off_red, total;
+};
+ReweightPlan plan_reweight(int64_t M, int L, int q);
+hipError_t launch_reweight(const int8_t* msa, int64_t M, int L, int q, int32_t T,
+                           const ReweightPlan& plan, void* ws, int32_t* n_sim, double* w,
+                           double* meff, int32_t* dev_err, hipStream_t s);
+
+// ----- scoring.hip
+hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int L,
+                         int q, float* E, int32_t* dev_err, hipStream_t s);
+hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int L, int q,
+                               float* dE, hipStream_t s);
+size_t apc_ws_bytes(int L);
+hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fapc, void* ws,
+                      hipStream_t s);
+
+}  // namespace bmdca

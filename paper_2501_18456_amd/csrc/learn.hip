@@ -1,0 +1,136 @@
+// Boltzmann-learning epilogue of one epoch (adabmDCA 2.0, Sec. 2.1):
+//   - the convergence check: Pearson correlation between the connected
+//     correlations of data and model (Eq. 6), over i < j and all a, b;
+//   - the parameter update of Eq. (5).
+// Both read the chain counts C (FP64, full symmetric [Lq][Lq], exact
+// integers) and form p = C / N in FP64.  Contraction is off for this file, so
+// every expression is rounded exactly as written.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bmdca {
+
+constexpr int kPearsonBlocks = 1024;
+constexpr int kPearsonThreads = 256;
+
+size_t pearson_red_bytes() { return sizeof(double) * (3 * kPearsonBlocks + 8); }
+
+// Pass 1 (moments == 0): per-block sums of x and y.
+// Pass 2 (moments == 1): per-block sums of dx^2, dy^2, dx*dy about the means.
+// x = f2 - f1_i f1_j (data), y = p2 - p1_i p1_j (model).
+__global__ __launch_bounds__(kPearsonThreads) void k_pearson_pass(
+    const double* __restrict__ f1, const double* __restrict__ f2, const double* __restrict__ C,
+    int64_t N, int L, int q, int pass, double* __restrict__ red) {
+  __shared__ double sh[16];
+  const int Lq = L * q;
+  const size_t total = (size_t)Lq * Lq;
+  const double dn = (double)N;
+  double mx = 0.0, my = 0.0;
+  if (pass == 1) {
+    mx = red[3 * kPearsonBlocks + 0];
+    my = red[3 * kPearsonBlocks + 1];
+  }
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
+    if (r1 / q >= r2 / q) continue;
+    const double x = f2[k] - f1[r1] * f1[r2];
+    const double p1a = C[(size_t)r1 * Lq + r1] / dn;
+    const double p1b = C[(size_t)r2 * Lq + r2] / dn;
+    const double y = C[k] / dn - p1a * p1b;
+    if (pass == 0) {
+      s0 += x;
+      s1 += y;
+    } else {
+      const double dx = x - mx, dy = y - my;
+      s0 += dx * dx;
+      s1 += dy * dy;
+      s2 += dx * dy;
+    }
+  }
+  const double t0 = block_sum_f64(s0, sh);
+  const double t1 = block_sum_f64(s1, sh);
+  const double t2 = block_sum_f64(s2, sh);
+  if (threadIdx.x == 0) {
+    red[3 * blockIdx.x + 0] = t0;
+    red[3 * blockIdx.x + 1] = t1;
+    red[3 * blockIdx.x + 2] = t2;
+  }
+}
+
+// Sums the block partials in block order.  Pass 0: means into red tail;
+// pass 1: the coefficient into *out.
+__global__ void k_pearson_finish(double* __restrict__ red, int L, int q, int pass,
+                                 double* __restrict__ out, int32_t* dev_err) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = 0; k < kPearsonBlocks; ++k) {
+    a += red[3 * k + 0];
+    b += red[3 * k + 1];
+    c += red[3 * k + 2];
+  }
+  if (pass == 0) {
+    const double n = (double)L * (double)(L - 1) / 2.0 * (double)q * (double)q;
+    red[3 * kPearsonBlocks + 0] = a / n;
+    red[3 * kPearsonBlocks + 1] = b / n;
+  } else {
+    const double r = c / sqrt(a * b);
+    *out = r;
+    if (!isfinite(r) && dev_err) atomicOr(dev_err, 2);
+  }
+}
+
+hipError_t launch_pearson(const double* f1, const double* f2, const double* C, int64_t N, int L,
+                          int q, double* red, double* out, int32_t* dev_err, hipStream_t s) {
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_pearson_pass, dim3(kPearsonBlocks), dim3(kPearsonThreads), 0, s, f1, f2,
+                       C, N, L, q, pass, red);
+    hipLaunchKernelGGL(k_pearson_finish, dim3(1), dim3(64), 0, s, red, L, q, pass, out, dev_err);
+  }
+  return hipGetLastError();
+}
+
+// Eq. (5): J_ij(a,b) += lr (f_ij(a,b) - p_ij(a,b)) for i != j, J_ii = 0;
+// h_i(a) += lr (f_i(a) - p_i(a)); FP64, one rounding to FP32.
+__global__ void k_update(float* __restrict__ h, float* __restrict__ J,
+                         const double* __restrict__ f1, const double* __restrict__ f2,
+                         const double* __restrict__ C, int64_t N, int L, int q, double lr,
+                         int32_t* dev_err) {
+  const int Lq = L * q;
+  const size_t total = (size_t)Lq * Lq;
+  const double dn = (double)N;
+  bool bad = false;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
+    if (r1 / q == r2 / q) {
+      J[k] = 0.0f;
+      continue;
+    }
+    const double d = f2[k] - C[k] / dn;
+    const double t = lr * d;
+    const float v = (float)((double)J[k] + t);
+    J[k] = v;
+    bad |= !isfinite(v);
+  }
+  for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < (size_t)Lq;
+       r += (size_t)gridDim.x * blockDim.x) {
+    const double d = f1[r] - C[r * Lq + r] / dn;
+    const double t = lr * d;
+    const float v = (float)((double)h[r] + t);
+    h[r] = v;
+    bad |= !isfinite(v);
+  }
+  if (bad && dev_err) atomicOr(dev_err, 2);
+}
+
+hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
+                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s) {
+  const size_t total = (size_t)L * q * (size_t)L * q;
+  const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 16384);
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, s, h, J, f1, f2, C, N, L, q, lr, dev_err);
+  return hipGetLastError();
+}
+
+}  // namespace bmdca

@@ -1,0 +1,165 @@
+// Persistent-chain Gibbs sampler of the Potts model of Eq. (1)
+// (adabmDCA 2.0, Sec. 2.1, "Monte Carlo estimation of the gradient").
+//
+// Layout: chains int8 [N][L]; local fields H float32 [N][Lq] in HBM, one row
+// per chain; couplings J float32 [Lq][Lq] full-symmetric, so the row of
+// vertex (i, a) is one contiguous Lq vector and H can be kept current with two
+// coalesced row reads per accepted change.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bmdca {
+
+// ---------------------------------------------------------------------------
+// Uniform random initial chains: counter (i/4, 0, c, 1), word i%4,
+// token = (word * q) >> 32.
+// ---------------------------------------------------------------------------
+__global__ void k_init_chains(int8_t* __restrict__ chains, int64_t N, int L, int q, uint32_t k0,
+                              uint32_t k1) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * (int64_t)L) return;
+  const int64_t c = idx / L;
+  const int i = (int)(idx % L);
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)i >> 2, 0u, (uint32_t)c, 1u), k0, k1);
+  const uint32_t w = pick_word(r, i & 3);
+  chains[idx] = (int8_t)(((uint64_t)w * (uint64_t)q) >> 32);
+}
+
+hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t seed,
+                              hipStream_t s) {
+  const int64_t total = N * (int64_t)L;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_init_chains, dim3((unsigned)ceil_div(total, bs)), dim3(bs), 0, s, chains,
+                     N, L, q, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Local fields from scratch: H[c][r] = h[r] + sum_{k != site(r)} J[(k, s_k)][r],
+// summed in FP32 in the order k = 0..L-1.  By the symmetry of J this equals
+// h_j(b) + sum_{k != j} J_jk(b, s_k) for r = (j, b).
+// Grid: x over chains, y over 256-column slices of the row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ h,
+                                                      const float* __restrict__ J,
+                                                      const int8_t* __restrict__ chains, int64_t N,
+                                                      int L, int q, float* __restrict__ H,
+                                                      int32_t* dev_err) {
+  extern __shared__ int rowbase[];  // L entries: (k*q + s_k)
+  const int64_t c = blockIdx.x;
+  const int Lq = L * q;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    const int t = checked_token(chains[c * L + k], q, dev_err);
+    rowbase[k] = k * q + t;
+  }
+  __syncthreads();
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  if (r >= Lq) return;
+  const int site = r / q;
+  float acc = h[r];
+  for (int k = 0; k < L; ++k) {
+    if (k == site) continue;
+    acc += J[(size_t)rowbase[k] * Lq + r];
+  }
+  H[(size_t)c * Lq + r] = acc;
+}
+
+hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
+                               int L, int q, float* H, int32_t* dev_err, hipStream_t s) {
+  const int Lq = L * q;
+  const int bs = 256;
+  dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, bs));
+  hipLaunchKernelGGL(k_local_fields, grid, dim3(bs), sizeof(int) * L, s, h, J, chains, N, L, q, H,
+                     dev_err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gibbs sweeps, one wave64 per chain.
+//
+// Per site visit: lanes 0..q-1 read H[c][i*q + a], form l_a = beta*H, the
+// wave maximum, e_a = exp(l_a - max), the inclusive prefix sum S_a in lane
+// order, CDF_a = S_a / S_{q-1}, and the new state as the number of lanes
+// a <= q-2 with CDF_a <= u (ballot + popcount).  The uniform u comes from
+// Philox4x32-10 with counter (i/4, sweep, chain, 0), word i%4; one call per
+// four sites.
+// On a change a_old -> a_new all 64 lanes stream the chain's H row and the
+// two coupling rows: H[r] += J[(i,a_new)][r] - J[(i,a_old)][r], r outside
+// site i's own block.
+// ---------------------------------------------------------------------------
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict__ J,
+                                                        int8_t* __restrict__ chains,
+                                                        float* __restrict__ H, int64_t N, int L,
+                                                        int q, int sweeps, uint32_t k0,
+                                                        uint32_t k1, uint64_t sweep_offset,
+                                                        float beta,
+                                                        unsigned long long* flips_out) {
+  extern __shared__ int8_t tok_all[];
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int64_t c = (int64_t)blockIdx.x * WPB + wid;
+  if (c >= N) return;  // whole wave leaves; no block barriers below
+  const int Lpad = (L + 3) & ~3;
+  int8_t* tok = tok_all + wid * Lpad;
+  for (int i = lane; i < L; i += kWave) {
+    const int t = chains[c * L + i];
+    tok[i] = (int8_t)((t >= 0 && t < q) ? t : 0);  // invalid tokens were flagged by the field build
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+
+  const int Lq = L * q;
+  float* __restrict__ Hc = H + (size_t)c * Lq;
+  unsigned long long nflip = 0;
+  uint4 rnd = make_uint4(0, 0, 0, 0);
+  for (int sw = 0; sw < sweeps; ++sw) {
+    const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
+    for (int i = 0; i < L; ++i) {
+      if ((i & 3) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, (uint32_t)c, 0u), k0, k1);
+      const float u = word_to_uniform(pick_word(rnd, i & 3));
+      const int a_old = tok[i];
+      const float l = lane < q ? beta * Hc[i * q + lane] : -INFINITY;
+      const float mx = wave_max(l);
+      float e = lane < q ? expf(l - mx) : 0.0f;
+      // inclusive prefix sum over lanes (q <= 32)
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) {
+        const float t = __shfl_up(e, o, kWave);
+        if (lane >= o) e += t;
+      }
+      const float Z = __shfl(e, q - 1, kWave);
+      const float cdf = e / Z;
+      const bool below = (lane < q - 1) && (cdf <= u);
+      const int a_new = __popcll(__ballot(below));
+      if (a_new != a_old) {
+        const float* __restrict__ Jn = J + (size_t)(i * q + a_new) * Lq;
+        const float* __restrict__ Jo = J + (size_t)(i * q + a_old) * Lq;
+        const int blo = i * q, bhi = i * q + q;
+        for (int r = lane; r < Lq; r += kWave) {
+          if (r >= blo && r < bhi) continue;
+          Hc[r] += Jn[r] - Jo[r];
+        }
+        if (lane == 0) tok[i] = (int8_t)a_new;
+        ++nflip;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  for (int i = lane; i < L; i += kWave) chains[c * L + i] = tok[i];
+  if (flips_out && lane == 0) atomicAdd(flips_out, nflip);
+}
+
+hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
+                               int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
+                               unsigned long long* flips_out, hipStream_t s) {
+  constexpr int WPB = 4;
+  const int Lpad = (L + 3) & ~3;
+  hipLaunchKernelGGL(k_gibbs_hbm<WPB>, dim3((unsigned)ceil_div(N, WPB)), dim3(WPB * kWave),
+                     WPB * Lpad, s, J, chains, H, N, L, q, sweeps, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out);
+  return hipGetLastError();
+}
+
+}  // namespace bmdca

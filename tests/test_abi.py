@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every symbol include/bmdca.h declares, and
+rejects invalid arguments on the host (no GPU work is enqueued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_18456_amd import _lib as B
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "bmdca.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(bmdca_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["bmdca_reweight", "bmdca_stats", "bmdca_gibbs", "bmdca_energy", "bmdca_train_step",
+              "bmdca_single_mutant_scan", "bmdca_apc_frobenius", "bmdca_init_chains",
+              "bmdca_workspace_bytes", "bmdca_last_error", "bmdca_identity_threshold"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert n in B.SIGNATURES, f"binding misses {n}"
+
+
+def test_identity_threshold_agrees_with_oracle():
+    from oracle import oracle as O
+    for theta in [0.0, 0.3, 0.8, 0.9, 1.0]:
+        for L in [1, 7, 20, 35, 100, 256, 512]:
+            assert B.lib().bmdca_identity_threshold(theta, L) == O.identity_threshold(theta, L)
+
+
+def test_workspace_sizes():
+    lib = B.lib()
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10000, 100, 21, 0) >= 10000 * 2100 * 4
+    assert lib.bmdca_workspace_bytes(B.WS_TRAIN_STEP, 500, 20, 21, 1) > 500 * 420 * 4
+    assert lib.bmdca_workspace_bytes(B.WS_STATS, 20000, 100, 21, 1) > 2100 * 2100 * 8
+    assert lib.bmdca_workspace_bytes(B.WS_APC, 0, 64, 21, 0) >= 64 * 64 * 8
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10, 100, 1, 0) == 0       # q < 2
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10, 0, 21, 0) == 0        # L < 1
+    assert lib.bmdca_workspace_bytes(B.WS_REWEIGHT, 10, 600, 21, 0) == 0   # L > 512
+    assert lib.bmdca_workspace_bytes(99, 10, 10, 21, 0) == 0
+
+
+def test_host_validation_returns_status_without_gpu():
+    lib = B.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # null pointers
+    rc = lib.bmdca_gibbs(None, fake, fake, 10, 20, 21, 1, 0, 0, 1.0, fake, 1 << 30, 0, None, None)
+    assert rc == B.EINVAL and b"null" in lib.bmdca_last_error()
+    # q outside 2..32
+    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 33, 1, 0, 0, 1.0, fake, 1 << 30, 0, None, None)
+    assert rc == B.EINVAL and b"q=33" in lib.bmdca_last_error()
+    # non-finite beta
+    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 21, 1, 0, 0, float("inf"), fake, 1 << 30,
+                         0, None, None)
+    assert rc == B.ENONFINITE
+    # workspace too small
+    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 21, 1, 0, 0, 1.0, fake, 16, 0, None, None)
+    assert rc == B.EWORKSPACE
+    # theta outside [0,1]
+    rc = lib.bmdca_reweight(fake, 10, 20, 21, 1.5, fake, fake, fake, fake, 1 << 30, None, None)
+    assert rc == B.EINVAL
+    # non-finite learning rate
+    rc = lib.bmdca_train_step(fake, fake, fake, 10, 20, 21, fake, fake, float("nan"), 1, 0, 0, 1,
+                              fake, None, fake, 1 << 40, None, None)
+    assert rc == B.ENONFINITE
+    # unknown precision
+    rc = lib.bmdca_stats(fake, None, 10, 20, 21, -1.0, 7, fake, fake, fake, fake, 1 << 40, None,
+                         None)
+    assert rc == B.EINVAL
+    # gap outside range
+    rc = lib.bmdca_apc_frobenius(fake, 20, 21, 21, None, fake, fake, 1 << 20, None)
+    assert rc == B.EINVAL
+
+
+def test_product_path_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_2501_18456_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
+                assert "bmdca_oracle" not in text and "orc_" not in text, f
