@@ -128,26 +128,44 @@ def main():
     log(f"timed {args.steps} epochs: {ms_step:.2f} ms/epoch, {value:.3e} site-updates/s, "
         f"flip fraction {flip_frac:.3f}, pearson {float(pearson.cpu()[0]):.4f}")
 
-    # ---------------- dominant kernel: the sweep kernel alone (keep_fields)
-    H = api.workspace(B.WS_GIBBS, N, L, q)
-    api.gibbs(h, J, chains, 0, seed_chain, H_ws=H)  # build the fields once
+    # ---------------- the two sweep kernels alone, same chains and model
     reps = 5
+    visits = N * L * sweeps
+    ck = chains.clone()
     kflips = torch.zeros(1, dtype=torch.int64, device="cuda")
     t.start()
     for r in range(reps):
-        api.gibbs(h, J, chains, sweeps, seed_chain, sweep_offset=10**6 + r * sweeps, H_ws=H,
-                  flips=kflips, keep_fields=True)
+        api.gibbs(h, J, ck, sweeps, seed_chain, sweep_offset=10**6 + r * sweeps, flips=kflips,
+                  sampler="gather")
+    g_ms = t.stop_ms() / reps
+    gf = float(kflips.cpu()[0]) / reps
+    # gather form: every visit reads the q-vector of L-1 coupling rows from LDS
+    g_lds_bytes = visits * (L - 1) * q * 4
+    log(f"gather sweep kernel: {g_ms:.2f} ms per launch ({sweeps} sweeps), "
+        f"{visits / (g_ms * 1e-3):.3e} site-updates/s, LDS gather {g_lds_bytes / g_ms / 1e9:.0f} GB/s")
+
+    ck = chains.clone()
+    H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
+    api.gibbs(h, J, ck, 0, seed_chain, H_ws=H, sampler="fields")  # build the fields once
+    kflips.zero_()
+    t.start()
+    for r in range(reps):
+        api.gibbs(h, J, ck, sweeps, seed_chain, sweep_offset=10**6 + r * sweeps, H_ws=H,
+                  flips=kflips, keep_fields=True, sampler="fields")
     k_ms = t.stop_ms() / reps
     kf = float(kflips.cpu()[0]) / reps
-    visits = N * L * sweeps
     alg_bytes = visits * 4 * q + kf * 8 * (Lq - q) + 2 * N * L
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    log(f"sweep kernel: {k_ms:.2f} ms per launch ({sweeps} sweeps), flips/launch {kf:.3e}, "
+    log(f"field sweep kernel: {k_ms:.2f} ms per launch ({sweeps} sweeps), flips/launch {kf:.3e}, "
         f"algorithmic HBM bytes {alg_bytes / 1e9:.2f} GB -> {achieved:.0f} GB/s")
 
     # ---------------- BF16 vs FP32 statistics on the same alignment
     extras = {"epoch_ms": ms_step, "flip_fraction": flip_frac,
-              "pearson_after": float(pearson.cpu()[0]), "reweight_ms": rw_ms}
+              "pearson_after": float(pearson.cpu()[0]), "reweight_ms": rw_ms,
+              "gather_kernel": {"ms_per_launch": g_ms, "site_updates_per_s": visits / (g_ms * 1e-3),
+                                "lds_gather_GBps": g_lds_bytes / g_ms / 1e6},
+              "field_kernel": {"ms_per_launch": k_ms, "site_updates_per_s": visits / (k_ms * 1e-3),
+                               "alg_hbm_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS}}
     other = "bf16x2" if args.prec == "fp32" else "fp32"
     stat_ms = {args.prec: st_ms}
     t.start()

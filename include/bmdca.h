@@ -64,6 +64,21 @@ typedef enum {
                              chunks of at most 512 rows flushed into FP64 */
 } bmdca_prec;
 
+/* Sampler selection and options, OR-ed into the `flags` argument of
+ * bmdca_gibbs, the `prec` argument of bmdca_train_step, and the `prec`
+ * argument of bmdca_workspace_bytes for BMDCA_WS_GIBBS / BMDCA_WS_TRAIN_STEP.
+ * Without a sampler bit the library picks the gather form whenever the model
+ * fits it (L <= 512, q <= 32) and the field form otherwise.  Both forms use
+ * the same draw rule and Philox counters; they differ only in FP32 rounding
+ * of the local fields. */
+#define BMDCA_SAMPLER_FIELDS 0x10 /* per-chain local fields H in HBM, updated
+                                     incrementally on every accepted change */
+#define BMDCA_SAMPLER_GATHER 0x20 /* local fields recomputed at every visit
+                                     from coupling blocks staged in LDS,
+                                     chains of a workgroup in lockstep */
+#define BMDCA_GIBBS_KEEP_FIELDS 0x40 /* field form only: H_ws already holds
+                                        the fields of these chains */
+
 /* Bits OR-ed into *dev_err. */
 #define BMDCA_DEVERR_TOKEN 1
 #define BMDCA_DEVERR_NONFINITE 2
@@ -142,22 +157,26 @@ int bmdca_stats(const int8_t* X, const double* w, int64_t M, int32_t L,
  * CDF_a = S_a / S_{q-1}; a_new = #{a in 0..q-2 : CDF_a <= u}, with the
  * uniform u = (w >> 8) * 2^-24 from the Philox4x32-10 word w = out[i % 4],
  * key = seed, counter (i / 4, sweep_offset + s, c, 0) for chain c and sweep s.
- * The local fields are kept per chain in H_ws (float32 [N][Lq], HBM) and
- * updated incrementally on every accepted change:
- * H += J[(i,new),:] - J[(i,old),:].
+ * Two kernels implement it (flags, see BMDCA_SAMPLER_*):
+ *  - field form: the local fields are kept per chain in H_ws (float32
+ *    [N][Lq], HBM), rebuilt from h, J and the chains at the start of the
+ *    call, and updated incrementally on every accepted change,
+ *    H += J[(i,new),:] - J[(i,old),:];
+ *  - gather form: H_i is recomputed at every visit from a copy of the
+ *    coupling blocks that the call re-lays out in H_ws.
  * chains  int8 [N][L] in/out
- * H_ws    float32 [N][Lq] scratch, at least
- *         bmdca_workspace_bytes(BMDCA_WS_GIBBS, N, L, q, 0) bytes
- * keep_fields 0: rebuild H_ws from h, J and the chains first (always valid);
- *         1: H_ws already holds the local fields of these chains under these
- *         h and J (left by the previous call on the same buffers), so the
+ * H_ws    scratch of bmdca_workspace_bytes(BMDCA_WS_GIBBS, N, L, q, flags)
+ *         bytes
+ * flags   BMDCA_SAMPLER_* selection; BMDCA_GIBBS_KEEP_FIELDS (field form):
+ *         H_ws already holds the local fields of these chains under these h
+ *         and J (left by the previous call on the same buffers), so the
  *         rebuild is skipped -- for sampling in several slices of sweeps.
  * flips_out optional device uint64: the number of accepted changes is added.
  * Arithmetic is FP32; the state is integer. */
 int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
                 int32_t L, int32_t q, int32_t sweeps, uint64_t seed,
                 uint64_t sweep_offset, float beta, float* H_ws,
-                size_t H_ws_bytes, int32_t keep_fields,
+                size_t H_ws_bytes, int32_t flags,
                 unsigned long long* flips_out, void* stream);
 
 /* DCA energies of a batch of sequences, Eq. (1) (Sec. 4.3, "Scoring a
@@ -184,6 +203,7 @@ int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B,
  * h, J     float32, updated in place
  * chains   int8 [N][L] in/out
  * f1, f2   double data frequencies as produced by bmdca_stats
+ * prec     bmdca_prec of the count product, OR-ed with BMDCA_SAMPLER_*
  * pearson  double [1] out (device)
  * flips_out optional device uint64, accepted changes added
  * ws       scratch, bmdca_workspace_bytes(BMDCA_WS_TRAIN_STEP, N, L, q, prec)

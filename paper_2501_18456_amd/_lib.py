@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libbmdca.so")
 OK, EINVAL, ETOKEN, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_BF16X2 = 0, 1
 DEVERR_TOKEN, DEVERR_NONFINITE = 1, 2
+SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS = 0x10, 0x20, 0x40
+SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER}
 WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY = range(7)
 
 _p, _i32, _i64, _u64, _f64, _f32, _sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,

@@ -54,6 +54,10 @@ def _prec(prec) -> int:
     return PREC[prec] if isinstance(prec, str) else int(prec)
 
 
+def _sampler(sampler) -> int:
+    return B.SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
+
+
 def workspace_bytes(kind: int, MN: int, L: int, q: int, prec=B.PREC_BF16X2) -> int:
     n = B.lib().bmdca_workspace_bytes(kind, MN, L, q, _prec(prec))
     if n == 0:
@@ -118,22 +122,23 @@ def stats(X, q: int, w=None, pseudocount: float = -1.0, prec="bf16x2", ws=None, 
 
 
 def gibbs(h, J, chains, sweeps: int, seed: int, sweep_offset: int = 0, beta: float = 1.0,
-          H_ws=None, flips=None, keep_fields: bool = False):
+          H_ws=None, flips=None, keep_fields: bool = False, sampler="auto"):
     """Sweeps the chains in place (Sec. 2.1). Returns the chains tensor.
-    keep_fields=True continues from the local fields a previous call left in
-    H_ws for the same h, J and chains."""
+    sampler: "auto", "fields" (local fields in HBM, incremental) or "gather".
+    keep_fields=True (field form) continues from the local fields a previous
+    call left in H_ws for the same h, J and chains."""
     L, q = _model(h, J)
     _dev(chains, torch.int8, "chains", 2)
     N = chains.shape[0]
     if chains.shape[1] != L:
         raise ValueError("chains must be [N, L]")
+    flags = _sampler(sampler) | (B.GIBBS_KEEP_FIELDS if keep_fields else 0)
     if H_ws is None:
         if keep_fields:
             raise ValueError("keep_fields needs the H_ws of the previous call")
-        H_ws = workspace(B.WS_GIBBS, N, L, q, 0, chains.device)
+        H_ws = workspace(B.WS_GIBBS, N, L, q, flags, chains.device)
     check(B.lib().bmdca_gibbs(_ptr(h), _ptr(J), _ptr(chains), N, L, q, sweeps, seed, sweep_offset,
-                              beta, _ptr(H_ws), _nbytes(H_ws), int(keep_fields), _ptr(flips),
-                              _stream()))
+                              beta, _ptr(H_ws), _nbytes(H_ws), flags, _ptr(flips), _stream()))
     return chains
 
 
@@ -150,7 +155,7 @@ def energy(h, J, seqs, dev_err=None, out=None):
 
 
 def train_step(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: int,
-               prec="bf16x2", ws=None, pearson=None, flips=None, dev_err=None):
+               prec="bf16x2", ws=None, pearson=None, flips=None, dev_err=None, sampler="auto"):
     """One epoch (Sec. 2.1); h, J and chains are updated in place.
     Returns the device scalar holding the Pearson coefficient."""
     L, q = _model(h, J)
@@ -158,7 +163,7 @@ def train_step(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: i
     _dev(f1, torch.float64, "f1")
     _dev(f2, torch.float64, "f2")
     N = chains.shape[0]
-    p = _prec(prec)
+    p = _prec(prec) | _sampler(sampler)
     if ws is None:
         ws = workspace(B.WS_TRAIN_STEP, N, L, q, p, chains.device)
     if pearson is None:

@@ -50,6 +50,27 @@ int check_model(int32_t L, int32_t q) {
     if (_rc != BMDCA_OK) return _rc;  \
   } while (0)
 
+size_t gibbs_bytes(int64_t N, int L, int q) { return align256(sizeof(float) * (size_t)N * L * q); }
+
+constexpr int kPrecMask = 0x0F;
+constexpr int kSamplerMask = BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER;
+
+// Sampler choice: 1 = gather form, 0 = field form, -1 = invalid request.
+int pick_gather(int flags, int L, int q) {
+  const int sel = flags & kSamplerMask;
+  if (sel == kSamplerMask) return -1;
+  if (sel == BMDCA_SAMPLER_FIELDS) return 0;
+  const bool ok = gather_supported(L, q);
+  if (sel == BMDCA_SAMPLER_GATHER) return ok ? 1 : -1;
+  return ok ? 1 : 0;
+}
+
+// Sampler scratch: the local fields (field form) or the re-laid-out
+// coupling blocks (gather form).
+size_t field_bytes(int64_t N, int L, int q, int flags) {
+  return pick_gather(flags, L, q) == 1 ? gather_ws_bytes(L, q) : gibbs_bytes(N, L, q);
+}
+
 // Train-step workspace: H, chain-count planes (via the stats plan over N
 // rows), full count matrix C, Pearson reductions.
 struct TrainPlan {
@@ -60,17 +81,15 @@ struct TrainPlan {
 TrainPlan plan_train(int64_t N, int L, int q, int prec) {
   TrainPlan t{};
   const size_t Lq = (size_t)L * q;
-  t.sp = plan_stats(N, L, q, prec);
+  t.sp = plan_stats(N, L, q, prec & kPrecMask);
   size_t o = 0;
-  t.off_H = o;     o = align256(o + sizeof(float) * (size_t)N * Lq);
+  t.off_H = o;     o = align256(o + field_bytes(N, L, q, prec));
   t.off_stats = o; o = align256(o + t.sp.total);
   t.off_C = o;     o = align256(o + sizeof(double) * Lq * Lq);
   t.off_red = o;   o = align256(o + pearson_red_bytes());
   t.total = o;
   return t;
 }
-
-size_t gibbs_bytes(int64_t N, int L, int q) { return align256(sizeof(float) * (size_t)N * L * q); }
 
 }  // namespace
 
@@ -92,10 +111,10 @@ size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q, int
       if (MN < 1) return 0;
       return plan_stats(MN, L, q, prec).total;
     case BMDCA_WS_GIBBS:
-      if (MN < 1) return 0;
-      return gibbs_bytes(MN, L, q);
+      if (MN < 1 || pick_gather(prec, L, q) < 0) return 0;
+      return field_bytes(MN, L, q, prec);
     case BMDCA_WS_TRAIN_STEP:
-      if (MN < 1) return 0;
+      if (MN < 1 || pick_gather(prec, L, q) < 0) return 0;
       return plan_train(MN, L, q, prec).total;
     case BMDCA_WS_APC:
       return apc_ws_bytes(L);
@@ -156,18 +175,29 @@ int bmdca_stats(const int8_t* X, const double* w, int64_t M, int32_t L, int32_t 
 
 int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,
                 int32_t sweeps, uint64_t seed, uint64_t sweep_offset, float beta, float* H_ws,
-                size_t H_ws_bytes, int32_t keep_fields, unsigned long long* flips_out,
+                size_t H_ws_bytes, int32_t flags, unsigned long long* flips_out,
                 void* stream) {
   BMDCA_TRY(check_model(L, q));
-  BMDCA_REQUIRE(h && J && chains && H_ws, "null pointer argument");
+  BMDCA_REQUIRE(h && J && chains, "null pointer argument");
   BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
   BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
   if (!std::isfinite(beta)) return fail(BMDCA_ENONFINITE, "beta is not finite");
+  const int gather = pick_gather(flags, L, q);
+  BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", flags, L, q);
+  hipStream_t s = (hipStream_t)stream;
+  BMDCA_REQUIRE(H_ws, "H_ws is NULL");
+  if (gather) {
+    if (H_ws_bytes < gather_ws_bytes(L, q))
+      return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
+                  gather_ws_bytes(L, q));
+    return hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed, sweep_offset, beta,
+                                          flips_out, nullptr, H_ws, s),
+                      "gibbs/gather");
+  }
   if (H_ws_bytes < gibbs_bytes(N, L, q))
     return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
                 gibbs_bytes(N, L, q));
-  hipStream_t s = (hipStream_t)stream;
-  if (!keep_fields)
+  if (!(flags & BMDCA_GIBBS_KEEP_FIELDS))
     BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H_ws, nullptr, s),
                          "gibbs/fields"));
   if (sweeps == 0) return BMDCA_OK;
@@ -196,7 +226,11 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, i
   BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)N);
   BMDCA_REQUIRE(L >= 2, "train_step needs L >= 2 (got %d)", L);
   BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
-  BMDCA_REQUIRE(prec == BMDCA_PREC_FP32 || prec == BMDCA_PREC_BF16X2, "prec=%d unknown", prec);
+  const int pr = prec & kPrecMask;
+  BMDCA_REQUIRE(pr == BMDCA_PREC_FP32 || pr == BMDCA_PREC_BF16X2, "prec=%d unknown", pr);
+  BMDCA_REQUIRE((prec & ~(kPrecMask | kSamplerMask)) == 0, "prec flags 0x%x unknown", prec);
+  const int gather = pick_gather(prec, L, q);
+  BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", prec, L, q);
   if (!std::isfinite(lr)) return fail(BMDCA_ENONFINITE, "lr is not finite");
   const TrainPlan plan = plan_train(N, L, q, prec);
   if (ws_bytes < plan.total)
@@ -208,13 +242,20 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, i
   double* C = reinterpret_cast<double*>(base + plan.off_C);
   double* red = reinterpret_cast<double*>(base + plan.off_red);
   const int Lq = L * q;
-  BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H, dev_err, s),
-                       "train_step/fields"));
-  if (sweeps > 0)
-    BMDCA_TRY(hip_status(launch_gibbs_sweeps(J, chains, H, N, L, q, sweeps, seed,
-                                             epoch * (uint64_t)sweeps, 1.0f, flips_out, s),
-                         "train_step/sweeps"));
-  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, prec, plan.sp, sws,
+  if (gather) {
+    BMDCA_TRY(hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed,
+                                             epoch * (uint64_t)sweeps, 1.0f, flips_out, dev_err,
+                                             H, s),
+                         "train_step/gather"));
+  } else {
+    BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H, dev_err, s),
+                         "train_step/fields"));
+    if (sweeps > 0)
+      BMDCA_TRY(hip_status(launch_gibbs_sweeps(J, chains, H, N, L, q, sweeps, seed,
+                                               epoch * (uint64_t)sweeps, 1.0f, flips_out, s),
+                           "train_step/sweeps"));
+  }
+  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, pr, plan.sp, sws,
                                               dev_err, s),
                        "train_step/counts"));
   BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));

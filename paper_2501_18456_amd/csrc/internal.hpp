@@ -17,6 +17,14 @@ hipError_t launch_local_fields(const float* h, const float* J, const int8_t* cha
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, hipStream_t s);
+// Gather form (local fields recomputed per visit from LDS-staged coupling
+// blocks); needs no field workspace.
+bool gather_supported(int L, int q);
+size_t gather_ws_bytes(int L, int q);  // re-laid-out coupling blocks
+hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, int64_t N, int L,
+                               int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
+                               unsigned long long* flips_out, int32_t* dev_err, void* ws,
+                               hipStream_t s);
 
 // ----- stats.hip
 // Workspace carve-up of the one-hot statistics product for M rows.

@@ -162,4 +162,338 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Gibbs sweeps with the local fields recomputed at every visit (gather form).
+//
+// A workgroup runs a group of chains in lockstep over the sites.  At site i
+// every chain needs H_i(a) = h_i(a) + sum_{j != i} J_ij(a, s_j), i.e. row s_j
+// of the q x q block J_ji for every j, the same blocks for all chains.
+//
+//   - Each call first copies J into the workspace as Jt[i][j][b][a'] (a'
+//     padded to QP = q rounded up to 4, pad entries 0): Jt[i][j][b][a] =
+//     J_ij(a, b) = J[(j,b)][(i,a)].  Site i's blocks are then one contiguous
+//     L*q*QP run and the row a' = 0..QP-1 a chain needs is 16-byte aligned.
+//   - Site i's run is streamed into LDS in chunks of JC sites by direct
+//     global->LDS loads issued ahead of use into a ring of slots.
+//   - G lanes serve one chain; lane g owns the R = JC/G consecutive sites
+//     g*R .. g*R+R-1 of every chunk, reads their tokens with one LDS load, and
+//     adds the row of each with QP/4 16-byte LDS loads.
+//   - At the end of the site the G partial sums meet by xor-shuffles (the same
+//     value in every lane of the chain), all G lanes run the same draw and lane
+//     g = 0 stores the new token.
+// Draw rule and Philox counters are those of the field form (the CDF test
+// S_a / S_{q-1} <= u is evaluated as S_a <= u * S_{q-1}).
+//
+// Synchronisation: one workgroup barrier per chunk-step.  The slot written at
+// step t + A (A = loads ahead, ring of A + 2 slots) was last read at step
+// t + A - (A + 2) = t - 2, which every wave finished before the barrier of
+// step t - 1; the loads of step t are complete once at most the A younger
+// steps' loads are outstanding (s_waitcnt vmcnt).
+// ---------------------------------------------------------------------------
+#ifndef BMDCA_GATHER_G
+#define BMDCA_GATHER_G 4
+#endif
+#ifndef BMDCA_GATHER_W
+#define BMDCA_GATHER_W 4
+#endif
+#ifndef BMDCA_GATHER_ODD_QUADS
+#define BMDCA_GATHER_ODD_QUADS 0
+#endif
+constexpr int kGG = BMDCA_GATHER_G;   // lanes per chain
+constexpr int kGWv = BMDCA_GATHER_W;  // waves per workgroup
+constexpr int kGR = kGG >= 4 ? 16 / kGG : 4;  // sites per lane per chunk (divides 4)
+constexpr int kGJC = kGG * kGR;       // sites per chunk
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Row pitch of Jt: q rounded up to a multiple of 4 floats (16-byte rows); with
+// an odd number of 16-byte quads per row, consecutive rows start in 8
+// different LDS bank groups, which keeps the 16-byte gathers of lanes that
+// read different rows mostly conflict-free.
+__host__ __device__ constexpr int gather_qp(int q) {
+  return BMDCA_GATHER_ODD_QUADS ? ((((q + 3) / 4) % 2) ? ((q + 3) & ~3) : ((q + 3) & ~3) + 4)
+                                : ((q + 3) & ~3);
+}
+
+// 16-byte loads per thread per chunk-step.
+__host__ __device__ constexpr int gather_items(int q) {
+  return (kGJC * q * gather_qp(q) + 4 * kGWv * 64 - 1) / (4 * kGWv * 64);
+}
+
+struct GatherShape {
+  int ahead;   // chunk-steps loaded ahead (ring = ahead + 2 slots)
+  int slot;    // floats per slot
+  size_t lds;  // dynamic LDS bytes
+};
+
+static GatherShape gather_shape(int L, int q) {
+  const int slot = 4 * kGWv * 64 * gather_items(q);
+  const size_t tok = (size_t)((L + 3) / 4) * ((64 / kGG) * kGWv) * sizeof(uint32_t);
+  for (int ahead = 2; ahead >= 1; --ahead) {
+    const size_t lds = (size_t)(ahead + 2) * slot * sizeof(float) + tok;
+    if (lds <= 160 * 1024 - 256) return {ahead, slot, lds};
+  }
+  return {0, 0, 0};
+}
+
+bool gather_supported(int L, int q) { return L <= 512 && q <= 32 && gather_shape(L, q).ahead > 0; }
+
+size_t gather_ws_bytes(int L, int q) {
+  return align256(sizeof(float) * (size_t)L * L * q * gather_qp(q));
+}
+
+// Jt[i][j][b][a'] = J[(j*q + b)][(i*q + a')] for a' < q, else 0.
+__global__ void k_gather_layout(const float* __restrict__ J, int L, int q, float* __restrict__ Jt) {
+  const int QP = gather_qp(q);
+  const size_t total = (size_t)L * L * q * QP;
+  const size_t Lq = (size_t)L * q;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % QP);
+    const size_t r = e / QP;  // ((i*L + j)*q + b)
+    const int b = (int)(r % q);
+    const size_t ij = r / q;
+    const int j = (int)(ij % L), i = (int)(ij / L);
+    Jt[e] = (a < q) ? J[((size_t)j * q + b) * Lq + (size_t)i * q + a] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+template <int Q>
+__global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
+    const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
+    int64_t N, int L, int ahead, int slot, int cpb, int sweeps, uint32_t k0, uint32_t k1,
+    uint64_t sweep_offset, float beta, unsigned long long* flips_out, int32_t* dev_err) {
+  constexpr int G = kGG, W = kGWv, R = kGR, JC = kGJC;
+  constexpr int kT = W * 64, kCPW = 64 / G, kCPB = kCPW * W;
+  constexpr int QP = gather_qp(Q), kQ4 = QP / 4;
+  constexpr int kP = gather_items(Q);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __attribute__((aligned(16))) unsigned char g_smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int cl = lane % kCPW, g = lane / kCPW;
+  const int cb = wid * kCPW + cl;  // chain slot in the workgroup
+  const int nslot = ahead + 2;
+  float* ring = reinterpret_cast<float*>(g_smem);                             // [nslot][slot]
+  uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [L/4][kCPB]
+  unsigned char* tokb = reinterpret_cast<unsigned char*>(tokw);
+  const int L4 = (L + 3) >> 2;
+  const int64_t c = (int64_t)blockIdx.x * cpb + cb;
+  const bool has_chain = cb < cpb;
+  const bool active = has_chain && (c < N);
+  const int nchunk = (L + JC - 1) / JC;
+  const uint32_t site_bytes = (uint32_t)((size_t)L * Q * QP * sizeof(float));
+  const uint32_t chunk_bytes = (uint32_t)(JC * Q * QP * sizeof(float));
+
+  for (int k = g; k < L4; k += G) {
+    uint32_t v = 0;
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * k + e;
+      int t = 0;
+      if (active && j < L) t = checked_token(chains[c * L + j], Q, dev_err);
+      v |= (uint32_t)t << (8 * e);
+    }
+    tokw[k * kCPB + cb] = v;
+  }
+
+  // Chunk-step (i, k) -> ring slot sl: bytes [k*chunk_bytes, +chunk_bytes) of
+  // site i's run, read through a buffer resource that ends with the run (the
+  // hardware returns 0 past it).  Item p of this thread is the 16 bytes at
+  // 16*(tid + kT*p) of the slot.
+  auto issue_chunk = [&](int i, int k, int sl) {
+    const uint32_t off = (uint32_t)i * site_bytes + (uint32_t)k * chunk_bytes;
+    const uint32_t left = site_bytes - (uint32_t)k * chunk_bytes;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const char*>(Jt) + off), (short)0, (int)left, 0x00020000);
+    float* dst0 = ring + (size_t)sl * slot;
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+      float* dst = dst0 + 4 * (wid * 64 + kT * p);  // wave-uniform base; lane adds 16*lane
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)dst, 16, 16 * (tid + kT * p), 0, 0, 0);
+    }
+  };
+
+  const int64_t T = (int64_t)sweeps * L * nchunk;
+  // prefetch cursor: step tn = t + ahead, as (site, chunk, slot)
+  int pi = 0, pk = 0, psl = 0;
+  auto advance = [&](int& ii, int& kk, int& sl) {
+    if (++kk == nchunk) {
+      kk = 0;
+      if (++ii == L) ii = 0;
+    }
+    if (++sl == nslot) sl = 0;
+  };
+  for (int64_t t = 0; t < ahead && t < T; ++t) {
+    issue_chunk(pi, pk, psl);
+    advance(pi, pk, psl);
+  }
+
+  float acc[QP];
+  float hreg[Q];
+#pragma unroll
+  for (int a = 0; a < QP; ++a) acc[a] = 0.0f;
+  unsigned long long nflip = 0;
+  int i = 0, k = 0, sw = 0, csl = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    if (k == 0) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) hreg[a] = h[i * Q + a];  // used at the draw of site i
+    }
+    const int64_t rest = T - 1 - t;  // steps after this one
+    if (rest >= ahead) {
+      issue_chunk(pi, pk, psl);
+      advance(pi, pk, psl);
+    }
+    compiler_fence();
+    // this step's loads are done once at most the younger steps' are pending
+    const int64_t younger = rest < ahead ? rest : ahead;
+    if (younger >= 2) {
+      __builtin_amdgcn_s_waitcnt(((2 * kP) & 15) | (((2 * kP) >> 4) << 14) | 0x0F70);
+    } else if (younger == 1) {
+      __builtin_amdgcn_s_waitcnt((kP & 15) | ((kP >> 4) << 14) | 0x0F70);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
+
+    // ---- this lane's R sites of the chunk
+    const float* jb = ring + (size_t)csl * slot;
+    const int j0 = k * JC + g * R;
+    if (has_chain && j0 < L) {
+      // the R tokens of j0 .. j0+R-1 share one dword (R divides 4 and j0 % R == 0)
+      const uint32_t tk = tokw[(j0 >> 2) * kCPB + cb] >> (8 * (j0 & 3));
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        if (j < L && j != i) {
+          const int s = (int)((tk >> (8 * r)) & 0xFF);
+          const f4* row = reinterpret_cast<const f4*>(jb + ((g * R + r) * Q + s) * QP);
+#pragma unroll
+          for (int v = 0; v < kQ4; ++v) {
+            const f4 x = row[v];
+            acc[4 * v + 0] += x[0];
+            acc[4 * v + 1] += x[1];
+            acc[4 * v + 2] += x[2];
+            acc[4 * v + 3] += x[3];
+          }
+        }
+      }
+    }
+
+    if (k == nchunk - 1) {
+      // ---- combine the G partial sums, draw, store the token
+#pragma unroll
+      for (int o = kCPW; o < 64; o <<= 1)
+#pragma unroll
+        for (int a = 0; a < Q; ++a) acc[a] += __shfl_xor(acc[a], o, kWave);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        acc[a] = beta * (hreg[a] + acc[a]);
+        mx = fmaxf(mx, acc[a]);
+      }
+      float run = 0.0f;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        run += __expf(acc[a] - mx);
+        acc[a] = run;  // S_a
+      }
+      const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
+      const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, (uint32_t)c, 0u), k0, k1);
+      const float uz = word_to_uniform(pick_word(rnd, i & 3)) * run;
+      int anew = 0;
+#pragma unroll
+      for (int a = 0; a < Q - 1; ++a) anew += (acc[a] <= uz) ? 1 : 0;
+      if (g == 0 && has_chain) {
+        unsigned char* tp = tokb + ((i >> 2) * kCPB + cb) * 4 + (i & 3);
+        if (active && anew != (int)*tp) ++nflip;
+        *tp = (unsigned char)anew;
+      }
+#pragma unroll
+      for (int a = 0; a < QP; ++a) acc[a] = 0.0f;
+    }
+    if (++csl == nslot) csl = 0;
+    if (++k == nchunk) {
+      k = 0;
+      if (++i == L) {
+        i = 0;
+        ++sw;
+      }
+    }
+  }
+  __syncthreads();
+  if (active)
+    for (int j = g; j < L; j += G) chains[c * L + j] = (int8_t)tokb[((j >> 2) * kCPB + cb) * 4 + (j & 3)];
+  if (flips_out) {
+    unsigned long long tot = nflip;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
+    if (lane == 0 && tot) atomicAdd(flips_out, tot);
+  }
+}
+
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int Q>
+static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chains, int64_t N,
+                                  int L, int sweeps, uint64_t seed, uint64_t sweep_offset,
+                                  float beta, unsigned long long* flips_out, int32_t* dev_err,
+                                  hipStream_t s) {
+  const GatherShape gs = gather_shape(L, Q);
+  if (gs.ahead == 0) return hipErrorInvalidValue;
+  constexpr int kCPB = (64 / kGG) * kGWv;
+  // chains per workgroup: spread the chains over all CUs in as few rounds as
+  // the workgroup size allows (one workgroup per CU at a time)
+  const int64_t cus = device_cus();
+  const int64_t rounds = ceil_div(N, cus * kCPB);
+  const int cpb = (int)std::min<int64_t>(kCPB, ceil_div(N, rounds * cus));
+  const unsigned nb = (unsigned)ceil_div(N, cpb);
+  auto kern = k_gibbs_gather<Q>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kGWv * 64), gs.lds, s, h, Jt, chains, N, L, gs.ahead,
+                     gs.slot, cpb, sweeps, (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset,
+                     beta, flips_out, dev_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, int64_t N, int L,
+                               int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
+                               unsigned long long* flips_out, int32_t* dev_err, void* ws,
+                               hipStream_t s) {
+  float* Jt = static_cast<float*>(ws);
+  {
+    const size_t total = (size_t)L * L * q * gather_qp(q);
+    const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 65536);
+    hipLaunchKernelGGL(k_gather_layout, dim3(nb), dim3(256), 0, s, J, L, q, Jt);
+  }
+  switch (q) {
+#define BMDCA_GQ(n) \
+  case n:           \
+    return launch_gather_q<n>(h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, dev_err, s);
+    BMDCA_GQ(2) BMDCA_GQ(3) BMDCA_GQ(4) BMDCA_GQ(5) BMDCA_GQ(6) BMDCA_GQ(7) BMDCA_GQ(8)
+    BMDCA_GQ(9) BMDCA_GQ(10) BMDCA_GQ(11) BMDCA_GQ(12) BMDCA_GQ(13) BMDCA_GQ(14) BMDCA_GQ(15)
+    BMDCA_GQ(16) BMDCA_GQ(17) BMDCA_GQ(18) BMDCA_GQ(19) BMDCA_GQ(20) BMDCA_GQ(21) BMDCA_GQ(22)
+    BMDCA_GQ(23) BMDCA_GQ(24) BMDCA_GQ(25) BMDCA_GQ(26) BMDCA_GQ(27) BMDCA_GQ(28) BMDCA_GQ(29)
+    BMDCA_GQ(30) BMDCA_GQ(31) BMDCA_GQ(32)
+#undef BMDCA_GQ
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace bmdca

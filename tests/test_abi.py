@@ -43,7 +43,13 @@ def test_identity_threshold_agrees_with_oracle():
 
 def test_workspace_sizes():
     lib = B.lib()
-    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10000, 100, 21, 0) >= 10000 * 2100 * 4
+    F = B.SAMPLER_FIELDS
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10000, 100, 21, F) >= 10000 * 2100 * 4
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10000, 100, 21, B.SAMPLER_GATHER) == 100 * 100 * 21 * 24 * 4
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10, 600, 21, B.SAMPLER_GATHER) == 0  # L > 512
+    assert lib.bmdca_workspace_bytes(B.WS_GIBBS, 10, 600, 21, 0) >= 10 * 600 * 21 * 4  # auto
+    assert (lib.bmdca_workspace_bytes(B.WS_TRAIN_STEP, 5000, 20, 21, 1 | F)
+            - lib.bmdca_workspace_bytes(B.WS_TRAIN_STEP, 5000, 20, 21, 1)) >= 5000 * 420 * 4 - 20 * 20 * 21 * 24 * 4
     assert lib.bmdca_workspace_bytes(B.WS_TRAIN_STEP, 500, 20, 21, 1) > 500 * 420 * 4
     assert lib.bmdca_workspace_bytes(B.WS_STATS, 20000, 100, 21, 1) > 2100 * 2100 * 8
     assert lib.bmdca_workspace_bytes(B.WS_APC, 0, 64, 21, 0) >= 64 * 64 * 8
@@ -67,8 +73,13 @@ def test_host_validation_returns_status_without_gpu():
                          0, None, None)
     assert rc == B.ENONFINITE
     # workspace too small
-    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 21, 1, 0, 0, 1.0, fake, 16, 0, None, None)
+    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 21, 1, 0, 0, 1.0, fake, 16, B.SAMPLER_FIELDS,
+                         None, None)
     assert rc == B.EWORKSPACE
+    # both sampler bits at once
+    rc = lib.bmdca_gibbs(fake, fake, fake, 10, 20, 21, 1, 0, 0, 1.0, fake, 1 << 30, 0x30, None,
+                         None)
+    assert rc == B.EINVAL
     # theta outside [0,1]
     rc = lib.bmdca_reweight(fake, 10, 20, 21, 1.5, fake, fake, fake, fake, 1 << 30, None, None)
     assert rc == B.EINVAL

@@ -57,9 +57,9 @@ def test_init_chains_bitexact(N, L, q):
 def test_local_fields_match_oracle(L, q, N):
     h, J = synth.planted_dense(L, q, seed=40 + L, sigma_J=0.3)
     ch = O.init_chains(N, L, q, seed=41)
-    H = torch.empty(api.workspace_bytes(B.WS_GIBBS, N, L, q) // 4, dtype=torch.float32,
-                    device="cuda")
-    api.gibbs(dev(h), dev(J), dev(ch), sweeps=0, seed=0, H_ws=H)
+    H = torch.empty(api.workspace_bytes(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS) // 4,
+                    dtype=torch.float32, device="cuda")
+    api.gibbs(dev(h), dev(J), dev(ch), sweeps=0, seed=0, H_ws=H, sampler="fields")
     Hg = host(H)[: N * L * q].reshape(N, L * q)
     for c in range(N):
         Ho = O.local_fields(h, J, ch[c], q)
@@ -67,8 +67,9 @@ def test_local_fields_match_oracle(L, q, N):
 
 
 # ----------------------------------------------------------------- Gibbs trajectories
-@pytest.mark.parametrize("L,q,N,sJ", [(20, 21, 500, 0.1), (33, 5, 300, 0.5)])
-def test_gibbs_trajectory_single_sweeps(L, q, N, sJ):
+@pytest.mark.parametrize("sampler", ["fields", "gather"])
+@pytest.mark.parametrize("L,q,N,sJ", [(20, 21, 500, 0.1), (33, 5, 300, 0.5), (70, 21, 130, 0.2)])
+def test_gibbs_trajectory_single_sweeps(L, q, N, sJ, sampler):
     """Shared Philox counters: identical states after every sweep except at
     boundary events, after which the chain is resynchronised to the oracle."""
     h, J = synth.planted_dense(L, q, seed=50 + L, sigma_J=sJ)
@@ -77,7 +78,7 @@ def test_gibbs_trajectory_single_sweeps(L, q, N, sJ):
     hg, Jg, chg = dev(h), dev(J), dev(ch)
     excused = 0
     for s in range(12):
-        api.gibbs(hg, Jg, chg, sweeps=1, seed=seed, sweep_offset=s)
+        api.gibbs(hg, Jg, chg, sweeps=1, seed=seed, sweep_offset=s, sampler=sampler)
         orc, mg, _ = O.gibbs(h, J, ch, q, sweeps=1, seed=seed, sweep_offset=s, want_margins=True)
         g = host(chg)
         bad = check_trajectory(g, orc, mg)
@@ -95,11 +96,12 @@ def test_gibbs_multi_sweep_drift_and_states():
     L, q, N = 20, 21, 400
     h, J = synth.planted_dense(L, q, seed=60, sigma_J=0.1)
     ch = O.init_chains(N, L, q, seed=61)
-    H = torch.empty(api.workspace_bytes(B.WS_GIBBS, N, L, q) // 4, dtype=torch.float32,
-                    device="cuda")
+    H = torch.empty(api.workspace_bytes(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS) // 4,
+                    dtype=torch.float32, device="cuda")
     flips = torch.zeros(1, dtype=torch.int64, device="cuda")
     chg = dev(ch)
-    api.gibbs(dev(h), dev(J), chg, sweeps=10, seed=62, sweep_offset=5, H_ws=H, flips=flips)
+    api.gibbs(dev(h), dev(J), chg, sweeps=10, seed=62, sweep_offset=5, H_ws=H, flips=flips,
+              sampler="fields")
     g = host(chg)
     orc, mg, oflips = O.gibbs(h, J, ch, q, sweeps=10, seed=62, sweep_offset=5, want_margins=True)
     bad = np.nonzero((g != orc).any(axis=1))[0]
@@ -114,20 +116,42 @@ def test_gibbs_multi_sweep_drift_and_states():
         assert int(host(flips)[0]) == oflips
 
 
+@pytest.mark.parametrize("L,q,N", [(20, 21, 400), (150, 21, 64), (37, 4, 200)])
+def test_gibbs_gather_multi_sweep_states(L, q, N):
+    """Gather form, ten sweeps in one call: every chain that ends in a state
+    different from the oracle's went through a boundary event; flips agree
+    when none did."""
+    h, J = synth.planted_dense(L, q, seed=63 + L, sigma_J=0.1)
+    ch = O.init_chains(N, L, q, seed=64)
+    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chg = dev(ch)
+    api.gibbs(dev(h), dev(J), chg, sweeps=10, seed=65, sweep_offset=3, flips=flips,
+              sampler="gather")
+    g = host(chg)
+    orc, mg, oflips = O.gibbs(h, J, ch, q, sweeps=10, seed=65, sweep_offset=3, want_margins=True)
+    bad = np.nonzero((g != orc).any(axis=1))[0]
+    for c in bad:
+        assert mg[c].min() < BOUNDARY
+    assert len(bad) <= max(2, N // 50)
+    if len(bad) == 0:
+        assert int(host(flips)[0]) == oflips
+
+
 def _sidak_z(n_tests, alpha=0.01):
     from scipy.stats import norm
     a1 = 1 - (1 - alpha) ** (1.0 / n_tests)
     return norm.ppf(1 - a1 / 2)
 
 
-def test_gibbs_stationary_tiny_model():
+@pytest.mark.parametrize("sampler", ["fields", "gather"])
+def test_gibbs_stationary_tiny_model(sampler):
     """L=4, q=3: 10^5 chains x 50 sweeps; every p_i and p_ij within the
     Sidak-corrected 3-sigma-equivalent band of exact enumeration."""
     L, q, N = 4, 3, 100000
     h, J = synth.planted_dense(L, q, seed=70, sigma_J=1.0)
     p1, p2, _ = O.enumerate_exact(h, J, L, q)
     chg = api.init_chains(N, L, q, seed=71)
-    api.gibbs(dev(h), dev(J), chg, sweeps=50, seed=72)
+    api.gibbs(dev(h), dev(J), chg, sweeps=50, seed=72, sampler=sampler)
     Y = onehot(host(chg).astype(np.int64), q)
     s1, s2 = Y.mean(0), Y.T @ Y / N
     z1 = np.abs(s1 - p1) / np.sqrt(np.maximum(p1 * (1 - p1), 1e-12) / N)
@@ -135,16 +159,17 @@ def test_gibbs_stationary_tiny_model():
     assert max(z1.max(), z2.max()) < _sidak_z(len(p1) + p2.size)
 
 
-def test_gibbs_beta_zero_is_uniform_and_two_state():
+@pytest.mark.parametrize("sampler", ["fields", "gather"])
+def test_gibbs_beta_zero_is_uniform_and_two_state(sampler):
     N = 200000
     h = np.array([[0.3, -0.9]], dtype=np.float32)
     J = np.zeros((2, 2), dtype=np.float32)
     chg = torch.zeros((N, 1), dtype=torch.int8, device="cuda")
-    api.gibbs(dev(h), dev(J), chg, sweeps=1, seed=5)
+    api.gibbs(dev(h), dev(J), chg, sweeps=1, seed=5, sampler=sampler)
     p = np.exp(-0.9) / (np.exp(0.3) + np.exp(-0.9))
     f = host(chg).mean()
     assert abs(f - p) < 5 * np.sqrt(p * (1 - p) / N)
-    api.gibbs(dev(h), dev(J), chg, sweeps=1, seed=6, beta=0.0)
+    api.gibbs(dev(h), dev(J), chg, sweeps=1, seed=6, beta=0.0, sampler=sampler)
     assert abs(host(chg).mean() - 0.5) < 5 * np.sqrt(0.25 / N)
 
 
@@ -256,7 +281,8 @@ def c1_problem(L=20, q=21, M=500, N=500):
     return h, J, msa, w, f1, f2, chains
 
 
-def test_train_step_c1_epochs():
+@pytest.mark.parametrize("sampler", ["fields", "gather"])
+def test_train_step_c1_epochs(sampler):
     """20 epochs, lr 0.05, 10 sweeps, N = 500, both sides fed the same data
     frequencies: chains, h and J bit-exact after every epoch without boundary
     events; Pearson within 1e-12. After a boundary event both sides restart
@@ -267,12 +293,12 @@ def test_train_step_c1_epochs():
     J = np.zeros((L * q, L * q), np.float32)
     hg, Jg, cg = dev(h), dev(J), dev(chains)
     f1g, f2g = dev(f1), dev(f2)
-    ws = api.workspace(B.WS_TRAIN_STEP, 500, L, q, B.PREC_BF16X2)
+    ws = api.workspace(B.WS_TRAIN_STEP, 500, L, q, B.PREC_BF16X2 | B.SAMPLER[sampler])
     e = err_flag()
     events = 0
     for ep in range(20):
         pr = api.train_step(hg, Jg, cg, f1g, f2g, 0.05, 10, seed=4001, epoch=ep, prec="bf16x2",
-                            ws=ws, dev_err=e)
+                            ws=ws, dev_err=e, sampler=sampler)
         h2, J2, ch2, r, mg, _ = O.train_step(h, J, chains, f1, f2, q, 0.05, 10, 4001, ep,
                                              want_margins=True)
         gch = host(cg)
