@@ -540,3 +540,58 @@ int orc_enumerate(const float* h, const float* J, int32_t L, int32_t q,
     free(lw);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Single entries of the definitions above, for checks at sizes where the    */
+/* full tables are too slow to build here.  Same arithmetic, same order.     */
+/* ------------------------------------------------------------------------ */
+
+/* n_sim for the listed rows only (Eq. 7). */
+void orc_reweight_rows(const int8_t* msa, int64_t M, int32_t L, double theta,
+                       const int64_t* rows, int64_t nrows, int32_t* n_sim)
+{
+    int32_t T = orc_identity_threshold(theta, L);
+    for (int64_t k = 0; k < nrows; ++k) {
+        const int64_t m = rows[k];
+        int32_t count = 0;
+        for (int64_t n = 0; n < M; ++n) {
+            int32_t same = 0;
+            for (int32_t i = 0; i < L; ++i)
+                same += (msa[m * L + i] == msa[n * L + i]);
+            if (same >= T) count += 1;
+        }
+        n_sim[k] = count;
+    }
+}
+
+/* f2'[(r1),(r2)] for the listed pairs (Eqs. 3, 8, 9), given M_eff as
+ * computed by orc_stats (sum of w in ascending m). */
+void orc_stats_entries(const int8_t* X, const double* w, int64_t M, int32_t L,
+                       int32_t q, double pseudocount, const int64_t* r1,
+                       const int64_t* r2, int64_t n, double* out)
+{
+    double meff = 0.0;
+    for (int64_t m = 0; m < M; ++m) meff += (w ? w[m] : 1.0);
+    const double alpha = pseudocount < 0.0 ? 1.0 / meff : pseudocount;
+    const double qq = (double)q * (double)q;
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t i = (int32_t)(r1[k] / q), a = (int32_t)(r1[k] % q);
+        const int32_t j = (int32_t)(r2[k] / q), b = (int32_t)(r2[k] % q);
+        double s = 0.0;
+        if (i == j) {
+            for (int64_t m = 0; m < M; ++m)
+                if (X[m * L + i] == a) s += (w ? w[m] : 1.0);
+            double f1 = s / meff;
+            double t1 = (1.0 - alpha) * f1;
+            double t2 = alpha / (double)q;
+            out[k] = (a == b) ? t1 + t2 : 0.0;
+        } else {
+            for (int64_t m = 0; m < M; ++m)
+                if (X[m * L + i] == a && X[m * L + j] == b) s += (w ? w[m] : 1.0);
+            double f = s / meff;
+            double t1 = (1.0 - alpha) * f;
+            double t2 = alpha / qq;
+            out[k] = t1 + t2;
+        }
+    }
+}

@@ -70,6 +70,8 @@ def _declare(L):
         "orc_mutant_scan": (None, [_p, _p, _p, _i32, _i32, _p]),
         "orc_apc_frobenius": (None, [_p, _i32, _i32, _i32, _p, _p]),
         "orc_enumerate": (C.c_int, [_p, _p, _i32, _i32, _f64, _p, _p, _p]),
+        "orc_reweight_rows": (None, [_p, _i64, _i32, _f64, _p, _i64, _p]),
+        "orc_stats_entries": (None, [_p, _p, _i64, _i32, _i32, _f64, _p, _p, _i64, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -138,6 +140,29 @@ def stats(X, q: int, w=None, pseudocount: float = -1.0):
     wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
     lib().orc_stats(_ptr(X), _ptr(wv), M, L, q, pseudocount, _ptr(f1), _ptr(f2), _ptr(meff))
     return f1, f2, float(meff[0])
+
+
+def reweight_rows(msa, rows, theta: float = 0.8):
+    """N^(m) of Eq. (7) for the listed rows only."""
+    msa = _i8(msa)
+    M, L = msa.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros(len(rows), dtype=np.int32)
+    lib().orc_reweight_rows(_ptr(msa), M, L, theta, _ptr(rows), len(rows), _ptr(out))
+    return out
+
+
+def stats_entries(X, q: int, r1, r2, w=None, pseudocount: float = -1.0):
+    """Entries f2'[r1[k], r2[k]] of the pseudocounted two-site table."""
+    X = _i8(X)
+    M, L = X.shape
+    r1 = np.ascontiguousarray(r1, dtype=np.int64)
+    r2 = np.ascontiguousarray(r2, dtype=np.int64)
+    out = np.zeros(len(r1), dtype=np.float64)
+    wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    lib().orc_stats_entries(_ptr(X), _ptr(wv), M, L, q, pseudocount, _ptr(r1), _ptr(r2),
+                            len(r1), _ptr(out))
+    return out
 
 
 # --------------------------------------------------------------------------

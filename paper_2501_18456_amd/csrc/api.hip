@@ -211,9 +211,9 @@ int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, 
   (void)ws;
   (void)ws_bytes;
   BMDCA_TRY(check_model(L, q));
-  BMDCA_REQUIRE(h && J && seqs && E, "null pointer argument");
   BMDCA_REQUIRE(B >= 0 && B <= (int64_t)1 << 31, "B=%lld outside 0..2^31", (long long)B);
-  if (B == 0) return BMDCA_OK;
+  if (B == 0) return BMDCA_OK;  // nothing to score; seqs and E may be NULL
+  BMDCA_REQUIRE(h && J && seqs && E, "null pointer argument");
   return hip_status(launch_energy(h, J, seqs, B, L, q, E, dev_err, (hipStream_t)stream), "energy");
 }
 

@@ -1,0 +1,273 @@
+"""Parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark uses: sampled outputs the oracle computes one by
+one, plus invariants that hold at any size.  Edge cases at the end.
+
+Workloads (synthetic, seeded):
+  protein scale   L=100, q=21, N=10 000 chains, M=20 000 rows
+  precision form  L=256, q=21, N=20 000 chains, M=100 000 weighted rows
+  RNA-like        L=400, q=5,  N=4096 chains
+  largest served  L=512, q=21 (energies, mutant scan, contact scores)
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2501_18456_amd import api, synth
+from paper_2501_18456_amd import _lib as B
+
+pytestmark = pytest.mark.gpu
+BOUNDARY = 1e-5
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+_cache = {}
+
+
+def protein_problem():
+    if "protein" not in _cache:
+        L, q, M = 100, 21, 20000
+        h, J = synth.planted_sparse(L, q, seed=1002, sigma_J=0.5, gap_mass=0.15)
+        X = synth.clustered_msa(M, L, q, seed=2002, n_families=40, mut_rate=0.25)
+        _cache["protein"] = (h, J, X)
+    return _cache["protein"]
+
+
+def precision_msa():
+    if "precision" not in _cache:
+        L, q, M = 256, 21, 100000
+        X = synth.clustered_msa(M, L, q, seed=2003, n_families=200, mut_rate=0.3)
+        w = synth.weights_open_unit(M, 4003)
+        _cache["precision"] = (X, w)
+    return _cache["precision"]
+
+
+def sample_pairs(Lq, n, seed):
+    g = np.random.default_rng(seed)
+    r1 = g.integers(0, Lq, n)
+    r2 = g.integers(0, Lq, n)
+    return r1, r2
+
+
+# ---------------------------------------------------------------- protein scale
+def test_protein_reweight_sampled_rows():
+    _, _, X = protein_problem()
+    n, w, meff = api.reweight(dev(X), 21, 0.8)
+    n, w = host(n), host(w)
+    rows = np.random.default_rng(5).choice(len(X), 60, replace=False)
+    ref = O.reweight_rows(X, rows, 0.8)
+    assert np.array_equal(n[rows], ref)
+    assert np.array_equal(w[rows], 1.0 / ref)
+    assert n.max() > 1  # the alignment is redundant at 80% identity
+    assert abs(host(meff)[0] - w.sum()) <= 1e-10 * w.sum()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x2", 1e-5)])
+def test_protein_stats_sampled_entries(prec, tol):
+    _, _, X = protein_problem()
+    L, q = 100, 21
+    w = synth.weights_open_unit(len(X), 6)
+    f1, f2, meff = api.stats(dev(X), q, dev(w), -1.0, prec)
+    f1, f2 = host(f1), host(f2)
+    r1, r2 = sample_pairs(L * q, 3000, 7)
+    ref = O.stats_entries(X, q, r1, r2, w, -1.0)
+    assert np.abs(f2[r1, r2] - ref).max() <= tol
+    d = np.arange(L * q)
+    assert np.abs(f1 - O.stats_entries(X, q, d, d, w, -1.0)).max() <= tol
+    assert np.array_equal(f2, f2.T)
+    F2 = f2.reshape(L, q, L, q)
+    marg = F2.sum(axis=3)  # sum over b of f_ij(a, b) = f_i(a) for j != i
+    off = ~np.eye(L, dtype=bool)
+    assert np.abs(marg.transpose(0, 2, 1)[off] - f1.reshape(L, q)[:, None, :].repeat(L, 1)[off]).max() <= q * tol
+
+
+@pytest.mark.parametrize("sampler", ["gather", "fields"])
+def test_protein_epoch(sampler):
+    """One epoch at full size: sampled chains follow the oracle's trajectories
+    (boundary events excused); h, J satisfy the update's invariants."""
+    h_true, J_true, X = protein_problem()
+    L, q, N, lr = 100, 21, 10000, 0.05
+    _, w, _ = O.reweight(X[:2000], 0.8)  # weights of a block; any weights will do here
+    ww = np.ones(len(X))
+    ww[:2000] = w
+    f1, f2, _ = O.stats(X, q, ww, -1.0)
+    h0 = np.log(f1).astype(np.float32).reshape(L, q)
+    J0 = J_true * 0.5  # a non-trivial starting model
+    ch0 = O.init_chains(N, L, q, seed=3002)
+    hg, Jg, cg = dev(h0), dev(J0), dev(ch0)
+    pr = api.train_step(hg, Jg, cg, dev(f1), dev(f2), lr, 10, seed=3002, epoch=3, prec="fp32",
+                        sampler=sampler)
+    g = host(cg)
+    # sampled slices of chains against the oracle
+    for c0 in (0, 4321, N - 37):
+        sl = slice(c0, c0 + 37)
+        ref, mg, _ = O.gibbs_range(h0, J0, ch0[sl], c0, q, 10, 3002, sweep_offset=30,
+                                   want_margins=True)
+        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
+        for c in bad:
+            assert mg[c].min() < BOUNDARY
+        assert len(bad) <= 2
+    # invariants of the update (Eq. 5) relating the two outputs
+    h1, J1 = host(hg).astype(np.float64), host(Jg)
+    assert np.array_equal(J1, J1.T)
+    J4 = J1.reshape(L, q, L, q)
+    assert all(np.all(J4[i, :, i, :] == 0) for i in range(L))
+    dJ = (J1.astype(np.float64) - J0.astype(np.float64)).reshape(L, q, L, q) / lr
+    dh = (h1 - h0.astype(np.float64)).reshape(L, q) / lr
+    # sum_b (f_ij - p_ij)(a, b) = f_i(a) - p_i(a) for every j != i
+    s = dJ.sum(axis=3)  # [i, a, j]
+    for i in (0, 17, 99):
+        for j in (3, 50, 98):
+            if i != j:
+                assert np.abs(s[i, :, j] - dh[i]).max() < 2e-3  # fp32 rounding of q entries / lr
+    # Pearson against the chains the epoch produced
+    Y = np.zeros((N, L * q), np.float32)
+    Y[np.arange(N)[:, None], np.arange(L)[None, :] * q + g] = 1.0
+    C = torch.from_numpy(Y).cuda()
+    P2 = (C.T @ C).double().cpu().numpy() / N
+    P1 = np.diag(P2).copy()
+    assert abs(host(pr)[0] - O.pearson(f1, f2, P1, P2, L, q)) < 1e-10
+
+
+# ---------------------------------------------------------------- precision form
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp32", 1e-6)])
+def test_precision_stats_sampled_entries(prec, tol):
+    X, w = precision_msa()
+    L, q = 256, 21
+    f1, f2, meff = api.stats(dev(X), q, dev(w), -1.0, prec)
+    r1, r2 = sample_pairs(L * q, 800, 8)
+    sel = torch.from_numpy(r1 * (L * q) + r2).cuda()
+    got = host(f2.reshape(-1)[sel])
+    ref = O.stats_entries(X, q, r1, r2, w, -1.0)
+    err = np.abs(got - ref).max()
+    print(f"precision-form stats {prec}: max |f2 - oracle| over 800 entries = {err:.3e}")
+    assert err <= tol
+    d = np.arange(0, L * q, 7)
+    assert np.abs(host(f1)[d] - O.stats_entries(X, q, d, d, w, -1.0)).max() <= tol
+    assert bool((f2 == f2.T).all())
+    assert abs(host(meff)[0] - w.sum()) <= 1e-10 * w.sum()
+
+
+def test_precision_gibbs_sampled_chains():
+    L, q, N = 256, 21, 20000
+    h, J = synth.planted_dense(L, q, seed=1003, sigma_J=0.05)
+    ch0 = O.init_chains(N, L, q, seed=3003)
+    cg = dev(ch0)
+    api.gibbs(dev(h), dev(J), cg, 2, seed=3003, sweep_offset=7)
+    g = host(cg)
+    for c0 in (0, 12345, N - 20):
+        sl = slice(c0, c0 + 20)
+        ref, mg, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 2, 3003, sweep_offset=7,
+                                   want_margins=True)
+        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
+        for c in bad:
+            assert mg[c].min() < BOUNDARY
+        assert len(bad) <= 1
+
+
+# ---------------------------------------------------------------- RNA-like
+def test_rna_gibbs_and_counts():
+    L, q, N = 400, 5, 4096
+    h, J = synth.planted_dense(L, q, seed=1004, sigma_J=0.05)
+    ch0 = O.init_chains(N, L, q, seed=3004)
+    cg = dev(ch0)
+    api.gibbs(dev(h), dev(J), cg, 1, seed=3004)
+    g = host(cg)
+    for c0 in (0, 2000):
+        sl = slice(c0, c0 + 16)
+        ref, mg, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 1, 3004, want_margins=True)
+        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
+        for c in bad:
+            assert mg[c].min() < BOUNDARY
+    # unit-weight statistics of these chains: bit-exact sampled entries
+    f1, f2, _ = api.stats(cg, q, None, 0.0, "bf16x2")
+    r1, r2 = sample_pairs(L * q, 500, 9)
+    assert np.array_equal(host(f2)[r1, r2], O.stats_entries(g, q, r1, r2, None, 0.0))
+
+
+# ---------------------------------------------------------------- largest served model
+def test_largest_model_scores():
+    L, q = 512, 21
+    h, J = synth.planted_dense(L, q, seed=1005, sigma_J=0.02)
+    S = synth.random_sequences(1500, L, q, 10)
+    E = host(api.energy(dev(h), dev(J), dev(S)))
+    Eo = O.energy(h, J, S, q)
+    assert np.abs(E - Eo).max() <= 1e-4 * np.abs(Eo).max()
+    wt = S[:2]
+    dE = host(api.single_mutant_scan(dev(h), dev(J), dev(wt))).reshape(2, L, q)
+    g = np.random.default_rng(11)
+    for b in range(2):
+        e0 = O.energy(h, J, wt[b:b + 1], q)[0]
+        for _ in range(40):
+            i, a = int(g.integers(L)), int(g.integers(q))
+            t = wt[b].copy()
+            t[i] = a
+            ref = O.energy(h, J, t[None], q)[0] - e0
+            assert abs(dE[b, i, a] - ref) <= 1e-4 * (1 + abs(e0))
+    F, Fa = api.apc_frobenius(dev(J), L, q, 0)
+    Fo, Fao = O.apc_frobenius(J, L, q, 0)
+    assert np.abs(host(Fa) - Fao).max() <= 1e-5 * np.abs(Fo).max()
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_single_chain_two_sites():
+    L, q = 2, 2
+    h, J = synth.planted_dense(L, q, seed=12, sigma_J=0.5)
+    ch0 = O.init_chains(1, L, q, seed=13)
+    for sampler in ("gather", "fields"):
+        cg = dev(ch0)
+        api.gibbs(dev(h), dev(J), cg, 5, seed=14, sampler=sampler)
+        ref, mg, _ = O.gibbs(h, J, ch0, q, 5, 14, want_margins=True)
+        if not np.array_equal(host(cg), ref):
+            assert mg.min() < BOUNDARY
+    X = ch0
+    f1, f2, _ = api.stats(dev(X), q, None, -1.0)
+    o1, o2, _ = O.stats(X, q, None, -1.0)
+    assert np.array_equal(host(f1), o1) and np.array_equal(host(f2), o2)
+    n, w, meff = api.reweight(dev(X), q, 0.8)
+    assert host(n)[0] == 1 and host(meff)[0] == 1.0
+    hg, Jg = dev(h), dev(J)
+    f1d, f2d = dev(o1), dev(o2)
+    e = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pr = api.train_step(hg, Jg, dev(ch0), f1d, f2d, 0.05, 2, 15, 0, dev_err=e)
+    # one chain has no connected correlations: the Pearson coefficient is 0/0
+    # on both sides (flagged), the parameters stay finite
+    _, _, _, r, _, _ = O.train_step(h, J, ch0, o1, o2, q, 0.05, 2, 15, 0)
+    assert np.isnan(r) and np.isnan(host(pr)[0])
+    assert int(host(e)[0]) == B.DEVERR_NONFINITE
+    assert np.isfinite(host(hg)).all() and np.isfinite(host(Jg)).all()
+
+
+def test_edge_empty_batch_and_zero_sweeps():
+    L, q = 30, 21
+    h, J = synth.planted_dense(L, q, seed=16, sigma_J=0.1)
+    out = api.energy(dev(h), dev(J), torch.empty((0, L), dtype=torch.int8, device="cuda"))
+    assert out.numel() == 0
+    ch0 = O.init_chains(70, L, q, seed=17)
+    for sampler in ("gather", "fields"):
+        cg = dev(ch0)
+        api.gibbs(dev(h), dev(J), cg, 0, seed=18, sampler=sampler)
+        assert np.array_equal(host(cg), ch0)
+
+
+def test_edge_ragged_tiles_and_tail_rows():
+    """Lq not a multiple of the 128-wide tiles, M not a multiple of the 64-row
+    stage, single-row alignment."""
+    for (L, q, M) in [(13, 11, 1), (13, 11, 65), (29, 7, 1000)]:
+        X = synth.clustered_msa(M, L, q, seed=19 + M)
+        w = synth.weights_open_unit(M, 20)
+        for prec in ("fp32", "bf16x2"):
+            f1, f2, _ = api.stats(dev(X), q, None, -1.0, prec)
+            o1, o2, _ = O.stats(X, q, None, -1.0)
+            assert np.array_equal(host(f2), o2)
+            g1, g2, _ = api.stats(dev(X), q, dev(w), 0.3, prec)
+            p1, p2, _ = O.stats(X, q, w, 0.3)
+            assert np.abs(host(g2) - p2).max() <= 1e-5

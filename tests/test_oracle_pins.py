@@ -438,3 +438,23 @@ def test_apc_gauge_invariance_and_symmetry():
     Bz = J.reshape(L, q, L, q)[1, :, 4, :].astype(np.float64)
     Bz = Bz - Bz.mean(1, keepdims=True) - Bz.mean(0, keepdims=True) + Bz.mean()
     assert abs(F[1, 4] - np.linalg.norm(Bz[1:, 1:])) < 1e-12
+
+
+# ---------------------------------------------------------------- sampled-entry forms
+def test_sampled_entry_forms_agree_with_full_tables():
+    """The single-entry forms used for large-size checks equal the pinned full
+    tables exactly (same arithmetic in the same order)."""
+    L, q, M = 9, 5, 250
+    X = synth.clustered_msa(M, L, q, seed=40)
+    w = synth.weights_open_unit(M, 41)
+    for ww in (None, w):
+        f1, f2, _ = O.stats(X, q, ww, -1.0)
+        g = np.random.default_rng(42)
+        r1 = g.integers(0, L * q, 300)
+        r2 = g.integers(0, L * q, 300)
+        assert np.array_equal(O.stats_entries(X, q, r1, r2, ww, -1.0), f2[r1, r2])
+        d = np.arange(L * q)
+        assert np.array_equal(O.stats_entries(X, q, d, d, ww, -1.0), f1)
+    n, _, _ = O.reweight(X, 0.8)
+    rows = np.array([0, 7, 100, 249])
+    assert np.array_equal(O.reweight_rows(X, rows, 0.8), n[rows])
