@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-chains", type=int, default=4000,
                     help="chains in the oracle's timed sample epoch")
     return ap.parse_args()
@@ -73,6 +75,14 @@ def main():
     from paper_2501_18456_amd import _lib as B
 
     torch.cuda.set_device(0)
+    if args.profile_copy_mib:
+        # a copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the others
+        n = args.profile_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     L, q, N, M, sweeps, lr = 100, 21, 10000, 20000, 10, 0.05
     Lq = L * q
     seed_model, seed_msa, seed_chain = 1002, 2002, 3002
