@@ -8,11 +8,13 @@
 //   - tokens are first transposed to site-major XT[L][Mpad] so that the
 //     tokens of one site for consecutive rows are contiguous;
 //   - a workgroup owns a 128x128 output tile (only tiles on or above the
-//     diagonal) and walks K in stages of 64 rows; each stage scatters the
-//     one-hot entries of its rows into zeroed LDS tiles (one write per
-//     (row, site), the rest of the tile is zero), the four waves run
-//     32x32 MFMAs on a 64x64 sub-tile each, and the same threads then clear
-//     exactly the entries they set;
+//     diagonal) and walks K in stages of 64 rows; the operand tiles are
+//     double-buffered in LDS: while the four waves run 32x32 MFMAs on a 64x64
+//     sub-tile each from one buffer, every thread clears the one-hot entries
+//     it set two stages ago in the other buffer and writes those of the next
+//     stage there (one write per (row, site); padding and out-of-tile
+//     entries go to a trash row that is never read), so a stage needs one
+//     barrier;
 //   - BF16: one-hot values are exact; a weight is split into hi + lo BF16
 //     parts (two products into the same FP32 accumulator); FP32 partial sums
 //     are flushed into FP64 registers every 512 rows.  Unit weights give
@@ -33,7 +35,6 @@ constexpr int kKT = 64;                // rows per K stage
 constexpr int kFlushStages = 8;        // 8 * 64 = 512 rows per FP32 partial sum
 constexpr int kRowB = kKT * 2 + 16;    // BF16 tile row stride in bytes (padded)
 constexpr int kRowF = kKT + 1;         // FP32 tile row stride in floats (padded)
-constexpr int kItems = 5;              // packed 4-token items per thread and operand
 
 enum { MODE_UNIT_BF16 = 0, MODE_HILO_BF16 = 1, MODE_F32 = 2 };
 
@@ -42,20 +43,40 @@ static int mode_of(int prec, bool weighted) {
   return weighted ? MODE_HILO_BF16 : MODE_UNIT_BF16;
 }
 
+// Tiles (ti, tj) of kTR rows x 128 columns that hold some (r, c) with r <= c.
+static int64_t product_tiles(int Lq, int tr) {
+  const int nA = (int)ceil_div(Lq, tr), nB = (int)ceil_div(Lq, kTile);
+  int64_t n = 0;
+  for (int ti = 0; ti < nA; ++ti) n += nB - (ti * tr) / kTile;
+  return n;
+}
+
 StatsPlan plan_stats(int64_t M, int L, int q, int prec) {
-  (void)prec;
   StatsPlan p{};
   const int64_t Lq = (int64_t)L * q;
   p.Mpad = ceil_div(M, kKT) * kKT;
   p.ntile = (int)ceil_div(Lq, kTile);
   p.nupper = p.ntile * (p.ntile + 1) / 2;
-  // Split K so that the grid holds at least ~2 workgroups per CU (256 CUs),
-  // keeping every split at least 8 stages long.
+  // K splits: trade grid balance against the FP64 plane every split writes
+  // and the finish reads back (~5 TB/s).  BF16 (hi+lo tiles of 64 rows, two
+  // workgroups per CU): a stage costs 1024 cycles per CU pair of tiles; FP32
+  // (128-row tiles, one per CU): 8192 cycles.
   const int64_t stages = p.Mpad / kKT;
-  int64_t want = ceil_div(512, p.nupper);
-  int64_t maxs = std::max<int64_t>(1, stages / 8);
-  int64_t sp = std::min<int64_t>(want, maxs);
-  sp = std::min<int64_t>(sp, 16);
+  const int64_t tiles = product_tiles((int)Lq, prec == 0 ? kTile : 64);
+  const int64_t slots = prec == 0 ? 256 : 512;
+  const double stage_us = (prec == 0 ? 8192.0 : 1024.0) / 2400.0;
+  const double plane_us = (double)p.nupper * kTile * kTile * 8.0 * 3.0 / 5.0e6;
+  const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(16, stages / 4));
+  int64_t sp = 1;
+  double best = 0.0;
+  for (int64_t c = 1; c <= maxs; ++c) {
+    const double t = (double)ceil_div(tiles * c, slots) * (double)ceil_div(stages, c) * stage_us +
+                     (double)c * plane_us;
+    if (c == 1 || t < best) {
+      best = t;
+      sp = c;
+    }
+  }
   p.kchunk = ceil_div(stages, sp) * kKT;
   p.splits = (int)ceil_div(p.Mpad, p.kchunk);
   size_t o = 0;
@@ -125,157 +146,192 @@ __global__ void k_prep_weights(const double* __restrict__ w, int64_t M, int64_t 
 
 // ---------------------------------------------------------------------------
 // Main product kernel.
+//
+// Entry ownership: wave w owns the sites i_lo + w + 4p (p < NP) of an operand
+// tile and lane l owns row m0 + l of a stage, so a thread holds one token per
+// (site, stage) and writes one entry, row (site*q + token - R0), column l.
+// Distinct sites give distinct rows, so no two threads share a live entry.
 // ---------------------------------------------------------------------------
 struct Operand {
   int R0;      // first output row/column of the tile
   int i_lo;    // first site overlapping the tile
-  int nitems;  // (site, 4-row group) items: nsites * kKT/4
+  int nsites;  // sites overlapping the tile
 };
 
-__device__ __forceinline__ Operand make_operand(int R0, int L, int q) {
+__device__ __forceinline__ Operand make_operand(int R0, int rows, int L, int q) {
   Operand o;
   o.R0 = R0;
   o.i_lo = R0 / q;
-  const int i_hi = min(L - 1, (R0 + kTile - 1) / q);
-  o.nitems = (i_hi - o.i_lo + 1) * (kKT / 4);
+  const int i_hi = min(L - 1, (R0 + rows - 1) / q);
+  o.nsites = i_hi - o.i_lo + 1;
   return o;
 }
 
-// Packed tokens of the items this thread owns in stage m0.
-__device__ __forceinline__ void load_items(const int8_t* __restrict__ XT, int64_t Mpad,
-                                           const Operand& o, int64_t m0, uint32_t (&tok)[kItems]) {
+// Sites per 128-row tile are at most 127/q + 2; a pass gives one site to
+// every wave.
+static int passes_needed(int q, int waves) { return (int)ceil_div(127 / q + 2, waves); }
+
+template <int NW, int NP>
+__device__ __forceinline__ void load_tokens(const int8_t* __restrict__ XT, int64_t Mpad,
+                                            const Operand& o, int64_t m0, int wid, int lane,
+                                            int (&tok)[NP]) {
 #pragma unroll
-  for (int t = 0; t < kItems; ++t) {
-    const int it = threadIdx.x + t * 256;
-    tok[t] = 0xFFFFFFFFu;
-    if (it < o.nitems) {
-      const int si = o.i_lo + it / (kKT / 4);
-      const int g = it % (kKT / 4);
-      tok[t] = *reinterpret_cast<const uint32_t*>(XT + (size_t)si * Mpad + m0 + 4 * g);
+  for (int p = 0; p < NP; ++p) {
+    const int s = wid + NW * p;
+    // padding (-1) reads as 255: past every tile row for any site base
+    tok[p] = (s < o.nsites) ? (int)(uint8_t)XT[(size_t)(o.i_lo + s) * Mpad + m0 + lane] : 255;
+  }
+}
+
+// Writes value(s) at this thread's entries; a padding token or a row outside
+// the tile goes to the trash row ROWS.
+template <int MODE, int NW, int NP, int ROWS>
+__device__ __forceinline__ void put_entries(const Operand& o, int q, int wid, int lane,
+                                            const int (&tok)[NP], unsigned char* t0,
+                                            unsigned char* t1, bool two, uint16_t v0, uint16_t v1,
+                                            float vf) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int s = wid + NW * p;
+    if (s >= o.nsites) break;  // wave-uniform
+    // base is wave-uniform and in (-q, ROWS); tokens are in [0, q) or 255
+    const int base = (o.i_lo + s) * q - o.R0;
+    const int r = (int)min((unsigned)(tok[p] + base), (unsigned)ROWS);
+    if (MODE == MODE_F32) {
+      *reinterpret_cast<float*>(t0 + r * (kRowF * 4) + 4 * lane) = vf;
+    } else {
+      const int off = r * kRowB + 2 * lane;
+      *reinterpret_cast<uint16_t*>(t0 + off) = v0;
+      if (MODE == MODE_HILO_BF16 && two) *reinterpret_cast<uint16_t*>(t1 + off) = v1;
     }
   }
 }
 
-// Scatter (or clear) the one-hot entries of this thread's items.
+// Output tile kTR x 128 per workgroup of four waves (2 x 2 wave tiles).  The
+// hi+lo form takes 64-row tiles: its waves hold 32x64 (FP32 hi and lo sums
+// plus FP64 sums) and two workgroups share a CU, so one's barrier is
+// covered by the other's matrix work.  The other forms take 128 x 128.
 template <int MODE>
-__device__ __forceinline__ void scatter_items(const Operand& o, int q, const uint32_t (&tok)[kItems],
-                                              bool weighted_operand, bool clear,
-                                              const uint16_t* whi_s, const uint16_t* wlo_s,
-                                              const float* wf_s, unsigned char* t0,
-                                              unsigned char* t1) {
-#pragma unroll
-  for (int t = 0; t < kItems; ++t) {
-    const int it = threadIdx.x + t * 256;
-    if (it >= o.nitems) continue;
-    const int si = o.i_lo + it / (kKT / 4);
-    const int g = it % (kKT / 4);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int tk = (int)(int8_t)((tok[t] >> (8 * e)) & 0xFF);
-      if (tk < 0) continue;
-      const int row = si * q + tk - o.R0;
-      if (row < 0 || row >= kTile) continue;
-      const int ml = 4 * g + e;
-      if (MODE == MODE_F32) {
-        float v = clear ? 0.0f : (weighted_operand ? wf_s[ml] : 1.0f);
-        reinterpret_cast<float*>(t0)[row * kRowF + ml] = v;
-      } else {
-        uint16_t v0 = clear ? 0 : (weighted_operand ? whi_s[ml] : (uint16_t)0x3F80);
-        *reinterpret_cast<uint16_t*>(t0 + row * kRowB + 2 * ml) = v0;
-        if (MODE == MODE_HILO_BF16 && weighted_operand) {
-          uint16_t v1 = clear ? 0 : wlo_s[ml];
-          *reinterpret_cast<uint16_t*>(t1 + row * kRowB + 2 * ml) = v1;
-        }
-      }
-    }
-  }
-}
+struct ProductShape {
+  static constexpr int kWaves = 4;
+  static constexpr int kTR = (MODE == MODE_HILO_BF16) ? 64 : kTile;
+  static constexpr int kRB = kTR / 64;  // 32-row blocks per wave
+};
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_onehot_products(const int8_t* __restrict__ XT,
-                                                         int64_t Mpad, int L, int q,
-                                                         const uint16_t* __restrict__ whi,
-                                                         const uint16_t* __restrict__ wlo,
-                                                         const float* __restrict__ wf,
-                                                         int ntile, int64_t kchunk,
-                                                         double* __restrict__ P) {
+
+template <int MODE, int NP>
+__global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO_BF16) ? 2 : 1) void k_onehot_products(
+    const int8_t* __restrict__ XT, int64_t Mpad, int L, int q, const uint16_t* __restrict__ whi,
+    const uint16_t* __restrict__ wlo, const float* __restrict__ wf, int ntile, int64_t kchunk,
+    double* __restrict__ P) {
+  constexpr int NW = ProductShape<MODE>::kWaves;
+  constexpr int RB = ProductShape<MODE>::kRB;
+  constexpr int TR = ProductShape<MODE>::kTR;
+  constexpr int kThreads = 64 * NW;
   constexpr bool kWeighted = (MODE != MODE_UNIT_BF16);
-  constexpr int kOpBytes = (MODE == MODE_F32) ? kTile * kRowF * 4 : kTile * kRowB;
-  constexpr int kNumA = (MODE == MODE_HILO_BF16) ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[(kNumA + 1) * kOpBytes];
-  __shared__ uint16_t s_whi[2][kKT];
-  __shared__ uint16_t s_wlo[2][kKT];
-  __shared__ float s_wf[2][kKT];
-  unsigned char* tA = smem;
-  unsigned char* tA2 = smem + kOpBytes;  // lo part (HILO only)
-  unsigned char* tB = smem + kNumA * kOpBytes;
+  constexpr bool kLo = (MODE == MODE_HILO_BF16);
+  // one extra (trash) row per operand tile
+  constexpr int kRowBytes = (MODE == MODE_F32) ? kRowF * 4 : kRowB;
+  constexpr int kOpA = (TR + 1) * kRowBytes;
+  constexpr int kOpB = (kTile + 1) * kRowBytes;
+  constexpr int kNumA = kLo ? 2 : 1;
+  constexpr int kBuf = kNumA * kOpA + kOpB;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * kBuf];
 
-  // Upper-triangle tile of this workgroup.
+  // Tile of this workgroup: row tile ti, column tiles from (ti*TR)/128 on.
   int t = blockIdx.x, ti = 0;
-  while (t >= ntile - ti) {
-    t -= ntile - ti;
+  while (t >= ntile - (ti * TR) / kTile) {
+    t -= ntile - (ti * TR) / kTile;
     ++ti;
   }
-  const int tj = ti + t;
+  const int tj = (ti * TR) / kTile + t;
   const int Lq = L * q;
-  const Operand oa = make_operand(ti * kTile, L, q);
-  const Operand ob = make_operand(tj * kTile, L, q);
+  const Operand oa = make_operand(ti * TR, TR, L, q);
+  const Operand ob = make_operand(tj * kTile, kTile, L, q);
   const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
   const int64_t kend = min(kbeg + kchunk, Mpad);
 
-  // Zero the operand tiles once; afterwards every stage clears what it set.
-  for (int k = threadIdx.x * 16; k < (kNumA + 1) * kOpBytes; k += 256 * 16)
+  for (int k = threadIdx.x * 16; k < 2 * kBuf; k += kThreads * 16)
     *reinterpret_cast<uint4*>(smem + k) = make_uint4(0, 0, 0, 0);
 
-  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-  const int wr = wid / 2, wc = wid % 2;
+  const int lane = threadIdx.x % 64;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int wr = wid / 2, wc = wid % 2;  // wave tile: rows 32*RB*wr.., columns 64*wc..
   const int lrow = lane % 32, lhalf = lane / 32;
+  constexpr uint16_t kOne = 0x3F80;  // BF16 1.0
 
-  f32x16 acc[4];
+  // acc[rb][cb]: hi (or only) products; lacc: lo products (hi+lo form).
+  f32x16 acc[RB][2], lacc[kLo ? RB : 1][2];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
-  constexpr int kD = kWeighted ? 4 : 1;  // FP64 sums are only kept for weighted forms
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[b][c][v] = 0.0f;
+        if (kLo) lacc[b][c][v] = 0.0f;
+      }
+  constexpr int kD = kWeighted ? RB * 2 : 1;  // FP64 sums only for weighted forms
   double dacc[kD][16];
 #pragma unroll
   for (int b = 0; b < kD; ++b)
 #pragma unroll
     for (int v = 0; v < 16; ++v) dacc[b][v] = 0.0;
 
-  uint32_t curA[kItems], curB[kItems], nxtA[kItems], nxtB[kItems];
-  // Prologue: stage kbeg.
-  if (kbeg < kend) {
-    load_items(XT, Mpad, oa, kbeg, curA);
-    load_items(XT, Mpad, ob, kbeg, curB);
-    if (threadIdx.x < kKT) {
-      s_whi[0][threadIdx.x] = whi[kbeg + threadIdx.x];
-      s_wlo[0][threadIdx.x] = wlo[kbeg + threadIdx.x];
-      s_wf[0][threadIdx.x] = wf[kbeg + threadIdx.x];
+  // Tokens of the previous, current, next and after-next stage.
+  int aP[NP], bP[NP], aC[NP], bC[NP], aN[NP], bN[NP], aNN[NP], bNN[NP];
+  uint16_t hiN = 0, loN = 0, hiNN = 0, loNN = 0;
+  float fN = 0.0f, fNN = 0.0f;
+  auto load_w = [&](int64_t m, uint16_t& hi, uint16_t& lo, float& f) {
+    if (MODE == MODE_HILO_BF16) {
+      hi = whi[m + lane];
+      lo = wlo[m + lane];
     }
+    if (MODE == MODE_F32) f = wf[m + lane];
+  };
+  auto put_a = [&](const int(&tok)[NP], unsigned char* buf, bool clear, uint16_t hi, uint16_t lo,
+                   float f) {
+    const uint16_t v0 = clear ? (uint16_t)0 : (MODE == MODE_HILO_BF16 ? hi : kOne);
+    const uint16_t v1 = clear ? (uint16_t)0 : lo;
+    const float vf = clear ? 0.0f : f;
+    put_entries<MODE, NW, NP, TR>(oa, q, wid, lane, tok, buf, buf + kOpA, true, v0, v1, vf);
+  };
+  auto put_b = [&](const int(&tok)[NP], unsigned char* buf, bool clear) {
+    put_entries<MODE, NW, NP, kTile>(ob, q, wid, lane, tok, buf + kNumA * kOpA, nullptr, false,
+                              clear ? (uint16_t)0 : kOne, 0, clear ? 0.0f : 1.0f);
+  };
+
+  load_tokens<NW, NP>(XT, Mpad, oa, kbeg, wid, lane, aC);
+  load_tokens<NW, NP>(XT, Mpad, ob, kbeg, wid, lane, bC);
+  uint16_t hi0 = 0, lo0 = 0;
+  float f0 = 0.0f;
+  load_w(kbeg, hi0, lo0, f0);
+  if (kbeg + kKT < kend) {
+    load_tokens<NW, NP>(XT, Mpad, oa, kbeg + kKT, wid, lane, aN);
+    load_tokens<NW, NP>(XT, Mpad, ob, kbeg + kKT, wid, lane, bN);
+    load_w(kbeg + kKT, hiN, loN, fN);
   }
   __syncthreads();
-  if (kbeg < kend) {
-    scatter_items<MODE>(oa, q, curA, kWeighted, false, s_whi[0], s_wlo[0], s_wf[0], tA, tA2);
-    scatter_items<MODE>(ob, q, curB, false, false, s_whi[0], s_wlo[0], s_wf[0], tB, tB);
-  }
+  put_a(aC, smem, false, hi0, lo0, f0);
+  put_b(bC, smem, false);
   __syncthreads();
 
-  int stage = 0;
-  for (int64_t m0 = kbeg; m0 < kend; m0 += kKT, ++stage) {
-    const int64_t mn = m0 + kKT;
-    const bool has_next = mn < kend;
-    uint16_t pw_hi = 0, pw_lo = 0;
-    float pw_f = 0.0f;
-    if (has_next) {
-      load_items(XT, Mpad, oa, mn, nxtA);
-      load_items(XT, Mpad, ob, mn, nxtB);
-      if (threadIdx.x < kKT) {
-        pw_hi = whi[mn + threadIdx.x];
-        pw_lo = wlo[mn + threadIdx.x];
-        pw_f = wf[mn + threadIdx.x];
-      }
+  const int arow0 = 32 * RB * wr + lrow;  // first A row of this lane
+  const int brow0 = 64 * wc + lrow;       // first B row of this lane
+  int st = 0;
+  for (int64_t m0 = kbeg; m0 < kend; m0 += kKT, ++st) {
+    const bool has1 = m0 + kKT < kend;
+    const bool has2 = m0 + 2 * kKT < kend;
+    if (has2) {
+      load_tokens<NW, NP>(XT, Mpad, oa, m0 + 2 * kKT, wid, lane, aNN);
+      load_tokens<NW, NP>(XT, Mpad, ob, m0 + 2 * kKT, wid, lane, bNN);
+      load_w(m0 + 2 * kKT, hiNN, loNN, fNN);
     }
+    const unsigned char* cur = smem + (st & 1) * kBuf;
+    unsigned char* other = smem + ((st & 1) ^ 1) * kBuf;
+    const unsigned char* tA = cur;
+    const unsigned char* tA2 = cur + kOpA;
+    const unsigned char* tB = cur + kNumA * kOpA;
     // ---- matrix-core phase on stage m0
     if (MODE == MODE_F32) {
       const float* fA = reinterpret_cast<const float*>(tA);
@@ -283,91 +339,132 @@ __global__ __launch_bounds__(256) void k_onehot_products(const int8_t* __restric
 #pragma unroll 4
       for (int kk = 0; kk < kKT / 2; ++kk) {
         const int k = 2 * kk + lhalf;
-        const float a0 = fA[(64 * wr + lrow) * kRowF + k];
-        const float a1 = fA[(64 * wr + 32 + lrow) * kRowF + k];
-        const float b0 = fB[(64 * wc + lrow) * kRowF + k];
-        const float b1 = fB[(64 * wc + 32 + lrow) * kRowF + k];
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[3], 0, 0, 0);
+        float a[RB], b[2];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) a[rb] = fA[(arow0 + 32 * rb) * kRowF + k];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) b[cb] = fB[(brow0 + 32 * cb) * kRowF + k];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < kKT / 16; ++kk) {
         const int kb = 2 * (16 * kk + 8 * lhalf);
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(tA + (64 * wr + lrow) * kRowB + kb);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(tA + (64 * wr + 32 + lrow) * kRowB + kb);
-        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(tB + (64 * wc + lrow) * kRowB + kb);
-        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(tB + (64 * wc + 32 + lrow) * kRowB + kb);
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[3], 0, 0, 0);
-        if (MODE == MODE_HILO_BF16) {
-          const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(tA2 + (64 * wr + lrow) * kRowB + kb);
-          const bf16x8 c1 =
-              *reinterpret_cast<const bf16x8*>(tA2 + (64 * wr + 32 + lrow) * kRowB + kb);
-          acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(c0, b0, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(c0, b1, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(c1, b0, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(c1, b1, acc[3], 0, 0, 0);
+        bf16x8 a[RB], c[RB], b[2];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          a[rb] = *reinterpret_cast<const bf16x8*>(tA + (arow0 + 32 * rb) * kRowB + kb);
+          if (kLo) c[rb] = *reinterpret_cast<const bf16x8*>(tA2 + (arow0 + 32 * rb) * kRowB + kb);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          b[cb] = *reinterpret_cast<const bf16x8*>(tB + (brow0 + 32 * cb) * kRowB + kb);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+        if (kLo) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              lacc[rb][cb] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(c[rb], b[cb], lacc[rb][cb], 0, 0, 0);
         }
       }
     }
-    const int nb = (stage + 1) & 1;
-    if (has_next && threadIdx.x < kKT) {
-      s_whi[nb][threadIdx.x] = pw_hi;
-      s_wlo[nb][threadIdx.x] = pw_lo;
-      s_wf[nb][threadIdx.x] = pw_f;
+    // ---- other buffer: clear stage m0 - kKT, set stage m0 + kKT.  Nobody
+    // reads it during this stage (its last readers passed the previous barrier).
+    if (st > 0) {
+      put_a(aP, other, true, 0, 0, 0.0f);
+      put_b(bP, other, true);
     }
-    __syncthreads();
-    // ---- clear stage m0, set stage m0 + kKT (the same thread owns a cell in both)
-    scatter_items<MODE>(oa, q, curA, kWeighted, true, nullptr, nullptr, nullptr, tA, tA2);
-    scatter_items<MODE>(ob, q, curB, false, true, nullptr, nullptr, nullptr, tB, tB);
-    if (has_next) {
-      scatter_items<MODE>(oa, q, nxtA, kWeighted, false, s_whi[nb], s_wlo[nb], s_wf[nb], tA, tA2);
-      scatter_items<MODE>(ob, q, nxtB, false, false, s_whi[nb], s_wlo[nb], s_wf[nb], tB, tB);
-#pragma unroll
-      for (int k = 0; k < kItems; ++k) {
-        curA[k] = nxtA[k];
-        curB[k] = nxtB[k];
-      }
+    if (has1) {
+      put_a(aN, other, false, hiN, loN, fN);
+      put_b(bN, other, false);
     }
     if constexpr (kWeighted) {
-      if (((stage + 1) % kFlushStages) == 0 || !has_next) {
+      if (((st + 1) % kFlushStages) == 0 || !has1) {
 #pragma unroll
-        for (int b = 0; b < kD; ++b)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            dacc[b][v] += (double)acc[b][v];
-            acc[b][v] = 0.0f;
-          }
+          for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              double add = (double)acc[rb][cb][v];
+              if (kLo) add += (double)lacc[rb][cb][v];
+              dacc[rb * 2 + cb][v] += add;
+              acc[rb][cb][v] = 0.0f;
+              if (kLo) lacc[rb][cb][v] = 0.0f;
+            }
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      aP[p] = aC[p];
+      bP[p] = bC[p];
+      aC[p] = aN[p];
+      bC[p] = bN[p];
+      aN[p] = aNN[p];
+      bN[p] = bNN[p];
+    }
+    hiN = hiNN;
+    loN = loNN;
+    fN = fNN;
   }
 
   // ---- write this split's plane.  Accumulator element v of lane l in a
   // 32x32 block holds row 8*(v/4) + 4*(l/32) + v%4, column l%32.
   double* __restrict__ Ps = P + (size_t)blockIdx.y * (size_t)Lq * Lq;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int bi = b / 2, bj = b % 2;
-    const int col = tj * kTile + 64 * wc + 32 * bj + lrow;
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = ti * kTile + 64 * wr + 32 * bi + 8 * (v / 4) + 4 * lhalf + (v % 4);
-      if (row < Lq && col < Lq) {
-        double val;
-        if constexpr (kWeighted)
-          val = dacc[b][v];
-        else
-          val = (double)acc[b][v];
-        Ps[(size_t)row * Lq + col] = val;
+    for (int cb = 0; cb < 2; ++cb) {
+      const int col = tj * kTile + 64 * wc + 32 * cb + lrow;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = ti * TR + 32 * RB * wr + 32 * rb + 8 * (v / 4) + 4 * lhalf + (v % 4);
+        if (row < Lq && col < Lq) {
+          double val;
+          if constexpr (kWeighted)
+            val = dacc[rb * 2 + cb][v];
+          else
+            val = (double)acc[rb][cb][v];
+          Ps[(size_t)row * Lq + col] = val;
+        }
       }
     }
-  }
+}
+
+template <int MODE>
+static void launch_products_mode(int q, int splits, hipStream_t s, const int8_t* XT, int64_t Mpad,
+                                 int L, const uint16_t* whi, const uint16_t* wlo, const float* wf,
+                                 int64_t kchunk, double* P) {
+  constexpr int NW = ProductShape<MODE>::kWaves;
+  const int np = passes_needed(q, NW);
+  const dim3 block(64 * NW);
+  const int ntile = (int)ceil_div(L * q, kTile);
+  const dim3 grid((unsigned)product_tiles(L * q, ProductShape<MODE>::kTR), (unsigned)splits);
+#define BMDCA_LAUNCH_NP(N)                                                                    \
+  hipLaunchKernelGGL((k_onehot_products<MODE, N>), grid, block, 0, s, XT, Mpad, L, q, whi, wlo, \
+                     wf, ntile, kchunk, P)
+  if (np <= 1)
+    BMDCA_LAUNCH_NP(1);
+  else if (np <= 2)
+    BMDCA_LAUNCH_NP(2);
+  else if (np <= 4)
+    BMDCA_LAUNCH_NP(4);
+  else if (np <= 9)
+    BMDCA_LAUNCH_NP(9);
+  else
+    BMDCA_LAUNCH_NP(17);  // q >= 2 needs at most 17 passes of 4 waves
+#undef BMDCA_LAUNCH_NP
 }
 
 hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
@@ -384,50 +481,69 @@ hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, i
                      dim3(256), 0, s, X, M, L, q, XT, plan.Mpad, dev_err);
   hipLaunchKernelGGL(k_prep_weights, dim3((unsigned)ceil_div(plan.Mpad, 256)), dim3(256), 0, s, w,
                      M, plan.Mpad, whi, wlo, wf);
-  dim3 grid((unsigned)plan.nupper, (unsigned)plan.splits);
   switch (mode_of(prec, w != nullptr)) {
     case MODE_UNIT_BF16:
-      hipLaunchKernelGGL(k_onehot_products<MODE_UNIT_BF16>, grid, dim3(256), 0, s, XT, plan.Mpad, L,
-                         q, whi, wlo, wf, plan.ntile, plan.kchunk, P);
+      launch_products_mode<MODE_UNIT_BF16>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
+                                           plan.kchunk, P);
       break;
     case MODE_HILO_BF16:
-      hipLaunchKernelGGL(k_onehot_products<MODE_HILO_BF16>, grid, dim3(256), 0, s, XT, plan.Mpad, L,
-                         q, whi, wlo, wf, plan.ntile, plan.kchunk, P);
+      launch_products_mode<MODE_HILO_BF16>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
+                                           plan.kchunk, P);
       break;
     default:
-      hipLaunchKernelGGL(k_onehot_products<MODE_F32>, grid, dim3(256), 0, s, XT, plan.Mpad, L, q,
-                         whi, wlo, wf, plan.ntile, plan.kchunk, P);
+      launch_products_mode<MODE_F32>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
+                                     plan.kchunk, P);
       break;
   }
   return hipGetLastError();
 }
 
-// Canonical (upper) position of (r1, r2): min/max always lies in a computed tile.
-__device__ __forceinline__ double sum_planes(const double* __restrict__ P, int S, size_t plane,
-                                             int Lq, int r1, int r2) {
-  const int a = min(r1, r2), b = max(r1, r2);
-  const size_t k = (size_t)a * Lq + b;
-  double v = 0.0;
-  for (int s = 0; s < S; ++s) v += P[(size_t)s * plane + k];
-  return v;
+// ---------------------------------------------------------------------------
+// Finish: the partial planes hold only tiles on or above the diagonal.  A
+// 64x64 output block (bi, bj) reads the stored block (min, max) coalesced,
+// summed over the splits in split order, and mirrors it through LDS.
+// ---------------------------------------------------------------------------
+constexpr int kFin = 64;
+
+__device__ __forceinline__ void load_sym_block(const double* __restrict__ P, int S, int Lq, int bi,
+                                               int bj, double (*sh)[kFin + 1]) {
+  const int r0 = min(bi, bj) * kFin, c0 = max(bi, bj) * kFin;
+  const size_t plane = (size_t)Lq * Lq;
+  for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
+    const int r = e / kFin, c = e % kFin;
+    double v = 0.0;
+    if (r0 + r < Lq && c0 + c < Lq) {
+      const size_t k = (size_t)(r0 + r) * Lq + c0 + c;
+      for (int sp = 0; sp < S; ++sp) v += P[(size_t)sp * plane + k];
+    }
+    sh[r][c] = v;
+  }
+  __syncthreads();
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ P, int S, int Lq,
-                                  double* __restrict__ C) {
-  const size_t plane = (size_t)Lq * Lq;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < plane;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
-    C[k] = sum_planes(P, S, plane, Lq, r1, r2);
+// Value of output (R1, R2) = stored (min, max), both inside block (bi, bj).
+__device__ __forceinline__ double sym_value(const double (*sh)[kFin + 1], int bi, int bj, int R1,
+                                            int R2) {
+  const int a = min(R1, R2), b = max(R1, R2);
+  return sh[a - min(bi, bj) * kFin][b - max(bi, bj) * kFin];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ P, int S,
+                                                         int Lq, double* __restrict__ C) {
+  __shared__ double sh[kFin][kFin + 1];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  load_sym_block(P, S, Lq, bi, bj, sh);
+  for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
+    const int R1 = bi * kFin + e / kFin, R2 = bj * kFin + e % kFin;
+    if (R1 < Lq && R2 < Lq) C[(size_t)R1 * Lq + R2] = sym_value(sh, bi, bj, R1, R2);
   }
 }
 
 hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq, double* C,
                                   hipStream_t s) {
   const double* P = reinterpret_cast<const double*>(static_cast<const char*>(ws) + plan.off_part);
-  const size_t plane = (size_t)Lq * Lq;
-  const unsigned nb = (unsigned)std::min<size_t>(ceil_div(plane, 256), 16384);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, P, plan.splits, Lq, C);
+  const unsigned nb = (unsigned)ceil_div(Lq, kFin);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nb, nb), dim3(256), 0, s, P, plan.splits, Lq, C);
   return hipGetLastError();
 }
 
@@ -451,21 +567,24 @@ hipError_t launch_meff(const double* w, int64_t M, double* meff, hipStream_t s) 
 // f1[r] = (1-alpha) * (C[r][r] / meff) + alpha / q
 // f2 = (1-alpha) * (C / meff) + alpha / q^2 off the diagonal blocks,
 //      delta_ab f1 on them.  Expression order follows the definitions.
-__global__ void k_stats_epilogue(const double* __restrict__ P, int S, int L, int q,
-                                 const double* __restrict__ meff_p, double pc,
-                                 double* __restrict__ f1, double* __restrict__ f2) {
+__global__ __launch_bounds__(256) void k_stats_epilogue(const double* __restrict__ P, int S, int L,
+                                                        int q, const double* __restrict__ meff_p,
+                                                        double pc, double* __restrict__ f1,
+                                                        double* __restrict__ f2) {
+  __shared__ double sh[kFin][kFin + 1];
   const int Lq = L * q;
-  const size_t plane = (size_t)Lq * Lq;
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  load_sym_block(P, S, Lq, bi, bj, sh);
   const double meff = *meff_p;
   const double alpha = pc < 0.0 ? 1.0 / meff : pc;
   const double qq = (double)q * (double)q;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < plane;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
+  for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
+    const int r1 = bi * kFin + e / kFin, r2 = bj * kFin + e % kFin;
+    if (r1 >= Lq || r2 >= Lq) continue;
     double out;
     if (r1 / q == r2 / q) {
       if (r1 == r2) {
-        const double f = sum_planes(P, S, plane, Lq, r1, r1) / meff;
+        const double f = sym_value(sh, bi, bj, r1, r1) / meff;
         const double t1 = (1.0 - alpha) * f;
         const double t2 = alpha / (double)q;
         out = t1 + t2;
@@ -474,12 +593,12 @@ __global__ void k_stats_epilogue(const double* __restrict__ P, int S, int L, int
         out = 0.0;
       }
     } else {
-      const double f = sum_planes(P, S, plane, Lq, r1, r2) / meff;
+      const double f = sym_value(sh, bi, bj, r1, r2) / meff;
       const double t1 = (1.0 - alpha) * f;
       const double t2 = alpha / qq;
       out = t1 + t2;
     }
-    f2[k] = out;
+    f2[(size_t)r1 * Lq + r2] = out;
   }
 }
 
@@ -487,9 +606,8 @@ hipError_t launch_stats_epilogue(const StatsPlan& plan, const void* ws, int L, i
                                  const double* meff, double pseudocount, double* f1, double* f2,
                                  hipStream_t s) {
   const double* P = reinterpret_cast<const double*>(static_cast<const char*>(ws) + plan.off_part);
-  const size_t plane = (size_t)L * q * (size_t)L * q;
-  const unsigned nb = (unsigned)std::min<size_t>(ceil_div(plane, 256), 16384);
-  hipLaunchKernelGGL(k_stats_epilogue, dim3(nb), dim3(256), 0, s, P, plan.splits, L, q, meff,
+  const unsigned nb = (unsigned)ceil_div(L * q, kFin);
+  hipLaunchKernelGGL(k_stats_epilogue, dim3(nb, nb), dim3(256), 0, s, P, plan.splits, L, q, meff,
                      pseudocount, f1, f2);
   return hipGetLastError();
 }

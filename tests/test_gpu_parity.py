@@ -186,9 +186,9 @@ def test_stats_unit_weights_bitexact(prec, L, q, M):
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp32", 1e-6)])
-def test_stats_weighted(prec, tol):
-    L, q, M = 20, 21, 1500
-    X = synth.clustered_msa(M, L, q, seed=90)
+@pytest.mark.parametrize("L,q,M", [(20, 21, 1500), (37, 5, 700), (9, 2, 500), (13, 3, 400)])
+def test_stats_weighted(L, q, M, prec, tol):
+    X = synth.clustered_msa(M, L, q, seed=90 + q)
     w = synth.weights_open_unit(M, 91)
     f1g, f2g, mg = api.stats(dev(X), q, dev(w), -1.0, prec)
     f1o, f2o, mo = O.stats(X, q, w, -1.0)
