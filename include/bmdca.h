@@ -21,8 +21,10 @@
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     call only enqueues work on it and returns; results are ready once the
  *     stream has been synchronised.
- *   - The library keeps no hidden state between calls.  Calls on different
- *     streams do not share memory unless the caller passes the same buffers.
+ *   - The library keeps no hidden state between calls, apart from the lane
+ *     streams of the group calls (created once per device) and graph
+ *     handles the caller owns.  Calls on different streams do not share
+ *     memory unless the caller passes the same buffers.
  *
  * Errors:
  *   - Host-side validation (null pointers, sizes, q outside 2..32, theta
@@ -215,6 +217,79 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L,
                      int32_t prec, double* pearson,
                      unsigned long long* flips_out, void* ws, size_t ws_bytes,
                      int32_t* dev_err, void* stream);
+
+/* ---- Grouped training (many independent models, one replayable epoch) ----
+ *
+ * The training loop of Sec. 2.1 run for several independent models at once.
+ * The arithmetic of each model is exactly that of bmdca_train_step; what
+ * changes is where the epoch number and the stop condition live: in a small
+ * device record per model, so that one captured HIP graph can be replayed
+ * every epoch with unchanged kernel arguments. */
+
+/* Device-resident control record of one model (24 bytes, caller-owned,
+ * device memory; the caller writes it before the first epoch). */
+typedef struct bmdca_train_ctl {
+    uint64_t epoch;        /* epochs run so far; the next epoch samples sweeps
+                              epoch*sweeps .. epoch*sweeps + sweeps - 1 */
+    int32_t active;        /* 0: every kernel of this model returns at once
+                              (its h, J, chains and counters stay as they are) */
+    int32_t converged_at;  /* set to `epoch` when the target was reached */
+    double target_pearson; /* > 0: after an epoch whose Pearson coefficient
+                              (Eq. 6) is >= this value, active becomes 0 -- the
+                              stop criterion of Sec. 2.1 */
+} bmdca_train_ctl;
+
+/* One model of a group: the arguments of bmdca_train_step, with the epoch
+ * taken from ctl->epoch.  All pointers are device pointers except the record
+ * array itself, which is host memory read during the call. */
+typedef struct bmdca_train_problem {
+    float* h;
+    float* J;
+    int8_t* chains;
+    const double* f1;
+    const double* f2;
+    double* pearson;
+    unsigned long long* flips_out; /* optional */
+    int32_t* dev_err;              /* optional */
+    bmdca_train_ctl* ctl;          /* required */
+    void* ws;                      /* bmdca_workspace_bytes(BMDCA_WS_TRAIN_STEP, ...) */
+    size_t ws_bytes;
+    int64_t N;
+    int32_t L;
+    int32_t q;
+    double lr;
+    uint64_t seed;
+    int32_t sweeps;
+    int32_t prec; /* bmdca_prec | BMDCA_SAMPLER_* */
+} bmdca_train_problem;
+
+/* Enqueues one epoch of every model of the group on `stream`: the models are
+ * spread over `lanes` (1..16) streams forked from `stream` and joined back
+ * into it (largest models first, each to the least-loaded lane), so small
+ * models run side by side.  Each model runs bmdca_train_step with its epoch
+ * read from ctl->epoch, then advances its record: if active, epoch += 1 and
+ * the target test above.  Every model's results are the same as its own
+ * bmdca_train_step calls with the same epochs (bit for bit).
+ * The call may be captured into a HIP graph (it allocates no device memory
+ * and enqueues no memset); bmdca_train_group_graph does exactly that.  The
+ * lane streams are created once per device (default priority) and kept;
+ * group calls are serialised by a library lock. */
+int bmdca_train_group_step(const bmdca_train_problem* probs, int32_t n,
+                           int32_t lanes, void* stream);
+
+/* A captured, instantiated group epoch (opaque, owned by the caller). */
+typedef struct bmdca_graph_s* bmdca_graph;
+
+/* Captures bmdca_train_group_step(probs, n, lanes, stream) into a graph and
+ * instantiates it; nothing runs.  The problem records are frozen into the
+ * graph: the buffers they name must stay allocated while the graph lives.
+ * *out receives the handle; on error *out is NULL. */
+int bmdca_train_group_graph(const bmdca_train_problem* probs, int32_t n,
+                            int32_t lanes, void* stream, bmdca_graph* out);
+/* Enqueues one replay (one epoch of every active model) on `stream`. */
+int bmdca_graph_launch(bmdca_graph g, void* stream);
+/* Frees the graph (NULL is accepted). */
+int bmdca_graph_destroy(bmdca_graph g);
 
 /* Single-mutant library (Sec. 4.4): for each of B wild types,
  * dE[b][i*q + a] = E(wild type with site i set to a) - E(wild type)

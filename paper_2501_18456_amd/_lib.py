@@ -22,6 +22,23 @@ WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY = r
 _p, _i32, _i64, _u64, _f64, _f32, _sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,
                                           C.c_double, C.c_float, C.c_size_t)
 
+
+class TrainProblem(C.Structure):
+    """bmdca_train_problem (include/bmdca.h), field for field."""
+    _fields_ = [
+        ("h", _p), ("J", _p), ("chains", _p), ("f1", _p), ("f2", _p), ("pearson", _p),
+        ("flips_out", _p), ("dev_err", _p), ("ctl", _p), ("ws", _p), ("ws_bytes", _sz),
+        ("N", _i64), ("L", _i32), ("q", _i32), ("lr", _f64), ("seed", _u64),
+        ("sweeps", _i32), ("prec", _i32),
+    ]
+
+
+class TrainCtl(C.Structure):
+    """bmdca_train_ctl (include/bmdca.h): the device record's byte layout."""
+    _fields_ = [("epoch", _u64), ("active", _i32), ("converged_at", _i32),
+                ("target_pearson", _f64)]
+
+
 SIGNATURES = {
     "bmdca_workspace_bytes": (_sz, [_i32, _i64, _i32, _i32, _i32]),
     "bmdca_last_error": (C.c_char_p, []),
@@ -37,7 +54,13 @@ SIGNATURES = {
                                    _i32, _p, _p, _p, _sz, _p, _p]),
     "bmdca_single_mutant_scan": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p]),
     "bmdca_apc_frobenius": (C.c_int, [_p, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "bmdca_train_group_step": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p]),
+    "bmdca_train_group_graph": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p,
+                                          C.POINTER(_p)]),
+    "bmdca_graph_launch": (C.c_int, [_p, _p]),
+    "bmdca_graph_destroy": (C.c_int, [_p]),
 }
+
 
 _lib = None
 

@@ -174,6 +174,88 @@ def train_step(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: i
     return pearson
 
 
+# ------------------------------------------------------------ grouped training
+def train_ctl(device, target_pearson: float = 0.0, epoch: int = 0, active: bool = True):
+    """A device control record (bmdca_train_ctl) as a uint8 tensor of its 24 bytes."""
+    rec = B.TrainCtl(epoch, 1 if active else 0, -1, float(target_pearson))
+    host = torch.frombuffer(bytearray(bytes(rec)), dtype=torch.uint8)
+    return host.to(device)
+
+
+def read_ctl(ctl) -> dict:
+    """The fields of a device control record (synchronises on the copy)."""
+    rec = B.TrainCtl.from_buffer_copy(bytes(ctl.cpu().numpy().tobytes()))
+    return {"epoch": rec.epoch, "active": bool(rec.active), "converged_at": rec.converged_at,
+            "target_pearson": rec.target_pearson}
+
+
+class TrainModel:
+    """One model of a training group: its tensors and epoch arguments, the
+    bmdca_train_problem record that names them, and its control record."""
+
+    def __init__(self, h, J, chains, f1, f2, lr: float, sweeps: int, seed: int,
+                 prec="bf16x2", sampler="auto", target_pearson: float = 0.0, ws=None,
+                 flips=None, dev_err=None):
+        L, q = _model(h, J)
+        _dev(chains, torch.int8, "chains", 2)
+        _dev(f1, torch.float64, "f1")
+        _dev(f2, torch.float64, "f2")
+        self.h, self.J, self.chains, self.f1, self.f2 = h, J, chains, f1, f2
+        self.L, self.q, self.N = L, q, chains.shape[0]
+        self.prec = _prec(prec) | _sampler(sampler)
+        dev = chains.device
+        self.ws = ws if ws is not None else workspace(B.WS_TRAIN_STEP, self.N, L, q, self.prec, dev)
+        self.pearson = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.flips, self.dev_err = flips, dev_err
+        self.ctl = train_ctl(dev, target_pearson)
+        self.record = B.TrainProblem(
+            _ptr(h), _ptr(J), _ptr(chains), _ptr(f1), _ptr(f2), _ptr(self.pearson), _ptr(flips),
+            _ptr(dev_err), _ptr(self.ctl), _ptr(self.ws), _nbytes(self.ws), self.N, L, q,
+            float(lr), int(seed), int(sweeps), self.prec)
+
+
+def _records(models):
+    arr = (B.TrainProblem * len(models))()
+    for k, m in enumerate(models):
+        arr[k] = m.record
+    return arr
+
+
+def train_group_step(models, lanes: int = 8):
+    """One epoch of every active model (bmdca_train_group_step)."""
+    arr = _records(models)
+    check(B.lib().bmdca_train_group_step(arr, len(models), lanes, _stream()))
+
+
+class TrainGroupGraph:
+    """A captured group epoch (bmdca_train_group_graph); launch() replays it.
+    Capture runs on a side stream; the models must stay alive with it."""
+
+    def __init__(self, models, lanes: int = 8):
+        self.models = list(models)
+        self._stream = torch.cuda.Stream()
+        self._stream.wait_stream(torch.cuda.current_stream())
+        handle = B._p()
+        arr = _records(self.models)
+        check(B.lib().bmdca_train_group_graph(arr, len(self.models), lanes,
+                                              self._stream.cuda_stream, B.C.byref(handle)))
+        self.handle = handle
+
+    def launch(self):
+        check(B.lib().bmdca_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if self.handle:
+            check(B.lib().bmdca_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def single_mutant_scan(h, J, wt, ws=None, out=None):
     """Sec. 4.4: dE float32 [B, L*q] for wild types wt int8 [B, L]."""
     L, q = _model(h, J)

@@ -1,9 +1,14 @@
 // C-ABI entry points of libbmdca (declared in include/bmdca.h): host-side
 // validation, workspace carve-up, and the kernel sequence of each call.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
+#include <mutex>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/bmdca.h"
 #include "common.hpp"
@@ -91,7 +96,167 @@ TrainPlan plan_train(int64_t N, int L, int q, int prec) {
   return t;
 }
 
+// Host-side validation shared by the single and grouped training calls.
+int check_train(const bmdca_train_problem& p) {
+  BMDCA_TRY(check_model(p.L, p.q));
+  BMDCA_REQUIRE(p.h && p.J && p.chains && p.f1 && p.f2 && p.pearson && p.ws,
+                "null pointer argument");
+  BMDCA_REQUIRE(p.N >= 1 && p.N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)p.N);
+  BMDCA_REQUIRE(p.L >= 2, "train_step needs L >= 2 (got %d)", p.L);
+  BMDCA_REQUIRE(p.sweeps >= 0, "sweeps=%d negative", p.sweeps);
+  const int pr = p.prec & kPrecMask;
+  BMDCA_REQUIRE(pr == BMDCA_PREC_FP32 || pr == BMDCA_PREC_BF16X2, "prec=%d unknown", pr);
+  BMDCA_REQUIRE((p.prec & ~(kPrecMask | kSamplerMask)) == 0, "prec flags 0x%x unknown", p.prec);
+  BMDCA_REQUIRE(pick_gather(p.prec, p.L, p.q) >= 0, "sampler flags 0x%x not usable for L=%d q=%d",
+                p.prec, p.L, p.q);
+  if (!std::isfinite(p.lr)) return fail(BMDCA_ENONFINITE, "lr is not finite");
+  const TrainPlan plan = plan_train(p.N, p.L, p.q, p.prec);
+  if (p.ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "train_step workspace %zu < %zu bytes", p.ws_bytes, plan.total);
+  return BMDCA_OK;
+}
+
+// The kernel sequence of one epoch (arguments already validated).  `epoch`
+// is used when ctl.epoch is null.
+int enqueue_train(const bmdca_train_problem& p, uint64_t epoch, const DevCtl& ctl,
+                  hipStream_t s) {
+  const int N = (int)p.N, L = p.L, q = p.q;
+  const int pr = p.prec & kPrecMask;
+  const int gather = pick_gather(p.prec, L, q);
+  const TrainPlan plan = plan_train(p.N, L, q, p.prec);
+  char* base = static_cast<char*>(p.ws);
+  float* H = reinterpret_cast<float*>(base + plan.off_H);
+  void* sws = base + plan.off_stats;
+  double* C = reinterpret_cast<double*>(base + plan.off_C);
+  double* red = reinterpret_cast<double*>(base + plan.off_red);
+  const int Lq = L * q;
+  const uint64_t sweep0 = ctl.epoch ? 0 : epoch * (uint64_t)p.sweeps;
+  if (gather) {
+    BMDCA_TRY(hip_status(launch_gibbs_gather(p.h, p.J, p.chains, N, L, q, p.sweeps, p.seed, sweep0,
+                                             1.0f, p.flips_out, p.dev_err, H, s, ctl),
+                         "train_step/gather"));
+  } else {
+    BMDCA_TRY(hip_status(launch_local_fields(p.h, p.J, p.chains, N, L, q, H, p.dev_err, s,
+                                             ctl.active),
+                         "train_step/fields"));
+    if (p.sweeps > 0)
+      BMDCA_TRY(hip_status(launch_gibbs_sweeps(p.J, p.chains, H, N, L, q, p.sweeps, p.seed, sweep0,
+                                               1.0f, p.flips_out, s, ctl),
+                           "train_step/sweeps"));
+  }
+  BMDCA_TRY(hip_status(launch_onehot_products(p.chains, nullptr, N, L, q, pr, plan.sp, sws,
+                                              p.dev_err, s, ctl.active),
+                       "train_step/counts"));
+  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));
+  BMDCA_TRY(hip_status(launch_pearson(p.f1, p.f2, C, N, L, q, red, p.pearson, p.dev_err, s),
+                       "train_step/pearson"));
+  return hip_status(launch_update(p.h, p.J, p.f1, p.f2, C, N, L, q, p.lr, p.dev_err, s,
+                                  ctl.active),
+                    "train_step/update");
+}
+
+// ----- grouped epochs: lane streams forked from and joined into the caller's
+constexpr int kMaxLanes = 16;
+
+struct LanePool {
+  int device = -1;
+  hipStream_t lanes[kMaxLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxLanes] = {};
+  int created = 0;
+};
+
+std::mutex g_group_mu;
+LanePool g_pools[64];  // per device ordinal
+
+LanePool* pool_for_current() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  LanePool* lp = &g_pools[dev];
+  lp->device = dev;
+  return lp;
+}
+
+hipError_t ensure_lanes_locked(int lanes) {
+  LanePool* lp = pool_for_current();
+  if (!lp) return hipErrorInvalidDevice;
+  if (!lp->fork) {
+    hipError_t e = hipEventCreateWithFlags(&lp->fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  while (lp->created < lanes) {
+    const int k = lp->created;
+    hipError_t e = hipStreamCreateWithFlags(&lp->lanes[k], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&lp->join[k], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    ++lp->created;
+  }
+  return hipSuccess;
+}
+
+hipError_t ensure_lanes(int lanes) {
+  std::lock_guard<std::mutex> lock(g_group_mu);
+  return ensure_lanes_locked(lanes);
+}
+
+// Relative cost of one model's epoch: site visits times the local-field
+// work per visit, plus the count product.
+double model_cost(const bmdca_train_problem& p) {
+  const double Lq = (double)p.L * p.q;
+  return (double)p.N * p.L * (p.sweeps > 0 ? p.sweeps : 1) * Lq + (double)p.N * Lq * Lq / 64.0;
+}
+
+int enqueue_group(const bmdca_train_problem* probs, int n, int lanes, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_group_mu);
+  BMDCA_TRY(hip_status(ensure_lanes_locked(lanes), "group lanes"));
+  LanePool* lp = pool_for_current();
+  // Largest first, each to the least-loaded lane (ties: lowest lane).
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return model_cost(probs[a]) > model_cost(probs[b]);
+  });
+  std::vector<double> load(lanes, 0.0);
+  std::vector<int> lane_of(n, 0);
+  for (int k : order) {
+    int best = 0;
+    for (int l = 1; l < lanes; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_of[k] = best;
+    load[best] += model_cost(probs[k]);
+  }
+  // CU share of each model's sampler grid: the lane's share of the chip.
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int share = std::max(1, cus / lanes);
+  BMDCA_TRY(hip_status(hipEventRecord(lp->fork, s), "group fork"));
+  for (int l = 0; l < lanes; ++l)
+    BMDCA_TRY(hip_status(hipStreamWaitEvent(lp->lanes[l], lp->fork, 0), "group fork"));
+  for (int k : order) {
+    const bmdca_train_problem& p = probs[k];
+    hipStream_t ls = lp->lanes[lane_of[k]];
+    DevCtl ctl;
+    auto* rec = reinterpret_cast<char*>(p.ctl);
+    ctl.epoch = reinterpret_cast<const uint64_t*>(rec + offsetof(bmdca_train_ctl, epoch));
+    ctl.active = reinterpret_cast<const int32_t*>(rec + offsetof(bmdca_train_ctl, active));
+    ctl.cu_share = lanes > 1 ? share : 0;
+    BMDCA_TRY(enqueue_train(p, 0, ctl, ls));
+    BMDCA_TRY(hip_status(launch_ctl_advance(p.ctl, p.pearson, ls), "group ctl"));
+  }
+  for (int l = 0; l < lanes; ++l) {
+    BMDCA_TRY(hip_status(hipEventRecord(lp->join[l], lp->lanes[l]), "group join"));
+    BMDCA_TRY(hip_status(hipStreamWaitEvent(s, lp->join[l], 0), "group join"));
+  }
+  return BMDCA_OK;
+}
+
 }  // namespace
+
+struct bmdca_graph_s {
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -221,47 +386,88 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, i
                      const double* f1, const double* f2, double lr, int32_t sweeps, uint64_t seed,
                      uint64_t epoch, int32_t prec, double* pearson, unsigned long long* flips_out,
                      void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
-  BMDCA_TRY(check_model(L, q));
-  BMDCA_REQUIRE(h && J && chains && f1 && f2 && pearson && ws, "null pointer argument");
-  BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)N);
-  BMDCA_REQUIRE(L >= 2, "train_step needs L >= 2 (got %d)", L);
-  BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
-  const int pr = prec & kPrecMask;
-  BMDCA_REQUIRE(pr == BMDCA_PREC_FP32 || pr == BMDCA_PREC_BF16X2, "prec=%d unknown", pr);
-  BMDCA_REQUIRE((prec & ~(kPrecMask | kSamplerMask)) == 0, "prec flags 0x%x unknown", prec);
-  const int gather = pick_gather(prec, L, q);
-  BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", prec, L, q);
-  if (!std::isfinite(lr)) return fail(BMDCA_ENONFINITE, "lr is not finite");
-  const TrainPlan plan = plan_train(N, L, q, prec);
-  if (ws_bytes < plan.total)
-    return fail(BMDCA_EWORKSPACE, "train_step workspace %zu < %zu bytes", ws_bytes, plan.total);
-  hipStream_t s = (hipStream_t)stream;
-  char* base = static_cast<char*>(ws);
-  float* H = reinterpret_cast<float*>(base + plan.off_H);
-  void* sws = base + plan.off_stats;
-  double* C = reinterpret_cast<double*>(base + plan.off_C);
-  double* red = reinterpret_cast<double*>(base + plan.off_red);
-  const int Lq = L * q;
-  if (gather) {
-    BMDCA_TRY(hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed,
-                                             epoch * (uint64_t)sweeps, 1.0f, flips_out, dev_err,
-                                             H, s),
-                         "train_step/gather"));
-  } else {
-    BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H, dev_err, s),
-                         "train_step/fields"));
-    if (sweeps > 0)
-      BMDCA_TRY(hip_status(launch_gibbs_sweeps(J, chains, H, N, L, q, sweeps, seed,
-                                               epoch * (uint64_t)sweeps, 1.0f, flips_out, s),
-                           "train_step/sweeps"));
+  bmdca_train_problem p{};
+  p.h = h;
+  p.J = J;
+  p.chains = chains;
+  p.f1 = f1;
+  p.f2 = f2;
+  p.pearson = pearson;
+  p.flips_out = flips_out;
+  p.dev_err = dev_err;
+  p.ws = ws;
+  p.ws_bytes = ws_bytes;
+  p.N = N;
+  p.L = L;
+  p.q = q;
+  p.lr = lr;
+  p.seed = seed;
+  p.sweeps = sweeps;
+  p.prec = prec;
+  BMDCA_TRY(check_train(p));
+  return enqueue_train(p, epoch, DevCtl(), (hipStream_t)stream);
+}
+
+int bmdca_train_group_step(const bmdca_train_problem* probs, int32_t n, int32_t lanes,
+                           void* stream) {
+  BMDCA_REQUIRE(probs && n >= 1, "group needs at least one problem");
+  BMDCA_REQUIRE(lanes >= 1 && lanes <= kMaxLanes, "lanes=%d outside 1..%d", lanes, kMaxLanes);
+  for (int32_t k = 0; k < n; ++k) {
+    const int rc = check_train(probs[k]);
+    if (rc != BMDCA_OK) return fail(rc, "problem %d: %s", k, g_err.c_str());
+    if (!probs[k].ctl) return fail(BMDCA_EINVAL, "problem %d: ctl is required", k);
   }
-  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, pr, plan.sp, sws,
-                                              dev_err, s),
-                       "train_step/counts"));
-  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));
-  BMDCA_TRY(hip_status(launch_pearson(f1, f2, C, N, L, q, red, pearson, dev_err, s),
-                       "train_step/pearson"));
-  return hip_status(launch_update(h, J, f1, f2, C, N, L, q, lr, dev_err, s), "train_step/update");
+  return enqueue_group(probs, n, lanes, (hipStream_t)stream);
+}
+
+int bmdca_train_group_graph(const bmdca_train_problem* probs, int32_t n, int32_t lanes,
+                            void* stream, bmdca_graph* out) {
+  BMDCA_REQUIRE(out, "null pointer argument");
+  *out = nullptr;
+  BMDCA_REQUIRE(probs && n >= 1, "group needs at least one problem");
+  BMDCA_REQUIRE(lanes >= 1 && lanes <= kMaxLanes, "lanes=%d outside 1..%d", lanes, kMaxLanes);
+  for (int32_t k = 0; k < n; ++k) {
+    const int rc = check_train(probs[k]);
+    if (rc != BMDCA_OK) return fail(rc, "problem %d: %s", k, g_err.c_str());
+    if (!probs[k].ctl) return fail(BMDCA_EINVAL, "problem %d: ctl is required", k);
+  }
+  BMDCA_REQUIRE(stream, "graph capture needs a created stream (not NULL)");
+  hipStream_t s = (hipStream_t)stream;
+  // Lanes are created before capture begins.
+  BMDCA_TRY(hip_status(ensure_lanes(lanes), "group lanes"));
+  BMDCA_TRY(hip_status(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture"));
+  const int rc = enqueue_group(probs, n, lanes, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &graph);
+  if (rc != BMDCA_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  BMDCA_TRY(hip_status(ec, "end capture"));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  BMDCA_TRY(hip_status(ei, "graph instantiate"));
+  auto* g = new (std::nothrow) bmdca_graph_s;
+  if (!g) {
+    hipGraphExecDestroy(exec);
+    return fail(BMDCA_EINVAL, "out of host memory");
+  }
+  g->exec = exec;
+  *out = g;
+  return BMDCA_OK;
+}
+
+int bmdca_graph_launch(bmdca_graph g, void* stream) {
+  BMDCA_REQUIRE(g && g->exec, "null graph");
+  return hip_status(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+}
+
+int bmdca_graph_destroy(bmdca_graph g) {
+  if (!g) return BMDCA_OK;
+  const hipError_t e = g->exec ? hipGraphExecDestroy(g->exec) : hipSuccess;
+  delete g;
+  return hip_status(e, "graph destroy");
 }
 
 int bmdca_single_mutant_scan(const float* h, const float* J, const int8_t* wt, int64_t B,

@@ -8,15 +8,25 @@
 
 namespace bmdca {
 
+// Device-side control of one model inside a graph-replayed group epoch.  All
+// fields are optional: with the defaults a launch behaves as a plain call.
+struct DevCtl {
+  const uint64_t* epoch = nullptr;  // sampler sweep offset += *epoch * sweeps
+  const int32_t* active = nullptr;  // *active == 0: the kernel returns at once
+  int cu_share = 0;                 // CUs the sampler grid is sized for (0: all)
+};
+
 // ----- sampler.hip
 hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t seed,
                               hipStream_t s);
 // H[c][r] = h[r] + sum_{k != r/q} J[(k, chains[c][k])][r] for c < N.
 hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
-                               int L, int q, float* H, int32_t* dev_err, hipStream_t s);
+                               int L, int q, float* H, int32_t* dev_err, hipStream_t s,
+                               const int32_t* active = nullptr);
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
-                               unsigned long long* flips_out, hipStream_t s);
+                               unsigned long long* flips_out, hipStream_t s,
+                               const DevCtl& ctl = DevCtl());
 // Gather form (local fields recomputed per visit from LDS-staged coupling
 // blocks); needs no field workspace.
 bool gather_supported(int L, int q);
@@ -24,7 +34,7 @@ size_t gather_ws_bytes(int L, int q);  // re-laid-out coupling blocks
 hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, int64_t N, int L,
                                int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, int32_t* dev_err, void* ws,
-                               hipStream_t s);
+                               hipStream_t s, const DevCtl& ctl = DevCtl());
 
 // ----- stats.hip
 // Workspace carve-up of the one-hot statistics product for M rows.
@@ -42,7 +52,7 @@ StatsPlan plan_stats(int64_t M, int L, int q, int prec);
 // sum_m w_m [x_mi == a][x_mj == b].  w == nullptr: unit weights.
 hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
                                   int prec, const StatsPlan& plan, void* ws, int32_t* dev_err,
-                                  hipStream_t s);
+                                  hipStream_t s, const int32_t* active = nullptr);
 // Sum of the partial planes into the full symmetric matrix C (FP64).
 hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq, double* C,
                                   hipStream_t s);
@@ -60,7 +70,11 @@ size_t pearson_red_bytes();
 hipError_t launch_pearson(const double* f1, const double* f2, const double* C, int64_t N, int L,
                           int q, double* red, double* out, int32_t* dev_err, hipStream_t s);
 hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
-                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s);
+                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s,
+                         const int32_t* active = nullptr);
+// Group epoch epilogue of one model: if active, epoch += 1 and, with a
+// positive target, active = 0 once the Pearson coefficient reaches it.
+hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s);
 
 // ----- reweight.hip
 struct ReweightPlan {

@@ -96,7 +96,8 @@ hipError_t launch_pearson(const double* f1, const double* f2, const double* C, i
 __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
                          const double* __restrict__ f1, const double* __restrict__ f2,
                          const double* __restrict__ C, int64_t N, int L, int q, double lr,
-                         int32_t* dev_err) {
+                         int32_t* dev_err, const int32_t* __restrict__ active) {
+  if (active && *active == 0) return;
   const int Lq = L * q;
   const size_t total = (size_t)Lq * Lq;
   const double dn = (double)N;
@@ -126,10 +127,37 @@ __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
 }
 
 hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
-                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s) {
+                         int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s,
+                         const int32_t* active) {
   const size_t total = (size_t)L * q * (size_t)L * q;
   const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 16384);
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, s, h, J, f1, f2, C, N, L, q, lr, dev_err);
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, s, h, J, f1, f2, C, N, L, q, lr, dev_err,
+                     active);
+  return hipGetLastError();
+}
+
+// Layout of the public bmdca_train_ctl record (bmdca.h): epoch u64 at 0,
+// active i32 at 8, converged_at i32 at 12, target f64 at 16.
+struct CtlRecord {
+  uint64_t epoch;
+  int32_t active;
+  int32_t converged_at;
+  double target;
+};
+static_assert(sizeof(CtlRecord) == 24, "control record layout");
+
+__global__ void k_ctl_advance(CtlRecord* __restrict__ ctl, const double* __restrict__ pearson) {
+  if (threadIdx.x != 0 || ctl->active == 0) return;
+  ctl->epoch += 1;
+  const double r = *pearson;
+  if (ctl->target > 0.0 && r >= ctl->target) {
+    ctl->active = 0;
+    ctl->converged_at = (int32_t)ctl->epoch;
+  }
+}
+
+hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_advance, dim3(1), dim3(64), 0, s, static_cast<CtlRecord*>(ctl), pearson);
   return hipGetLastError();
 }
 

@@ -44,7 +44,9 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
                                                       const float* __restrict__ J,
                                                       const int8_t* __restrict__ chains, int64_t N,
                                                       int L, int q, float* __restrict__ H,
-                                                      int32_t* dev_err) {
+                                                      int32_t* dev_err,
+                                                      const int32_t* __restrict__ active) {
+  if (active && *active == 0) return;
   extern __shared__ int rowbase[];  // L entries: (k*q + s_k)
   const int64_t c = blockIdx.x;
   const int Lq = L * q;
@@ -65,12 +67,13 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
 }
 
 hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
-                               int L, int q, float* H, int32_t* dev_err, hipStream_t s) {
+                               int L, int q, float* H, int32_t* dev_err, hipStream_t s,
+                               const int32_t* active) {
   const int Lq = L * q;
   const int bs = 256;
   dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, bs));
   hipLaunchKernelGGL(k_local_fields, grid, dim3(bs), sizeof(int) * L, s, h, J, chains, N, L, q, H,
-                     dev_err);
+                     dev_err, active);
   return hipGetLastError();
 }
 
@@ -94,7 +97,11 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
                                                         int q, int sweeps, uint32_t k0,
                                                         uint32_t k1, uint64_t sweep_offset,
                                                         float beta,
-                                                        unsigned long long* flips_out) {
+                                                        unsigned long long* flips_out,
+                                                        const uint64_t* __restrict__ epoch,
+                                                        const int32_t* __restrict__ active) {
+  if (active && *active == 0) return;
+  if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   extern __shared__ int8_t tok_all[];
   const int lane = threadIdx.x % kWave;
   const int wid = threadIdx.x / kWave;
@@ -153,12 +160,12 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
 
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
-                               unsigned long long* flips_out, hipStream_t s) {
+                               unsigned long long* flips_out, hipStream_t s, const DevCtl& ctl) {
   constexpr int WPB = 4;
   const int Lpad = (L + 3) & ~3;
   hipLaunchKernelGGL(k_gibbs_hbm<WPB>, dim3((unsigned)ceil_div(N, WPB)), dim3(WPB * kWave),
                      WPB * Lpad, s, J, chains, H, N, L, q, sweeps, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out);
+                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, ctl.epoch, ctl.active);
   return hipGetLastError();
 }
 
@@ -243,7 +250,9 @@ size_t gather_ws_bytes(int L, int q) {
 }
 
 // Jt[i][j][b][a'] = J[(j*q + b)][(i*q + a')] for a' < q, else 0.
-__global__ void k_gather_layout(const float* __restrict__ J, int L, int q, float* __restrict__ Jt) {
+__global__ void k_gather_layout(const float* __restrict__ J, int L, int q, float* __restrict__ Jt,
+                                const int32_t* __restrict__ active) {
+  if (active && *active == 0) return;
   const int QP = gather_qp(q);
   const size_t total = (size_t)L * L * q * QP;
   const size_t Lq = (size_t)L * q;
@@ -264,7 +273,10 @@ template <int Q>
 __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
     int64_t N, int L, int ahead, int slot, int cpb, int sweeps, uint32_t k0, uint32_t k1,
-    uint64_t sweep_offset, float beta, unsigned long long* flips_out, int32_t* dev_err) {
+    uint64_t sweep_offset, float beta, unsigned long long* flips_out, int32_t* dev_err,
+    const uint64_t* __restrict__ epoch, const int32_t* __restrict__ run) {
+  if (run && *run == 0) return;  // whole grid leaves before any barrier
+  if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   constexpr int G = kGG, W = kGWv, R = kGR, JC = kGJC;
   constexpr int kT = W * 64, kCPW = 64 / G, kCPB = kCPW * W;
   constexpr int QP = gather_qp(Q), kQ4 = QP / 4;
@@ -451,13 +463,13 @@ template <int Q>
 static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chains, int64_t N,
                                   int L, int sweeps, uint64_t seed, uint64_t sweep_offset,
                                   float beta, unsigned long long* flips_out, int32_t* dev_err,
-                                  hipStream_t s) {
+                                  hipStream_t s, const DevCtl& ctl) {
   const GatherShape gs = gather_shape(L, Q);
   if (gs.ahead == 0) return hipErrorInvalidValue;
   constexpr int kCPB = (64 / kGG) * kGWv;
   // chains per workgroup: spread the chains over all CUs in as few rounds as
   // the workgroup size allows (one workgroup per CU at a time)
-  const int64_t cus = device_cus();
+  const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
   const int64_t rounds = ceil_div(N, cus * kCPB);
   const int cpb = (int)std::min<int64_t>(kCPB, ceil_div(N, rounds * cus));
   const unsigned nb = (unsigned)ceil_div(N, cpb);
@@ -467,24 +479,25 @@ static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chain
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kGWv * 64), gs.lds, s, h, Jt, chains, N, L, gs.ahead,
                      gs.slot, cpb, sweeps, (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset,
-                     beta, flips_out, dev_err);
+                     beta, flips_out, dev_err, ctl.epoch, ctl.active);
   return hipGetLastError();
 }
 
 hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, int64_t N, int L,
                                int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, int32_t* dev_err, void* ws,
-                               hipStream_t s) {
+                               hipStream_t s, const DevCtl& ctl) {
   float* Jt = static_cast<float*>(ws);
   {
     const size_t total = (size_t)L * L * q * gather_qp(q);
     const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 65536);
-    hipLaunchKernelGGL(k_gather_layout, dim3(nb), dim3(256), 0, s, J, L, q, Jt);
+    hipLaunchKernelGGL(k_gather_layout, dim3(nb), dim3(256), 0, s, J, L, q, Jt, ctl.active);
   }
   switch (q) {
 #define BMDCA_GQ(n) \
   case n:           \
-    return launch_gather_q<n>(h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, dev_err, s);
+    return launch_gather_q<n>(h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, \
+                              dev_err, s, ctl);
     BMDCA_GQ(2) BMDCA_GQ(3) BMDCA_GQ(4) BMDCA_GQ(5) BMDCA_GQ(6) BMDCA_GQ(7) BMDCA_GQ(8)
     BMDCA_GQ(9) BMDCA_GQ(10) BMDCA_GQ(11) BMDCA_GQ(12) BMDCA_GQ(13) BMDCA_GQ(14) BMDCA_GQ(15)
     BMDCA_GQ(16) BMDCA_GQ(17) BMDCA_GQ(18) BMDCA_GQ(19) BMDCA_GQ(20) BMDCA_GQ(21) BMDCA_GQ(22)

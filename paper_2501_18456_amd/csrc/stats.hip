@@ -223,7 +223,8 @@ template <int MODE, int NP>
 __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO_BF16) ? 2 : 1) void k_onehot_products(
     const int8_t* __restrict__ XT, int64_t Mpad, int L, int q, const uint16_t* __restrict__ whi,
     const uint16_t* __restrict__ wlo, const float* __restrict__ wf, int ntile, int64_t kchunk,
-    double* __restrict__ P) {
+    double* __restrict__ P, const int32_t* __restrict__ active) {
+  if (active && *active == 0) return;  // whole grid leaves before any barrier
   constexpr int NW = ProductShape<MODE>::kWaves;
   constexpr int RB = ProductShape<MODE>::kRB;
   constexpr int TR = ProductShape<MODE>::kTR;
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
 template <int MODE>
 static void launch_products_mode(int q, int splits, hipStream_t s, const int8_t* XT, int64_t Mpad,
                                  int L, const uint16_t* whi, const uint16_t* wlo, const float* wf,
-                                 int64_t kchunk, double* P) {
+                                 int64_t kchunk, double* P, const int32_t* active) {
   constexpr int NW = ProductShape<MODE>::kWaves;
   const int np = passes_needed(q, NW);
   const dim3 block(64 * NW);
@@ -453,7 +454,7 @@ static void launch_products_mode(int q, int splits, hipStream_t s, const int8_t*
   const dim3 grid((unsigned)product_tiles(L * q, ProductShape<MODE>::kTR), (unsigned)splits);
 #define BMDCA_LAUNCH_NP(N)                                                                    \
   hipLaunchKernelGGL((k_onehot_products<MODE, N>), grid, block, 0, s, XT, Mpad, L, q, whi, wlo, \
-                     wf, ntile, kchunk, P)
+                     wf, ntile, kchunk, P, active)
   if (np <= 1)
     BMDCA_LAUNCH_NP(1);
   else if (np <= 2)
@@ -469,7 +470,7 @@ static void launch_products_mode(int q, int splits, hipStream_t s, const int8_t*
 
 hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
                                   int prec, const StatsPlan& plan, void* ws, int32_t* dev_err,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int32_t* active) {
   char* base = static_cast<char*>(ws);
   int8_t* XT = reinterpret_cast<int8_t*>(base + plan.off_xt);
   uint16_t* whi = reinterpret_cast<uint16_t*>(base + plan.off_whi);
@@ -484,15 +485,15 @@ hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, i
   switch (mode_of(prec, w != nullptr)) {
     case MODE_UNIT_BF16:
       launch_products_mode<MODE_UNIT_BF16>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
-                                           plan.kchunk, P);
+                                           plan.kchunk, P, active);
       break;
     case MODE_HILO_BF16:
       launch_products_mode<MODE_HILO_BF16>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
-                                           plan.kchunk, P);
+                                           plan.kchunk, P, active);
       break;
     default:
       launch_products_mode<MODE_F32>(q, plan.splits, s, XT, plan.Mpad, L, whi, wlo, wf,
-                                     plan.kchunk, P);
+                                     plan.kchunk, P, active);
       break;
   }
   return hipGetLastError();

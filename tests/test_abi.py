@@ -104,3 +104,58 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
                 assert "bmdca_oracle" not in text and "orc_" not in text, f
+
+
+def test_group_records_match_header_layout(tmp_path):
+    """ctypes records == the C structs of include/bmdca.h (offsets and sizes from gcc)."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    fields_p = [f for f, _ in B.TrainProblem._fields_]
+    fields_c = [f for f, _ in B.TrainCtl._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){',
+             'printf("P %zu\\n", sizeof(bmdca_train_problem));',
+             'printf("C %zu\\n", sizeof(bmdca_train_ctl));']
+    lines += [f'printf("p {f} %zu\\n", offsetof(bmdca_train_problem, {f}));' for f in fields_p]
+    lines += [f'printf("c {f} %zu\\n", offsetof(bmdca_train_ctl, {f}));' for f in fields_c]
+    lines += ['return 0;}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:-1]): int(l.split()[-1]) for l in out if l}
+    assert got[("P",)] == ctypes.sizeof(B.TrainProblem)
+    assert got[("C",)] == ctypes.sizeof(B.TrainCtl) == 24
+    for f in fields_p:
+        assert got[("p", f)] == getattr(B.TrainProblem, f).offset, f
+    for f in fields_c:
+        assert got[("c", f)] == getattr(B.TrainCtl, f).offset, f
+
+
+def test_group_host_validation_without_gpu():
+    lib = B.lib()
+    fake = ctypes.c_void_p(0x1000).value
+    p = B.TrainProblem(fake, fake, fake, fake, fake, fake, None, None, fake, fake, 1 << 40,
+                       100, 20, 21, 0.05, 1, 10, 1)
+    arr = (B.TrainProblem * 2)(p, p)
+    assert lib.bmdca_train_group_step(arr, 0, 4, None) == B.EINVAL          # empty group
+    assert lib.bmdca_train_group_step(arr, 2, 0, None) == B.EINVAL          # lanes < 1
+    assert lib.bmdca_train_group_step(arr, 2, 17, None) == B.EINVAL         # lanes > 16
+    bad = B.TrainProblem.from_buffer_copy(bytes(p))
+    bad.ctl = None
+    arr2 = (B.TrainProblem * 2)(p, bad)
+    assert lib.bmdca_train_group_step(arr2, 2, 4, None) == B.EINVAL
+    assert b"problem 1" in lib.bmdca_last_error() and b"ctl" in lib.bmdca_last_error()
+    bad = B.TrainProblem.from_buffer_copy(bytes(p))
+    bad.q = 40
+    arr3 = (B.TrainProblem * 1)(bad)
+    assert lib.bmdca_train_group_step(arr3, 1, 4, None) == B.EINVAL
+    assert b"q=40" in lib.bmdca_last_error()
+    bad = B.TrainProblem.from_buffer_copy(bytes(p))
+    bad.ws_bytes = 16
+    arr4 = (B.TrainProblem * 1)(bad)
+    assert lib.bmdca_train_group_step(arr4, 1, 4, None) == B.EWORKSPACE
+    g = ctypes.c_void_p()
+    assert lib.bmdca_train_group_graph(arr, 2, 4, None, ctypes.byref(g)) == B.EINVAL  # NULL stream
+    assert g.value is None
+    assert lib.bmdca_graph_destroy(None) == B.OK
+    assert lib.bmdca_graph_launch(None, None) == B.EINVAL
