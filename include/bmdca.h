@@ -183,9 +183,12 @@ int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
 
 /* DCA energies of a batch of sequences, Eq. (1) (Sec. 4.3, "Scoring a
  * sequence set"): E[b] = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i, s_j), FP32
- * terms summed in FP64, rounded once to float32.
+ * terms summed in FP64, rounded once to float32.  The pair sum of a sequence
+ * is formed in an order fixed by L alone, so a sequence's energy does not
+ * depend on the other sequences of the batch (bit for bit).
  * seqs int8 [B][L]; E float32 [B] out (both may be NULL when B == 0).
- * ws   scratch, bmdca_workspace_bytes(BMDCA_WS_ENERGY, B, L, q, 0)
+ * ws   scratch, bmdca_workspace_bytes(BMDCA_WS_ENERGY, B, L, q, 0) (may be
+ *      NULL when B == 0)
  * dev_err optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1. */
 int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B,
                  int32_t L, int32_t q, float* E, void* ws, size_t ws_bytes,

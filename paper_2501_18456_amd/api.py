@@ -142,15 +142,17 @@ def gibbs(h, J, chains, sweeps: int, seed: int, sweep_offset: int = 0, beta: flo
     return chains
 
 
-def energy(h, J, seqs, dev_err=None, out=None):
+def energy(h, J, seqs, dev_err=None, out=None, ws=None):
     """Eq. (1) energies: float32 [B]."""
     L, q = _model(h, J)
     _dev(seqs, torch.int8, "seqs", 2)
     Bn = seqs.shape[0]
     if out is None:
         out = torch.empty(Bn, dtype=torch.float32, device=seqs.device)
-    check(B.lib().bmdca_energy(_ptr(h), _ptr(J), _ptr(seqs), Bn, L, q, _ptr(out), None, 0,
-                               _ptr(dev_err), _stream()))
+    if ws is None and Bn > 0:
+        ws = workspace(B.WS_ENERGY, Bn, L, q, 0, seqs.device)
+    check(B.lib().bmdca_energy(_ptr(h), _ptr(J), _ptr(seqs), Bn, L, q, _ptr(out), _ptr(ws),
+                               0 if ws is None else _nbytes(ws), _ptr(dev_err), _stream()))
     return out
 
 

@@ -287,7 +287,8 @@ size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q, int
       if (MN < 1) return 0;
       return gibbs_bytes(MN, L, q);
     case BMDCA_WS_ENERGY:
-      return 256;
+      if (MN < 0) return 0;
+      return plan_energy(MN, L, q).total;
     default:
       return 0;
   }
@@ -373,13 +374,15 @@ int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N, int32
 
 int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int32_t L,
                  int32_t q, float* E, void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   BMDCA_TRY(check_model(L, q));
   BMDCA_REQUIRE(B >= 0 && B <= (int64_t)1 << 31, "B=%lld outside 0..2^31", (long long)B);
-  if (B == 0) return BMDCA_OK;  // nothing to score; seqs and E may be NULL
-  BMDCA_REQUIRE(h && J && seqs && E, "null pointer argument");
-  return hip_status(launch_energy(h, J, seqs, B, L, q, E, dev_err, (hipStream_t)stream), "energy");
+  if (B == 0) return BMDCA_OK;  // nothing to score; seqs, E and ws may be NULL
+  BMDCA_REQUIRE(h && J && seqs && E && ws, "null pointer argument");
+  const EnergyPlan plan = plan_energy(B, L, q);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "energy workspace %zu < %zu bytes", ws_bytes, plan.total);
+  return hip_status(launch_energy(h, J, seqs, B, L, q, E, plan, ws, dev_err, (hipStream_t)stream),
+                    "energy");
 }
 
 int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,

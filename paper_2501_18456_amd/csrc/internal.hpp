@@ -48,6 +48,11 @@ struct StatsPlan {
 };
 StatsPlan plan_stats(int64_t M, int L, int q, int prec);
 
+// X [M][L] -> XT [L][Mpad] (Mpad a multiple of 64); padding rows and invalid
+// tokens become -1, invalid tokens also raise BMDCA_DEVERR_TOKEN.
+hipError_t launch_transpose_tokens(const int8_t* X, int64_t M, int L, int q, int8_t* XT,
+                                  int64_t Mpad, int32_t* dev_err, hipStream_t s);
+
 // Statistics product: partial planes P[s][Lq][Lq] (upper tiles only) of
 // sum_m w_m [x_mi == a][x_mj == b].  w == nullptr: unit weights.
 hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
@@ -88,8 +93,17 @@ hipError_t launch_reweight(const int8_t* msa, int64_t M, int L, int q, int32_t T
                            double* meff, int32_t* dev_err, hipStream_t s);
 
 // ----- scoring.hip
+// Energy workspace: site-major tokens and per-part FP64 pair sums.
+struct EnergyPlan {
+  int64_t Bpad;    // sequences padded to 64
+  int64_t steps;   // (column chunk, row site) steps over all pairs i < j
+  int parts;       // contiguous step ranges (a function of L only)
+  size_t off_xt, off_part, total;
+};
+EnergyPlan plan_energy(int64_t B, int L, int q);
 hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int L,
-                         int q, float* E, int32_t* dev_err, hipStream_t s);
+                         int q, float* E, const EnergyPlan& plan, void* ws, int32_t* dev_err,
+                         hipStream_t s);
 hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int L, int q,
                                float* dE, hipStream_t s);
 size_t apc_ws_bytes(int L);

@@ -10,40 +10,198 @@
 namespace bmdca {
 
 // ---------------------------------------------------------------------------
-// Energy, one wave64 per sequence: FP32 terms accumulated in FP64 per lane,
-// then a fixed-order wave reduction; rounded once to FP32.
+// Energy of a batch, Eq. (1), tiled over sequences and coupling tiles.
+//
+// The pairs i < j are walked as steps (column chunk jc of kEJC sites, row
+// site i), jc outer: a step needs the q x (kEJC*q) tile of J with rows
+// (i, a) and columns (j, b), j in the chunk.  A workgroup owns 1024
+// sequences (four per thread) and one contiguous range of steps; it stages
+// each tile in LDS once (double-buffered through registers) and every
+// sequence picks J[(i, s_i), (j, s_j)] for its own tokens.  The FP32 terms
+// are summed in FP64 in step order, one FP64 partial sum per (range,
+// sequence); the finish adds the fields and the partials in range order.
+// The ranges depend on L only, so a sequence's energy does not depend on the
+// rest of the batch.
 // ---------------------------------------------------------------------------
-constexpr int kEnergyWaves = 4;
+constexpr int kEJC = 16;
+constexpr int kEThreads = 256;
+constexpr int kESeq = 4;                       // sequences per thread
+constexpr int kESeqBlock = kEThreads * kESeq;  // sequences per workgroup
 
-__global__ __launch_bounds__(kEnergyWaves * 64) void k_energy(const float* __restrict__ h,
-                                                              const float* __restrict__ J,
-                                                              const int8_t* __restrict__ seqs,
-                                                              int64_t B, int L, int q,
-                                                              float* __restrict__ E,
-                                                              int32_t* dev_err) {
-  extern __shared__ int cols_all[];  // per wave: L entries (j*q + s_j)
-  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-  const int64_t b = (int64_t)blockIdx.x * kEnergyWaves + wid;
-  if (b >= B) return;
-  int* cols = cols_all + wid * L;
-  const int Lq = L * q;
-  for (int i = lane; i < L; i += 64) cols[i] = i * q + checked_token(seqs[b * L + i], q, dev_err);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  double acc = 0.0;
-  for (int i = lane; i < L; i += 64) acc -= (double)h[cols[i]];
-  for (int i = 0; i < L; ++i) {
-    const float* __restrict__ row = J + (size_t)cols[i] * Lq;
-    for (int j = i + 1 + lane; j < L; j += 64) acc -= (double)row[cols[j]];
+// Row sites of chunk jc that pair with some j > i in the chunk.
+__host__ __device__ inline int energy_rows(int jc, int L) {
+  return min(jc * kEJC + kEJC - 1, L - 1);
+}
+
+EnergyPlan plan_energy(int64_t B, int L, int q) {
+  (void)q;
+  EnergyPlan p{};
+  p.Bpad = ceil_div(std::max<int64_t>(B, 1), 64) * 64;
+  p.steps = 0;
+  for (int jc = 0; jc * kEJC < L; ++jc) p.steps += energy_rows(jc, L);
+  p.parts = p.steps == 0 ? 0 : (int)std::min<int64_t>(128, std::max<int64_t>(1, p.steps / 32));
+  size_t o = 0;
+  p.off_xt = o;   o = align256(o + (size_t)L * p.Bpad);
+  p.off_part = o; o = align256(o + sizeof(double) * (size_t)p.parts * p.Bpad);
+  p.total = o;
+  return p;
+}
+
+template <int Q>
+__global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restrict__ J,
+                                                            const int8_t* __restrict__ XT,
+                                                            int64_t Bpad, int64_t B, int L,
+                                                            int64_t steps, int parts,
+                                                            double* __restrict__ part) {
+  constexpr int kW = kEJC * Q;                                 // tile row length
+  constexpr int kNV = (Q * kW + kEThreads - 1) / kEThreads;    // tile floats per thread
+  __shared__ float tile[2][Q * kW];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int64_t t0 = steps * p / parts, t1 = steps * (p + 1) / parts;
+  const int Lq = L * Q;
+  int64_t bs[kESeq];
+#pragma unroll
+  for (int k = 0; k < kESeq; ++k) bs[k] = (int64_t)blockIdx.x * kESeqBlock + tid + kEThreads * k;
+
+  // (jc, i) of step t0
+  int jc = 0;
+  int64_t r = t0;
+  while (r >= energy_rows(jc, L)) {
+    r -= energy_rows(jc, L);
+    ++jc;
   }
-  acc = wave_sum_f64(acc);
-  if (lane == 0) E[b] = (float)acc;
+  int i = (int)r;
+
+  auto tok = [&](int site, int k) -> int {
+    const int t = (bs[k] < B) ? (int)XT[(size_t)site * Bpad + bs[k]] : 0;
+    return t < 0 ? 0 : t;  // invalid tokens were flagged by the transpose
+  };
+  float v[kNV];
+  auto load_tile = [&](int ti, int tjc) {
+    const int w = min(kEJC, L - tjc * kEJC) * Q;  // valid columns
+#pragma unroll
+    for (int n = 0; n < kNV; ++n) {
+      const int e = tid + kEThreads * n;
+      const int a = e / kW, c = e % kW;
+      v[n] = (a < Q && c < w) ? J[(size_t)(ti * Q + a) * Lq + tjc * kW + c] : 0.0f;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int n = 0; n < kNV; ++n) {
+      const int e = tid + kEThreads * n;
+      if (e < Q * kW) tile[buf][e] = v[n];
+    }
+  };
+
+  double acc[kESeq];
+#pragma unroll
+  for (int k = 0; k < kESeq; ++k) acc[k] = 0.0;
+  int sj[kESeq][kEJC];
+  auto load_chunk = [&](int cjc) {
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k)
+#pragma unroll
+      for (int jj = 0; jj < kEJC; ++jj) {
+        const int j = cjc * kEJC + jj;
+        sj[k][jj] = (j < L) ? tok(j, k) : 0;
+      }
+  };
+
+  if (t0 < t1) {
+    load_tile(i, jc);
+    store_tile(0);
+    load_chunk(jc);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    // next step's coordinates and tile (in flight during this step)
+    int ni = i + 1, njc = jc;
+    if (ni >= energy_rows(jc, L)) {
+      ni = 0;
+      ++njc;
+    }
+    const bool more = t + 1 < t1;
+    if (more) load_tile(ni, njc);
+    int si[kESeq];
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) si[k] = tok(i, k) * kW;
+    const float* tb = tile[buf];
+#pragma unroll
+    for (int jj = 0; jj < kEJC; ++jj) {
+      const int j = jc * kEJC + jj;
+      if (j > i && j < L) {  // uniform over the workgroup
+#pragma unroll
+        for (int k = 0; k < kESeq; ++k) acc[k] += (double)tb[si[k] + jj * Q + sj[k][jj]];
+      }
+    }
+    if (more) {
+      store_tile(buf ^ 1);
+      if (njc != jc) load_chunk(njc);
+    }
+    __syncthreads();
+    buf ^= 1;
+    i = ni;
+    jc = njc;
+  }
+#pragma unroll
+  for (int k = 0; k < kESeq; ++k)
+    if (bs[k] < B) part[(size_t)p * Bpad + bs[k]] = acc[k];
+}
+
+__global__ void k_energy_finish(const float* __restrict__ h, const int8_t* __restrict__ XT,
+                                int64_t Bpad, int64_t B, int L, int q, int parts,
+                                const double* __restrict__ part, float* __restrict__ E) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double acc = 0.0;
+  for (int i = 0; i < L; ++i) {
+    int t = XT[(size_t)i * Bpad + b];
+    if (t < 0) t = 0;
+    acc -= (double)h[i * q + t];
+  }
+  for (int p = 0; p < parts; ++p) acc -= part[(size_t)p * Bpad + b];
+  E[b] = (float)acc;
+}
+
+template <int Q>
+static void launch_energy_q(const float* J, const int8_t* XT, int64_t B, int L,
+                            const EnergyPlan& plan, double* part, hipStream_t s) {
+  const dim3 grid((unsigned)ceil_div(B, kESeqBlock), (unsigned)plan.parts);
+  hipLaunchKernelGGL(k_energy_pairs<Q>, grid, dim3(kEThreads), 0, s, J, XT, plan.Bpad, B, L,
+                     plan.steps, plan.parts, part);
 }
 
 hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int L,
-                         int q, float* E, int32_t* dev_err, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3((unsigned)ceil_div(B, kEnergyWaves)), dim3(kEnergyWaves * 64),
-                     sizeof(int) * L * kEnergyWaves, s, h, J, seqs, B, L, q, E, dev_err);
+                         int q, float* E, const EnergyPlan& plan, void* ws, int32_t* dev_err,
+                         hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  int8_t* XT = reinterpret_cast<int8_t*>(base + plan.off_xt);
+  double* part = reinterpret_cast<double*>(base + plan.off_part);
+  hipError_t e = launch_transpose_tokens(seqs, B, L, q, XT, plan.Bpad, dev_err, s);
+  if (e != hipSuccess) return e;
+  if (plan.parts > 0) {
+    switch (q) {
+#define BMDCA_EQ(n)                                        \
+  case n:                                                  \
+    launch_energy_q<n>(J, XT, B, L, plan, part, s); \
+    break;
+      BMDCA_EQ(2) BMDCA_EQ(3) BMDCA_EQ(4) BMDCA_EQ(5) BMDCA_EQ(6) BMDCA_EQ(7) BMDCA_EQ(8)
+      BMDCA_EQ(9) BMDCA_EQ(10) BMDCA_EQ(11) BMDCA_EQ(12) BMDCA_EQ(13) BMDCA_EQ(14) BMDCA_EQ(15)
+      BMDCA_EQ(16) BMDCA_EQ(17) BMDCA_EQ(18) BMDCA_EQ(19) BMDCA_EQ(20) BMDCA_EQ(21) BMDCA_EQ(22)
+      BMDCA_EQ(23) BMDCA_EQ(24) BMDCA_EQ(25) BMDCA_EQ(26) BMDCA_EQ(27) BMDCA_EQ(28) BMDCA_EQ(29)
+      BMDCA_EQ(30) BMDCA_EQ(31) BMDCA_EQ(32)
+#undef BMDCA_EQ
+      default:
+        return hipErrorInvalidValue;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_energy_finish, dim3((unsigned)ceil_div(B, 256)), dim3(256), 0, s, h, XT,
+                     plan.Bpad, B, L, q, plan.parts, part, E);
   return hipGetLastError();
 }
 

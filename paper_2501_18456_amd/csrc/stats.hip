@@ -121,6 +121,13 @@ __global__ __launch_bounds__(256) void k_transpose_tokens(const int8_t* __restri
   }
 }
 
+hipError_t launch_transpose_tokens(const int8_t* X, int64_t M, int L, int q, int8_t* XT,
+                                  int64_t Mpad, int32_t* dev_err, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_tokens, dim3((unsigned)(Mpad / 64), (unsigned)ceil_div(L, 64)),
+                     dim3(256), 0, s, X, M, L, q, XT, Mpad, dev_err);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
   uint32_t b = __float_as_uint(f);
   b += 0x7FFFu + ((b >> 16) & 1u);

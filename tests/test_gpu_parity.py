@@ -236,13 +236,27 @@ def term_scale(h, J, S, q):
     return np.array(out)
 
 
-@pytest.mark.parametrize("L,q,Bn", [(30, 21, 1000), (130, 21, 64), (9, 5, 257)])
+# several 1024-sequence blocks with a ragged tail; L below, at and across the
+# 16-site column chunks; q across the template range
+@pytest.mark.parametrize("L,q,Bn", [(30, 21, 1000), (130, 21, 64), (9, 5, 257), (1, 21, 5),
+                                    (2, 2, 3000), (16, 3, 100), (17, 32, 2100), (100, 21, 2500)])
 def test_energy(L, q, Bn):
     h, J = synth.planted_dense(L, q, seed=110 + L, sigma_J=0.3)
     S = synth.random_sequences(Bn, L, q, 111)
     Eg = host(api.energy(dev(h), dev(J), dev(S)))
     Eo = O.energy(h, J, S, q)
     assert np.all(np.abs(Eg - Eo) <= 1e-4 * term_scale(h, J, S, q))
+
+
+def test_energy_independent_of_batch():
+    """A sequence scores the same bits alone, in a small batch and in a large one."""
+    L, q = 77, 21
+    h, J = synth.planted_dense(L, q, seed=112, sigma_J=0.3)
+    S = synth.random_sequences(3000, L, q, 113)
+    big = host(api.energy(dev(h), dev(J), dev(S)))
+    for lo, hi in [(0, 1), (1500, 1501), (2047, 2300), (5, 1029)]:
+        part = host(api.energy(dev(h), dev(J), dev(S[lo:hi])))
+        assert np.array_equal(part, big[lo:hi])
 
 
 def test_single_mutant_scan():
