@@ -159,3 +159,32 @@ def test_group_host_validation_without_gpu():
     assert g.value is None
     assert lib.bmdca_graph_destroy(None) == B.OK
     assert lib.bmdca_graph_launch(None, None) == B.EINVAL
+
+
+def test_serving_workload_and_summary_without_gpu():
+    """Request generator: seeded, Poisson arrivals at the asked rate, sizes in
+    range; summary percentiles from known latencies."""
+    import numpy as np
+    from paper_2501_18456_amd import serve
+    Ls = (64, 128)
+    a = serve.poisson_requests(400, 50.0, Ls, 21, seed=3)
+    b = serve.poisson_requests(400, 50.0, Ls, 21, seed=3)
+    assert [r.kind for r in a] == [r.kind for r in b] and [r.arrival for r in a] == [r.arrival for r in b]
+    gaps = np.diff([0.0] + [r.arrival for r in a])
+    assert abs(gaps.mean() - 1 / 50.0) < 0.25 / 50.0
+    for r in a:
+        L = Ls[r.model]
+        if r.kind == "energy":
+            assert 1000 <= r.seqs.shape[0] <= 100000 and r.seqs.shape[1] == L
+            assert r.seqs.min() >= 0 and r.seqs.max() < 21
+        elif r.kind == "mutant":
+            assert r.wt.shape == (L,)
+        else:
+            assert 100 <= r.n_chains <= 10000 and r.sweeps == 50
+    reqs = []
+    for k in range(100):
+        r = serve.Request(k, "energy", 0, 0.0)
+        r.t_done = (k + 1) * 1e-3
+        reqs.append(r)
+    s = serve.summarize(reqs)
+    assert abs(s["energy"]["p50_ms"] - 50.5) < 1e-9 and abs(s["energy"]["p99_ms"] - 99.01) < 1e-9
