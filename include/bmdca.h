@@ -181,6 +181,30 @@ int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
                 size_t H_ws_bytes, int32_t flags,
                 unsigned long long* flips_out, void* stream);
 
+/* Random stream of one chain for bmdca_gibbs_streams (24 bytes). */
+typedef struct bmdca_chain_stream {
+    uint64_t seed;         /* Philox key of the chain's draws */
+    uint64_t sweep_offset; /* global sweep index of the call's first sweep */
+    uint32_t chain;        /* chain index used in the Philox counter */
+    uint32_t reserved;     /* 0 */
+} bmdca_chain_stream;
+
+/* bmdca_gibbs over chains that come from different requests: chain c makes
+ * exactly the draws of chain streams[c].chain in a bmdca_gibbs call with
+ * seed streams[c].seed and sweep_offset streams[c].sweep_offset, so chains
+ * of several callers can be swept in one launch with the results each would
+ * get alone (same sampler form).  All chains run `sweeps` sweeps.
+ * streams  device array [N], caller-owned
+ * cus      compute units the launch is sized for (0 = the whole device): a
+ *          smaller share packs more chains into each workgroup and streams
+ *          the couplings fewer times, for launches that share the GPU
+ * Other arguments as bmdca_gibbs (seed/sweep_offset come from `streams`). */
+int bmdca_gibbs_streams(const float* h, const float* J, int8_t* chains, int64_t N,
+                        int32_t L, int32_t q, int32_t sweeps,
+                        const bmdca_chain_stream* streams, float beta, float* H_ws,
+                        size_t H_ws_bytes, int32_t flags, int32_t cus,
+                        unsigned long long* flips_out, void* stream);
+
 /* DCA energies of a batch of sequences, Eq. (1) (Sec. 4.3, "Scoring a
  * sequence set"): E[b] = -sum_i h_i(s_i) - sum_{i<j} J_ij(s_i, s_j), FP32
  * terms summed in FP64, rounded once to float32.  The pair sum of a sequence

@@ -33,6 +33,12 @@ class TrainProblem(C.Structure):
     ]
 
 
+class ChainStream(C.Structure):
+    """bmdca_chain_stream (include/bmdca.h)."""
+    _fields_ = [("seed", _u64), ("sweep_offset", _u64), ("chain", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 class TrainCtl(C.Structure):
     """bmdca_train_ctl (include/bmdca.h): the device record's byte layout."""
     _fields_ = [("epoch", _u64), ("active", _i32), ("converged_at", _i32),
@@ -49,6 +55,8 @@ SIGNATURES = {
                               _p]),
     "bmdca_gibbs": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _i32, _u64, _u64, _f32, _p, _sz,
                               _i32, _p, _p]),
+    "bmdca_gibbs_streams": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _i32, _p, _f32, _p, _sz,
+                                      _i32, _i32, _p, _p]),
     "bmdca_energy": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p, _p]),
     "bmdca_train_step": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32, _u64, _u64,
                                    _i32, _p, _p, _p, _sz, _p, _p]),

@@ -9,6 +9,7 @@ Shapes: h float32 [L, q]; J float32 [L*q, L*q]; tokens int8 [rows, L].
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import _lib as B
@@ -139,6 +140,34 @@ def gibbs(h, J, chains, sweeps: int, seed: int, sweep_offset: int = 0, beta: flo
         H_ws = workspace(B.WS_GIBBS, N, L, q, flags, chains.device)
     check(B.lib().bmdca_gibbs(_ptr(h), _ptr(J), _ptr(chains), N, L, q, sweeps, seed, sweep_offset,
                               beta, _ptr(H_ws), _nbytes(H_ws), flags, _ptr(flips), _stream()))
+    return chains
+
+
+def chain_streams(seeds, offsets, chains, device="cuda"):
+    """Device table of bmdca_chain_stream records from per-chain numpy arrays."""
+    n = len(seeds)
+    rec = np.zeros(n, dtype=[("seed", "<u8"), ("sweep_offset", "<u8"), ("chain", "<u4"),
+                             ("reserved", "<u4")])
+    rec["seed"], rec["sweep_offset"], rec["chain"] = seeds, offsets, chains
+    host = torch.frombuffer(bytearray(rec.tobytes()), dtype=torch.uint8).pin_memory()
+    return host.to(device, non_blocking=True)
+
+
+def gibbs_streams(h, J, chains, sweeps: int, streams, beta: float = 1.0, H_ws=None, flips=None,
+                  sampler="auto", cus: int = 0):
+    """bmdca_gibbs_streams: chain c draws as described by streams[c]."""
+    L, q = _model(h, J)
+    _dev(chains, torch.int8, "chains", 2)
+    _dev(streams, torch.uint8, "streams", 1)
+    N = chains.shape[0]
+    if streams.numel() != 24 * N:
+        raise ValueError("streams must hold one 24-byte record per chain")
+    flags = _sampler(sampler)
+    if H_ws is None:
+        H_ws = workspace(B.WS_GIBBS, N, L, q, flags, chains.device)
+    check(B.lib().bmdca_gibbs_streams(_ptr(h), _ptr(J), _ptr(chains), N, L, q, sweeps,
+                                      _ptr(streams), beta, _ptr(H_ws), _nbytes(H_ws), flags, cus,
+                                      _ptr(flips), _stream()))
     return chains
 
 

@@ -96,6 +96,46 @@ TrainPlan plan_train(int64_t N, int L, int q, int prec) {
   return t;
 }
 
+// Host validation and launches of a sampling call (plain or with per-chain
+// streams in ctl).
+int gibbs_impl(const float* h, const float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,
+               int32_t sweeps, uint64_t seed, uint64_t sweep_offset, float beta, float* H_ws,
+               size_t H_ws_bytes, int32_t flags, unsigned long long* flips_out,
+               const DevCtl& ctl, hipStream_t s) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(h && J && chains, "null pointer argument");
+  BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
+  BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
+  if (!std::isfinite(beta)) return fail(BMDCA_ENONFINITE, "beta is not finite");
+  const int gather = pick_gather(flags, L, q);
+  BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", flags, L, q);
+  BMDCA_REQUIRE(H_ws, "H_ws is NULL");
+  if (gather) {
+    if (H_ws_bytes < gather_ws_bytes(L, q))
+      return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
+                  gather_ws_bytes(L, q));
+    return hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed, sweep_offset, beta,
+                                          flips_out, nullptr, H_ws, s, ctl),
+                      "gibbs/gather");
+  }
+  if (H_ws_bytes < gibbs_bytes(N, L, q))
+    return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
+                gibbs_bytes(N, L, q));
+  if (!(flags & BMDCA_GIBBS_KEEP_FIELDS))
+    BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H_ws, nullptr, s),
+                         "gibbs/fields"));
+  if (sweeps == 0) return BMDCA_OK;
+  return hip_status(launch_gibbs_sweeps(J, chains, H_ws, N, L, q, sweeps, seed, sweep_offset, beta,
+                                        flips_out, s, ctl),
+                    "gibbs/sweeps");
+}
+
+static_assert(sizeof(ChainStream) == sizeof(bmdca_chain_stream), "chain stream layout");
+static_assert(offsetof(ChainStream, seed) == offsetof(bmdca_chain_stream, seed), "layout");
+static_assert(offsetof(ChainStream, sweep_offset) == offsetof(bmdca_chain_stream, sweep_offset),
+              "layout");
+static_assert(offsetof(ChainStream, chain) == offsetof(bmdca_chain_stream, chain), "layout");
+
 // Host-side validation shared by the single and grouped training calls.
 int check_train(const bmdca_train_problem& p) {
   BMDCA_TRY(check_model(p.L, p.q));
@@ -343,33 +383,21 @@ int bmdca_gibbs(const float* h, const float* J, int8_t* chains, int64_t N, int32
                 int32_t sweeps, uint64_t seed, uint64_t sweep_offset, float beta, float* H_ws,
                 size_t H_ws_bytes, int32_t flags, unsigned long long* flips_out,
                 void* stream) {
-  BMDCA_TRY(check_model(L, q));
-  BMDCA_REQUIRE(h && J && chains, "null pointer argument");
-  BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
-  BMDCA_REQUIRE(sweeps >= 0, "sweeps=%d negative", sweeps);
-  if (!std::isfinite(beta)) return fail(BMDCA_ENONFINITE, "beta is not finite");
-  const int gather = pick_gather(flags, L, q);
-  BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", flags, L, q);
-  hipStream_t s = (hipStream_t)stream;
-  BMDCA_REQUIRE(H_ws, "H_ws is NULL");
-  if (gather) {
-    if (H_ws_bytes < gather_ws_bytes(L, q))
-      return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
-                  gather_ws_bytes(L, q));
-    return hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed, sweep_offset, beta,
-                                          flips_out, nullptr, H_ws, s),
-                      "gibbs/gather");
-  }
-  if (H_ws_bytes < gibbs_bytes(N, L, q))
-    return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
-                gibbs_bytes(N, L, q));
-  if (!(flags & BMDCA_GIBBS_KEEP_FIELDS))
-    BMDCA_TRY(hip_status(launch_local_fields(h, J, chains, N, L, q, H_ws, nullptr, s),
-                         "gibbs/fields"));
-  if (sweeps == 0) return BMDCA_OK;
-  return hip_status(launch_gibbs_sweeps(J, chains, H_ws, N, L, q, sweeps, seed, sweep_offset, beta,
-                                        flips_out, s),
-                    "gibbs/sweeps");
+  return gibbs_impl(h, J, chains, N, L, q, sweeps, seed, sweep_offset, beta, H_ws, H_ws_bytes,
+                    flags, flips_out, DevCtl(), (hipStream_t)stream);
+}
+
+int bmdca_gibbs_streams(const float* h, const float* J, int8_t* chains, int64_t N, int32_t L,
+                        int32_t q, int32_t sweeps, const bmdca_chain_stream* streams, float beta,
+                        float* H_ws, size_t H_ws_bytes, int32_t flags, int32_t cus,
+                        unsigned long long* flips_out, void* stream) {
+  BMDCA_REQUIRE(streams, "streams is NULL");
+  BMDCA_REQUIRE(cus >= 0, "cus=%d negative", cus);
+  DevCtl ctl;
+  ctl.streams = reinterpret_cast<const ChainStream*>(streams);
+  ctl.cu_share = cus;
+  return gibbs_impl(h, J, chains, N, L, q, sweeps, 0, 0, beta, H_ws, H_ws_bytes, flags, flips_out,
+                    ctl, (hipStream_t)stream);
 }
 
 int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int32_t L,

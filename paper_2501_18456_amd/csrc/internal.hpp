@@ -8,12 +8,22 @@
 
 namespace bmdca {
 
-// Device-side control of one model inside a graph-replayed group epoch.  All
-// fields are optional: with the defaults a launch behaves as a plain call.
+// Random stream of one chain (the public bmdca_chain_stream): the chain
+// draws as chain `chain` of a call with key `seed` and `sweep_offset`.
+struct ChainStream {
+  uint64_t seed;
+  uint64_t sweep_offset;
+  uint32_t chain;
+  uint32_t reserved;
+};
+
+// Device-side controls of a launch.  All fields are optional: with the
+// defaults a launch behaves as a plain call.
 struct DevCtl {
   const uint64_t* epoch = nullptr;  // sampler sweep offset += *epoch * sweeps
   const int32_t* active = nullptr;  // *active == 0: the kernel returns at once
   int cu_share = 0;                 // CUs the sampler grid is sized for (0: all)
+  const ChainStream* streams = nullptr;  // per-chain random streams (sampler)
 };
 
 // ----- sampler.hip

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
                                                         float beta,
                                                         unsigned long long* flips_out,
                                                         const uint64_t* __restrict__ epoch,
-                                                        const int32_t* __restrict__ active) {
+                                                        const int32_t* __restrict__ active,
+                                                        const ChainStream* __restrict__ streams) {
   if (active && *active == 0) return;
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   extern __shared__ int8_t tok_all[];
@@ -107,6 +108,14 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
   const int wid = threadIdx.x / kWave;
   const int64_t c = (int64_t)blockIdx.x * WPB + wid;
   if (c >= N) return;  // whole wave leaves; no block barriers below
+  uint32_t cid = (uint32_t)c;
+  if (streams) {
+    const ChainStream st = streams[c];
+    k0 = (uint32_t)st.seed;
+    k1 = (uint32_t)(st.seed >> 32);
+    cid = st.chain;
+    sweep_offset += st.sweep_offset;
+  }
   const int Lpad = (L + 3) & ~3;
   int8_t* tok = tok_all + wid * Lpad;
   for (int i = lane; i < L; i += kWave) {
@@ -123,7 +132,7 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
   for (int sw = 0; sw < sweeps; ++sw) {
     const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
     for (int i = 0; i < L; ++i) {
-      if ((i & 3) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, (uint32_t)c, 0u), k0, k1);
+      if ((i & 3) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
       const float u = word_to_uniform(pick_word(rnd, i & 3));
       const int a_old = tok[i];
       const float l = lane < q ? beta * Hc[i * q + lane] : -INFINITY;
@@ -165,7 +174,8 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
   const int Lpad = (L + 3) & ~3;
   hipLaunchKernelGGL(k_gibbs_hbm<WPB>, dim3((unsigned)ceil_div(N, WPB)), dim3(WPB * kWave),
                      WPB * Lpad, s, J, chains, H, N, L, q, sweeps, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, ctl.epoch, ctl.active);
+                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, ctl.epoch, ctl.active,
+                     ctl.streams);
   return hipGetLastError();
 }
 
@@ -274,7 +284,8 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
     int64_t N, int L, int ahead, int slot, int cpb, int sweeps, uint32_t k0, uint32_t k1,
     uint64_t sweep_offset, float beta, unsigned long long* flips_out, int32_t* dev_err,
-    const uint64_t* __restrict__ epoch, const int32_t* __restrict__ run) {
+    const uint64_t* __restrict__ epoch, const int32_t* __restrict__ run,
+    const ChainStream* __restrict__ streams) {
   if (run && *run == 0) return;  // whole grid leaves before any barrier
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   constexpr int G = kGG, W = kGWv, R = kGR, JC = kGJC;
@@ -294,6 +305,14 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
   const int64_t c = (int64_t)blockIdx.x * cpb + cb;
   const bool has_chain = cb < cpb;
   const bool active = has_chain && (c < N);
+  uint32_t cid = (uint32_t)c;
+  if (streams && active) {
+    const ChainStream st = streams[c];
+    k0 = (uint32_t)st.seed;
+    k1 = (uint32_t)(st.seed >> 32);
+    cid = st.chain;
+    sweep_offset += st.sweep_offset;
+  }
   const int nchunk = (L + JC - 1) / JC;
   const uint32_t site_bytes = (uint32_t)((size_t)L * Q * QP * sizeof(float));
   const uint32_t chunk_bytes = (uint32_t)(JC * Q * QP * sizeof(float));
@@ -413,7 +432,7 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
         acc[a] = run;  // S_a
       }
       const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
-      const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, (uint32_t)c, 0u), k0, k1);
+      const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
       const float uz = word_to_uniform(pick_word(rnd, i & 3)) * run;
       int anew = 0;
 #pragma unroll
@@ -479,7 +498,7 @@ static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chain
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kGWv * 64), gs.lds, s, h, Jt, chains, N, L, gs.ahead,
                      gs.slot, cpb, sweeps, (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset,
-                     beta, flips_out, dev_err, ctl.epoch, ctl.active);
+                     beta, flips_out, dev_err, ctl.epoch, ctl.active, ctl.streams);
   return hipGetLastError();
 }
 

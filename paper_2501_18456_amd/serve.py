@@ -7,15 +7,19 @@ set, the single-mutant library, sampling) served to a stream of requests:
   - admission by HBM footprint: a request is admitted, in arrival order, once
     the memory its inputs, outputs and workspace need fits the budget beside
     everything in flight; a request that can never fit is refused at once;
-  - continuous batching: at every scheduler tick the admitted energy requests
-    of one model go out as one bmdca_energy launch and the admitted mutant
-    scans of one model as one bmdca_single_mutant_scan launch; a sampling
-    request runs in chunks of `chunk_sweeps` sweeps (global sweep index
-    continuing across chunks), so requests that arrive meanwhile start at the
-    next chunk boundary instead of waiting for the whole request;
+  - continuous batching (iteration-level): each (kind, model) pair has at most
+    one launch in flight; when it is free, everything of that pair that is
+    ready goes out as one launch -- the admitted energy requests of the model
+    as one bmdca_energy call, its mutant scans as one
+    bmdca_single_mutant_scan call, and its sampling requests as one
+    bmdca_gibbs_streams call over all their chains for the next
+    `chunk_sweeps` sweeps (each chain keeps its own request's key, chain
+    index and sweep count).  Requests that arrive while a launch runs join
+    the next one, at the next chunk boundary for sampling;
   - launches go to `lanes` streams (default priority) and overlap on the GPU;
-    completion is seen by polling events, results are copied back on the
-    lane that made them.
+    every (kind, model) pair has a fixed lane, so a batch never waits on
+    another lane's work; completion is seen by polling events, results are
+    copied back on the lane that made them.
 
 A request's result does not depend on what else is in flight: energies of a
 sequence are independent of the batch (fixed pair order per L), mutant scans
@@ -67,7 +71,6 @@ class _Live:
     req: Request
     lane: int
     inp: torch.Tensor | None = None       # device input (sequences, wild type, chains)
-    ws: torch.Tensor | None = None        # sampling workspace
     host_in: torch.Tensor | None = None   # pinned input, alive until uploaded
     host_out: torch.Tensor | None = None  # pinned result
     dev_out: torch.Tensor | None = None   # device result, alive until copied
@@ -80,6 +83,7 @@ class _Launch:
     event: torch.cuda.Event
     lives: list
     kind: str
+    model: int
 
 
 @dataclass
@@ -91,17 +95,18 @@ class Stats:
 
 class Server:
     def __init__(self, models, budget_bytes: int, lanes: int = 4, chunk_sweeps: int = 5,
-                 device="cuda"):
-        """models: list of (h float32 [L, q], J float32 [Lq, Lq]) device tensors."""
+                 sample_cus: int = 0, device="cuda"):
+        """models: list of (h float32 [L, q], J float32 [Lq, Lq]) device tensors.
+        sample_cus: compute units a sampling launch is sized for (0: all)."""
         self.models = []
         for h, J in models:
             L, q = api._model(h, J)
             self.models.append((h, J, L, q))
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_sweeps)
+        self.sample_cus = int(sample_cus)
         self.device = device
         self.lanes = [torch.cuda.Stream(device=device) for _ in range(lanes)]
-        self.lane_load = [0] * lanes
         self.stats = Stats()
 
     # ------------------------------------------------------------ footprints
@@ -118,9 +123,12 @@ class Server:
         raise ValueError(f"unknown request kind {r.kind}")
 
     # ------------------------------------------------------------ admission
+    def lane_of(self, kind: str, model: int) -> int:
+        return (len(KINDS) * model + KINDS.index(kind)) % len(self.lanes)
+
     def _admit(self, r: Request, now: float) -> _Live:
         h, J, L, q = self.models[r.model]
-        lane = min(range(len(self.lanes)), key=lambda k: self.lane_load[k])
+        lane = self.lane_of(r.kind, r.model)
         lv = _Live(r, lane)
         s = self.lanes[lane]
         with torch.cuda.stream(s):
@@ -130,22 +138,14 @@ class Server:
                 lv.inp = lv.host_in.to(self.device, non_blocking=True)
             else:
                 lv.inp = api.init_chains(r.n_chains, L, q, r.seed, device=self.device)
-                flags = B.SAMPLER_GATHER if L <= 512 else 0
-                lv.ws = api.workspace(B.WS_GIBBS, r.n_chains, L, q, flags, self.device)
         r.t_admit = now
-        self.lane_load[lane] += 1
         return lv
 
     # ------------------------------------------------------------ launches
     def _launch_group(self, kind: str, model: int, lives: list) -> _Launch:
         """One batched launch for several admitted requests of one model."""
         h, J, L, q = self.models[model]
-        lane = lives[0].lane
-        s = self.lanes[lane]
-        for lv in lives[1:]:  # inputs uploaded on other lanes
-            if lv.lane != lane:
-                s.wait_stream(self.lanes[lv.lane])
-                lv.inp.record_stream(s)
+        s = self.lanes[lives[0].lane]  # the lane of (kind, model): inputs were uploaded there
         with torch.cuda.stream(s):
             if kind == "energy":
                 seqs = lives[0].inp if len(lives) == 1 else torch.cat([lv.inp for lv in lives])
@@ -171,26 +171,42 @@ class Server:
             lv.dev_out = out
         self.stats.launches[kind] += 1
         self.stats.batched[kind] += len(lives)
-        return _Launch(ev, lives, kind)
+        return _Launch(ev, lives, kind, model)
 
-    def _launch_chunk(self, lv: _Live) -> _Launch:
-        r = lv.req
-        h, J, L, q = self.models[r.model]
-        s = self.lanes[lv.lane]
-        n = min(self.chunk, r.sweeps - lv.done_sweeps)
+    def _launch_samples(self, model: int, lives: list) -> _Launch:
+        """The next chunk of every listed sampling request of one model, as one
+        launch over all their chains."""
+        h, J, L, q = self.models[model]
+        s = self.lanes[lives[0].lane]  # the lane of (sample, model)
+        n = min(self.chunk, min(lv.req.sweeps - lv.done_sweeps for lv in lives))
+        counts = [lv.req.n_chains for lv in lives]
+        seeds = np.concatenate([np.full(k, lv.req.seed, dtype=np.uint64)
+                                for k, lv in zip(counts, lives)])
+        offs = np.concatenate([np.full(k, lv.done_sweeps, dtype=np.uint64)
+                               for k, lv in zip(counts, lives)])
+        ids = np.concatenate([np.arange(k, dtype=np.uint32) for k in counts])
+        sampler = "gather" if L <= 512 else "fields"
         with torch.cuda.stream(s):
-            api.gibbs(h, J, lv.inp, n, r.seed, sweep_offset=lv.done_sweeps, H_ws=lv.ws,
-                      sampler="gather" if L <= 512 else "fields")
-            lv.done_sweeps += n
-            if lv.done_sweeps == r.sweeps:
-                lv.host_out = torch.empty(tuple(lv.inp.shape), dtype=torch.int8, pin_memory=True)
-                lv.host_out.copy_(lv.inp, non_blocking=True)
+            chains = lives[0].inp if len(lives) == 1 else torch.cat([lv.inp for lv in lives])
+            table = api.chain_streams(seeds, offs, ids, self.device)
+            api.gibbs_streams(h, J, chains, n, table, sampler=sampler, cus=self.sample_cus)
+            o = 0
+            for k, lv in zip(counts, lives):
+                if len(lives) > 1:
+                    lv.inp.copy_(chains[o:o + k])
+                o += k
+                lv.done_sweeps += n
+                if lv.done_sweeps == lv.req.sweeps:
+                    lv.host_out = torch.empty(tuple(lv.inp.shape), dtype=torch.int8,
+                                              pin_memory=True)
+                    lv.host_out.copy_(lv.inp, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        lv.busy = True
+        for lv in lives:
+            lv.busy = True
         self.stats.launches["sample"] += 1
-        self.stats.batched["sample"] += 1
-        return _Launch(ev, [lv], "sample")
+        self.stats.batched["sample"] += len(lives)
+        return _Launch(ev, lives, "sample", model)
 
     # ------------------------------------------------------------ main loop
     def run(self, requests, realtime: bool = True, idle_sleep: float = 20e-6):
@@ -228,15 +244,16 @@ class Server:
                 self.stats.peak_bytes = max(self.stats.peak_bytes, in_use)
             # batched launches of everything ready
             groups: dict = {}
+            busy_keys = {(ln.kind, ln.model) for ln in inflight}
             for lv in ready:
-                if lv.busy:
-                    continue
-                if lv.req.kind == "sample":
-                    inflight.append(self._launch_chunk(lv))
-                else:
-                    groups.setdefault((lv.req.kind, lv.req.model), []).append(lv)
+                key = (lv.req.kind, lv.req.model)
+                if not lv.busy and key not in busy_keys:
+                    groups.setdefault(key, []).append(lv)
             for (kind, model), lives in groups.items():
-                inflight.append(self._launch_group(kind, model, lives))
+                if kind == "sample":
+                    inflight.append(self._launch_samples(model, lives))
+                else:
+                    inflight.append(self._launch_group(kind, model, lives))
             # completions
             progressed = False
             still = []
@@ -253,10 +270,9 @@ class Server:
                         continue  # next chunk at the next tick
                     r.result = lv.host_out.numpy()
                     r.t_done = t
-                    lv.dev_out = lv.host_in = lv.ws = None
+                    lv.dev_out = lv.host_in = None
                     ready.remove(lv)
                     in_use -= r.footprint
-                    self.lane_load[lv.lane] -= 1
             inflight = still
             if not progressed and idle_sleep > 0:
                 time.sleep(idle_sleep)

@@ -112,11 +112,14 @@ def test_group_records_match_header_layout(tmp_path):
     src = tmp_path / "layout.c"
     fields_p = [f for f, _ in B.TrainProblem._fields_]
     fields_c = [f for f, _ in B.TrainCtl._fields_]
+    fields_s = [f for f, _ in B.ChainStream._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){',
              'printf("P %zu\\n", sizeof(bmdca_train_problem));',
-             'printf("C %zu\\n", sizeof(bmdca_train_ctl));']
+             'printf("C %zu\\n", sizeof(bmdca_train_ctl));',
+             'printf("S %zu\\n", sizeof(bmdca_chain_stream));']
     lines += [f'printf("p {f} %zu\\n", offsetof(bmdca_train_problem, {f}));' for f in fields_p]
     lines += [f'printf("c {f} %zu\\n", offsetof(bmdca_train_ctl, {f}));' for f in fields_c]
+    lines += [f'printf("s {f} %zu\\n", offsetof(bmdca_chain_stream, {f}));' for f in fields_s]
     lines += ['return 0;}']
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
@@ -129,6 +132,9 @@ def test_group_records_match_header_layout(tmp_path):
         assert got[("p", f)] == getattr(B.TrainProblem, f).offset, f
     for f in fields_c:
         assert got[("c", f)] == getattr(B.TrainCtl, f).offset, f
+    assert got[("S",)] == ctypes.sizeof(B.ChainStream) == 24
+    for f in fields_s:
+        assert got[("s", f)] == getattr(B.ChainStream, f).offset, f
 
 
 def test_group_host_validation_without_gpu():

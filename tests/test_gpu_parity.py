@@ -359,3 +359,24 @@ def test_train_step_nonfinite_flag():
     e = err_flag()
     api.train_step(hg, Jg, dev(chains), dev(f1), dev(f2), 1e300, 1, 1, 0, dev_err=e)
     assert int(host(e)[0]) & B.DEVERR_NONFINITE
+
+
+@pytest.mark.parametrize("sampler", ["gather", "fields"])
+@pytest.mark.parametrize("cus", [0, 8])
+def test_gibbs_streams_equal_separate_calls(sampler, cus):
+    """Chains of two callers swept in one launch through a stream table make
+    the same draws as in their own calls (keys, chain indices, sweep offsets)."""
+    L, q = 45, 21
+    h, J = synth.planted_dense(L, q, seed=130, sigma_J=0.3)
+    hg, Jg = dev(h), dev(J)
+    a0, b0 = api.init_chains(300, L, q, seed=131), api.init_chains(77, L, q, seed=132)
+    a, b = a0.clone(), b0.clone()
+    api.gibbs(hg, Jg, a, 6, seed=1111, sweep_offset=0, sampler=sampler)
+    api.gibbs(hg, Jg, b, 6, seed=2222, sweep_offset=35, sampler=sampler)
+    both = torch.cat([a0, b0])
+    seeds = np.array([1111] * 300 + [2222] * 77, dtype=np.uint64)
+    offs = np.array([0] * 300 + [35] * 77, dtype=np.uint64)
+    ids = np.concatenate([np.arange(300), np.arange(77)]).astype(np.uint32)
+    st = api.chain_streams(seeds, offs, ids)
+    api.gibbs_streams(hg, Jg, both, 6, st, sampler=sampler, cus=cus)
+    assert torch.equal(both[:300], a) and torch.equal(both[300:], b)

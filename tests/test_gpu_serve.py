@@ -47,12 +47,13 @@ def test_results_same_alone_and_in_mix(models, realtime):
         ref = alone(models, r)
         assert r.result.shape == ref.shape
         assert np.array_equal(r.result, ref), f"request {r.rid} ({r.kind}) differs from alone"
-    if not realtime:  # all arrived at once: energy and mutant launches were merged
-        assert srv.stats.batched["energy"] > srv.stats.launches["energy"]
-        assert srv.stats.batched["mutant"] > srv.stats.launches["mutant"]
-    # chunked sampling: 12 sweeps in chunks of 5 -> 3 launches per request
+    # chunked sampling: 12 sweeps in chunks of at most 5 -> at least 3 chunks a request
     n_sample = sum(r.kind == "sample" for r in reqs)
-    assert srv.stats.launches["sample"] == 3 * n_sample
+    assert srv.stats.batched["sample"] >= 3 * n_sample
+    if not realtime:  # all arrived at once: launches of one model were merged
+        for kind in serve.KINDS:
+            assert srv.stats.batched[kind] > srv.stats.launches[kind], kind
+        assert srv.stats.batched["sample"] == 3 * n_sample
     s = serve.summarize(reqs)
     assert s["refused"] == 0 and all(s[k]["p99_ms"] >= s[k]["p50_ms"] for k in serve.KINDS)
 
