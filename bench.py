@@ -42,10 +42,12 @@ def parse():
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-chains", type=int, default=4000,
                     help="chains in the oracle's timed sample epoch")
-    ap.add_argument("--workload", default="protein", choices=["protein", "group", "serve"],
-                    help="protein: one model at protein scale (default); group: 64 uneven "
-                         "models trained together in one captured graph per epoch; serve: "
-                         "request loop over 8 resident models at three arrival rates")
+    ap.add_argument("--workload", default="protein",
+                    choices=["protein", "precision", "group", "serve"],
+                    help="protein: one model at protein scale (default); precision: BF16 hi+lo "
+                         "vs FP32 statistics at L=256, M=1e5 and the epoch at N=2e4; group: 64 "
+                         "uneven models trained together in one captured graph per epoch; "
+                         "serve: request loop over 8 resident models at three arrival rates")
     ap.add_argument("--lanes", type=int, default=8, help="group/serve: concurrent lane streams")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
@@ -78,6 +80,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "precision":
+        return bench_precision(args)
     if args.workload == "group":
         return bench_group(args)
     if args.workload == "serve":
@@ -261,6 +265,97 @@ def main():
                                "sample": f"one epoch of the same workload with {n_s} of the "
                                          f"{N} chains ({cpu_s:.1f} s, single thread)"}
         log(f"oracle: {cpu_s:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """Precision form: the weighted two-site statistics product in BF16 hi+lo
+    against FP32 (L = 256, q = 21, M = 100 000 rows with weights in (0, 1]),
+    and the training epoch in both forms at N = 20 000 chains."""
+    import numpy as np
+    import torch
+
+    from paper_2501_18456_amd import api, synth
+    from paper_2501_18456_amd import _lib as B
+
+    torch.cuda.set_device(0)
+    L, q, M, N, sweeps, lr = 256, 21, 100000, 20000, 10, 0.05
+    Lq = L * q
+    h_true, J_true = synth.planted_dense(L, q, seed=1003, sigma_J=0.05)
+    ht, Jt = torch.from_numpy(h_true).cuda(), torch.from_numpy(J_true).cuda()
+    msa = api.init_chains(M, L, q, seed=2003)
+    api.gibbs(ht, Jt, msa, sweeps=50, seed=2003)
+    w = torch.from_numpy(synth.weights_open_unit(M, 4003)).cuda()
+    torch.cuda.synchronize()
+    log(f"precision form: L={L} q={q} M={M} (50 sweeps of a planted model), weights in (0, 1]")
+    t = Timer()
+    res, ms = {}, {}
+    for prec in ("bf16x2", "fp32"):
+        ws = api.workspace(B.WS_STATS, M, L, q, prec)
+        out = (torch.empty(Lq, dtype=torch.float64, device="cuda"),
+               torch.empty((Lq, Lq), dtype=torch.float64, device="cuda"),
+               torch.empty(1, dtype=torch.float64, device="cuda"))
+        api.stats(msa, q, w, -1.0, prec, ws=ws, out=out)
+        t.start()
+        for _ in range(args.steps):
+            api.stats(msa, q, w, -1.0, prec, ws=ws, out=out)
+        ms[prec] = t.stop_ms() / args.steps
+        res[prec] = (out[0].clone(), out[1].clone())
+        del ws, out
+        torch.cuda.empty_cache()
+    d1 = float((res["bf16x2"][0] - res["fp32"][0]).abs().max())
+    d2 = float((res["bf16x2"][1] - res["fp32"][1]).abs().max())
+    # dense MFMA work of the product: 128-wide (64 x 128 for hi+lo) tiles on or
+    # above the diagonal, K = M rows padded to 64, hi and lo products
+    Mpad = -(-M // 64) * 64
+    tiles64 = sum(-(-Lq // 128) - (ti * 64) // 128 for ti in range(-(-Lq // 64)))
+    flops_bf16 = 2.0 * 2 * Mpad * 64 * 128 * tiles64
+    tiles128 = (-(-Lq // 128)) * (-(-Lq // 128) + 1) // 2
+    flops_fp32 = 2.0 * Mpad * 128 * 128 * tiles128
+    tf_bf16 = flops_bf16 / (ms["bf16x2"] * 1e-3) / 1e12
+    tf_fp32 = flops_fp32 / (ms["fp32"] * 1e-3) / 1e12
+    log(f"stats bf16x2 {ms['bf16x2']:.2f} ms ({tf_bf16:.0f} TFLOP/s tile-level), fp32 "
+        f"{ms['fp32']:.2f} ms ({tf_fp32:.0f} TFLOP/s); max |bf16x2 - fp32| f1 {d1:.2e} f2 {d2:.2e}")
+    f1, f2 = res["bf16x2"]
+    del res
+    torch.cuda.empty_cache()
+    epoch_ms = {}
+    for prec in ("bf16x2", "fp32"):
+        h = torch.log(f1).to(torch.float32).reshape(L, q).contiguous()
+        J = torch.zeros((Lq, Lq), dtype=torch.float32, device="cuda")
+        ch = api.init_chains(N, L, q, seed=3003)
+        wst = api.workspace(B.WS_TRAIN_STEP, N, L, q, prec)
+        for ep in range(args.warmup):
+            api.train_step(h, J, ch, f1, f2, lr, sweeps, 3003, ep, prec, wst)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            api.train_step(h, J, ch, f1, f2, lr, sweeps, 3003, args.warmup + k, prec, wst)
+        torch.cuda.synchronize()
+        epoch_ms[prec] = (time.perf_counter() - t0) * 1e3 / args.steps
+        del wst
+        torch.cuda.empty_cache()
+    value = N * L * sweeps / (epoch_ms["bf16x2"] * 1e-3)
+    log(f"epoch bf16x2 {epoch_ms['bf16x2']:.1f} ms, fp32 {epoch_ms['fp32']:.1f} ms")
+    out = {
+        "metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": epoch_ms["bf16x2"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (planted dense Potts model; alignment sampled from it; "
+                "weights 1 - U[0,1))",
+        "config": {"workload": "precision form: weighted statistics at L=256, q=21, M=100000; "
+                               "epoch at N=20000", "L": L, "q": q, "msa_rows": M, "chains": N,
+                   "sweeps_per_step": sweeps},
+        "roofline": {"kernel": "bmdca_stats BF16 hi+lo (one-hot product and its epilogue)",
+                     "bound": "mfma", "achieved": tf_bf16, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tf_bf16 / 2500.0, "traffic": None,
+                     "call_ms": ms["bf16x2"], "alg_flops_per_call": flops_bf16},
+        "extras": {"stats_ms": ms, "stats_fp32_tflops": tf_fp32,
+                   "stats_fp32_frac_of_157": tf_fp32 / 157.3,
+                   "bf16x2_vs_fp32_maxabs": {"f1": d1, "f2": d2},
+                   "epoch_ms": epoch_ms, "site_updates_per_s": {
+                       p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()}},
+    }
     print(json.dumps(out), flush=True)
 
 
