@@ -43,9 +43,11 @@ def parse():
     ap.add_argument("--cpu-chains", type=int, default=4000,
                     help="chains in the oracle's timed sample epoch")
     ap.add_argument("--workload", default="protein",
-                    choices=["protein", "precision", "group", "serve"],
+                    choices=["protein", "precision", "scoring", "group", "serve"],
                     help="protein: one model at protein scale (default); precision: BF16 hi+lo "
-                         "vs FP32 statistics at L=256, M=1e5 and the epoch at N=2e4; group: 64 "
+                         "vs FP32 statistics at L=256, M=1e5 and the epoch at N=2e4; scoring: "
+                         "reweighting at M=1e5 and energies, mutant scans, contact scores of an "
+                         "L=512 model; group: 64 "
                          "uneven models trained together in one captured graph per epoch; "
                          "serve: request loop over 8 resident models at three arrival rates")
     ap.add_argument("--lanes", type=int, default=8, help="group/serve: concurrent lane streams")
@@ -82,6 +84,8 @@ def main():
         sys.exit(2)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "scoring":
+        return bench_scoring(args)
     if args.workload == "group":
         return bench_group(args)
     if args.workload == "serve":
@@ -355,6 +359,108 @@ def bench_precision(args):
                    "bf16x2_vs_fp32_maxabs": {"f1": d1, "f2": d2},
                    "epoch_ms": epoch_ms, "site_updates_per_s": {
                        p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()}},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_scoring(args):
+    """Pre-processing and scoring kernels at their largest workload sizes:
+    reweighting of M = 100 000 rows at L = 256 (integer pair counts), and for a
+    resident L = 512, q = 21 model: energies of 100 000 sequences, mutant scans
+    of 64 wild types, the APC contact map."""
+    import numpy as np
+    import torch
+
+    from paper_2501_18456_amd import api, synth
+    from paper_2501_18456_amd import _lib as B
+
+    torch.cuda.set_device(0)
+    t = Timer()
+    # ---- reweighting: L = 256, q = 21, M = 100 000 rows drawn from a planted model
+    L, q, M = 256, 21, 100000
+    h_true, J_true = synth.planted_dense(L, q, seed=1003, sigma_J=0.05)
+    msa = api.init_chains(M, L, q, seed=2003)
+    api.gibbs(torch.from_numpy(h_true).cuda(), torch.from_numpy(J_true).cuda(), msa, 50, 2003)
+    ws = api.workspace(B.WS_REWEIGHT, M, L, q, 0)
+    api.reweight(msa, q, 0.8, ws=ws)
+    t.start()
+    for _ in range(args.steps):
+        n_sim, w, meff = api.reweight(msa, q, 0.8, ws=ws)
+    rw_ms = t.stop_ms() / args.steps
+    P, W = 5, -(-L // 32)
+    # per pair: one three-input bit operation per plane word ((a ^ b) | c, the
+    # first plane a plain XOR), one popcount-accumulate per word, threshold
+    # test, count and loop step
+    ops_pair = W * P + W + 3
+    rw_ops = float(M) * M * ops_pair
+    # 32-bit VALU lane operations per second: 256 CUs x 128 lanes/clk x 2.4 GHz
+    # (the FP32 vector peak 157.3 TFLOP/s over 2 flops per FMA)
+    int_peak = 256 * 128 * 2.4e9
+    log(f"reweight M={M} L={L}: {rw_ms:.1f} ms, {M * M / (rw_ms * 1e-3):.3e} pairs/s, "
+        f"{rw_ops / (rw_ms * 1e-3) / 1e12:.2f} Tops/s ({100 * rw_ops / (rw_ms * 1e-3) / int_peak:.1f}% "
+        f"of integer VALU peak); max n_sim {int(n_sim.max())}, M_eff {float(meff.item()):.1f}")
+    del msa, ws, n_sim, w
+    torch.cuda.empty_cache()
+    # ---- scoring of a resident L = 512 model
+    L, q = 512, 21
+    Lq = L * q
+    h, J = synth.planted_dense(L, q, seed=5007, sigma_J=0.02)
+    hg, Jg = torch.from_numpy(h).cuda(), torch.from_numpy(J).cuda()
+    Bn = 100000
+    S = torch.from_numpy(synth.random_sequences(Bn, L, q, 6)).cuda()
+    wse = api.workspace(B.WS_ENERGY, Bn, L, q, 0)
+    E = torch.empty(Bn, dtype=torch.float32, device="cuda")
+    api.energy(hg, Jg, S, out=E, ws=wse)
+    t.start()
+    for _ in range(args.steps):
+        api.energy(hg, Jg, S, out=E, ws=wse)
+    en_ms = t.stop_ms() / args.steps
+    pairs = Bn * L * (L - 1) / 2
+    blocks = -(-Bn // 1024)
+    tiles = sum(min(16 * jc + 15, L - 1) for jc in range(-(-L // 16)))
+    lds_bytes = pairs * 4 + blocks * tiles * q * 16 * q * 4  # lookups + staged tiles
+    lds_peak = 256 * 128 * 2.4e9
+    log(f"energy B={Bn} L={L}: {en_ms:.2f} ms, {Bn / (en_ms * 1e-3):.3e} sequences/s, "
+        f"{pairs / (en_ms * 1e-3):.3e} pair terms/s, LDS {lds_bytes / (en_ms * 1e-3) / 1e12:.1f} TB/s")
+    del S, wse, E
+    torch.cuda.empty_cache()
+    nw = 64
+    WT = torch.from_numpy(synth.random_sequences(nw, L, q, 7)).cuda()
+    wsm = api.workspace(B.WS_MUTANT, nw, L, q, 0)
+    dE = torch.empty((nw, Lq), dtype=torch.float32, device="cuda")
+    api.single_mutant_scan(hg, Jg, WT, ws=wsm, out=dE)
+    t.start()
+    for _ in range(args.steps):
+        api.single_mutant_scan(hg, Jg, WT, ws=wsm, out=dE)
+    mu_ms = t.stop_ms() / args.steps
+    mu_bytes = nw * (L * Lq * 4 + 2 * Lq * 4)  # L coupling rows per wild type, fields, output
+    log(f"mutant scans {nw} wild types L={L}: {mu_ms:.2f} ms, {mu_bytes / (mu_ms * 1e-3) / 1e9:.0f} GB/s")
+    t.start()
+    for _ in range(args.steps):
+        F, Fa = api.apc_frobenius(Jg, L, q, 0)
+    apc_ms = t.stop_ms() / args.steps
+    apc_bytes = Lq * Lq * 4
+    log(f"APC Frobenius L={L}: {apc_ms:.2f} ms, {apc_bytes / (apc_ms * 1e-3) / 1e9:.0f} GB/s")
+    out = {
+        "metric": METRIC, "value": Bn / (en_ms * 1e-3), "unit": "sequences/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": en_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (planted models; uniform random sequences)",
+        "config": {"workload": "scoring of an L=512, q=21 model (energies of 100000 sequences, "
+                               "64 mutant scans, APC) and reweighting of 100000 rows at L=256"},
+        "roofline": {"kernel": "k_energy_pairs (energies)", "bound": "lds",
+                     "achieved": lds_bytes / (en_ms * 1e-3) / 1e9, "peak": lds_peak / 1e9,
+                     "unit": "GB/s", "frac": lds_bytes / (en_ms * 1e-3) / lds_peak,
+                     "traffic": None, "call_ms": en_ms, "alg_bytes_per_call": lds_bytes},
+        "extras": {
+            "reweight": {"ms": rw_ms, "pairs_per_s": M * M / (rw_ms * 1e-3),
+                         "int_ops_per_s": rw_ops / (rw_ms * 1e-3),
+                         "alu_frac": rw_ops / (rw_ms * 1e-3) / int_peak, "M": M, "L": 256},
+            "mutant_scan": {"ms": mu_ms, "wild_types": nw, "GBps": mu_bytes / (mu_ms * 1e-3) / 1e9,
+                            "hbm_frac": mu_bytes / (mu_ms * 1e-3) / 8e12},
+            "apc": {"ms": apc_ms, "GBps": apc_bytes / (apc_ms * 1e-3) / 1e9,
+                    "hbm_frac": apc_bytes / (apc_ms * 1e-3) / 8e12},
+        },
     }
     print(json.dumps(out), flush=True)
 

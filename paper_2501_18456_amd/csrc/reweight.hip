@@ -6,9 +6,9 @@
 // differ at a position iff some plane differs there, so
 //   mismatches = sum_w popcount(OR_p (plane_p[m][w] XOR plane_p[n][w]))
 // and identical positions = L - mismatches (padding bits are 0 in both rows).
-// A thread owns one row m and keeps its planes in registers; a workgroup
-// stages 256 rows n at a time in LDS and every lane reads the same n
-// (broadcast).  Counts are exact integers.
+// A thread owns one or two rows m and keeps their planes in registers; a
+// workgroup stages 256 rows n at a time in LDS and every lane reads the same
+// n (broadcast).  Counts are exact integers.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -16,6 +16,11 @@ namespace bmdca {
 
 constexpr int kRwThreads = 256;
 constexpr int kMaxPlanes = 5;  // q <= 32
+// Truth table of (a ^ b) | c for v_bitop3_b32(a, b, c): bit (4a + 2b + c).
+#ifndef BMDCA_XOR_OR_TABLE
+#define BMDCA_XOR_OR_TABLE 0xBE
+#endif
+constexpr unsigned kXorOr = BMDCA_XOR_OR_TABLE;
 
 static int planes_for(int q) {
   int p = 0;
@@ -55,43 +60,74 @@ __global__ void k_encode_planes(const int8_t* __restrict__ msa, int64_t M, int L
   for (int p = 0; p < P; ++p) planes[((size_t)m * kMaxPlanes + p) * W + w] = bits[p];
 }
 
-template <int W>
+// Pair counts.  Grid (row blocks, column splits): a workgroup compares its
+// 256*R rows (R per thread, planes in registers) with one contiguous range
+// of columns, staged 256 rows at a time in LDS (every lane reads the same
+// column: broadcast), and adds its counts to n_sim with integer atomics
+// (exact in any order).
+template <int P, int W, int R>
 __global__ __launch_bounds__(kRwThreads) void k_count_similar(const uint32_t* __restrict__ planes,
-                                                              int64_t M, int P, int L, int T,
+                                                              int64_t M, int L, int T,
+                                                              int64_t cols_per_split,
                                                               int32_t* __restrict__ n_sim) {
-  __shared__ uint32_t sh[kRwThreads * kMaxPlanes * W];
-  const int64_t m = (int64_t)blockIdx.x * kRwThreads + threadIdx.x;
-  uint32_t mine[kMaxPlanes][W];
+  __shared__ uint32_t sh[kRwThreads * P * W];
+  const int64_t m0 = (int64_t)blockIdx.x * kRwThreads * R + threadIdx.x;
+  uint32_t mine[R][P][W];
 #pragma unroll
-  for (int p = 0; p < kMaxPlanes; ++p)
+  for (int r = 0; r < R; ++r) {
+    const int64_t m = m0 + (int64_t)kRwThreads * r;
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-      mine[p][w] = (m < M && p < P) ? planes[((size_t)m * kMaxPlanes + p) * W + w] : 0u;
-  int count = 0;
-  for (int64_t n0 = 0; n0 < M; n0 += kRwThreads) {
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        mine[r][p][w] = (m < M) ? planes[((size_t)m * kMaxPlanes + p) * W + w] : 0u;
+  }
+  int count[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) count[r] = 0;
+  const int64_t c0 = (int64_t)blockIdx.y * cols_per_split;
+  const int64_t c1 = std::min<int64_t>(c0 + cols_per_split, M);
+  for (int64_t n0 = c0; n0 < c1; n0 += kRwThreads) {
     __syncthreads();
-    const int64_t nload = std::min<int64_t>(kRwThreads, M - n0);
-    for (int k = threadIdx.x; k < kRwThreads * kMaxPlanes * W; k += kRwThreads) {
-      const int nl = k / (kMaxPlanes * W);
-      sh[k] = (nl < nload) ? planes[(size_t)(n0 + nl) * kMaxPlanes * W + (k % (kMaxPlanes * W))]
-                           : 0u;
+    const int nload = (int)std::min<int64_t>(kRwThreads, c1 - n0);
+    for (int k = threadIdx.x; k < nload * P * W; k += kRwThreads) {
+      const int nl = k / (P * W), pw = k % (P * W);
+      sh[k] = planes[(size_t)(n0 + nl) * kMaxPlanes * W + pw];
     }
     __syncthreads();
     for (int nl = 0; nl < nload; ++nl) {
-      const uint32_t* o = sh + nl * kMaxPlanes * W;
-      int mism = 0;
+      const uint32_t* o = sh + nl * P * W;
+      int mism[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) mism[r] = 0;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        uint32_t d = 0;
+        uint32_t ow[P];
 #pragma unroll
-        for (int p = 0; p < kMaxPlanes; ++p)
-          if (p < P) d |= mine[p][w] ^ o[p * W + w];
-        mism += __popc(d);
+        for (int p = 0; p < P; ++p) ow[p] = o[p * W + w];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          // d = OR_p (mine_p ^ other_p), one three-input bit operation per plane
+          uint32_t d = mine[r][0][w] ^ ow[0];
+#pragma unroll
+          for (int p = 1; p < P; ++p) d = __builtin_amdgcn_bitop3_b32(mine[r][p][w], ow[p], d, kXorOr);
+          mism[r] += __popc(d);
+        }
       }
-      count += (L - mism >= T) ? 1 : 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) count[r] += (L - mism[r] >= T) ? 1 : 0;
     }
   }
-  if (m < M) n_sim[m] = count;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t m = m0 + (int64_t)kRwThreads * r;
+    if (m < M && count[r] > 0) atomicAdd(n_sim + m, count[r]);
+  }
+}
+
+__global__ void k_zero_counts(int32_t* __restrict__ n, int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) n[i] = 0;
 }
 
 __global__ __launch_bounds__(1024) void k_weights_meff(const int32_t* __restrict__ n_sim,
@@ -108,11 +144,31 @@ __global__ __launch_bounds__(1024) void k_weights_meff(const int32_t* __restrict
   if (threadIdx.x == 0) *meff = t;
 }
 
+template <int P, int W>
+static void launch_count_pw(const uint32_t* planes, int64_t M, int L, int T, int32_t* n_sim,
+                            hipStream_t s) {
+  // two rows per thread while the planes fit comfortably in registers
+  constexpr int R = (P * W <= 40) ? 2 : 1;
+  const int64_t rowblocks = ceil_div(M, (int64_t)kRwThreads * R);
+  // column splits: about 2048 workgroups in all, every split >= 256 columns
+  const int64_t colblocks = ceil_div(M, (int64_t)kRwThreads);
+  const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(colblocks, ceil_div(2048, rowblocks)));
+  const int64_t per = ceil_div(colblocks, splits) * kRwThreads;
+  const int64_t used = ceil_div(M, per);
+  hipLaunchKernelGGL((k_count_similar<P, W, R>), dim3((unsigned)rowblocks, (unsigned)used),
+                     dim3(kRwThreads), 0, s, planes, M, L, T, per, n_sim);
+}
+
 template <int W>
 static void launch_count_w(const uint32_t* planes, int64_t M, int P, int L, int T, int32_t* n_sim,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_count_similar<W>, dim3((unsigned)ceil_div(M, kRwThreads)),
-                     dim3(kRwThreads), 0, s, planes, M, P, L, T, n_sim);
+  switch (P) {
+    case 1: launch_count_pw<1, W>(planes, M, L, T, n_sim, s); break;
+    case 2: launch_count_pw<2, W>(planes, M, L, T, n_sim, s); break;
+    case 3: launch_count_pw<3, W>(planes, M, L, T, n_sim, s); break;
+    case 4: launch_count_pw<4, W>(planes, M, L, T, n_sim, s); break;
+    default: launch_count_pw<5, W>(planes, M, L, T, n_sim, s); break;
+  }
 }
 
 hipError_t launch_reweight(const int8_t* msa, int64_t M, int L, int q, int32_t T,
@@ -123,6 +179,7 @@ hipError_t launch_reweight(const int8_t* msa, int64_t M, int L, int q, int32_t T
   // Unused planes (p >= P) are never read; padding bits are written as 0.
   hipLaunchKernelGGL(k_encode_planes, dim3((unsigned)ceil_div(M * W, 256)), dim3(256), 0, s, msa,
                      M, L, q, P, W, planes, dev_err);
+  hipLaunchKernelGGL(k_zero_counts, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s, n_sim, M);
   switch (W) {
 #define BMDCA_RW_CASE(n) \
   case n:                \
