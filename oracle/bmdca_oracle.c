@@ -595,3 +595,63 @@ void orc_stats_entries(const int8_t* X, const double* w, int64_t M, int32_t L,
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Equilibrium sampling of a trained model (Sec. 4.1, sampling and its       */
+/* convergence criterion): chains start from data sequences drawn according  */
+/* to their weights and are compared with a permuted copy of themselves      */
+/* (SeqID(t)) and with themselves at time t/2 (SeqID(t, t/2)).               */
+/* ------------------------------------------------------------------------ */
+
+/* Weighted draw with replacement of n row indices, row m with probability
+ * w_m / W.  With the prefix sums C_m = w_0 + ... + w_m (ascending m) and
+ * W = C_{M-1}, draw k takes u from counter (k/4, 0, 0, 2), word k%4,
+ * u = (word >> 8) 2^-24, and returns the first m with C_m > u W.  When
+ * margins != NULL, margins[k] = distance from u W to the nearest C_m. */
+void orc_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed,
+                   int32_t* rows, double* margins)
+{
+    double* C = (double*)malloc(sizeof(double) * (size_t)M);
+    double run = 0.0;
+    for (int64_t m = 0; m < M; ++m) {
+        run += w[m];
+        C[m] = run;
+    }
+    const double W = C[M - 1];
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t word = philox_word(seed, (uint32_t)(k >> 2), 0u, 0u, 2u, (int)(k & 3));
+        const double t = (double)(word >> 8) * (1.0 / 16777216.0) * W;
+        int64_t m = 0;
+        while (C[m] <= t) ++m;
+        rows[k] = (int32_t)m;
+        if (margins) {
+            double d = C[m] - t;
+            if (m > 0 && t - C[m - 1] < d) d = t - C[m - 1];
+            margins[k] = d;
+        }
+    }
+    free(C);
+}
+
+/* SeqID(a, b) = (1/L) sum_i [a_i == b_i], the normalised overlap.  Over the
+ * N pairs (A[k], B[perm[k]]) (B[k] when perm is NULL): out[0] = the mean
+ * SeqID, out[1] = its standard deviation over the pairs, both from the exact
+ * integer sums S1 = sum_k n_k and S2 = sum_k n_k^2 of the identity counts
+ * n_k: mean = S1 / (N L), var = S2 / (N L^2) - mean^2 (0 if negative). */
+void orc_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, int64_t N,
+               int32_t L, double* out)
+{
+    int64_t S1 = 0, S2 = 0;
+    for (int64_t k = 0; k < N; ++k) {
+        const int8_t* b = B + (int64_t)(perm ? perm[k] : k) * L;
+        int64_t same = 0;
+        for (int32_t i = 0; i < L; ++i) same += (A[k * L + i] == b[i]);
+        S1 += same;
+        S2 += same * same;
+    }
+    const double mean = (double)S1 / ((double)N * (double)L);
+    const double m2 = (double)S2 / ((double)N * (double)L * (double)L);
+    const double var = m2 - mean * mean;
+    out[0] = mean;
+    out[1] = sqrt(var > 0.0 ? var : 0.0);
+}

@@ -72,6 +72,8 @@ def _declare(L):
         "orc_enumerate": (C.c_int, [_p, _p, _i32, _i32, _f64, _p, _p, _p]),
         "orc_reweight_rows": (None, [_p, _i64, _i32, _f64, _p, _i64, _p]),
         "orc_stats_entries": (None, [_p, _p, _i64, _i32, _i32, _f64, _p, _p, _i64, _p]),
+        "orc_draw_rows": (None, [_p, _i64, _i64, _u64, _p, _p]),
+        "orc_seqid": (None, [_p, _p, _p, _i64, _i32, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -281,3 +283,52 @@ def enumerate_exact(h, J, L: int, q: int, beta: float = 1.0):
     if rc != 0:
         raise ValueError("q^L too large for enumeration")
     return p1, p2, float(lz[0])
+
+
+# --------------------------------------------------------------------------
+# Equilibrium sampling and its convergence criterion (Sec. 4.1)
+# --------------------------------------------------------------------------
+def draw_rows(w, n: int, seed: int, want_margins: bool = False):
+    """n row indices drawn with replacement, row m with probability w_m / sum w."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    rows = np.zeros(n, dtype=np.int32)
+    mg = np.zeros(n, dtype=np.float64) if want_margins else None
+    lib().orc_draw_rows(_ptr(w), w.size, n, seed, _ptr(rows), _ptr(mg))
+    return (rows, mg) if want_margins else rows
+
+
+def seqid(A, B, perm=None):
+    """(mean, std) of SeqID(A[k], B[perm[k]]) over the rows k."""
+    A, B = _i8(A), _i8(B)
+    out = np.zeros(2, dtype=np.float64)
+    pr = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    lib().orc_seqid(_ptr(A), _ptr(B), _ptr(pr), A.shape[0], A.shape[1], _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def mixing_time(h, J, msa, w, q: int, nmeasure: int, seed: int, perm, max_sweeps: int = 10000,
+                beta: float = 1.0):
+    """Mixing time of Sec. 4.1: nmeasure chains start from data rows drawn by
+    weight; at t = 0, 1, 2, 4, ... sweeps SeqID(t) (chains vs the permuted
+    chains) and SeqID(t, t/2) (chains vs the previous checkpoint) are
+    recorded; t_mix is the first t where the two means are within the sum of
+    their errors of the mean.  Returns (t_mix or None, records [(t, mean1,
+    std1, mean2, std2)], chains)."""
+    n = int(nmeasure)
+    rows = draw_rows(w, n, seed)
+    A = _i8(msa)[rows].copy()
+    prev = A.copy()
+    m1, s1 = seqid(A, A, perm)
+    records = [(0, m1, s1, 1.0, 0.0)]
+    t_prev, t = 0, 1
+    while t <= max_sweeps:
+        A = gibbs(h, J, A, q, t - t_prev, seed, sweep_offset=t_prev, beta=beta)[0]
+        m1, s1 = seqid(A, A, perm)
+        m2, s2 = seqid(A, prev)
+        records.append((t, m1, s1, m2, s2))
+        if abs(m2 - m1) <= (s1 + s2) / np.sqrt(n):
+            return t, records, A
+        prev = A.copy()
+        t_prev, t = t, 2 * t
+    return None, records, A
+

@@ -458,3 +458,98 @@ def test_sampled_entry_forms_agree_with_full_tables():
     n, _, _ = O.reweight(X, 0.8)
     rows = np.array([0, 7, 100, 249])
     assert np.array_equal(O.reweight_rows(X, rows, 0.8), n[rows])
+
+
+# ------------------------------------------- equilibrium sampling (Sec. 4.1)
+def _philox_uniform(seed, ctr):
+    """u = (word >> 8) 2^-24 of one Philox word (generator pinned by the KATs)."""
+    k, word = ctr
+    out = O.philox4x32_10([k >> 2, 0, 0, 2], [seed & 0xFFFFFFFF, seed >> 32])
+    return float(int(out[word]) >> 8) / 16777216.0
+
+
+def test_draw_rows_pins():
+    seed = 0x1234_5678_9ABC
+    # integer weights: prefix sums exact, the draw is floor(u * M)
+    M, n = 1000, 300
+    rows = O.draw_rows(np.ones(M), n, seed)
+    ref = [int(np.floor(_philox_uniform(seed, (k, k & 3)) * M)) for k in range(n)]
+    assert rows.tolist() == ref
+    # all mass on one row; zero-weight rows never drawn
+    w = np.zeros(40)
+    w[7] = 2.5
+    assert set(O.draw_rows(w, 500, 9).tolist()) == {7}
+    assert set(O.draw_rows(np.array([0.0, 1.0, 0.0, 3.0, 0.0]), 2000, 10).tolist()) == {1, 3}
+    # frequencies follow w / sum(w)
+    g = np.random.default_rng(11)
+    w = 1.0 - g.random(20)
+    n = 200000
+    cnt = np.bincount(O.draw_rows(w, n, 12), minlength=20)
+    p = w / w.sum()
+    assert np.all(np.abs(cnt - n * p) <= 5 * np.sqrt(n * p * (1 - p)))
+
+
+def test_seqid_pins():
+    g = np.random.default_rng(13)
+    N, L, q = 300, 37, 21
+    A = g.integers(0, q, size=(N, L)).astype(np.int8)
+    assert O.seqid(A, A) == (1.0, 0.0)
+    # B differs from A at exactly d_k positions of row k: identity counts L - d_k
+    d = g.integers(0, L + 1, size=N)
+    B = A.copy()
+    for k in range(N):
+        pos = g.choice(L, size=d[k], replace=False)
+        B[k, pos] = (B[k, pos] + g.integers(1, q, size=d[k])) % q
+    x = (L - d) / L
+    m, s = O.seqid(A, B)
+    assert abs(m - x.mean()) <= 1e-15 and abs(s - x.std()) <= 1e-12
+    # with a permutation: pairs (A[k], B[perm[k]])
+    perm = g.permutation(N).astype(np.int32)
+    m, s = O.seqid(A, A, perm)
+    xs = (A == A[perm]).mean(axis=1)
+    assert abs(m - xs.mean()) <= 1e-15 and abs(s - xs.std()) <= 1e-12
+    # independent uniform sequences: overlap 1/q
+    assert abs(m - 1.0 / q) <= 5 * np.sqrt((1 / q) * (1 - 1 / q) / (N * L))
+
+
+def test_mixing_time_pins():
+    g = np.random.default_rng(14)
+    L, q, N = 12, 5, 3000
+    perm = np.roll(np.arange(N), N // 2).astype(np.int32)
+    # data: strongly redundant rows, so that SeqID starts well above 1/q
+    base = g.integers(0, q, size=(4, L)).astype(np.int8)
+    msa = base[g.integers(0, 4, size=500)]
+    w = np.ones(500)
+    # beta = 0: one sweep resamples every site uniformly, independently of the past
+    h, J = synth.planted_dense(L, q, seed=15, sigma_J=0.5)
+    t, rec, _ = O.mixing_time(h, J, msa, w, q, N, 16, perm, max_sweeps=64, beta=0.0)
+    assert rec[0][0] == 0 and rec[0][3] == 1.0 and rec[0][1] > 0.3  # SeqID(0, 0) = 1
+    # mixed after the first sweep; the merge test itself fluctuates at the level
+    # of the errors of the mean, so it may fire one checkpoint later
+    assert t in (1, 2)
+    err = 5 * np.sqrt((1 / q) * (1 - 1 / q) / (N * L))
+    assert abs(rec[1][1] - 1 / q) <= err and abs(rec[1][3] - 1 / q) <= err
+    # independent sites (J = 0): one sweep draws every site from its marginal
+    # p_i(a) ~ exp(h_i(a)), independently of the past.  After one sweep two
+    # chains overlap by c = (1/L) sum_i sum_a p_i(a)^2 (SeqID(1)) and a chain
+    # overlaps its data start by (1/L) sum_i p_i(start_i) (SeqID(1, 0)); from
+    # the second sweep on both overlaps are c, so the curves merge at t = 2.
+    t, rec, _ = O.mixing_time(h, np.zeros_like(J), msa, w, q, N, 17, perm, max_sweeps=64)
+    p = np.exp(h.reshape(L, q).astype(np.float64))
+    p /= p.sum(axis=1, keepdims=True)
+    c = float((p ** 2).sum(axis=1).mean())
+    start = msa[O.draw_rows(w, N, 17)]
+    c0 = float(p[np.arange(L)[None, :], start].mean())
+    tol = 5 * np.sqrt(c * (1 - c) / (N * L))
+    assert abs(rec[1][1] - c) <= tol and abs(rec[1][3] - c0) <= tol
+    assert abs(rec[2][1] - c) <= tol and abs(rec[2][3] - c) <= tol
+    assert t in (2, 4)
+    # strong ferromagnetic couplings (J_ij(a, a) = 1.2): memory of the start lasts
+    Jf = np.zeros_like(J)
+    for i in range(L):
+        for j in range(L):
+            if i != j:
+                for a in range(q):
+                    Jf[i * q + a, j * q + a] = 1.2
+    t, rec, _ = O.mixing_time(np.zeros_like(h), Jf, msa, w, q, N, 18, perm, max_sweeps=64)
+    assert t is None or t >= 4
