@@ -84,6 +84,7 @@ typedef enum {
 /* Bits OR-ed into *dev_err. */
 #define BMDCA_DEVERR_TOKEN 1
 #define BMDCA_DEVERR_NONFINITE 2
+#define BMDCA_DEVERR_INDEX 4 /* a row index or permutation entry out of range */
 
 /* Workspace kinds for bmdca_workspace_bytes. */
 typedef enum {
@@ -93,7 +94,9 @@ typedef enum {
     BMDCA_WS_TRAIN_STEP = 3, /* MN = N */
     BMDCA_WS_APC = 4,        /* MN ignored */
     BMDCA_WS_MUTANT = 5,     /* MN = B (wild types) */
-    BMDCA_WS_ENERGY = 6      /* MN = B (sequences) */
+    BMDCA_WS_ENERGY = 6,     /* MN = B (sequences) */
+    BMDCA_WS_DRAW = 7,       /* MN = M (weights); L, q ignored but must be valid */
+    BMDCA_WS_SEQID = 8       /* MN ignored */
 } bmdca_ws_kind;
 
 /* Bytes of device scratch memory the call `kind` needs for these sizes
@@ -339,6 +342,45 @@ int bmdca_single_mutant_scan(const float* h, const float* J, const int8_t* wt,
 int bmdca_apc_frobenius(const float* J, int32_t L, int32_t q, int32_t gap,
                         float* F, float* F_apc, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* ---- Equilibrium sampling (Sec. 4.1: sampling from a trained model) ----
+ *
+ * The sampling routine first measures the mixing time: chains start from
+ * data sequences drawn according to their weights, and the overlap
+ * SeqID(a, b) = (1/L) sum_i [a_i == b_i] is averaged over chain pairs, once
+ * against a permutation of the chains (SeqID(t)) and once against the same
+ * chains at time t/2 (SeqID(t, t/2)); the mixing time is where the two
+ * curves meet.  These calls are its building blocks (with bmdca_gibbs). */
+
+/* n row indices drawn with replacement, row m with probability w_m / W,
+ * W = sum of w: with C_m = w_0 + ... + w_m (ascending m), draw k takes the
+ * uniform u of Philox counter (k/4, 0, 0, 2), word k%4, u = (word >> 8) 2^-24,
+ * key = seed, and returns the first m with C_m > u W.
+ * w       double [M] >= 0 (device); rows int32 [n] out
+ * ws      scratch, bmdca_workspace_bytes(BMDCA_WS_DRAW, M, 1, 2, 0)
+ * dev_err optional; BMDCA_DEVERR_NONFINITE if W is not positive and finite
+ *         (every row is then 0). */
+int bmdca_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed,
+                    int32_t* rows, void* ws, size_t ws_bytes, int32_t* dev_err,
+                    void* stream);
+
+/* out[k][.] = X[rows[k]][.] for k < n (int8 rows of length L).
+ * dev_err optional; BMDCA_DEVERR_INDEX for an index outside 0..M-1 (row 0
+ * is copied instead). */
+int bmdca_gather_rows(const int8_t* X, int64_t M, int32_t L,
+                      const int32_t* rows, int64_t n, int8_t* out,
+                      int32_t* dev_err, void* stream);
+
+/* Mean and standard deviation of SeqID(A[k], B[perm[k]]) over k < N (B[k]
+ * when perm is NULL), from the exact integer sums S1, S2 of the identity
+ * counts: out[0] = S1 / (N L), out[1] = sqrt(S2 / (N L^2) - out[0]^2).
+ * A, B int8 [N][L]; perm int32 [N] (device, may be NULL); out double [2].
+ * ws      scratch, bmdca_workspace_bytes(BMDCA_WS_SEQID, 0, L, 2, 0)
+ * dev_err optional; BMDCA_DEVERR_INDEX for a perm entry outside 0..N-1
+ *         (that pair is skipped). */
+int bmdca_seqid(const int8_t* A, const int8_t* B, const int32_t* perm,
+                int64_t N, int32_t L, double* out, void* ws, size_t ws_bytes,
+                int32_t* dev_err, void* stream);
 
 #ifdef __cplusplus
 }

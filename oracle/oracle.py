@@ -314,7 +314,7 @@ def mixing_time(h, J, msa, w, q: int, nmeasure: int, seed: int, perm, max_sweeps
     recorded; t_mix is the first t where the two means are within the sum of
     their errors of the mean.  Returns (t_mix or None, records [(t, mean1,
     std1, mean2, std2)], chains)."""
-    n = int(nmeasure)
+    n = int(min(nmeasure, np.shape(msa)[0]))  # min(nmeasure, data size), as the paper's table states
     rows = draw_rows(w, n, seed)
     A = _i8(msa)[rows].copy()
     prev = A.copy()

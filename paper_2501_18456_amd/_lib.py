@@ -14,10 +14,11 @@ LIB_PATH = os.path.join(HERE, "libbmdca.so")
 # status codes (bmdca_status)
 OK, EINVAL, ETOKEN, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_BF16X2 = 0, 1
-DEVERR_TOKEN, DEVERR_NONFINITE = 1, 2
+DEVERR_TOKEN, DEVERR_NONFINITE, DEVERR_INDEX = 1, 2, 4
 SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS = 0x10, 0x20, 0x40
 SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER}
-WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY = range(7)
+(WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY, WS_DRAW,
+ WS_SEQID) = range(9)
 
 _p, _i32, _i64, _u64, _f64, _f32, _sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,
                                           C.c_double, C.c_float, C.c_size_t)
@@ -62,6 +63,9 @@ SIGNATURES = {
                                    _i32, _p, _p, _p, _sz, _p, _p]),
     "bmdca_single_mutant_scan": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p]),
     "bmdca_apc_frobenius": (C.c_int, [_p, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "bmdca_draw_rows": (C.c_int, [_p, _i64, _i64, _u64, _p, _p, _sz, _p, _p]),
+    "bmdca_gather_rows": (C.c_int, [_p, _i64, _i32, _p, _i64, _p, _p, _p]),
+    "bmdca_seqid": (C.c_int, [_p, _p, _p, _i64, _i32, _p, _p, _sz, _p, _p]),
     "bmdca_train_group_step": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p]),
     "bmdca_train_group_graph": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p,
                                           C.POINTER(_p)]),

@@ -205,6 +205,50 @@ def train_step(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: i
     return pearson
 
 
+# ------------------------------------------------------- equilibrium sampling
+def draw_rows(w, n: int, seed: int, dev_err=None, ws=None):
+    """n row indices drawn with probability w / sum(w) (int32 device tensor)."""
+    _dev(w, torch.float64, "w", 1)
+    M = w.numel()
+    rows = torch.empty(n, dtype=torch.int32, device=w.device)
+    if ws is None:
+        ws = workspace(B.WS_DRAW, M, 1, 2, 0, w.device)
+    check(B.lib().bmdca_draw_rows(_ptr(w), M, n, seed, _ptr(rows), _ptr(ws), _nbytes(ws),
+                                  _ptr(dev_err), _stream()))
+    return rows
+
+
+def gather_rows(X, rows, dev_err=None):
+    """X[rows] for an int8 [M, L] tensor and int32 row indices."""
+    _dev(X, torch.int8, "X", 2)
+    _dev(rows, torch.int32, "rows", 1)
+    M, L = X.shape
+    out = torch.empty((rows.numel(), L), dtype=torch.int8, device=X.device)
+    check(B.lib().bmdca_gather_rows(_ptr(X), M, L, _ptr(rows), rows.numel(), _ptr(out),
+                                    _ptr(dev_err), _stream()))
+    return out
+
+
+def seqid(A, Bm, perm=None, dev_err=None, ws=None, out=None):
+    """Device double [2]: mean and standard deviation of SeqID(A[k], B[perm[k]])."""
+    _dev(A, torch.int8, "A", 2)
+    _dev(Bm, torch.int8, "B", 2)
+    if A.shape != Bm.shape:
+        raise ValueError("A and B must have the same shape")
+    if perm is not None:
+        _dev(perm, torch.int32, "perm", 1)
+        if perm.numel() != A.shape[0]:
+            raise ValueError("perm must have one entry per row")
+    N, L = A.shape
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = workspace(B.WS_SEQID, 0, L, 2, 0, A.device)
+    check(B.lib().bmdca_seqid(_ptr(A), _ptr(Bm), _ptr(perm), N, L, _ptr(out), _ptr(ws),
+                              _nbytes(ws), _ptr(dev_err), _stream()))
+    return out
+
+
 # ------------------------------------------------------------ grouped training
 def train_ctl(device, target_pearson: float = 0.0, epoch: int = 0, active: bool = True):
     """A device control record (bmdca_train_ctl) as a uint8 tensor of its 24 bytes."""

@@ -329,6 +329,11 @@ size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q, int
     case BMDCA_WS_ENERGY:
       if (MN < 0) return 0;
       return plan_energy(MN, L, q).total;
+    case BMDCA_WS_DRAW:
+      if (MN < 1) return 0;
+      return draw_ws_bytes(MN);
+    case BMDCA_WS_SEQID:
+      return seqid_ws_bytes();
     default:
       return 0;
   }
@@ -411,6 +416,38 @@ int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, 
     return fail(BMDCA_EWORKSPACE, "energy workspace %zu < %zu bytes", ws_bytes, plan.total);
   return hip_status(launch_energy(h, J, seqs, B, L, q, E, plan, ws, dev_err, (hipStream_t)stream),
                     "energy");
+}
+
+int bmdca_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed, int32_t* rows,
+                    void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_REQUIRE(M >= 1 && M < ((int64_t)1 << 31), "M=%lld outside 1..2^31-1", (long long)M);
+  BMDCA_REQUIRE(n >= 0 && n < ((int64_t)1 << 34), "n=%lld outside 0..2^34-1", (long long)n);
+  BMDCA_REQUIRE(w && ws && (rows || n == 0), "null pointer argument");
+  if (ws_bytes < draw_ws_bytes(M))
+    return fail(BMDCA_EWORKSPACE, "draw workspace %zu < %zu bytes", ws_bytes, draw_ws_bytes(M));
+  return hip_status(launch_draw_rows(w, M, n, seed, rows, ws, dev_err, (hipStream_t)stream),
+                    "draw_rows");
+}
+
+int bmdca_gather_rows(const int8_t* X, int64_t M, int32_t L, const int32_t* rows, int64_t n,
+                      int8_t* out, int32_t* dev_err, void* stream) {
+  BMDCA_REQUIRE(M >= 1 && L >= 1 && L <= kMaxL, "M=%lld, L=%d invalid", (long long)M, L);
+  BMDCA_REQUIRE(n >= 0 && n * (int64_t)L < ((int64_t)1 << 40), "n=%lld invalid", (long long)n);
+  if (n == 0) return BMDCA_OK;
+  BMDCA_REQUIRE(X && rows && out, "null pointer argument");
+  return hip_status(launch_gather_rows(X, M, L, rows, n, out, dev_err, (hipStream_t)stream),
+                    "gather_rows");
+}
+
+int bmdca_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, int64_t N, int32_t L,
+                double* out, void* ws, size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 31), "N=%lld outside 1..2^31-1", (long long)N);
+  BMDCA_REQUIRE(L >= 1 && L <= kMaxL, "L=%d outside 1..%d", L, kMaxL);
+  BMDCA_REQUIRE(A && B && out && ws, "null pointer argument");
+  if (ws_bytes < seqid_ws_bytes())
+    return fail(BMDCA_EWORKSPACE, "seqid workspace %zu < %zu bytes", ws_bytes, seqid_ws_bytes());
+  return hip_status(launch_seqid(A, B, perm, N, L, out, ws, dev_err, (hipStream_t)stream),
+                    "seqid");
 }
 
 int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,

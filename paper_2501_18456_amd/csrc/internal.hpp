@@ -120,4 +120,14 @@ size_t apc_ws_bytes(int L);
 hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fapc, void* ws,
                       hipStream_t s);
 
+// ----- equilibrium.hip
+size_t draw_ws_bytes(int64_t M);
+size_t seqid_ws_bytes();
+hipError_t launch_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed, int32_t* rows,
+                            void* ws, int32_t* dev_err, hipStream_t s);
+hipError_t launch_gather_rows(const int8_t* X, int64_t M, int L, const int32_t* rows, int64_t n,
+                              int8_t* out, int32_t* dev_err, hipStream_t s);
+hipError_t launch_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, int64_t N, int L,
+                        double* out, void* ws, int32_t* dev_err, hipStream_t s);
+
 }  // namespace bmdca

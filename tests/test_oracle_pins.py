@@ -518,8 +518,8 @@ def test_mixing_time_pins():
     perm = np.roll(np.arange(N), N // 2).astype(np.int32)
     # data: strongly redundant rows, so that SeqID starts well above 1/q
     base = g.integers(0, q, size=(4, L)).astype(np.int8)
-    msa = base[g.integers(0, 4, size=500)]
-    w = np.ones(500)
+    msa = base[g.integers(0, 4, size=4000)]
+    w = np.ones(4000)
     # beta = 0: one sweep resamples every site uniformly, independently of the past
     h, J = synth.planted_dense(L, q, seed=15, sigma_J=0.5)
     t, rec, _ = O.mixing_time(h, J, msa, w, q, N, 16, perm, max_sweeps=64, beta=0.0)
