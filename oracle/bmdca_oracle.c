@@ -655,3 +655,53 @@ void orc_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, int64_t N,
     out[0] = mean;
     out[1] = sqrt(var > 0.0 ? var : 0.0);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Metropolis-Hastings sampling (Sec. 2.1 names it beside Gibbs; the          */
+/* sampler options of the training and sampling tables).  The paper does not */
+/* write the acceptance rule; this is textbook single-site Metropolis with a  */
+/* uniform proposal among the other q-1 states: at site i (order 0..L-1) in   */
+/* state a, propose a' uniformly from the q-1 states != a and accept with     */
+/* probability min(1, exp(beta (H_i(a') - H_i(a)))), which is the ratio       */
+/* P(s')/P(s) of Eq. (1) for a single-site change.  Random words: Philox      */
+/* counter (i/2, global sweep, chain, 3), words 2(i%2) (proposal) and         */
+/* 2(i%2)+1 (acceptance); a' = (a + 1 + ((word * (q-1)) >> 32)) mod q,        */
+/* u = (word >> 8) 2^-24, accept iff u < exp(beta (H_i(a') - H_i(a))).  The   */
+/* margin of a visit is |u - min(1, exp(beta (H_i(a') - H_i(a))))|.           */
+/* ------------------------------------------------------------------------ */
+void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_t N,
+                          int64_t c0, int32_t L, int32_t q, int32_t sweeps,
+                          uint64_t seed, uint64_t sweep_offset, double beta,
+                          double* margins, int64_t* flips)
+{
+    double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
+    int64_t nflip = 0;
+    for (int64_t c = 0; c < N; ++c) {
+        int8_t* s = chains + c * L;
+        for (int32_t sw = 0; sw < sweeps; ++sw) {
+            uint64_t sg = sweep_offset + (uint64_t)sw;
+            for (int32_t i = 0; i < L; ++i) {
+                orc_local_field(h, J, s, L, q, i, Hi);
+                const uint32_t wp = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg,
+                                                (uint32_t)(c0 + c), 3u, 2 * (i & 1));
+                const uint32_t wa = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg,
+                                                (uint32_t)(c0 + c), 3u, 2 * (i & 1) + 1);
+                const int32_t a = s[i];
+                const int32_t ap = (a + 1 + (int32_t)(((uint64_t)wp * (uint64_t)(q - 1)) >> 32)) % q;
+                const double u = (double)(wa >> 8) * (1.0 / 16777216.0);
+                const double p = exp(beta * (Hi[ap] - Hi[a]));
+                const int accept = u < p;
+                if (margins) {
+                    const double pc = p < 1.0 ? p : 1.0;
+                    margins[((size_t)c * sweeps + sw) * L + i] = fabs(u - pc);
+                }
+                if (accept) {
+                    s[i] = (int8_t)ap;
+                    nflip += 1;
+                }
+            }
+        }
+    }
+    if (flips) *flips = nflip;
+    free(Hi);
+}

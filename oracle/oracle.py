@@ -73,6 +73,8 @@ def _declare(L):
         "orc_reweight_rows": (None, [_p, _i64, _i32, _f64, _p, _i64, _p]),
         "orc_stats_entries": (None, [_p, _p, _i64, _i32, _i32, _f64, _p, _p, _i64, _p]),
         "orc_draw_rows": (None, [_p, _i64, _i64, _u64, _p, _p]),
+        "orc_metropolis_range": (None, [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _u64, _u64,
+                                        _f64, _p, _p]),
         "orc_seqid": (None, [_p, _p, _p, _i64, _i32, _p]),
     }
     for name, (res, args) in sig.items():
@@ -212,6 +214,19 @@ def gibbs_range(h, J, chains, c0: int, q: int, sweeps: int, seed: int, sweep_off
     flips = np.zeros(1, dtype=np.int64)
     lib().orc_gibbs_range(_ptr(h), _ptr(J), _ptr(ch), N, c0, L, q, sweeps, seed, sweep_offset,
                           float(beta), _ptr(mg), _ptr(flips))
+    return ch, mg, int(flips[0])
+
+
+def metropolis(h, J, chains, q: int, sweeps: int, seed: int, sweep_offset: int = 0,
+               beta: float = 1.0, want_margins: bool = False, c0: int = 0):
+    """Single-site Metropolis sweeps. Returns (new chains, margins or None, flips)."""
+    h, J = _f32(h), _f32(J)
+    ch = _i8(chains).copy()
+    N, L = ch.shape
+    mg = np.zeros((N, sweeps, L), dtype=np.float64) if want_margins else None
+    flips = np.zeros(1, dtype=np.int64)
+    lib().orc_metropolis_range(_ptr(h), _ptr(J), _ptr(ch), N, c0, L, q, sweeps, seed,
+                               sweep_offset, float(beta), _ptr(mg), _ptr(flips))
     return ch, mg, int(flips[0])
 
 

@@ -553,3 +553,42 @@ def test_mixing_time_pins():
                     Jf[i * q + a, j * q + a] = 1.2
     t, rec, _ = O.mixing_time(np.zeros_like(h), Jf, msa, w, q, N, 18, perm, max_sweeps=64)
     assert t is None or t >= 4
+
+
+# ----------------------------------------------- Metropolis sampler (reading of Sec. 2.1)
+@pytest.mark.parametrize("sJ", [0.1, 1.0])
+def test_metropolis_stationary_marginals(sJ):
+    L, q = 4, 3
+    h, J = tiny_model(19, sJ=sJ)
+    p1, p2, _, _, _ = enumerate_numpy(h, J, L, q)
+    ch0 = O.init_chains(20000, L, q, seed=23)
+    ch, _, flips = O.metropolis(h, J, ch0, q, sweeps=60, seed=24)
+    zmax, ntest = _marginal_check(ch, q, p1, p2)
+    assert zmax < _sidak_z(ntest), zmax
+    assert flips > 0
+
+
+def test_metropolis_single_site_closed_forms():
+    h = np.array([[0.3, -0.9]], dtype=np.float32)
+    J = np.zeros((2, 2), dtype=np.float32)
+    n = 40000
+    # from state 0 the proposal is 1, accepted with probability exp(-1.2)
+    ch, _, _ = O.metropolis(h, J, np.zeros((n, 1), np.int8), 2, sweeps=1, seed=6)
+    p = np.exp(-1.2)
+    assert abs(ch.mean() - p) < 5 * np.sqrt(p * (1 - p) / n)
+    # from state 1 the move to 0 raises the probability: always accepted
+    ch, _, _ = O.metropolis(h, J, np.ones((n, 1), np.int8), 2, sweeps=1, seed=7)
+    assert ch.max() == 0
+
+
+def test_metropolis_beta_zero_always_moves_uniformly():
+    L, q, n = 9, 5, 20000
+    h, J = synth.planted_dense(L, q, seed=25, sigma_J=1.0)
+    ch0 = O.init_chains(n, L, q, seed=26)
+    ch, _, flips = O.metropolis(h, J, ch0, q, sweeps=1, seed=27, beta=0.0)
+    assert np.all(ch != ch0) and flips == n * L
+    step = (ch.astype(int) - ch0.astype(int)) % q
+    cnt = np.bincount(step.ravel(), minlength=q)
+    assert cnt[0] == 0
+    e = n * L / (q - 1)
+    assert np.all(np.abs(cnt[1:] - e) < 5 * np.sqrt(e))
