@@ -80,6 +80,18 @@ typedef enum {
                                      chains of a workgroup in lockstep */
 #define BMDCA_GIBBS_KEEP_FIELDS 0x40 /* field form only: H_ws already holds
                                         the fields of these chains */
+#define BMDCA_SAMPLER_METROPOLIS 0x80 /* single-site Metropolis instead of the
+                                        heat-bath draw (field form; not with
+                                        BMDCA_SAMPLER_GATHER): at site i in
+                                        state a propose a' uniformly among the
+                                        q-1 other states, Philox counter
+                                        (i/2, sweep, chain, 3), word 2(i%2):
+                                        a' = (a + 1 + ((w (q-1)) >> 32)) mod q;
+                                        accept iff u < exp(beta (H_i(a') -
+                                        H_i(a))), u = (w' >> 8) 2^-24 from word
+                                        2(i%2)+1.  The paper names the option
+                                        without its rule; this is the textbook
+                                        rule. */
 
 /* Bits OR-ed into *dev_err. */
 #define BMDCA_DEVERR_TOKEN 1

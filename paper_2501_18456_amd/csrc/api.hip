@@ -58,12 +58,14 @@ int check_model(int32_t L, int32_t q) {
 size_t gibbs_bytes(int64_t N, int L, int q) { return align256(sizeof(float) * (size_t)N * L * q); }
 
 constexpr int kPrecMask = 0x0F;
-constexpr int kSamplerMask = BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER;
+constexpr int kSamplerMask = BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER | BMDCA_SAMPLER_METROPOLIS;
 
 // Sampler choice: 1 = gather form, 0 = field form, -1 = invalid request.
 int pick_gather(int flags, int L, int q) {
-  const int sel = flags & kSamplerMask;
-  if (sel == kSamplerMask) return -1;
+  if (flags & BMDCA_SAMPLER_METROPOLIS)  // Metropolis runs in the field form
+    return (flags & BMDCA_SAMPLER_GATHER) ? -1 : 0;
+  const int sel = flags & (BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER);
+  if (sel == (BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER)) return -1;
   if (sel == BMDCA_SAMPLER_FIELDS) return 0;
   const bool ok = gather_supported(L, q);
   if (sel == BMDCA_SAMPLER_GATHER) return ok ? 1 : -1;
@@ -126,7 +128,7 @@ int gibbs_impl(const float* h, const float* J, int8_t* chains, int64_t N, int32_
                          "gibbs/fields"));
   if (sweeps == 0) return BMDCA_OK;
   return hip_status(launch_gibbs_sweeps(J, chains, H_ws, N, L, q, sweeps, seed, sweep_offset, beta,
-                                        flips_out, s, ctl),
+                                        flips_out, s, ctl, (flags & BMDCA_SAMPLER_METROPOLIS) != 0),
                     "gibbs/sweeps");
 }
 
@@ -181,7 +183,8 @@ int enqueue_train(const bmdca_train_problem& p, uint64_t epoch, const DevCtl& ct
                          "train_step/fields"));
     if (p.sweeps > 0)
       BMDCA_TRY(hip_status(launch_gibbs_sweeps(p.J, p.chains, H, N, L, q, p.sweeps, p.seed, sweep0,
-                                               1.0f, p.flips_out, s, ctl),
+                                               1.0f, p.flips_out, s, ctl,
+                                               (p.prec & BMDCA_SAMPLER_METROPOLIS) != 0),
                            "train_step/sweeps"));
   }
   BMDCA_TRY(hip_status(launch_onehot_products(p.chains, nullptr, N, L, q, pr, plan.sp, sws,

@@ -36,7 +36,7 @@ hipError_t launch_local_fields(const float* h, const float* J, const int8_t* cha
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, hipStream_t s,
-                               const DevCtl& ctl = DevCtl());
+                               const DevCtl& ctl = DevCtl(), bool metropolis = false);
 // Gather form (local fields recomputed per visit from LDS-staged coupling
 // blocks); needs no field workspace.
 bool gather_supported(int L, int q);

@@ -90,7 +90,11 @@ hipError_t launch_local_fields(const float* h, const float* J, const int8_t* cha
 // two coupling rows: H[r] += J[(i,a_new)][r] - J[(i,a_old)][r], r outside
 // site i's own block.
 // ---------------------------------------------------------------------------
-template <int WPB>
+// MH = true: single-site Metropolis instead of the heat-bath draw.  The
+// proposal a' is uniform among the q-1 states != a (Philox counter (i/2,
+// sweep, chain, 3), word 2(i%2): a' = (a + 1 + ((w (q-1)) >> 32)) mod q) and
+// is accepted iff u < exp(beta (H_i(a') - H_i(a))), u from word 2(i%2)+1.
+template <int WPB, bool MH>
 __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict__ J,
                                                         int8_t* __restrict__ chains,
                                                         float* __restrict__ H, int64_t N, int L,
@@ -132,22 +136,33 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
   for (int sw = 0; sw < sweeps; ++sw) {
     const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
     for (int i = 0; i < L; ++i) {
-      if ((i & 3) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
-      const float u = word_to_uniform(pick_word(rnd, i & 3));
       const int a_old = tok[i];
-      const float l = lane < q ? beta * Hc[i * q + lane] : -INFINITY;
-      const float mx = wave_max(l);
-      float e = lane < q ? expf(l - mx) : 0.0f;
-      // inclusive prefix sum over lanes (q <= 32)
+      int a_new;
+      if constexpr (MH) {
+        if ((i & 1) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 1, sg, cid, 3u), k0, k1);
+        const uint32_t wp = pick_word(rnd, 2 * (i & 1));
+        const float u = word_to_uniform(pick_word(rnd, 2 * (i & 1) + 1));
+        const int a_prop =
+            (a_old + 1 + (int)(((uint64_t)wp * (uint64_t)(q - 1)) >> 32)) % q;
+        const float d = Hc[i * q + a_prop] - Hc[i * q + a_old];  // same address in all lanes
+        a_new = (u < expf(beta * d)) ? a_prop : a_old;
+      } else {
+        if ((i & 3) == 0) rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
+        const float u = word_to_uniform(pick_word(rnd, i & 3));
+        const float l = lane < q ? beta * Hc[i * q + lane] : -INFINITY;
+        const float mx = wave_max(l);
+        float e = lane < q ? expf(l - mx) : 0.0f;
+        // inclusive prefix sum over lanes (q <= 32)
 #pragma unroll
-      for (int o = 1; o < 32; o <<= 1) {
-        const float t = __shfl_up(e, o, kWave);
-        if (lane >= o) e += t;
+        for (int o = 1; o < 32; o <<= 1) {
+          const float t = __shfl_up(e, o, kWave);
+          if (lane >= o) e += t;
+        }
+        const float Z = __shfl(e, q - 1, kWave);
+        const float cdf = e / Z;
+        const bool below = (lane < q - 1) && (cdf <= u);
+        a_new = __popcll(__ballot(below));
       }
-      const float Z = __shfl(e, q - 1, kWave);
-      const float cdf = e / Z;
-      const bool below = (lane < q - 1) && (cdf <= u);
-      const int a_new = __popcll(__ballot(below));
       if (a_new != a_old) {
         const float* __restrict__ Jn = J + (size_t)(i * q + a_new) * Lq;
         const float* __restrict__ Jo = J + (size_t)(i * q + a_old) * Lq;
@@ -169,13 +184,14 @@ __global__ __launch_bounds__(WPB * 64) void k_gibbs_hbm(const float* __restrict_
 
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
-                               unsigned long long* flips_out, hipStream_t s, const DevCtl& ctl) {
+                               unsigned long long* flips_out, hipStream_t s, const DevCtl& ctl,
+                               bool metropolis) {
   constexpr int WPB = 4;
   const int Lpad = (L + 3) & ~3;
-  hipLaunchKernelGGL(k_gibbs_hbm<WPB>, dim3((unsigned)ceil_div(N, WPB)), dim3(WPB * kWave),
-                     WPB * Lpad, s, J, chains, H, N, L, q, sweeps, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, ctl.epoch, ctl.active,
-                     ctl.streams);
+  auto kern = metropolis ? k_gibbs_hbm<WPB, true> : k_gibbs_hbm<WPB, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(N, WPB)), dim3(WPB * kWave), WPB * Lpad, s, J,
+                     chains, H, N, L, q, sweeps, (uint32_t)seed, (uint32_t)(seed >> 32),
+                     sweep_offset, beta, flips_out, ctl.epoch, ctl.active, ctl.streams);
   return hipGetLastError();
 }
 

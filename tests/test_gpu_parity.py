@@ -380,3 +380,55 @@ def test_gibbs_streams_equal_separate_calls(sampler, cus):
     st = api.chain_streams(seeds, offs, ids)
     api.gibbs_streams(hg, Jg, both, 6, st, sampler=sampler, cus=cus)
     assert torch.equal(both[:300], a) and torch.equal(both[300:], b)
+
+
+# ----------------------------------------------------------------- Metropolis
+def test_metropolis_trajectories_match_oracle():
+    L, q, N = 30, 21, 300
+    h, J = synth.planted_dense(L, q, seed=140, sigma_J=0.3)
+    ch0 = O.init_chains(N, L, q, seed=141)
+    cg = dev(ch0)
+    api.gibbs(dev(h), dev(J), cg, 1, seed=142, sampler="metropolis")
+    ref, mg, _ = O.metropolis(h, J, ch0, q, 1, 142, want_margins=True)
+    check_trajectory(host(cg), ref, mg)
+    # several sweeps, continued by offset: chains that differ met a boundary event
+    cg = dev(ch0)
+    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sampler="metropolis")
+    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sweep_offset=2, sampler="metropolis")
+    ref, mg, _ = O.metropolis(h, J, ch0, q, 4, 143, want_margins=True)
+    bad = np.nonzero((host(cg) != ref).any(axis=1))[0]
+    assert all(mg[c].min() < BOUNDARY for c in bad)
+    assert len(bad) <= N // 50
+
+
+def test_metropolis_stationary_marginals_vs_enumeration():
+    L, q, N = 4, 3, 100000
+    h, J = synth.planted_dense(L, q, seed=144, sigma_J=1.0)
+    p1, p2, _ = O.enumerate_exact(h, J, L, q)
+    cg = api.init_chains(N, L, q, seed=145)
+    api.gibbs(dev(h), dev(J), cg, 80, seed=146, sampler="metropolis")
+    Y = onehot(host(cg).astype(np.int64), q)
+    s1, s2 = Y.mean(0), Y.T @ Y / N
+    z = max((np.abs(s1 - p1) / np.sqrt(np.maximum(p1 * (1 - p1), 1e-12) / N)).max(),
+            (np.abs(s2 - p2) / np.sqrt(np.maximum(p2 * (1 - p2), 1e-12) / N)).max())
+    assert z < 4.5, z
+
+
+def test_train_step_with_metropolis_sweeps():
+    """train_step's sampler leg with the Metropolis flag is bmdca_gibbs with it."""
+    L, q, N = 20, 21, 500
+    h, J = synth.planted_dense(L, q, seed=147, sigma_J=0.1)
+    X = synth.clustered_msa(400, L, q, seed=148)
+    f1, f2, _ = api.stats(dev(X), q, None, -1.0, "fp32")
+    ch0 = O.init_chains(N, L, q, seed=149)
+    hg, Jg, cg = dev(h), dev(J), dev(ch0)
+    api.train_step(hg, Jg, cg, f1, f2, 0.05, 5, 150, 3, "bf16x2", sampler="metropolis")
+    c2 = dev(ch0)
+    api.gibbs(dev(h), dev(J), c2, 5, 150, sweep_offset=15, sampler="metropolis")
+    assert torch.equal(cg, c2)
+    # Metropolis has no gather form: rejected (no workspace size, and the call itself)
+    bad = B.SAMPLER_METROPOLIS | B.SAMPLER_GATHER
+    assert B.lib().bmdca_workspace_bytes(B.WS_GIBBS, N, L, q, bad) == 0
+    ws = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS)
+    with pytest.raises(B.BmdcaError):
+        api.gibbs(dev(h), dev(J), dev(ch0), 1, 1, H_ws=ws, sampler=bad)
