@@ -63,7 +63,7 @@ typedef enum {
     BMDCA_PREC_BF16X2 = 1 /* BF16 matrix cores; one-hot operands are exact in
                              BF16, each weight is split w = hi + lo into two
                              BF16 parts (two products), FP32 accumulation over
-                             chunks of at most 512 rows flushed into FP64 */
+                             chunks of at most 1024 rows flushed into FP64 */
 } bmdca_prec;
 
 /* Sampler selection and options, OR-ed into the `flags` argument of

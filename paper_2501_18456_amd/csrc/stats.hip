@@ -17,7 +17,7 @@
 //     barrier;
 //   - BF16: one-hot values are exact; a weight is split into hi + lo BF16
 //     parts (two products into the same FP32 accumulator); FP32 partial sums
-//     are flushed into FP64 registers every 512 rows.  Unit weights give
+//     are flushed into FP64 registers every 1024 rows.  Unit weights give
 //     integer counts, exact in FP32 below 2^24 rows.
 //   - FP32: 32x32x2 FP32 MFMAs on FP32 operands (the comparator form).
 // K may be split across workgroups; every split writes its own FP64 plane
@@ -32,11 +32,17 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kTile = 128;             // output tile edge
 constexpr int kKT = 64;                // rows per K stage
-constexpr int kFlushStages = 8;        // 8 * 64 = 512 rows per FP32 partial sum
 constexpr int kRowB = kKT * 2 + 16;    // BF16 tile row stride in bytes (padded)
 constexpr int kRowF = kKT + 1;         // FP32 tile row stride in floats (padded)
 
 enum { MODE_UNIT_BF16 = 0, MODE_HILO_BF16 = 1, MODE_F32 = 2 };
+
+// K stages per FP32 partial sum before it is added into FP64: 1024 rows in
+// the BF16 hi+lo form (one FP32 rounding per 16-row MFMA step: at most 64
+// roundings, <= 3.8e-6 relative, beside the <= 2^-18 of the hi+lo split),
+// 512 rows in the FP32 form (2-row MFMA steps).
+template <int MODE>
+constexpr int flush_stages() { return MODE == MODE_HILO_BF16 ? 16 : 8; }
 
 static int mode_of(int prec, bool weighted) {
   if (prec == 0) return MODE_F32;
@@ -185,8 +191,11 @@ __device__ __forceinline__ void load_tokens(const int8_t* __restrict__ XT, int64
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int s = wid + NW * p;
-    // padding (-1) reads as 255: past every tile row for any site base
-    tok[p] = (s < o.nsites) ? (int)(uint8_t)XT[(size_t)(o.i_lo + s) * Mpad + m0 + lane] : 255;
+    // padding (-1) reads as 255: past every tile row for any site base; a
+    // site beyond the tile reads a valid site and is replaced by 255
+    const int site = o.i_lo + min(s, o.nsites - 1);
+    const int t = (int)(uint8_t)XT[(size_t)site * Mpad + m0 + lane];
+    tok[p] = (s < o.nsites) ? t : 255;
   }
 }
 
@@ -200,8 +209,8 @@ __device__ __forceinline__ void put_entries(const Operand& o, int q, int wid, in
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int s = wid + NW * p;
-    if (s >= o.nsites) break;  // wave-uniform
-    // base is wave-uniform and in (-q, ROWS); tokens are in [0, q) or 255
+    // base is wave-uniform and > -q; tokens are in [0, q) or 255, and 255
+    // (padding, or a site past the tile) always lands in the trash row
     const int base = (o.i_lo + s) * q - o.R0;
     const int r = (int)min((unsigned)(tok[p] + base), (unsigned)ROWS);
     if (MODE == MODE_F32) {
@@ -286,8 +295,11 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
 #pragma unroll
     for (int v = 0; v < 16; ++v) dacc[b][v] = 0.0;
 
-  // Tokens of the previous, current, next and after-next stage.
+  // Tokens of the previous, current, next and after-next stage (previous:
+  // none yet, so its clears go to the trash row).
   int aP[NP], bP[NP], aC[NP], bC[NP], aN[NP], bN[NP], aNN[NP], bNN[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) aP[p] = bP[p] = 255;
   uint16_t hiN = 0, loN = 0, hiNN = 0, loNN = 0;
   float fN = 0.0f, fNN = 0.0f;
   auto load_w = [&](int64_t m, uint16_t& hi, uint16_t& lo, float& f) {
@@ -314,10 +326,11 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
   uint16_t hi0 = 0, lo0 = 0;
   float f0 = 0.0f;
   load_w(kbeg, hi0, lo0, f0);
-  if (kbeg + kKT < kend) {
-    load_tokens<NW, NP>(XT, Mpad, oa, kbeg + kKT, wid, lane, aN);
-    load_tokens<NW, NP>(XT, Mpad, ob, kbeg + kKT, wid, lane, bN);
-    load_w(kbeg + kKT, hiN, loN, fN);
+  {  // stage after the first (the last stage again when there is none)
+    const int64_t m1 = min(kbeg + kKT, kend - kKT);
+    load_tokens<NW, NP>(XT, Mpad, oa, m1, wid, lane, aN);
+    load_tokens<NW, NP>(XT, Mpad, ob, m1, wid, lane, bN);
+    load_w(m1, hiN, loN, fN);
   }
   __syncthreads();
   put_a(aC, smem, false, hi0, lo0, f0);
@@ -329,11 +342,11 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
   int st = 0;
   for (int64_t m0 = kbeg; m0 < kend; m0 += kKT, ++st) {
     const bool has1 = m0 + kKT < kend;
-    const bool has2 = m0 + 2 * kKT < kend;
-    if (has2) {
-      load_tokens<NW, NP>(XT, Mpad, oa, m0 + 2 * kKT, wid, lane, aNN);
-      load_tokens<NW, NP>(XT, Mpad, ob, m0 + 2 * kKT, wid, lane, bNN);
-      load_w(m0 + 2 * kKT, hiNN, loNN, fNN);
+    {  // loads two stages ahead (clamped to the last stage: used only if it exists)
+      const int64_t m2 = min(m0 + 2 * kKT, kend - kKT);
+      load_tokens<NW, NP>(XT, Mpad, oa, m2, wid, lane, aNN);
+      load_tokens<NW, NP>(XT, Mpad, ob, m2, wid, lane, bNN);
+      load_w(m2, hiNN, loNN, fNN);
     }
     const unsigned char* cur = smem + (st & 1) * kBuf;
     unsigned char* other = smem + ((st & 1) ^ 1) * kBuf;
@@ -387,26 +400,25 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
       }
     }
     // ---- other buffer: clear stage m0 - kKT, set stage m0 + kKT.  Nobody
-    // reads it during this stage (its last readers passed the previous barrier).
-    if (st > 0) {
-      put_a(aP, other, true, 0, 0, 0.0f);
-      put_b(bP, other, true);
-    }
-    if (has1) {
-      put_a(aN, other, false, hiN, loN, fN);
-      put_b(bN, other, false);
-    }
+    // reads it during this stage (its last readers passed the previous
+    // barrier).  Both run every stage: before the first stage the clears go
+    // to the trash row, after the last the buffer is not read again.
+    put_a(aP, other, true, 0, 0, 0.0f);
+    put_b(bP, other, true);
+    put_a(aN, other, false, hiN, loN, fN);
+    put_b(bN, other, false);
+
     if constexpr (kWeighted) {
-      if (((st + 1) % kFlushStages) == 0 || !has1) {
+      if (((st + 1) % flush_stages<MODE>()) == 0 || !has1) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
           for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              double add = (double)acc[rb][cb][v];
-              if (kLo) add += (double)lacc[rb][cb][v];
-              dacc[rb * 2 + cb][v] += add;
+              float part = acc[rb][cb][v];
+              if (kLo) part += lacc[rb][cb][v];  // lo <= 2^-8 hi: one FP32 rounding
+              dacc[rb * 2 + cb][v] += (double)part;
               acc[rb][cb][v] = 0.0f;
               if (kLo) lacc[rb][cb][v] = 0.0f;
             }
