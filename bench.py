@@ -341,6 +341,36 @@ def bench_precision(args):
         torch.cuda.empty_cache()
     value = N * L * sweeps / (epoch_ms["bf16x2"] * 1e-3)
     log(f"epoch bf16x2 {epoch_ms['bf16x2']:.1f} ms, fp32 {epoch_ms['fp32']:.1f} ms")
+    # the two sweep kernels at this size: H = N Lq 4 bytes = 430 MB, beyond the
+    # 256 MB last-level cache, so the field form's H traffic is HBM traffic
+    h = torch.log(f1).to(torch.float32).reshape(L, q).contiguous()
+    J = (0.05 * torch.randn((Lq, Lq), device="cuda", generator=torch.Generator("cuda").manual_seed(5)))
+    J = ((J + J.T) * 0.5).contiguous()
+    for i in range(L):
+        J[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0.0
+    ch = api.init_chains(N, L, q, seed=3005)
+    Hf = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
+    api.gibbs(h, J, ch, 1, 3005, H_ws=Hf, sampler="fields")
+    kfl = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ks = 5
+    t.start()
+    api.gibbs(h, J, ch, ks, 3005, sweep_offset=1, H_ws=Hf, flips=kfl, keep_fields=True,
+              sampler="fields")
+    f_ms = t.stop_ms()
+    flips = float(kfl.item())
+    visits = N * L * ks
+    fbytes = visits * 4 * q + flips * 8 * (Lq - q) + 2 * N * L
+    f_gbs = fbytes / (f_ms * 1e-3) / 1e9
+    Hg = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_GATHER)
+    api.gibbs(h, J, ch, 1, 3005, sweep_offset=100, H_ws=Hg, sampler="gather")
+    t.start()
+    api.gibbs(h, J, ch, ks, 3005, sweep_offset=101, H_ws=Hg, sampler="gather")
+    g_ms = t.stop_ms()
+    log(f"field form {ks} sweeps: {f_ms:.1f} ms, flip fraction {flips / visits:.3f}, "
+        f"{f_gbs:.0f} GB/s algorithmic HBM ({100 * f_gbs / HBM_PEAK_GBS:.0f}% of peak); "
+        f"gather form {g_ms:.1f} ms")
+    del Hf, Hg, ch, J
+    torch.cuda.empty_cache()
     out = {
         "metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": epoch_ms["bf16x2"],
@@ -358,7 +388,11 @@ def bench_precision(args):
                    "stats_fp32_frac_of_157": tf_fp32 / 157.3,
                    "bf16x2_vs_fp32_maxabs": {"f1": d1, "f2": d2},
                    "epoch_ms": epoch_ms, "site_updates_per_s": {
-                       p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()}},
+                       p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()},
+                   "field_kernel_5_sweeps": {"ms": f_ms, "flip_fraction": flips / visits,
+                                             "alg_hbm_GBps": f_gbs,
+                                             "hbm_frac": f_gbs / HBM_PEAK_GBS},
+                   "gather_kernel_5_sweeps_ms": g_ms},
     }
     print(json.dumps(out), flush=True)
 
