@@ -705,3 +705,115 @@ void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_
     if (flips) *flips = nflip;
     free(Hi);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Element decimation (edDCA, Sec. 2.4 "Element decimation DCA"): prune the   */
+/* active coupling elements whose removal perturbs the model least, measured  */
+/* by the symmetric Kullback-Leibler distance between the current model P and */
+/* P' = P with the single element J_ij(a,b) set to zero.                     */
+/*                                                                          */
+/* With x(s) = [s_i == a][s_j == b] and p = E_P[x], Eq. (1) gives             */
+/* P'(s) = P(s) exp(-J x(s)) Z / Z', Z'/Z = E_P[exp(-J x)] = 1 - p + p e^-J,  */
+/* hence KL(P||P') = J p + log(1 - p + p e^-J), KL(P'||P) = -J p' - log(...), */
+/* p' = E_P'[x] = p e^-J / (1 - p + p e^-J), and the symmetric distance is    */
+/* J (p - p') >= 0.  p is estimated by the chain frequency count / N.         */
+/* ------------------------------------------------------------------------ */
+double orc_skl_element(double J, double p)
+{
+    const double e = exp(-J);
+    const double d = 1.0 - p + p * e;
+    const double pp = p * e / d;
+    return J * (p - pp);
+}
+
+typedef struct {
+    double score;
+    int64_t key; /* r1 * Lq + r2, r1 < r2 */
+} orc_scored;
+
+static int orc_scored_cmp(const void* a, const void* b)
+{
+    const orc_scored* x = (const orc_scored*)a;
+    const orc_scored* y = (const orc_scored*)b;
+    if (x->score < y->score) return -1;
+    if (x->score > y->score) return 1;
+    return (x->key < y->key) ? -1 : (x->key > y->key);
+}
+
+/* One graph update.  Elements are the unordered pairs of vertices (r1, r2)
+ * with r1 < r2 in different sites; mask [Lq][Lq] (1 = active) and J are kept
+ * symmetric.  n_total = L (L-1) q^2 / 2; n_target = ceil(density n_total);
+ * with n_act active elements, k = min(max(1, floor(drate n_act)), n_act -
+ * n_target) elements (none if n_act <= n_target) with the smallest
+ * (score, r1 Lq + r2) are removed (mask = 0 and J = 0 on both triangles).
+ * Returns the number of active elements afterwards. */
+int64_t orc_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, int32_t L,
+                     int32_t q, double drate, double density)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double* p1 = (double*)malloc(sizeof(double) * (size_t)Lq);
+    double* p2 = (double*)malloc(sizeof(double) * (size_t)Lq * (size_t)Lq);
+    orc_chain_freqs(chains, N, L, q, p1, p2);
+    const int64_t n_total = (int64_t)L * (L - 1) / 2 * q * q;
+    const int64_t n_target = (int64_t)ceil(density * (double)n_total);
+    orc_scored* s = (orc_scored*)malloc(sizeof(orc_scored) * (size_t)n_total);
+    int64_t n_act = 0;
+    for (int64_t r1 = 0; r1 < Lq; ++r1)
+        for (int64_t r2 = r1 + 1; r2 < Lq; ++r2) {
+            if (r1 / q == r2 / q) continue;
+            const size_t k = IDX2(r1, r2, Lq);
+            if (!mask[k]) continue;
+            s[n_act].score = orc_skl_element((double)J[k], p2[k]);
+            s[n_act].key = r1 * Lq + r2;
+            ++n_act;
+        }
+    int64_t kk = 0;
+    if (n_act > n_target) {
+        kk = (int64_t)floor(drate * (double)n_act);
+        if (kk < 1) kk = 1;
+        if (kk > n_act - n_target) kk = n_act - n_target;
+    }
+    qsort(s, (size_t)n_act, sizeof(orc_scored), orc_scored_cmp);
+    for (int64_t t = 0; t < kk; ++t) {
+        const int64_t r1 = s[t].key / Lq, r2 = s[t].key % Lq;
+        mask[IDX2(r1, r2, Lq)] = 0;
+        mask[IDX2(r2, r1, Lq)] = 0;
+        J[IDX2(r1, r2, Lq)] = 0.0f;
+        J[IDX2(r2, r1, Lq)] = 0.0f;
+    }
+    free(s);
+    free(p1);
+    free(p2);
+    return n_act - kk;
+}
+
+/* Eq. (5) on a sparse graph: as orc_update, with inactive elements (mask 0)
+ * held at zero. */
+void orc_update_masked(float* h, float* J, const uint8_t* mask, const double* f1,
+                       const double* f2, const double* p1, const double* p2, int32_t L,
+                       int32_t q, double lr)
+{
+    const int64_t Lq = (int64_t)L * q;
+    orc_update(h, J, f1, f2, p1, p2, L, q, lr);
+    for (int64_t k = 0; k < Lq * Lq; ++k)
+        if (!mask[k]) J[k] = 0.0f;
+}
+
+/* orc_train_step on a sparse graph (masked update). */
+double orc_train_step_masked(float* h, float* J, const uint8_t* mask, int8_t* chains,
+                             int64_t N, int32_t L, int32_t q, const double* f1,
+                             const double* f2, double lr, int32_t sweeps, uint64_t seed,
+                             uint64_t epoch, double* margins, int64_t* flips)
+{
+    const int64_t Lq = (int64_t)L * q;
+    orc_gibbs(h, J, chains, N, L, q, sweeps, seed, epoch * (uint64_t)sweeps, 1.0,
+              margins, flips);
+    double* p1 = (double*)malloc(sizeof(double) * (size_t)Lq);
+    double* p2 = (double*)malloc(sizeof(double) * (size_t)Lq * (size_t)Lq);
+    orc_chain_freqs(chains, N, L, q, p1, p2);
+    double r = orc_pearson(f1, f2, p1, p2, L, q);
+    orc_update_masked(h, J, mask, f1, f2, p1, p2, L, q, lr);
+    free(p1);
+    free(p2);
+    return r;
+}

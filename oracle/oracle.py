@@ -76,6 +76,10 @@ def _declare(L):
         "orc_metropolis_range": (None, [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _u64, _u64,
                                         _f64, _p, _p]),
         "orc_seqid": (None, [_p, _p, _p, _i64, _i32, _p]),
+        "orc_skl_element": (_f64, [_f64, _f64]),
+        "orc_decimate": (_i64, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64]),
+        "orc_train_step_masked": (_f64, [_p, _p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32,
+                                         _u64, _u64, _p, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -346,4 +350,36 @@ def mixing_time(h, J, msa, w, q: int, nmeasure: int, seed: int, perm, max_sweeps
         prev = A.copy()
         t_prev, t = t, 2 * t
     return None, records, A
+
+
+# --------------------------------------------------------------------------
+# Element decimation (edDCA, Sec. 2.4)
+# --------------------------------------------------------------------------
+def skl_element(J: float, p: float) -> float:
+    """Symmetric KL between the model and the model without one coupling element."""
+    return lib().orc_skl_element(float(J), float(p))
+
+
+def decimate(J, mask, chains, q: int, drate: float, density: float):
+    """One graph update; returns (J, mask, active elements after)."""
+    Jc = _f32(J).copy()
+    mc = np.ascontiguousarray(mask, dtype=np.uint8).copy()
+    ch = _i8(chains)
+    N, L = ch.shape
+    n = lib().orc_decimate(_ptr(Jc), _ptr(mc), _ptr(ch), N, L, q, float(drate), float(density))
+    return Jc, mc, int(n)
+
+
+def train_step_masked(h, J, mask, chains, f1, f2, q: int, lr: float, sweeps: int, seed: int,
+                      epoch: int):
+    """Returns (h, J, chains, pearson)."""
+    h2, J2 = _f32(h).copy(), _f32(J).copy()
+    ch = _i8(chains).copy()
+    N, L = ch.shape
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    f1 = np.ascontiguousarray(f1, dtype=np.float64)
+    f2 = np.ascontiguousarray(f2, dtype=np.float64)
+    r = lib().orc_train_step_masked(_ptr(h2), _ptr(J2), _ptr(m), _ptr(ch), N, L, q, _ptr(f1),
+                                    _ptr(f2), float(lr), sweeps, seed, epoch, None, None)
+    return h2, J2, ch, r
 

@@ -592,3 +592,80 @@ def test_metropolis_beta_zero_always_moves_uniformly():
     assert cnt[0] == 0
     e = n * L / (q - 1)
     assert np.all(np.abs(cnt[1:] - e) < 5 * np.sqrt(e))
+
+
+# ------------------------------------------------- element decimation (edDCA, Sec. 2.4)
+def test_decimation_score_is_symmetric_kl_by_enumeration():
+    L, q = 3, 3
+    h, J = tiny_model(30, L=L, q=q, sJ=0.8)
+    _, p2, _, _, p = enumerate_numpy(h, J, L, q)
+    for (r1, r2) in [(0, 3), (1, 8), (4, 7), (2, 6)]:
+        J2 = J.copy()
+        J2[r1, r2] = J2[r2, r1] = 0.0
+        _, _, _, _, pp = enumerate_numpy(h, J2, L, q)
+        skl = float(np.sum((p - pp) * (np.log(p) - np.log(pp))))
+        assert abs(O.skl_element(J[r1, r2], p2[r1, r2]) - skl) <= 1e-12 * max(1.0, skl)
+        assert skl > 0
+    assert O.skl_element(0.0, 0.3) == 0.0 and O.skl_element(1.5, 0.0) == 0.0
+
+
+def _decimate_numpy(J, mask, chains, q, drate, density):
+    """Independent bookkeeping: numpy frequencies, lexicographic (score, index) order."""
+    N, L = chains.shape
+    Lq = L * q
+    Y = onehot(chains.astype(np.int64), q)
+    p2 = Y.T @ Y / N
+    r1, r2 = np.triu_indices(Lq, 1)
+    keep = (r1 // q != r2 // q) & (mask[r1, r2] == 1)
+    r1, r2 = r1[keep], r2[keep]
+    sc = np.array([O.skl_element(J[a, b], p2[a, b]) for a, b in zip(r1, r2)])
+    n_act = r1.size
+    n_total = L * (L - 1) // 2 * q * q
+    n_target = int(np.ceil(density * n_total))
+    k = 0 if n_act <= n_target else min(max(1, int(np.floor(drate * n_act))), n_act - n_target)
+    order = np.lexsort((r1 * Lq + r2, sc))[:k]
+    J2, m2 = J.copy(), mask.copy()
+    J2[r1[order], r2[order]] = J2[r2[order], r1[order]] = 0.0
+    m2[r1[order], r2[order]] = m2[r2[order], r1[order]] = 0
+    return J2, m2, n_act - k
+
+
+def test_decimation_selects_smallest_scores():
+    L, q, N = 7, 4, 300
+    h, J = synth.planted_dense(L, q, seed=31, sigma_J=0.6)
+    chains = O.init_chains(N, L, q, seed=32)
+    chains = O.gibbs(h, J, chains, q, 5, 33)[0]
+    mask = np.ones((L * q, L * q), dtype=np.uint8)
+    for i in range(L):
+        mask[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
+    Jd = J.copy()
+    for step in range(4):
+        ref = _decimate_numpy(Jd, mask, chains, q, 0.1, 0.3)
+        Jd, mask, n = O.decimate(Jd, mask, chains, q, 0.1, 0.3)
+        assert n == ref[2] and np.array_equal(mask, ref[1]) and np.array_equal(Jd, ref[0])
+        assert np.array_equal(mask, mask.T) and np.array_equal(Jd, Jd.T)
+    # the target density is never undershot, and a graph at the target stays
+    n_total = L * (L - 1) // 2 * q * q
+    for _ in range(60):
+        Jd, mask, n = O.decimate(Jd, mask, chains, q, 0.2, 0.3)
+    assert n == int(np.ceil(0.3 * n_total))
+    _, m3, n3 = O.decimate(Jd, mask, chains, q, 0.2, 0.3)
+    assert n3 == n and np.array_equal(m3, mask)
+
+
+def test_masked_update_holds_pruned_couplings_at_zero():
+    L, q, N = 6, 3, 200
+    h, J = synth.planted_dense(L, q, seed=34, sigma_J=0.5)
+    X = synth.clustered_msa(300, L, q, seed=35)
+    f1, f2 = O.stats(X, q, None, -1.0)[:2]
+    ch = O.init_chains(N, L, q, seed=36)
+    g = np.random.default_rng(37)
+    mask = (g.random((L * q, L * q)) < 0.5).astype(np.uint8)
+    mask = np.triu(mask, 1)
+    mask = mask + mask.T
+    Jm = J * mask
+    hm, Jm2, chm, rm = O.train_step_masked(h, Jm, mask, ch, f1, f2, q, 0.05, 3, 38, 2)
+    hu, Ju, chu, ru = O.train_step(h, Jm, ch, f1, f2, q, 0.05, 3, 38, 2)[:4]
+    assert np.array_equal(chm, chu) and rm == ru and np.array_equal(hm, hu)
+    assert np.all(Jm2[mask == 0] == 0.0)
+    assert np.array_equal(Jm2[mask == 1], Ju[mask == 1])
