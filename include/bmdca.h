@@ -108,7 +108,8 @@ typedef enum {
     BMDCA_WS_MUTANT = 5,     /* MN = B (wild types) */
     BMDCA_WS_ENERGY = 6,     /* MN = B (sequences) */
     BMDCA_WS_DRAW = 7,       /* MN = M (weights); L, q ignored but must be valid */
-    BMDCA_WS_SEQID = 8       /* MN ignored */
+    BMDCA_WS_SEQID = 8,      /* MN ignored */
+    BMDCA_WS_DECIMATE = 9    /* MN = N (chains) */
 } bmdca_ws_kind;
 
 /* Bytes of device scratch memory the call `kind` needs for these sizes
@@ -303,6 +304,9 @@ typedef struct bmdca_train_problem {
     uint64_t seed;
     int32_t sweeps;
     int32_t prec; /* bmdca_prec | BMDCA_SAMPLER_* */
+    const uint8_t* mask; /* optional coupling graph [Lq][Lq] (1 = active):
+                            pruned elements are held at 0 by the update, as
+                            bmdca_train_step_masked; NULL = fully connected */
 } bmdca_train_problem;
 
 /* Enqueues one epoch of every model of the group on `stream`: the models are
@@ -332,6 +336,42 @@ int bmdca_train_group_graph(const bmdca_train_problem* probs, int32_t n,
 int bmdca_graph_launch(bmdca_graph g, void* stream);
 /* Frees the graph (NULL is accepted). */
 int bmdca_graph_destroy(bmdca_graph g);
+
+/* ---- Sparse models by element decimation (edDCA, Sec. 2.4) ----
+ *
+ * A coupling graph is a mask uint8 [Lq][Lq] (device, caller-owned,
+ * symmetric; 1 = active element, diagonal blocks ignored). */
+
+/* bmdca_train_step on a sparse graph: Eq. (5) updates active elements only;
+ * elements with mask 0 are set to and held at 0.  Other arguments as
+ * bmdca_train_step (same workspace). */
+int bmdca_train_step_masked(float* h, float* J, const uint8_t* mask, int8_t* chains,
+                            int64_t N, int32_t L, int32_t q, const double* f1,
+                            const double* f2, double lr, int32_t sweeps,
+                            uint64_t seed, uint64_t epoch, int32_t prec,
+                            double* pearson, unsigned long long* flips_out,
+                            void* ws, size_t ws_bytes, int32_t* dev_err,
+                            void* stream);
+
+/* One graph update of element decimation: for every active element
+ * (r1, r2), r1 < r2 in different sites, with p = (count of chains with
+ * s_i = a and s_j = b) / N, the symmetric Kullback-Leibler distance between
+ * the model and the model without that element is, from Eq. (1),
+ *   D = J (p - p'),  p' = p e^-J / (1 - p + p e^-J)   (D >= 0).
+ * With n_act active elements, n_total = L (L-1) q^2 / 2 and n_target =
+ * ceil(density n_total), the k = min(max(1, floor(drate n_act)),
+ * n_act - n_target) elements with the smallest (D, r1 Lq + r2) are removed
+ * (none when n_act <= n_target): mask and J are zeroed on both triangles.
+ * The paper's prescription is "remove the drate fraction with the smallest
+ * symmetric KL distance"; the count rule and tie order are this library's.
+ * chains   int8 [N][L], the model's current chains
+ * n_active optional device int64 out: active elements after the update
+ * ws       scratch, bmdca_workspace_bytes(BMDCA_WS_DECIMATE, N, L, q, 0)
+ * dev_err  optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1. */
+int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N,
+                   int32_t L, int32_t q, double drate, double density,
+                   long long* n_active, void* ws, size_t ws_bytes,
+                   int32_t* dev_err, void* stream);
 
 /* Single-mutant library (Sec. 4.4): for each of B wild types,
  * dE[b][i*q + a] = E(wild type with site i set to a) - E(wild type)

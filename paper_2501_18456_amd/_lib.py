@@ -19,7 +19,7 @@ SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS, SAMPLER_METROPOLIS = 0x10, 0x
 SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER,
            "metropolis": SAMPLER_METROPOLIS}
 (WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY, WS_DRAW,
- WS_SEQID) = range(9)
+ WS_SEQID, WS_DECIMATE) = range(10)
 
 _p, _i32, _i64, _u64, _f64, _f32, _sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,
                                           C.c_double, C.c_float, C.c_size_t)
@@ -31,7 +31,7 @@ class TrainProblem(C.Structure):
         ("h", _p), ("J", _p), ("chains", _p), ("f1", _p), ("f2", _p), ("pearson", _p),
         ("flips_out", _p), ("dev_err", _p), ("ctl", _p), ("ws", _p), ("ws_bytes", _sz),
         ("N", _i64), ("L", _i32), ("q", _i32), ("lr", _f64), ("seed", _u64),
-        ("sweeps", _i32), ("prec", _i32),
+        ("sweeps", _i32), ("prec", _i32), ("mask", _p),
     ]
 
 
@@ -67,6 +67,9 @@ SIGNATURES = {
     "bmdca_draw_rows": (C.c_int, [_p, _i64, _i64, _u64, _p, _p, _sz, _p, _p]),
     "bmdca_gather_rows": (C.c_int, [_p, _i64, _i32, _p, _i64, _p, _p, _p]),
     "bmdca_seqid": (C.c_int, [_p, _p, _p, _i64, _i32, _p, _p, _sz, _p, _p]),
+    "bmdca_train_step_masked": (C.c_int, [_p, _p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32,
+                                          _u64, _u64, _i32, _p, _p, _p, _sz, _p, _p]),
+    "bmdca_decimate": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64, _p, _p, _sz, _p, _p]),
     "bmdca_train_group_step": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p]),
     "bmdca_train_group_graph": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p,
                                           C.POINTER(_p)]),

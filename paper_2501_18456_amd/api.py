@@ -249,6 +249,53 @@ def seqid(A, Bm, perm=None, dev_err=None, ws=None, out=None):
     return out
 
 
+# ----------------------------------------------------- sparse models (edDCA)
+def full_mask(L: int, q: int, device="cuda"):
+    """The fully connected coupling graph: 1 off the diagonal blocks."""
+    m = torch.ones((L * q, L * q), dtype=torch.uint8, device=device)
+    for i in range(L):
+        m[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
+    return m
+
+
+def train_step_masked(h, J, mask, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: int,
+                      prec="bf16x2", ws=None, pearson=None, flips=None, dev_err=None,
+                      sampler="auto"):
+    """train_step on the graph `mask`; returns the device Pearson scalar."""
+    L, q = _model(h, J)
+    _dev(mask, torch.uint8, "mask", 2)
+    _dev(chains, torch.int8, "chains", 2)
+    N = chains.shape[0]
+    p = _prec(prec) | _sampler(sampler)
+    if ws is None:
+        ws = workspace(B.WS_TRAIN_STEP, N, L, q, p, chains.device)
+    if pearson is None:
+        pearson = torch.empty(1, dtype=torch.float64, device=chains.device)
+    check(B.lib().bmdca_train_step_masked(_ptr(h), _ptr(J), _ptr(mask), _ptr(chains), N, L, q,
+                                          _ptr(f1), _ptr(f2), lr, sweeps, seed, epoch, p,
+                                          _ptr(pearson), _ptr(flips), _ptr(ws), _nbytes(ws),
+                                          _ptr(dev_err), _stream()))
+    return pearson
+
+
+def decimate(J, mask, chains, q: int, drate: float, density: float, ws=None, dev_err=None,
+             n_active=None):
+    """One element-decimation graph update (in place); returns the device
+    int64 count of active elements afterwards."""
+    _dev(J, torch.float32, "J", 2)
+    _dev(mask, torch.uint8, "mask", 2)
+    _dev(chains, torch.int8, "chains", 2)
+    N, L = chains.shape
+    if ws is None:
+        ws = workspace(B.WS_DECIMATE, N, L, q, 0, chains.device)
+    if n_active is None:
+        n_active = torch.empty(1, dtype=torch.int64, device=chains.device)
+    check(B.lib().bmdca_decimate(_ptr(J), _ptr(mask), _ptr(chains), N, L, q, float(drate),
+                                 float(density), _ptr(n_active), _ptr(ws), _nbytes(ws),
+                                 _ptr(dev_err), _stream()))
+    return n_active
+
+
 # ------------------------------------------------------------ grouped training
 def train_ctl(device, target_pearson: float = 0.0, epoch: int = 0, active: bool = True):
     """A device control record (bmdca_train_ctl) as a uint8 tensor of its 24 bytes."""
@@ -270,7 +317,7 @@ class TrainModel:
 
     def __init__(self, h, J, chains, f1, f2, lr: float, sweeps: int, seed: int,
                  prec="bf16x2", sampler="auto", target_pearson: float = 0.0, ws=None,
-                 flips=None, dev_err=None):
+                 flips=None, dev_err=None, mask=None):
         L, q = _model(h, J)
         _dev(chains, torch.int8, "chains", 2)
         _dev(f1, torch.float64, "f1")
@@ -283,10 +330,13 @@ class TrainModel:
         self.pearson = torch.zeros(1, dtype=torch.float64, device=dev)
         self.flips, self.dev_err = flips, dev_err
         self.ctl = train_ctl(dev, target_pearson)
+        if mask is not None:
+            _dev(mask, torch.uint8, "mask", 2)
+        self.mask = mask
         self.record = B.TrainProblem(
             _ptr(h), _ptr(J), _ptr(chains), _ptr(f1), _ptr(f2), _ptr(self.pearson), _ptr(flips),
             _ptr(dev_err), _ptr(self.ctl), _ptr(self.ws), _nbytes(self.ws), self.N, L, q,
-            float(lr), int(seed), int(sweeps), self.prec)
+            float(lr), int(seed), int(sweeps), self.prec, _ptr(mask))
 
 
 def _records(models):

@@ -194,7 +194,7 @@ int enqueue_train(const bmdca_train_problem& p, uint64_t epoch, const DevCtl& ct
   BMDCA_TRY(hip_status(launch_pearson(p.f1, p.f2, C, N, L, q, red, p.pearson, p.dev_err, s),
                        "train_step/pearson"));
   return hip_status(launch_update(p.h, p.J, p.f1, p.f2, C, N, L, q, p.lr, p.dev_err, s,
-                                  ctl.active),
+                                  ctl.active, p.mask),
                     "train_step/update");
 }
 
@@ -295,6 +295,24 @@ int enqueue_group(const bmdca_train_problem* probs, int n, int lanes, hipStream_
   return BMDCA_OK;
 }
 
+// Decimation workspace: chain-count planes, the count matrix, select state.
+struct DecimatePlan {
+  StatsPlan sp;
+  size_t off_stats, off_C, off_dec, total;
+};
+
+DecimatePlan plan_decimate(int64_t N, int L, int q) {
+  DecimatePlan d{};
+  const size_t Lq = (size_t)L * q;
+  d.sp = plan_stats(N, L, q, BMDCA_PREC_BF16X2);
+  size_t o = 0;
+  d.off_stats = o; o = align256(o + d.sp.total);
+  d.off_C = o;     o = align256(o + sizeof(double) * Lq * Lq);
+  d.off_dec = o;   o = align256(o + dec_ws_bytes(L, q));
+  d.total = o;
+  return d;
+}
+
 }  // namespace
 
 struct bmdca_graph_s {
@@ -337,6 +355,9 @@ size_t bmdca_workspace_bytes(int32_t kind, int64_t MN, int32_t L, int32_t q, int
       return draw_ws_bytes(MN);
     case BMDCA_WS_SEQID:
       return seqid_ws_bytes();
+    case BMDCA_WS_DECIMATE:
+      if (MN < 1) return 0;
+      return plan_decimate(MN, L, q).total;
     default:
       return 0;
   }
@@ -477,6 +498,60 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L, i
   p.prec = prec;
   BMDCA_TRY(check_train(p));
   return enqueue_train(p, epoch, DevCtl(), (hipStream_t)stream);
+}
+
+int bmdca_train_step_masked(float* h, float* J, const uint8_t* mask, int8_t* chains, int64_t N,
+                            int32_t L, int32_t q, const double* f1, const double* f2, double lr,
+                            int32_t sweeps, uint64_t seed, uint64_t epoch, int32_t prec,
+                            double* pearson, unsigned long long* flips_out, void* ws,
+                            size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_REQUIRE(mask, "mask is NULL");
+  bmdca_train_problem p{};
+  p.h = h;
+  p.J = J;
+  p.chains = chains;
+  p.f1 = f1;
+  p.f2 = f2;
+  p.pearson = pearson;
+  p.flips_out = flips_out;
+  p.dev_err = dev_err;
+  p.ws = ws;
+  p.ws_bytes = ws_bytes;
+  p.N = N;
+  p.L = L;
+  p.q = q;
+  p.lr = lr;
+  p.seed = seed;
+  p.sweeps = sweeps;
+  p.prec = prec;
+  p.mask = mask;
+  BMDCA_TRY(check_train(p));
+  return enqueue_train(p, epoch, DevCtl(), (hipStream_t)stream);
+}
+
+int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, int32_t L, int32_t q,
+                   double drate, double density, long long* n_active, void* ws, size_t ws_bytes,
+                   int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(L >= 2, "decimation needs L >= 2 (got %d)", L);
+  BMDCA_REQUIRE(J && mask && chains && ws, "null pointer argument");
+  BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)N);
+  BMDCA_REQUIRE(drate >= 0.0 && drate <= 1.0, "drate=%g outside [0, 1]", drate);
+  BMDCA_REQUIRE(density >= 0.0 && density <= 1.0, "density=%g outside [0, 1]", density);
+  const DecimatePlan plan = plan_decimate(N, L, q);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "decimate workspace %zu < %zu bytes", ws_bytes, plan.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = static_cast<char*>(ws);
+  void* sws = base + plan.off_stats;
+  double* C = reinterpret_cast<double*>(base + plan.off_C);
+  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, BMDCA_PREC_BF16X2, plan.sp,
+                                              sws, dev_err, s),
+                       "decimate/counts"));
+  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, L * q, C, s), "decimate/reduce"));
+  return hip_status(launch_decimate(J, mask, C, N, L, q, drate, density, n_active,
+                                    base + plan.off_dec, s),
+                    "decimate/select");
 }
 
 int bmdca_train_group_step(const bmdca_train_problem* probs, int32_t n, int32_t lanes,

@@ -1,0 +1,245 @@
+// Element decimation (edDCA; adabmDCA 2.0, Sec. 2.4): one graph update
+// removes the active coupling elements whose removal changes the model least.
+// For the element J_ij(a,b) with pairwise model marginal p (chain frequency),
+// the symmetric Kullback-Leibler distance between the model and the model
+// without that element follows from Eq. (1):
+//   p' = p e^-J / (1 - p + p e^-J),   D = J (p - p') >= 0.
+// The k smallest (D, r1 Lq + r2) over active elements r1 < r2 are removed
+// (mask and J zeroed on both triangles), k = min(max(1, floor(drate n_act)),
+// n_act - ceil(density n_total)).
+//
+// Selection is an exact radix select on 64-bit keys (the IEEE bits of D >= 0
+// order like the values): eight passes of 8-bit digit histograms narrow the
+// key of the k-th smallest element; ties at that key are taken in index
+// order with a block-level scan.  Everything after the counts stays on the
+// device.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bmdca {
+
+constexpr uint64_t kNoKey = ~0ull;
+constexpr int kDecThreads = 256;
+
+// Select state (device): [0] prefix of the k-th key found so far, [1] its
+// mask of decided bits, [2] rank still to find inside the prefix, [3] k,
+// [4] n_act, [5] count of keys below the final key, [6] ties to take.
+struct DecState {
+  unsigned long long prefix, pmask, rank, k, n_act, below, ties, pad;
+};
+
+__global__ __launch_bounds__(kDecThreads) void k_dec_keys(const float* __restrict__ J,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const double* __restrict__ C, int64_t N,
+                                                          int L, int q,
+                                                          unsigned long long* __restrict__ keys,
+                                                          unsigned long long* __restrict__ n_act) {
+  __shared__ unsigned long long sh[kDecThreads / 64];
+  const int Lq = L * q;
+  const size_t total = (size_t)Lq * Lq;
+  unsigned long long cnt = 0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int r1 = (int)(e / Lq), r2 = (int)(e % Lq);
+    uint64_t key = kNoKey;
+    if (r1 < r2 && r1 / q != r2 / q && mask[e]) {
+      const double p = C[e] / (double)N;
+      const double Jv = (double)J[e];
+      const double ex = exp(-Jv);
+      const double d = 1.0 - p + p * ex;
+      const double pp = p * ex / d;
+      const double D = Jv * (p - pp);
+      key = (uint64_t)__double_as_longlong(D > 0.0 ? D : 0.0);
+      ++cnt;
+    }
+    keys[e] = key;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kDecThreads / 64; ++w) s += sh[w];
+    if (s) atomicAdd(n_act, s);
+  }
+}
+
+// k from the active count and the targets; rank = k (1-based k-th smallest).
+__global__ void k_dec_init(DecState* st, double drate, int64_t n_target) {
+  if (threadIdx.x != 0) return;
+  const int64_t n_act = (int64_t)st->n_act;
+  int64_t k = 0;
+  if (n_act > n_target) {
+    k = (int64_t)floor(drate * (double)n_act);
+    if (k < 1) k = 1;
+    if (k > n_act - n_target) k = n_act - n_target;
+  }
+  st->k = (unsigned long long)k;
+  st->rank = (unsigned long long)k;
+  st->prefix = 0;
+  st->pmask = 0;
+  st->below = 0;
+  st->ties = 0;
+}
+
+__global__ void k_dec_zero(unsigned long long* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Histogram of digit `shift` over the keys that match the decided prefix.
+__global__ __launch_bounds__(kDecThreads) void k_dec_hist(const unsigned long long* __restrict__ keys,
+                                                          size_t total, const DecState* st,
+                                                          int shift,
+                                                          unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int h[256];
+  if (st->k == 0) return;
+  for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const unsigned long long pm = st->pmask, pf = st->prefix;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const unsigned long long key = keys[e];
+    if (key != kNoKey && (key & pm) == pf) atomicAdd(&h[(key >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 256; b += blockDim.x)
+    if (h[b]) atomicAdd(hist + b, (unsigned long long)h[b]);
+}
+
+// Fix digit `shift`: the bin where the running count reaches the rank.
+__global__ void k_dec_pick(DecState* st, int shift, const unsigned long long* __restrict__ hist) {
+  if (threadIdx.x != 0 || st->k == 0) return;
+  unsigned long long run = 0;
+  int b = 0;
+  for (; b < 256; ++b) {
+    if (run + hist[b] >= st->rank) break;
+    run += hist[b];
+  }
+  st->rank -= run;
+  st->below += run;
+  st->prefix |= (unsigned long long)b << shift;
+  st->pmask |= 255ull << shift;
+}
+
+// After the last digit: `below` counts keys < x inside the matching prefix
+// only at each level, which adds up to all keys < x; ties = k - below.
+__global__ void k_dec_finish(DecState* st) {
+  if (threadIdx.x != 0 || st->k == 0) return;
+  st->ties = st->k - st->below;
+}
+
+// Per-block count of keys equal to x.
+__global__ __launch_bounds__(kDecThreads) void k_dec_tie_count(const unsigned long long* __restrict__ keys,
+                                                               size_t total, const DecState* st,
+                                                               unsigned long long* __restrict__ blk) {
+  __shared__ unsigned long long sh[kDecThreads / 64];
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long c = 0;
+  if (st->k != 0 && e < total && keys[e] == st->prefix) c = 1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kDecThreads / 64; ++w) s += sh[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of the block tie counts in block order (one thread).
+__global__ void k_dec_tie_scan(unsigned long long* __restrict__ blk, int64_t nblk) {
+  if (threadIdx.x != 0) return;
+  unsigned long long run = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    const unsigned long long c = blk[b];
+    blk[b] = run;
+    run += c;
+  }
+}
+
+// Remove keys < x, and keys == x whose index-order rank is below `ties`.
+__global__ __launch_bounds__(kDecThreads) void k_dec_apply(const unsigned long long* __restrict__ keys,
+                                                           size_t total, int Lq, const DecState* st,
+                                                           const unsigned long long* __restrict__ blk,
+                                                           float* __restrict__ J,
+                                                           uint8_t* __restrict__ mask) {
+  __shared__ unsigned int tie_prefix[kDecThreads];
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (st->k == 0) return;
+  const unsigned long long x = st->prefix;
+  const unsigned long long key = (e < total) ? keys[e] : kNoKey;
+  const unsigned int tie = (key == x) ? 1u : 0u;
+  // inclusive scan of ties inside the block (index order)
+  tie_prefix[threadIdx.x] = tie;
+  __syncthreads();
+  for (int o = 1; o < kDecThreads; o <<= 1) {
+    const unsigned int v = threadIdx.x >= o ? tie_prefix[threadIdx.x - o] : 0u;
+    __syncthreads();
+    tie_prefix[threadIdx.x] += v;
+    __syncthreads();
+  }
+  bool prune = key < x;
+  if (tie) prune = (blk[blockIdx.x] + tie_prefix[threadIdx.x] - 1) < st->ties;
+  if (prune && key != kNoKey) {
+    const int r1 = (int)(e / Lq), r2 = (int)(e % Lq);
+    mask[e] = 0;
+    mask[(size_t)r2 * Lq + r1] = 0;
+    J[e] = 0.0f;
+    J[(size_t)r2 * Lq + r1] = 0.0f;
+  }
+}
+
+__global__ void k_dec_out(const DecState* st, long long* n_active_out) {
+  if (threadIdx.x == 0) *n_active_out = (long long)(st->n_act - st->k);
+}
+
+size_t dec_ws_bytes(int L, int q) {
+  const size_t Lq = (size_t)L * q;
+  return align256(sizeof(unsigned long long) * Lq * Lq) + align256(sizeof(DecState)) +
+         align256(sizeof(unsigned long long) * 256) +
+         align256(sizeof(unsigned long long) * ceil_div(Lq * Lq, (size_t)kDecThreads));
+}
+
+hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, int L, int q,
+                           double drate, double density, long long* n_active_out, void* ws,
+                           hipStream_t s) {
+  const size_t Lq = (size_t)L * q;
+  const size_t total = Lq * Lq;
+  char* base = static_cast<char*>(ws);
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(base);
+  base += align256(sizeof(unsigned long long) * total);
+  DecState* st = reinterpret_cast<DecState*>(base);
+  base += align256(sizeof(DecState));
+  unsigned long long* hist = reinterpret_cast<unsigned long long*>(base);
+  base += align256(sizeof(unsigned long long) * 256);
+  unsigned long long* blk = reinterpret_cast<unsigned long long*>(base);
+  const int64_t nblk = (int64_t)ceil_div(total, (size_t)kDecThreads);
+
+  const int64_t n_total = (int64_t)L * (L - 1) / 2 * q * q;
+  const int64_t n_target = (int64_t)ceil(density * (double)n_total);
+  const unsigned grid = (unsigned)std::min<size_t>(ceil_div(total, (size_t)kDecThreads), 8192);
+  hipLaunchKernelGGL(k_dec_zero, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<unsigned long long*>(st), (int)(sizeof(DecState) / 8));
+  hipLaunchKernelGGL(k_dec_keys, dim3(grid), dim3(kDecThreads), 0, s, J, mask, C, N, L, q, keys,
+                     &st->n_act);
+  hipLaunchKernelGGL(k_dec_init, dim3(1), dim3(64), 0, s, st, drate, n_target);
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(k_dec_zero, dim3(4), dim3(64), 0, s, hist, 256);
+    hipLaunchKernelGGL(k_dec_hist, dim3(grid), dim3(kDecThreads), 0, s, keys, total, st, shift, hist);
+    hipLaunchKernelGGL(k_dec_pick, dim3(1), dim3(64), 0, s, st, shift, hist);
+  }
+  hipLaunchKernelGGL(k_dec_finish, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_dec_tie_count, dim3((unsigned)nblk), dim3(kDecThreads), 0, s, keys, total,
+                     st, blk);
+  hipLaunchKernelGGL(k_dec_tie_scan, dim3(1), dim3(64), 0, s, blk, nblk);
+  hipLaunchKernelGGL(k_dec_apply, dim3((unsigned)nblk), dim3(kDecThreads), 0, s, keys, total,
+                     (int)Lq, st, blk, J, mask);
+  if (n_active_out)
+    hipLaunchKernelGGL(k_dec_out, dim3(1), dim3(64), 0, s, st, n_active_out);
+  return hipGetLastError();
+}
+
+}  // namespace bmdca

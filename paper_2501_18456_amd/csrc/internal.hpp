@@ -86,7 +86,7 @@ hipError_t launch_pearson(const double* f1, const double* f2, const double* C, i
                           int q, double* red, double* out, int32_t* dev_err, hipStream_t s);
 hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
                          int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s,
-                         const int32_t* active = nullptr);
+                         const int32_t* active = nullptr, const uint8_t* mask = nullptr);
 // Group epoch epilogue of one model: if active, epoch += 1 and, with a
 // positive target, active = 0 once the Pearson coefficient reaches it.
 hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s);
@@ -119,6 +119,13 @@ hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int 
 size_t apc_ws_bytes(int L);
 hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fapc, void* ws,
                       hipStream_t s);
+
+// ----- decimation.hip
+size_t dec_ws_bytes(int L, int q);
+// One edDCA graph update from the chain counts C (FP64 [Lq][Lq]).
+hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, int L, int q,
+                           double drate, double density, long long* n_active_out, void* ws,
+                           hipStream_t s);
 
 // ----- equilibrium.hip
 size_t draw_ws_bytes(int64_t M);

@@ -96,7 +96,8 @@ hipError_t launch_pearson(const double* f1, const double* f2, const double* C, i
 __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
                          const double* __restrict__ f1, const double* __restrict__ f2,
                          const double* __restrict__ C, int64_t N, int L, int q, double lr,
-                         int32_t* dev_err, const int32_t* __restrict__ active) {
+                         int32_t* dev_err, const int32_t* __restrict__ active,
+                         const uint8_t* __restrict__ mask) {
   if (active && *active == 0) return;
   const int Lq = L * q;
   const size_t total = (size_t)Lq * Lq;
@@ -105,7 +106,7 @@ __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
        k += (size_t)gridDim.x * blockDim.x) {
     const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
-    if (r1 / q == r2 / q) {
+    if (r1 / q == r2 / q || (mask && !mask[k])) {  // diagonal block or pruned element
       J[k] = 0.0f;
       continue;
     }
@@ -128,11 +129,11 @@ __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
 
 hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
                          int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s,
-                         const int32_t* active) {
+                         const int32_t* active, const uint8_t* mask) {
   const size_t total = (size_t)L * q * (size_t)L * q;
   const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 16384);
   hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, s, h, J, f1, f2, C, N, L, q, lr, dev_err,
-                     active);
+                     active, mask);
   return hipGetLastError();
 }
 
