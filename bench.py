@@ -473,7 +473,7 @@ def bench_scoring(args):
     for _ in range(args.steps):
         F, Fa = api.apc_frobenius(Jg, L, q, 0)
     apc_ms = t.stop_ms() / args.steps
-    apc_bytes = Lq * Lq * 4
+    apc_bytes = Lq * Lq * 4 // 2  # J is symmetric: the blocks j > i are read once
     log(f"APC Frobenius L={L}: {apc_ms:.2f} ms, {apc_bytes / (apc_ms * 1e-3) / 1e9:.0f} GB/s")
     out = {
         "metric": METRIC, "value": Bn / (en_ms * 1e-3), "unit": "sequences/s", "n_gpus": 1,

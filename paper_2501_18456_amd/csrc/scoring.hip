@@ -232,91 +232,114 @@ hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int 
 }
 
 // ---------------------------------------------------------------------------
-// APC Frobenius.  k_frob: one workgroup per unordered pair i < j; the q x q
-// block is moved to the zero-sum gauge over all states (FP64) and the squares
-// of the entries with a, b != gap are summed (fixed tree).  k_apc: row sums
-// S_i in ascending k, the total in ascending i, F_apc = F - S_i S_j / S.
+// APC Frobenius.  k_frob_rows: a workgroup owns block-row i and one chunk of
+// 16 sites j (only j > i are blocks): the q x 16q tile of rows (i, a) is read
+// coalesced into LDS, and 16 threads per block move it to the zero-sum gauge
+// over all states (FP64 row, column and total means) and sum the squares of
+// the entries with a, b != gap; F_ij = F_ji = sqrt of that sum.  J is read
+// once.  k_apc_rows: S_i = sum_k F_ik (one wave per row); k_apc_total: the
+// total in ascending i; k_apc_out: F_apc = F - S_i S_j / S, diagonals 0.
 // ---------------------------------------------------------------------------
+constexpr int kFJC = 16;
+
 size_t apc_ws_bytes(int L) { return align256(sizeof(double) * ((size_t)L * L + L + 8)); }
 
-__global__ __launch_bounds__(256) void k_frob(const float* __restrict__ J, int L, int q, int gap,
-                                              double* __restrict__ F) {
-  __shared__ double blk[32 * 32];
-  __shared__ double rm[32], cm[32];
-  __shared__ double sh[16];
-  int t = blockIdx.x, i = 0;
-  while (t >= L - 1 - i) {
-    t -= L - 1 - i;
-    ++i;
-  }
-  const int j = i + 1 + t;
+__global__ __launch_bounds__(256) void k_frob_rows(const float* __restrict__ J, int L, int q,
+                                                   int gap, double* __restrict__ F) {
+  extern __shared__ float tile[];  // q x (16 q)
+  const int i = blockIdx.y;
+  const int j0 = blockIdx.x * kFJC;
   const int Lq = L * q;
-  for (int k = threadIdx.x; k < q * q; k += blockDim.x) {
-    const int a = k / q, b = k % q;
-    blk[k] = (double)J[(size_t)(i * q + a) * Lq + j * q + b];
-  }
-  __syncthreads();
-  if (threadIdx.x < q) {
-    double s = 0.0;
-    for (int b = 0; b < q; ++b) s += blk[threadIdx.x * q + b];
-    rm[threadIdx.x] = s / (double)q;
-  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + q) {
-    const int b = threadIdx.x - 64;
-    double s = 0.0;
-    for (int a = 0; a < q; ++a) s += blk[a * q + b];
-    cm[b] = s / (double)q;
-  }
-  __syncthreads();
-  double all = 0.0;
-  for (int a = 0; a < q; ++a) all += rm[a];
-  all /= (double)q;
-  double ss = 0.0;
-  for (int k = threadIdx.x; k < q * q; k += blockDim.x) {
-    const int a = k / q, b = k % q;
-    if (a == gap || b == gap) continue;
-    const double z = blk[k] - rm[a] - cm[b] + all;
-    ss += z * z;
-  }
-  const double tot = block_sum_f64(ss, sh);
-  if (threadIdx.x == 0) {
-    const double f = sqrt(tot);
-    F[(size_t)i * L + j] = f;
-    F[(size_t)j * L + i] = f;
+  const int W = kFJC * q;
+  const int jb = threadIdx.x / 16, t = threadIdx.x % 16;  // block of the chunk, thread in it
+  if (j0 == 0 && threadIdx.x == 0) F[(size_t)i * L + i] = 0.0;  // never read as a pair
+  if (j0 + kFJC - 1 <= i) return;  // no j > i in this chunk (whole workgroup)
+  {
+    const int nj = min(kFJC, L - j0);
+    for (int e = threadIdx.x; e < q * nj * q; e += blockDim.x) {
+      const int a = e / (nj * q), c = e % (nj * q);
+      tile[a * W + c] = J[(size_t)(i * q + a) * Lq + (size_t)j0 * q + c];
+    }
+    __syncthreads();
+    if (jb < nj && j0 + jb > i) {
+      const float* blk = tile + jb * q;  // element (a, b) at blk[a * W + b]
+      // row means over b and column means over a (t covers rows/cols t, t+16)
+      double rs[2] = {0.0, 0.0}, cs[2] = {0.0, 0.0};
+      for (int u = 0; u < 2; ++u) {
+        const int r = t + 16 * u;
+        if (r < q)
+          for (int k = 0; k < q; ++k) {
+            rs[u] += (double)blk[r * W + k];
+            cs[u] += (double)blk[k * W + r];
+          }
+      }
+      // all threads of the group need every row/column mean: share through
+      // shuffles within the 16-lane group
+      double all = 0.0;
+      for (int u = 0; u < 2; ++u) all += rs[u];
+      for (int o = 8; o > 0; o >>= 1) all += __shfl_xor(all, o, 16);
+      const double mean_all = all / ((double)q * (double)q);
+      double ss = 0.0;
+      for (int a = 0; a < q; ++a) {
+        const double ra = __shfl(rs[a / 16], a % 16, 16) / (double)q;
+        for (int u = 0; u < 2; ++u) {
+          const int b = t + 16 * u;
+          if (b < q && a != gap && b != gap) {
+            const double z = (double)blk[a * W + b] - ra - cs[u] / (double)q + mean_all;
+            ss += z * z;
+          }
+        }
+      }
+      for (int o = 8; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 16);
+      if (t == 0) {
+        const double f = sqrt(ss);
+        const int j = j0 + jb;
+        F[(size_t)i * L + j] = f;
+        F[(size_t)j * L + i] = f;
+      }
+    }
   }
 }
 
-__global__ __launch_bounds__(1024) void k_apc(double* __restrict__ F, int L,
-                                              float* __restrict__ Fout,
-                                              float* __restrict__ Fapc) {
-  extern __shared__ double S[];  // L + 1
-  for (int i = threadIdx.x; i < L; i += blockDim.x) {
-    F[(size_t)i * L + i] = 0.0;
-    double s = 0.0;
-    for (int k = 0; k < L; ++k) s += (k == i) ? 0.0 : F[(size_t)i * L + k];
-    S[i] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int i = 0; i < L; ++i) tot += S[i];
-    S[L] = tot;
-  }
-  __syncthreads();
-  const double tot = S[L];
-  for (size_t k = threadIdx.x; k < (size_t)L * L; k += blockDim.x) {
-    const int i = (int)(k / L), j = (int)(k % L);
-    const double f = (i == j) ? 0.0 : F[k];
-    if (Fout) Fout[k] = (float)f;
-    Fapc[k] = (i == j) ? 0.0f : (float)(f - S[i] * S[j] / tot);
-  }
+__global__ __launch_bounds__(256) void k_apc_rows(const double* __restrict__ F, int L,
+                                                  double* __restrict__ S) {
+  const int lane = threadIdx.x % 64;
+  const int i = blockIdx.x * 4 + threadIdx.x / 64;
+  if (i >= L) return;
+  double s = 0.0;
+  for (int k = lane; k < L; k += 64) s += (k == i) ? 0.0 : F[(size_t)i * L + k];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) S[i] = s;
+}
+
+__global__ void k_apc_total(double* __restrict__ S, int L) {
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int i = 0; i < L; ++i) tot += S[i];
+  S[L] = tot;
+}
+
+__global__ void k_apc_out(const double* __restrict__ F, const double* __restrict__ S, int L,
+                          float* __restrict__ Fout, float* __restrict__ Fapc) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (size_t)L * L) return;
+  const int i = (int)(k / L), j = (int)(k % L);
+  const double f = (i == j) ? 0.0 : F[k];
+  if (Fout) Fout[k] = (float)f;
+  Fapc[k] = (i == j) ? 0.0f : (float)(f - S[i] * S[j] / S[L]);
 }
 
 hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fapc, void* ws,
                       hipStream_t s) {
   double* Fd = static_cast<double*>(ws);
-  const int npairs = L * (L - 1) / 2;
-  hipLaunchKernelGGL(k_frob, dim3((unsigned)npairs), dim3(256), 0, s, J, L, q, gap, Fd);
-  hipLaunchKernelGGL(k_apc, dim3(1), dim3(1024), sizeof(double) * (L + 1), s, Fd, L, F, Fapc);
+  double* S = Fd + (size_t)L * L;
+  const size_t lds = sizeof(float) * (size_t)q * kFJC * q;
+  hipLaunchKernelGGL(k_frob_rows, dim3((unsigned)ceil_div(L, kFJC), (unsigned)L), dim3(256), lds, s,
+                     J, L, q, gap, Fd);
+  hipLaunchKernelGGL(k_apc_rows, dim3((unsigned)ceil_div(L, 4)), dim3(256), 0, s, Fd, L, S);
+  hipLaunchKernelGGL(k_apc_total, dim3(1), dim3(64), 0, s, S, L);
+  hipLaunchKernelGGL(k_apc_out, dim3((unsigned)ceil_div((size_t)L * L, (size_t)256)), dim3(256), 0,
+                     s, Fd, S, L, F, Fapc);
   return hipGetLastError();
 }
 
