@@ -204,78 +204,120 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 //
 //   - Each call first copies J into the workspace as Jt[i][j][b][a'] (a'
 //     padded to QP = q rounded up to 4, pad entries 0): Jt[i][j][b][a] =
-//     J_ij(a, b) = J[(j,b)][(i,a)].  Site i's blocks are then one contiguous
-//     L*q*QP run and the row a' = 0..QP-1 a chain needs is 16-byte aligned.
+//     J_ij(a, b) = J[(j,b)][(i,a)].  Site i's blocks are one contiguous
+//     L*q*QP run, and the row a' = 0..QP-1 a chain needs is QP/4 16-byte
+//     quads.
 //   - Site i's run is streamed into LDS in chunks of JC sites by direct
-//     global->LDS loads issued ahead of use into a ring of slots.
-//   - G lanes serve one chain; lane g owns the R = JC/G consecutive sites
-//     g*R .. g*R+R-1 of every chunk, reads their tokens with one LDS load, and
-//     adds the row of each with QP/4 16-byte LDS loads.
-//   - At the end of the site the G partial sums meet by xor-shuffles (the same
-//     value in every lane of the chain), all G lanes run the same draw and lane
-//     g = 0 stores the new token.
+//     buffer->LDS loads, A chunks ahead of use, into a ring of A + 1 slots.
+//     JC is chosen per (L, q) to fill the LDS left over by the tokens.
+//   - Each chain owns 8 consecutive lanes, lane p = u * V + v (V = QP/4
+//     rounded up to a power of two, S = 8 / V site groups): lane (u, v) adds
+//     quad v of the rows of the sites j = u, u + S, u + 2S, ... of every
+//     chunk.  For q > 16 (S = 1) the 8 lanes of a chain read one row as
+//     contiguous quads, so the eight lanes the LDS serves together hit
+//     distinct banks; lanes v >= QP/4 stay idle.
+//   - Tokens live in LDS as bytes, position (j mod S, j div S), so that a
+//     lane reads the tokens of its next four sites with one 32-bit load.
+//   - At the end of the site the S partial quads meet by xor-shuffles, and
+//     the draw runs across the V lanes of a quad group: group max, FP32
+//     exponentials, an inclusive scan of the quad sums over v, the total
+//     S_{q-1} broadcast from the lane that holds state q-1, and a count of
+//     the states a <= q-2 with S_a <= u S_{q-1} summed over v.  Lane p = 0
+//     stores the new token.
 // Draw rule and Philox counters are those of the field form (the CDF test
 // S_a / S_{q-1} <= u is evaluated as S_a <= u * S_{q-1}).
 //
-// Synchronisation: one workgroup barrier per chunk-step.  The slot written at
-// step t + A (A = loads ahead, ring of A + 2 slots) was last read at step
-// t + A - (A + 2) = t - 2, which every wave finished before the barrier of
-// step t - 1; the loads of step t are complete once at most the A younger
-// steps' loads are outstanding (s_waitcnt vmcnt).
+// Synchronisation: one workgroup barrier per chunk-step.  Before it, each
+// wave waits for its share of the current chunk (vmcnt: at most the A - 1
+// younger chunks outstanding) and for its own LDS reads of the previous step
+// (lgkmcnt 0).  After it, the slot of the previous step is free for every
+// wave and receives the chunk A steps ahead.  A chain's tokens are read and
+// written only by its own lanes (one wave, LDS in order), so token updates
+// need no barrier.
 // ---------------------------------------------------------------------------
-#ifndef BMDCA_GATHER_G
-#define BMDCA_GATHER_G 4
-#endif
-#ifndef BMDCA_GATHER_W
-#define BMDCA_GATHER_W 4
-#endif
-#ifndef BMDCA_GATHER_ODD_QUADS
-#define BMDCA_GATHER_ODD_QUADS 0
-#endif
-constexpr int kGG = BMDCA_GATHER_G;   // lanes per chain
-constexpr int kGWv = BMDCA_GATHER_W;  // waves per workgroup
-constexpr int kGR = kGG >= 4 ? 16 / kGG : 4;  // sites per lane per chunk (divides 4)
-constexpr int kGJC = kGG * kGR;       // sites per chunk
+constexpr int kGLanes = 8;       // lanes per chain
+constexpr int kGMaxWaves = 16;   // waves per workgroup at most
+constexpr int kGMinWaves = 4;    // and at least
+// 1 KB loads per loading wave per chunk: a compile-time count (8, 16 or 31),
+// so that the wait for a chunk is an immediate; 31 keeps two younger chunks
+// within vmcnt's range.
+constexpr size_t kGLds = 160 * 1024 - 256;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Row pitch of Jt: q rounded up to a multiple of 4 floats (16-byte rows); with
-// an odd number of 16-byte quads per row, consecutive rows start in 8
-// different LDS bank groups, which keeps the 16-byte gathers of lanes that
-// read different rows mostly conflict-free.
-__host__ __device__ constexpr int gather_qp(int q) {
-  return BMDCA_GATHER_ODD_QUADS ? ((((q + 3) / 4) % 2) ? ((q + 3) & ~3) : ((q + 3) & ~3) + 4)
-                                : ((q + 3) & ~3);
+// Row pitch of Jt: q rounded up to a multiple of 4 floats (16-byte quads).
+__host__ __device__ constexpr int gather_qp(int q) { return (q + 3) & ~3; }
+// Lanes per quad group: quads per row rounded up to a power of two.
+__host__ __device__ constexpr int gather_v(int q) {
+  return gather_qp(q) / 4 <= 1 ? 1 : gather_qp(q) / 4 <= 2 ? 2 : gather_qp(q) / 4 <= 4 ? 4 : 8;
 }
-
-// 16-byte loads per thread per chunk-step.
-__host__ __device__ constexpr int gather_items(int q) {
-  return (kGJC * q * gather_qp(q) + 4 * kGWv * 64 - 1) / (4 * kGWv * 64);
-}
+// Site groups per chain.
+__host__ __device__ constexpr int gather_s(int q) { return kGLanes / gather_v(q); }
 
 struct GatherShape {
-  int ahead;   // chunk-steps loaded ahead (ring = ahead + 2 slots)
-  int slot;    // floats per slot
-  size_t lds;  // dynamic LDS bytes
+  int waves;      // waves per workgroup
+  int cpb;        // chains per workgroup
+  int jc;         // sites per chunk (multiple of 4 S)
+  int nchunk;     // chunks per site
+  int m4;         // token dwords per (chain, site group)
+  int ahead;      // chunks in flight (ring = ahead + 1 slots)
+  int items;      // 1 KB loads per loading wave per chunk
+  int nload;      // loading waves (waves 0..nload-1; wave w loads blocks w*items ...)
+  int slot;       // floats per ring slot (nload * items KB)
+  size_t lds;     // dynamic LDS bytes
+  unsigned blocks;
 };
 
-static GatherShape gather_shape(int L, int q) {
-  const int slot = 4 * kGWv * 64 * gather_items(q);
-  const size_t tok = (size_t)((L + 3) / 4) * ((64 / kGG) * kGWv) * sizeof(uint32_t);
-  for (int ahead = 2; ahead >= 1; --ahead) {
-    const size_t lds = (size_t)(ahead + 2) * slot * sizeof(float) + tok;
-    if (lds <= 160 * 1024 - 256) return {ahead, slot, lds};
-  }
-  return {0, 0, 0};
+// Token bytes per chain.
+static size_t gather_tok_bytes(int L, int q) {
+  const int S = gather_s(q);
+  return (size_t)S * (size_t)ceil_div(ceil_div(L, S), 4) * 4;
 }
 
-bool gather_supported(int L, int q) { return L <= 512 && q <= 32 && gather_shape(L, q).ahead > 0; }
+// Shape for `cpb` chains per workgroup; waves = 0 if it does not fit.
+static GatherShape gather_shape(int L, int q, int cpb) {
+  GatherShape g{};
+  const int S = gather_s(q);
+  const size_t site_row = (size_t)q * gather_qp(q) * sizeof(float);  // bytes per site of a chunk
+  // at least 4 waves, one per SIMD, to spread the chunk loads and barriers
+  g.waves = std::max<int>(kGMinWaves, (int)ceil_div(cpb, 64 / kGLanes));
+  if (g.waves < 1 || g.waves > kGMaxWaves) return GatherShape{};
+  const size_t tok = gather_tok_bytes(L, q) * (size_t)(g.waves * (64 / kGLanes));
+  const int nslot = 4;
+  if (tok >= kGLds) return GatherShape{};
+  const size_t per_slot = std::min((kGLds - tok) / nslot, (size_t)31 * g.waves * 1024);
+  const int lcap = (int)ceil_div(L, 4 * S) * 4 * S;
+  // largest chunk whose slot, padded to whole 16-byte loads per thread, fits
+  for (int jc = std::min((int)(per_slot / site_row) / (4 * S) * (4 * S), lcap); jc >= 4 * S;
+       jc -= 4 * S) {
+    g.nchunk = (int)ceil_div(L, jc);
+    g.jc = (int)ceil_div(ceil_div(L, g.nchunk), 4 * S) * 4 * S;  // balanced chunks
+    g.nchunk = (int)ceil_div(L, g.jc);
+    g.m4 = (int)ceil_div(ceil_div(L, S), 4);
+    g.ahead = nslot - 1;
+    g.cpb = cpb;
+    const int nblk = (int)ceil_div((size_t)g.jc * site_row, 1024);
+    for (int it : {8, 16, 31}) {  // the least padding that the waves can load
+      g.items = it;
+      g.nload = (int)ceil_div(nblk, it);
+      g.slot = g.nload * it * 256;
+      g.lds = (size_t)nslot * g.slot * sizeof(float) + tok;
+      if (g.nload <= g.waves && g.lds <= kGLds) return g;
+    }
+  }
+  return GatherShape{};
+}
+
+bool gather_supported(int L, int q) {
+  return L >= 1 && L <= 512 && q >= 2 && q <= 32 && gather_shape(L, q, 1).waves > 0;
+}
 
 size_t gather_ws_bytes(int L, int q) {
   return align256(sizeof(float) * (size_t)L * L * q * gather_qp(q));
 }
 
-// Jt[i][j][b][a'] = J[(j*q + b)][(i*q + a')] for a' < q, else 0.
+// Jt[i][j][b][a'] = J[(j*q + b)][(i*q + a')] for a' < q and j != i, else 0
+// (the block j = i is zero, so the sum over j may include it).
 __global__ void k_gather_layout(const float* __restrict__ J, int L, int q, float* __restrict__ Jt,
                                 const int32_t* __restrict__ active) {
   if (active && *active == 0) return;
@@ -289,38 +331,110 @@ __global__ void k_gather_layout(const float* __restrict__ J, int L, int q, float
     const int b = (int)(r % q);
     const size_t ij = r / q;
     const int j = (int)(ij % L), i = (int)(ij / L);
-    Jt[e] = (a < q) ? J[((size_t)j * q + b) * Lq + (size_t)i * q + a] : 0.0f;
+    Jt[e] = (a < q && j != i) ? J[((size_t)j * q + b) * Lq + (size_t)i * q + a] : 0.0f;
   }
 }
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-template <int Q>
-__global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
+// s_waitcnt vmcnt(N) lgkmcnt(0), N in [0, 63].
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0070);
+}
+
+// Lane exchanges inside the aligned 8-lane group of a chain with no LDS
+// traffic: DPP quad permutations, row shifts and the half-row mirror; the
+// xor-4 exchange by ds_swizzle.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7-i of each 8
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114;  // lane i <- lane i-k
+__device__ __forceinline__ float swz_xor4(float x) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x101F));
+}
+// over the V lanes of a quad group (V = 1, 2, 4, 8; groups aligned)
+template <int V>
+__device__ __forceinline__ float group_max(float x) {
+  if (V >= 2) x = fmaxf(x, dpp_f<kDppXor1>(x));
+  if (V >= 4) x = fmaxf(x, dpp_f<kDppXor2>(x));
+  if (V >= 8) x = fmaxf(x, dpp_f<kDppHalfMirror>(x));
+  return x;
+}
+template <int V>
+__device__ __forceinline__ int group_sum(int x) {
+  if (V >= 2) x += dpp_i<kDppXor1>(x);
+  if (V >= 4) x += dpp_i<kDppXor2>(x);
+  if (V >= 8) x += dpp_i<kDppHalfMirror>(x);
+  return x;
+}
+// inclusive prefix sum over v = 0..V-1
+template <int V>
+__device__ __forceinline__ float group_scan(float x, int v) {
+  if (V >= 2) { const float y = dpp_f<kDppShr1>(x); if (v >= 1) x += y; }
+  if (V >= 4) { const float y = dpp_f<kDppShr2>(x); if (v >= 2) x += y; }
+  if (V >= 8) { const float y = dpp_f<kDppShr4>(x); if (v >= 4) x += y; }
+  return x;
+}
+// value of lane SRC of the group, in every lane of it
+template <int V, int SRC>
+__device__ __forceinline__ float group_bcast(float x, int v) {
+  if constexpr (V == 1) {
+    return x;
+  } else if constexpr (V == 2) {
+    return dpp_f<SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6)>(x);
+  } else if constexpr (V == 4) {
+    return dpp_f<SRC * 0x55>(x);
+  } else {
+    const float x1 = dpp_f<(SRC & 3) * 0x55>(x);  // lane SRC%4 of each quad
+    const float x2 = dpp_f<kDppHalfMirror>(x1);   // the other quad's
+    return ((v & 4) == (SRC & 4)) ? x1 : x2;
+  }
+}
+// sum over the S = 8 / V site groups (lanes with the same v)
+template <int V>
+__device__ __forceinline__ float combine_sites(float x) {
+  if (V <= 1) x += dpp_f<kDppXor1>(x);
+  if (V <= 2) x += dpp_f<kDppXor2>(x);
+  if (V <= 4) x += swz_xor4(x);
+  return x;
+}
+
+template <int Q, int IT>
+__global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
-    int64_t N, int L, int ahead, int slot, int cpb, int sweeps, uint32_t k0, uint32_t k1,
-    uint64_t sweep_offset, float beta, unsigned long long* flips_out, int32_t* dev_err,
-    const uint64_t* __restrict__ epoch, const int32_t* __restrict__ run,
-    const ChainStream* __restrict__ streams) {
+    int64_t N, int L, int jc, int nchunk, int m4, int ahead, int nload, int slot, int cpb,
+    int sweeps, uint32_t k0, uint32_t k1, uint64_t sweep_offset, float beta,
+    unsigned long long* flips_out, int32_t* dev_err, const uint64_t* __restrict__ epoch,
+    const int32_t* __restrict__ run, const ChainStream* __restrict__ streams) {
   if (run && *run == 0) return;  // whole grid leaves before any barrier
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
-  constexpr int G = kGG, W = kGWv, R = kGR, JC = kGJC;
-  constexpr int kT = W * 64, kCPW = 64 / G, kCPB = kCPW * W;
-  constexpr int QP = gather_qp(Q), kQ4 = QP / 4;
-  constexpr int kP = gather_items(Q);
+  constexpr int QP = gather_qp(Q), NQ = QP / 4, V = gather_v(Q), S = gather_s(Q);
+  constexpr int vL = (Q - 1) / 4, eL = (Q - 1) % 4;  // lane and slot of state q-1
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ __attribute__((aligned(16))) unsigned char g_smem[];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int cl = lane % kCPW, g = lane / kCPW;
-  const int cb = wid * kCPW + cl;  // chain slot in the workgroup
-  const int nslot = ahead + 2;
+  const int T = blockDim.x, CPB = T / kGLanes;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int p = lane & (kGLanes - 1), u = p / V, v = p % V;
+  const int cb = tid / kGLanes;  // chain slot in the workgroup
+  const int nslot = ahead + 1;
   float* ring = reinterpret_cast<float*>(g_smem);                             // [nslot][slot]
-  uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [L/4][kCPB]
+  uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [S][m4][CPB]
   unsigned char* tokb = reinterpret_cast<unsigned char*>(tokw);
-  const int L4 = (L + 3) >> 2;
   const int64_t c = (int64_t)blockIdx.x * cpb + cb;
   const bool has_chain = cb < cpb;
   const bool active = has_chain && (c < N);
+  const bool reader = has_chain && v < NQ;
   uint32_t cid = (uint32_t)c;
   if (streams && active) {
     const ChainStream st = streams[c];
@@ -329,40 +443,48 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
     cid = st.chain;
     sweep_offset += st.sweep_offset;
   }
-  const int nchunk = (L + JC - 1) / JC;
-  const uint32_t site_bytes = (uint32_t)((size_t)L * Q * QP * sizeof(float));
-  const uint32_t chunk_bytes = (uint32_t)(JC * Q * QP * sizeof(float));
+  // byte of the token of site j in the chain's token area
+  auto tok_at = [&](int j) -> unsigned char* {
+    const int m = j / S;
+    return tokb + ((size_t)((j % S) * m4 + (m >> 2)) * CPB + cb) * 4 + (m & 3);
+  };
 
-  for (int k = g; k < L4; k += G) {
-    uint32_t v = 0;
+  for (int k = p; k < S * m4; k += kGLanes) {  // dword k = (site group, 4 positions)
+    const int uu = k / m4, mq = k % m4;
+    uint32_t w = 0;
     for (int e = 0; e < 4; ++e) {
-      const int j = 4 * k + e;
+      const int j = S * (4 * mq + e) + uu;
       int t = 0;
       if (active && j < L) t = checked_token(chains[c * L + j], Q, dev_err);
-      v |= (uint32_t)t << (8 * e);
+      w |= (uint32_t)t << (8 * e);
     }
-    tokw[k * kCPB + cb] = v;
+    tokw[k * CPB + cb] = w;
   }
 
-  // Chunk-step (i, k) -> ring slot sl: bytes [k*chunk_bytes, +chunk_bytes) of
+  const uint32_t site_bytes = (uint32_t)((size_t)L * Q * QP * sizeof(float));
+  const uint32_t chunk_bytes = (uint32_t)((size_t)jc * Q * QP * sizeof(float));
+  // Chunk-step (i, k) -> ring slot sl: bytes [k*chunk_bytes, +slot bytes) of
   // site i's run, read through a buffer resource that ends with the run (the
-  // hardware returns 0 past it).  Item p of this thread is the 16 bytes at
-  // 16*(tid + kT*p) of the slot.
+  // hardware returns 0 past it), as 1 KB blocks: loading wave w < nload
+  // issues exactly IT of them, blocks w*IT .. w*IT+IT-1, lane l the 16 bytes
+  // at 16 l of each.  Bytes past the chunk land in the slot's padding.
+  const bool loader = wid < nload;
   auto issue_chunk = [&](int i, int k, int sl) {
     const uint32_t off = (uint32_t)i * site_bytes + (uint32_t)k * chunk_bytes;
     const uint32_t left = site_bytes - (uint32_t)k * chunk_bytes;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(reinterpret_cast<const char*>(Jt) + off), (short)0, (int)left, 0x00020000);
-    float* dst0 = ring + (size_t)sl * slot;
+    float* dst0 = ring + (size_t)sl * slot + 256 * IT * wid;
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
-      float* dst = dst0 + 4 * (wid * 64 + kT * p);  // wave-uniform base; lane adds 16*lane
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)dst, 16, 16 * (tid + kT * p), 0, 0, 0);
+    for (int it = 0; it < IT; ++it) {
+      float* dst = dst0 + 256 * it;  // wave-uniform base; lane adds 16*lane
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)dst, 16,
+                                               1024 * (IT * wid + it) + 16 * lane, 0, 0, 0);
     }
   };
 
-  const int64_t T = (int64_t)sweeps * L * nchunk;
-  // prefetch cursor: step tn = t + ahead, as (site, chunk, slot)
+  const int64_t Tn = (int64_t)sweeps * L * nchunk;
+  // prefetch cursor: the next chunk-step to issue, as (site, chunk, slot)
   int pi = 0, pk = 0, psl = 0;
   auto advance = [&](int& ii, int& kk, int& sl) {
     if (++kk == nchunk) {
@@ -371,95 +493,117 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
     }
     if (++sl == nslot) sl = 0;
   };
-  for (int64_t t = 0; t < ahead && t < T; ++t) {
-    issue_chunk(pi, pk, psl);
+  for (int64_t t = 0; t < ahead && t < Tn; ++t) {
+    if (loader) issue_chunk(pi, pk, psl);
     advance(pi, pk, psl);
   }
 
-  float acc[QP];
-  float hreg[Q];
-#pragma unroll
-  for (int a = 0; a < QP; ++a) acc[a] = 0.0f;
+  f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  float hq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   unsigned long long nflip = 0;
+  const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
-  for (int64_t t = 0; t < T; ++t) {
-    if (k == 0) {
-#pragma unroll
-      for (int a = 0; a < Q; ++a) hreg[a] = h[i * Q + a];  // used at the draw of site i
-    }
-    const int64_t rest = T - 1 - t;  // steps after this one
-    if (rest >= ahead) {
-      issue_chunk(pi, pk, psl);
-      advance(pi, pk, psl);
-    }
+  for (int64_t t = 0; t < Tn; ++t) {
+    // chunk t is complete once at most the younger issued chunks (two at
+    // most: ahead = 3) are pending
+    const int64_t rest = Tn - 1 - t;
     compiler_fence();
-    // this step's loads are done once at most the younger steps' are pending
-    const int64_t younger = rest < ahead ? rest : ahead;
-    if (younger >= 2) {
-      __builtin_amdgcn_s_waitcnt(((2 * kP) & 15) | (((2 * kP) >> 4) << 14) | 0x0F70);
-    } else if (younger == 1) {
-      __builtin_amdgcn_s_waitcnt((kP & 15) | ((kP >> 4) << 14) | 0x0F70);
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-    }
+    if (rest >= 2)
+      wait_vm_lgkm0<2 * IT>();
+    else if (rest == 1)
+      wait_vm_lgkm0<IT>();
+    else
+      wait_vm_lgkm0<0>();
     __builtin_amdgcn_s_barrier();
     compiler_fence();
-
-    // ---- this lane's R sites of the chunk
-    const float* jb = ring + (size_t)csl * slot;
-    const int j0 = k * JC + g * R;
-    if (has_chain && j0 < L) {
-      // the R tokens of j0 .. j0+R-1 share one dword (R divides 4 and j0 % R == 0)
-      const uint32_t tk = tokw[(j0 >> 2) * kCPB + cb] >> (8 * (j0 & 3));
+    if (t + ahead < Tn) {
+      if (loader) issue_chunk(pi, pk, psl);
+      advance(pi, pk, psl);
+    }
+    if (k == 0) {
+      // h_i for this lane's quad (scalar loads of the row, lane select)
+      float hs[Q];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int j = j0 + r;
-        if (j < L && j != i) {
-          const int s = (int)((tk >> (8 * r)) & 0xFF);
-          const f4* row = reinterpret_cast<const f4*>(jb + ((g * R + r) * Q + s) * QP);
+      for (int a = 0; a < Q; ++a) hs[a] = h[i * Q + a];
 #pragma unroll
-          for (int v = 0; v < kQ4; ++v) {
-            const f4 x = row[v];
-            acc[4 * v + 0] += x[0];
-            acc[4 * v + 1] += x[1];
-            acc[4 * v + 2] += x[2];
-            acc[4 * v + 3] += x[3];
-          }
-        }
+      for (int e = 0; e < 4; ++e) {
+        float x = 0.0f;
+#pragma unroll
+        for (int vv = 0; vv < NQ; ++vv)
+          if (4 * vv + e < Q && v == vv) x = hs[4 * vv + e];
+        hq[e] = x;
       }
+    }
+
+    // ---- this lane's sites of the chunk: j = k*jc + S*r + u, r < jc/S.
+    // The rows of j = i (zero block) and of j >= L (past the end of the run,
+    // loaded as zeros) add nothing, so every position is added
+    // unconditionally; positions past the last token dword read any valid
+    // token.  Groups of 16 positions: 4 token loads, 16 row loads, the adds.
+    if (reader) {
+      const float* jb = ring + (size_t)csl * slot + 4 * v;
+      const int m0 = k * jcs;  // multiple of 4
+      const uint32_t* tw = tokw + (size_t)u * m4 * CPB + cb;
+      auto group = [&](int r0, bool tail) {
+        uint32_t tk[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) tk[d] = tw[min(((m0 + r0) >> 2) + d, m4 - 1) * CPB];
+        f4 x[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int s = (int)((tk[e >> 2] >> (8 * (e & 3))) & 0xFF);
+          const int r = tail ? min(r0 + e, jcs - 1) : r0 + e;
+          x[e] = *reinterpret_cast<const f4*>(jb + ((S * r + u) * Q + s) * QP);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          if (!tail || r0 + e < jcs) acc += x[e];
+      };
+      int r0 = 0;
+      for (; r0 + 16 <= jcs; r0 += 16) group(r0, false);
+      if (r0 < jcs) group(r0, true);
     }
 
     if (k == nchunk - 1) {
-      // ---- combine the G partial sums, draw, store the token
+      // ---- combine the S site groups, draw, store the token
 #pragma unroll
-      for (int o = kCPW; o < 64; o <<= 1)
-#pragma unroll
-        for (int a = 0; a < Q; ++a) acc[a] += __shfl_xor(acc[a], o, kWave);
+      for (int e = 0; e < 4; ++e) acc[e] = combine_sites<V>(acc[e]);
+      float l[4];
       float mx = -INFINITY;
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        acc[a] = beta * (hreg[a] + acc[a]);
-        mx = fmaxf(mx, acc[a]);
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = v < NQ && 4 * v + e < Q;
+        l[e] = ok ? beta * (hq[e] + acc[e]) : -INFINITY;
+        mx = fmaxf(mx, l[e]);
       }
-      float run = 0.0f;
+      mx = group_max<V>(mx);
+      float P[4];
+      float run_sum = 0.0f;
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        run += __expf(acc[a] - mx);
-        acc[a] = run;  // S_a
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = v < NQ && 4 * v + e < Q;
+        run_sum += ok ? __expf(l[e] - mx) : 0.0f;
+        P[e] = run_sum;
       }
+      // inclusive scan of the quad sums over v; exclusive = shifted by one
+      const float inc = group_scan<V>(run_sum, v);
+      float excl = V > 1 ? dpp_f<kDppShr1>(inc) : 0.0f;
+      if (v == 0) excl = 0.0f;
+      const float Stot = group_bcast<V, vL>(excl + P[eL], v);  // S_{q-1}
       const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
       const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
-      const float uz = word_to_uniform(pick_word(rnd, i & 3)) * run;
-      int anew = 0;
+      const float uz = word_to_uniform(pick_word(rnd, i & 3)) * Stot;
+      int cnt = 0;
 #pragma unroll
-      for (int a = 0; a < Q - 1; ++a) anew += (acc[a] <= uz) ? 1 : 0;
-      if (g == 0 && has_chain) {
-        unsigned char* tp = tokb + ((i >> 2) * kCPB + cb) * 4 + (i & 3);
-        if (active && anew != (int)*tp) ++nflip;
-        *tp = (unsigned char)anew;
+      for (int e = 0; e < 4; ++e)
+        if (v < NQ && 4 * v + e < Q - 1 && excl + P[e] <= uz) ++cnt;
+      cnt = group_sum<V>(cnt);
+      if (p == 0 && has_chain) {
+        unsigned char* tp = tok_at(i);
+        if (active && cnt != (int)*tp) ++nflip;
+        *tp = (unsigned char)cnt;
       }
-#pragma unroll
-      for (int a = 0; a < QP; ++a) acc[a] = 0.0f;
+      acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
     }
     if (++csl == nslot) csl = 0;
     if (++k == nchunk) {
@@ -472,7 +616,7 @@ __global__ __launch_bounds__(kGWv * 64) void k_gibbs_gather(
   }
   __syncthreads();
   if (active)
-    for (int j = g; j < L; j += G) chains[c * L + j] = (int8_t)tokb[((j >> 2) * kCPB + cb) * 4 + (j & 3)];
+    for (int j = p; j < L; j += kGLanes) chains[c * L + j] = (int8_t)*tok_at(j);
   if (flips_out) {
     unsigned long long tot = nflip;
 #pragma unroll
@@ -494,27 +638,35 @@ static int device_cus() {
   return cus;
 }
 
+// Chains per workgroup: spread the chains over the CUs (one workgroup per CU
+// at a time) in as few rounds as the largest workgroup that fits allows.
+static GatherShape gather_plan(int64_t N, int L, int q, int64_t cus) {
+  int cmax = kGMaxWaves * (64 / kGLanes);
+  while (cmax > 64 / kGLanes && gather_shape(L, q, cmax).waves == 0) cmax -= 64 / kGLanes;
+  const int64_t rounds = ceil_div(N, cus * cmax);
+  const int cpb = (int)std::min<int64_t>(cmax, ceil_div(N, rounds * cus));
+  GatherShape g = gather_shape(L, q, cpb);
+  g.blocks = (unsigned)ceil_div(N, (int64_t)cpb);
+  return g;
+}
+
 template <int Q>
 static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chains, int64_t N,
                                   int L, int sweeps, uint64_t seed, uint64_t sweep_offset,
                                   float beta, unsigned long long* flips_out, int32_t* dev_err,
                                   hipStream_t s, const DevCtl& ctl) {
-  const GatherShape gs = gather_shape(L, Q);
-  if (gs.ahead == 0) return hipErrorInvalidValue;
-  constexpr int kCPB = (64 / kGG) * kGWv;
-  // chains per workgroup: spread the chains over all CUs in as few rounds as
-  // the workgroup size allows (one workgroup per CU at a time)
   const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
-  const int64_t rounds = ceil_div(N, cus * kCPB);
-  const int cpb = (int)std::min<int64_t>(kCPB, ceil_div(N, rounds * cus));
-  const unsigned nb = (unsigned)ceil_div(N, cpb);
-  auto kern = k_gibbs_gather<Q>;
+  const GatherShape gs = gather_plan(N, L, Q, cus);
+  if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
+  auto kern = gs.items == 31 ? k_gibbs_gather<Q, 31>
+              : gs.items == 16 ? k_gibbs_gather<Q, 16> : k_gibbs_gather<Q, 8>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(kGWv * 64), gs.lds, s, h, Jt, chains, N, L, gs.ahead,
-                     gs.slot, cpb, sweeps, (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset,
-                     beta, flips_out, dev_err, ctl.epoch, ctl.active, ctl.streams);
+  hipLaunchKernelGGL(kern, dim3(gs.blocks), dim3(gs.waves * 64), gs.lds, s, h, Jt, chains, N, L,
+                     gs.jc, gs.nchunk, gs.m4, gs.ahead, gs.nload, gs.slot, gs.cpb, sweeps,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, dev_err,
+                     ctl.epoch, ctl.active, ctl.streams);
   return hipGetLastError();
 }
 

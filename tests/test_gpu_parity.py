@@ -137,6 +137,31 @@ def test_gibbs_gather_multi_sweep_states(L, q, N):
         assert int(host(flips)[0]) == oflips
 
 
+@pytest.mark.parametrize("L,q,N", [
+    # a chain's 8 lanes as 8, 4, 2 and 1 site groups (q <= 4, <= 8, <= 16, > 16)
+    (30, 2, 2600), (61, 3, 300), (45, 7, 2100), (130, 13, 700),
+    # several waves per workgroup, one chunk per site, many chunks, largest L and q
+    (77, 21, 2300), (24, 9, 3000), (200, 17, 120), (300, 32, 16), (512, 21, 10)])
+def test_gibbs_gather_lane_splits(L, q, N):
+    """Gather form over the lane layouts and workgroup shapes it picks from
+    (L, q, N): after three sweeps in one call every chain that differs from
+    the oracle went through a boundary event."""
+    h, J = synth.planted_dense(L, q, seed=163 + L, sigma_J=0.1)
+    ch = O.init_chains(N, L, q, seed=164)
+    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chg = dev(ch)
+    api.gibbs(dev(h), dev(J), chg, sweeps=3, seed=165, sweep_offset=7, flips=flips,
+              sampler="gather")
+    g = host(chg)
+    orc, mg, oflips = O.gibbs(h, J, ch, q, sweeps=3, seed=165, sweep_offset=7, want_margins=True)
+    bad = np.nonzero((g != orc).any(axis=1))[0]
+    for c in bad:
+        assert mg[c].min() < BOUNDARY
+    assert len(bad) <= max(2, N // 50)
+    if len(bad) == 0:
+        assert int(host(flips)[0]) == oflips
+
+
 def _sidak_z(n_tests, alpha=0.01):
     from scipy.stats import norm
     a1 = 1 - (1 - alpha) ** (1.0 / n_tests)
