@@ -25,6 +25,10 @@ if ROOT not in sys.path:
 
 METRIC = "Gibbs site-updates/s + epoch time, BF16 vs FP32 at ≤1e-5 stat err; p99 latency"
 HBM_PEAK_GBS = 8000.0
+# LDS read peak per CU and clock on gfx950: 256 bytes (twice the previous
+# generation's 128; a 64-lane read of contiguous 16-byte quads, 16 waves per
+# CU, sustains 213 B/clk on MI355X)
+LDS_BYTES_PER_CLK = 256
 
 
 def log(msg):
@@ -180,16 +184,17 @@ def main():
     # LDS traffic the gather form needs: every visit reads the q-vector of L-1
     # coupling rows; every workgroup stages site i's L-1 blocks of q x q once
     # per visit of site i (workgroup size as chosen by the library: chains
-    # spread over the CUs, at most 64 per workgroup)
+    # spread over the CUs in as few rounds as workgroups of at most 128
+    # chains allow; at L = 100 the tokens never limit that size)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    rounds = -(-N // (cus * 64))
-    cpb = min(64, -(-N // (rounds * cus)))
+    rounds = -(-N // (cus * 128))
+    cpb = min(128, -(-N // (rounds * cus)))
     nwg = -(-N // cpb)
     lds_gather = visits * (L - 1) * q * 4
     lds_stage = nwg * sweeps * L * (L - 1) * q * q * 4
     lds_bytes = lds_gather + lds_stage
     lds_gbs = lds_bytes / (g_ms * 1e-3) / 1e9
-    lds_peak = cus * 128 * 2.4e9 / 1e9  # 128 B/clk per CU at 2.4 GHz
+    lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9  # GB/s at 2.4 GHz
     log(f"gather sweep kernel: {g_ms:.3f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms re-layout), "
         f"{visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of {lds_peak:.0f}")
 
@@ -453,7 +458,7 @@ def bench_scoring(args):
     blocks = -(-Bn // 1024)
     tiles = sum(min(16 * jc + 15, L - 1) for jc in range(-(-L // 16)))
     lds_bytes = pairs * 4 + blocks * tiles * q * 16 * q * 4  # lookups + staged tiles
-    lds_peak = 256 * 128 * 2.4e9
+    lds_peak = 256 * LDS_BYTES_PER_CLK * 2.4e9
     log(f"energy B={Bn} L={L}: {en_ms:.2f} ms, {Bn / (en_ms * 1e-3):.3e} sequences/s, "
         f"{pairs / (en_ms * 1e-3):.3e} pair terms/s, LDS {lds_bytes / (en_ms * 1e-3) / 1e12:.1f} TB/s")
     del S, wse, E

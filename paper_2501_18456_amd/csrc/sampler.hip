@@ -208,8 +208,9 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 //     L*q*QP run, and the row a' = 0..QP-1 a chain needs is QP/4 16-byte
 //     quads.
 //   - Site i's run is streamed into LDS in chunks of JC sites by direct
-//     buffer->LDS loads, A chunks ahead of use, into a ring of A + 1 slots.
-//     JC is chosen per (L, q) to fill the LDS left over by the tokens.
+//     buffer->LDS loads, A = 3 chunks ahead of use, into a ring of A + 1
+//     slots.  JC is chosen per (L, q) to fill the LDS left over by the
+//     tokens.
 //   - Each chain owns 8 consecutive lanes, lane p = u * V + v (V = QP/4
 //     rounded up to a power of two, S = 8 / V site groups): lane (u, v) adds
 //     quad v of the rows of the sites j = u, u + S, u + 2S, ... of every
@@ -274,8 +275,9 @@ static size_t gather_tok_bytes(int L, int q) {
   return (size_t)S * (size_t)ceil_div(ceil_div(L, S), 4) * 4;
 }
 
-// Shape for `cpb` chains per workgroup; waves = 0 if it does not fit.
-static GatherShape gather_shape(int L, int q, int cpb) {
+// Shape for `cpb` chains per workgroup and a ring of `nslot` slots (3 or 4);
+// waves = 0 if it does not fit.
+static GatherShape gather_shape_n(int L, int q, int cpb, int nslot) {
   GatherShape g{};
   const int S = gather_s(q);
   const size_t site_row = (size_t)q * gather_qp(q) * sizeof(float);  // bytes per site of a chunk
@@ -283,7 +285,6 @@ static GatherShape gather_shape(int L, int q, int cpb) {
   g.waves = std::max<int>(kGMinWaves, (int)ceil_div(cpb, 64 / kGLanes));
   if (g.waves < 1 || g.waves > kGMaxWaves) return GatherShape{};
   const size_t tok = gather_tok_bytes(L, q) * (size_t)(g.waves * (64 / kGLanes));
-  const int nslot = 4;
   if (tok >= kGLds) return GatherShape{};
   const size_t per_slot = std::min((kGLds - tok) / nslot, (size_t)31 * g.waves * 1024);
   const int lcap = (int)ceil_div(L, 4 * S) * 4 * S;
@@ -298,6 +299,7 @@ static GatherShape gather_shape(int L, int q, int cpb) {
     g.cpb = cpb;
     const int nblk = (int)ceil_div((size_t)g.jc * site_row, 1024);
     for (int it : {8, 16, 31}) {  // the least padding that the waves can load
+      if ((nslot - 2) * it > 63) continue;  // vmcnt range of the younger chunks
       g.items = it;
       g.nload = (int)ceil_div(nblk, it);
       g.slot = g.nload * it * 256;
@@ -307,6 +309,11 @@ static GatherShape gather_shape(int L, int q, int cpb) {
   }
   return GatherShape{};
 }
+
+// A ring of 4 slots: three chunks in flight.  Measured at L = 100..512,
+// q = 21: 3 slots (larger chunks, two in flight) take 1.4-1.8x as long per
+// sweep, 5, 6 or 8 slots (smaller chunks, more steps) 1.5-2.5x.
+static GatherShape gather_shape(int L, int q, int cpb) { return gather_shape_n(L, q, cpb, 4); }
 
 bool gather_supported(int L, int q) {
   return L >= 1 && L <= 512 && q >= 2 && q <= 32 && gather_shape(L, q, 1).waves > 0;
@@ -504,13 +511,14 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
   for (int64_t t = 0; t < Tn; ++t) {
-    // chunk t is complete once at most the younger issued chunks (two at
-    // most: ahead = 3) are pending
+    // chunk t is complete once at most the younger issued chunks (ahead - 1
+    // of them, fewer at the end) are pending
     const int64_t rest = Tn - 1 - t;
+    const int younger = rest < ahead - 1 ? (int)rest : ahead - 1;
     compiler_fence();
-    if (rest >= 2)
+    if (younger >= 2)
       wait_vm_lgkm0<2 * IT>();
-    else if (rest == 1)
+    else if (younger == 1)
       wait_vm_lgkm0<IT>();
     else
       wait_vm_lgkm0<0>();
