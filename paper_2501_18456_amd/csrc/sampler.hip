@@ -211,12 +211,12 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 //     buffer->LDS loads, A = 3 chunks ahead of use, into a ring of A + 1
 //     slots.  JC is chosen per (L, q) to fill the LDS left over by the
 //     tokens.
-//   - Each chain owns 8 consecutive lanes, lane p = u * V + v (V = QP/4
-//     rounded up to a power of two, S = 8 / V site groups): lane (u, v) adds
-//     quad v of the rows of the sites j = u, u + S, u + 2S, ... of every
-//     chunk.  For q > 16 (S = 1) the 8 lanes of a chain read one row as
-//     contiguous quads, so the eight lanes the LDS serves together hit
-//     distinct banks; lanes v >= QP/4 stay idle.
+//   - Each chain owns LPC = 8 or 16 consecutive lanes (16 for q <= 8 when
+//     the chains per workgroup are few enough), lane p = u * V + v
+//     (V = QP/4 rounded up to a power of two, S = LPC / V site groups): lane
+//     (u, v) adds quad v of the rows of the sites j = u, u + S, u + 2S, ...
+//     of every chunk.  For q > 16 each 8 lanes of a chain read one row as
+//     contiguous quads; lanes v >= QP/4 stay idle.
 //   - Tokens live in LDS as bytes, position (j mod S, j div S), so that a
 //     lane reads the tokens of its next four sites with one 32-bit load.
 //   - At the end of the site the S partial quads meet by xor-shuffles, and
@@ -236,9 +236,12 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 // written only by its own lanes (one wave, LDS in order), so token updates
 // need no barrier.
 // ---------------------------------------------------------------------------
-constexpr int kGLanes = 8;       // lanes per chain
 constexpr int kGMaxWaves = 16;   // waves per workgroup at most
 constexpr int kGMinWaves = 4;    // and at least
+#ifndef BMDCA_GATHER_SHARE_CHAINS
+#define BMDCA_GATHER_SHARE_CHAINS 64
+#endif
+constexpr int kGShareChains = BMDCA_GATHER_SHARE_CHAINS;  // chains per workgroup on a CU share
 // 1 KB loads per loading wave per chunk: a compile-time count (8, 16 or 31),
 // so that the wait for a chunk is an immediate; 31 keeps two younger chunks
 // within vmcnt's range.
@@ -252,10 +255,11 @@ __host__ __device__ constexpr int gather_qp(int q) { return (q + 3) & ~3; }
 __host__ __device__ constexpr int gather_v(int q) {
   return gather_qp(q) / 4 <= 1 ? 1 : gather_qp(q) / 4 <= 2 ? 2 : gather_qp(q) / 4 <= 4 ? 4 : 8;
 }
-// Site groups per chain.
-__host__ __device__ constexpr int gather_s(int q) { return kGLanes / gather_v(q); }
+// Site groups per chain of `lpc` lanes (8 or 16).
+__host__ __device__ constexpr int gather_s(int q, int lpc) { return lpc / gather_v(q); }
 
 struct GatherShape {
+  int lpc;        // lanes per chain (8 or 16)
   int waves;      // waves per workgroup
   int cpb;        // chains per workgroup
   int jc;         // sites per chunk (multiple of 4 S)
@@ -270,21 +274,22 @@ struct GatherShape {
 };
 
 // Token bytes per chain.
-static size_t gather_tok_bytes(int L, int q) {
-  const int S = gather_s(q);
+static size_t gather_tok_bytes(int L, int q, int lpc) {
+  const int S = gather_s(q, lpc);
   return (size_t)S * (size_t)ceil_div(ceil_div(L, S), 4) * 4;
 }
 
 // Shape for `cpb` chains per workgroup and a ring of `nslot` slots (3 or 4);
 // waves = 0 if it does not fit.
-static GatherShape gather_shape_n(int L, int q, int cpb, int nslot) {
+static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc) {
   GatherShape g{};
-  const int S = gather_s(q);
+  const int S = gather_s(q, lpc);
   const size_t site_row = (size_t)q * gather_qp(q) * sizeof(float);  // bytes per site of a chunk
   // at least 4 waves, one per SIMD, to spread the chunk loads and barriers
-  g.waves = std::max<int>(kGMinWaves, (int)ceil_div(cpb, 64 / kGLanes));
+  g.lpc = lpc;
+  g.waves = std::max<int>(kGMinWaves, (int)ceil_div(cpb, 64 / lpc));
   if (g.waves < 1 || g.waves > kGMaxWaves) return GatherShape{};
-  const size_t tok = gather_tok_bytes(L, q) * (size_t)(g.waves * (64 / kGLanes));
+  const size_t tok = gather_tok_bytes(L, q, lpc) * (size_t)(g.waves * (64 / lpc));
   if (tok >= kGLds) return GatherShape{};
   const size_t per_slot = std::min((kGLds - tok) / nslot, (size_t)31 * g.waves * 1024);
   const int lcap = (int)ceil_div(L, 4 * S) * 4 * S;
@@ -313,10 +318,12 @@ static GatherShape gather_shape_n(int L, int q, int cpb, int nslot) {
 // A ring of 4 slots: three chunks in flight.  Measured at L = 100..512,
 // q = 21: 3 slots (larger chunks, two in flight) take 1.4-1.8x as long per
 // sweep, 5, 6 or 8 slots (smaller chunks, more steps) 1.5-2.5x.
-static GatherShape gather_shape(int L, int q, int cpb) { return gather_shape_n(L, q, cpb, 4); }
+static GatherShape gather_shape(int L, int q, int cpb, int lpc) {
+  return gather_shape_n(L, q, cpb, 4, lpc);
+}
 
 bool gather_supported(int L, int q) {
-  return L >= 1 && L <= 512 && q >= 2 && q <= 32 && gather_shape(L, q, 1).waves > 0;
+  return L >= 1 && L <= 512 && q >= 2 && q <= 32 && gather_shape(L, q, 1, 8).waves > 0;
 }
 
 size_t gather_ws_bytes(int L, int q) {
@@ -366,6 +373,7 @@ constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7-i of each 8
 constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114;  // lane i <- lane i-k
+constexpr int kDppRor8 = 0x128;       // lane i <- lane (i+8) mod 16 of each 16
 __device__ __forceinline__ float swz_xor4(float x) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x101F));
 }
@@ -407,16 +415,17 @@ __device__ __forceinline__ float group_bcast(float x, int v) {
     return ((v & 4) == (SRC & 4)) ? x1 : x2;
   }
 }
-// sum over the S = 8 / V site groups (lanes with the same v)
-template <int V>
+// sum over the S = LPC / V site groups (lanes with the same v)
+template <int V, int LPC>
 __device__ __forceinline__ float combine_sites(float x) {
   if (V <= 1) x += dpp_f<kDppXor1>(x);
   if (V <= 2) x += dpp_f<kDppXor2>(x);
   if (V <= 4) x += swz_xor4(x);
+  if (LPC == 16) x += dpp_f<kDppRor8>(x);  // lane i <- lane i^8 of each 16
   return x;
 }
 
-template <int Q, int IT>
+template <int Q, int IT, int LPC>
 __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
     int64_t N, int L, int jc, int nchunk, int m4, int ahead, int nload, int slot, int cpb,
@@ -425,15 +434,15 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     const int32_t* __restrict__ run, const ChainStream* __restrict__ streams) {
   if (run && *run == 0) return;  // whole grid leaves before any barrier
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
-  constexpr int QP = gather_qp(Q), NQ = QP / 4, V = gather_v(Q), S = gather_s(Q);
+  constexpr int QP = gather_qp(Q), NQ = QP / 4, V = gather_v(Q), S = gather_s(Q, LPC);
   constexpr int vL = (Q - 1) / 4, eL = (Q - 1) % 4;  // lane and slot of state q-1
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ __attribute__((aligned(16))) unsigned char g_smem[];
-  const int T = blockDim.x, CPB = T / kGLanes;
+  const int T = blockDim.x, CPB = T / LPC;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int p = lane & (kGLanes - 1), u = p / V, v = p % V;
-  const int cb = tid / kGLanes;  // chain slot in the workgroup
+  const int p = lane & (LPC - 1), u = p / V, v = p % V;
+  const int cb = tid / LPC;  // chain slot in the workgroup
   const int nslot = ahead + 1;
   float* ring = reinterpret_cast<float*>(g_smem);                             // [nslot][slot]
   uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [S][m4][CPB]
@@ -456,7 +465,7 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     return tokb + ((size_t)((j % S) * m4 + (m >> 2)) * CPB + cb) * 4 + (m & 3);
   };
 
-  for (int k = p; k < S * m4; k += kGLanes) {  // dword k = (site group, 4 positions)
+  for (int k = p; k < S * m4; k += LPC) {  // dword k = (site group, 4 positions)
     const int uu = k / m4, mq = k % m4;
     uint32_t w = 0;
     for (int e = 0; e < 4; ++e) {
@@ -575,7 +584,7 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     if (k == nchunk - 1) {
       // ---- combine the S site groups, draw, store the token
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] = combine_sites<V>(acc[e]);
+      for (int e = 0; e < 4; ++e) acc[e] = combine_sites<V, LPC>(acc[e]);
       float l[4];
       float mx = -INFINITY;
 #pragma unroll
@@ -624,7 +633,7 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   }
   __syncthreads();
   if (active)
-    for (int j = p; j < L; j += kGLanes) chains[c * L + j] = (int8_t)*tok_at(j);
+    for (int j = p; j < L; j += LPC) chains[c * L + j] = (int8_t)*tok_at(j);
   if (flips_out) {
     unsigned long long tot = nflip;
 #pragma unroll
@@ -647,13 +656,19 @@ static int device_cus() {
 }
 
 // Chains per workgroup: spread the chains over the CUs (one workgroup per CU
-// at a time) in as few rounds as the largest workgroup that fits allows.
-static GatherShape gather_plan(int64_t N, int L, int q, int64_t cus) {
-  int cmax = kGMaxWaves * (64 / kGLanes);
-  while (cmax > 64 / kGLanes && gather_shape(L, q, cmax).waves == 0) cmax -= 64 / kGLanes;
+// at a time) in as few rounds as the largest workgroup that fits allows, with
+// 8 lanes per chain.  For q <= 8 (rows of at most two quads) the same chains
+// then get 16 lanes each where that workgroup fits: twice the waves, each
+// with half the positions per step (q = 5, L = 400: 12% less time per sweep;
+// q = 21: 1.9x more, the per-wave step overhead doubles).
+static GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8) {
+  int cmax = std::min(cap, kGMaxWaves * (64 / 8));
+  while (cmax > 64 / 8 && gather_shape(L, q, cmax, 8).waves == 0) cmax -= 64 / 8;
   const int64_t rounds = ceil_div(N, cus * cmax);
   const int cpb = (int)std::min<int64_t>(cmax, ceil_div(N, rounds * cus));
-  GatherShape g = gather_shape(L, q, cpb);
+  GatherShape g{};
+  if (gather_v(q) <= 2) g = gather_shape(L, q, cpb, 16);
+  if (g.waves == 0) g = gather_shape(L, q, cpb, 8);
   g.blocks = (unsigned)ceil_div(N, (int64_t)cpb);
   return g;
 }
@@ -663,11 +678,19 @@ static hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chain
                                   int L, int sweeps, uint64_t seed, uint64_t sweep_offset,
                                   float beta, unsigned long long* flips_out, int32_t* dev_err,
                                   hipStream_t s, const DevCtl& ctl) {
+  // A launch on a share of the CUs (one of several models running at once)
+  // takes workgroups of at most kGShareChains chains: more, smaller
+  // workgroups let the largest models spread onto CUs the others free.
   const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
-  const GatherShape gs = gather_plan(N, L, Q, cus);
+  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, Q, cus, kGShareChains)
+                                          : gather_plan(N, L, Q, cus);
   if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
-  auto kern = gs.items == 31 ? k_gibbs_gather<Q, 31>
-              : gs.items == 16 ? k_gibbs_gather<Q, 16> : k_gibbs_gather<Q, 8>;
+  auto kern = gs.lpc == 16 ? (gs.items == 31   ? k_gibbs_gather<Q, 31, 16>
+                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 16>
+                                               : k_gibbs_gather<Q, 8, 16>)
+                           : (gs.items == 31   ? k_gibbs_gather<Q, 31, 8>
+                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 8>
+                                               : k_gibbs_gather<Q, 8, 8>);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
   if (e != hipSuccess) return e;
