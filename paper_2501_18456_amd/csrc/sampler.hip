@@ -281,7 +281,7 @@ static size_t gather_tok_bytes(int L, int q, int lpc) {
 
 // Shape for `cpb` chains per workgroup and a ring of `nslot` slots (3 or 4);
 // waves = 0 if it does not fit.
-static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc) {
+static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc, bool align) {
   GatherShape g{};
   const int S = gather_s(q, lpc);
   const size_t site_row = (size_t)q * gather_qp(q) * sizeof(float);  // bytes per site of a chunk
@@ -292,12 +292,22 @@ static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc) {
   const size_t tok = gather_tok_bytes(L, q, lpc) * (size_t)(g.waves * (64 / lpc));
   if (tok >= kGLds) return GatherShape{};
   const size_t per_slot = std::min((kGLds - tok) / nslot, (size_t)31 * g.waves * 1024);
+  // Chunks are a multiple of 4 S sites (4 token positions per lane, one
+  // token dword) and of 256 bytes: a chunk that starts off a 256-byte
+  // boundary of the run makes every load of it misaligned (L = 100, q = 21:
+  // 17-site chunks, 34272 bytes, took 1.8x the time per sweep of 16-site
+  // ones).
+  int step = 4 * S;
+  while (align && ((size_t)step * site_row) % 256 != 0) step += 4 * S;
   const int lcap = (int)ceil_div(L, 4 * S) * 4 * S;
-  // largest chunk whose slot, padded to whole 16-byte loads per thread, fits
+  // the largest chunk whose padded slots and tokens fit (a chunk of the
+  // whole run needs no alignment)
   for (int jc = std::min((int)(per_slot / site_row) / (4 * S) * (4 * S), lcap); jc >= 4 * S;
        jc -= 4 * S) {
     g.nchunk = (int)ceil_div(L, jc);
     g.jc = (int)ceil_div(ceil_div(L, g.nchunk), 4 * S) * 4 * S;  // balanced chunks
+    if (g.nchunk > 1) g.jc = (int)ceil_div(g.jc, step) * step;
+    if (g.jc > jc) continue;
     g.nchunk = (int)ceil_div(L, g.jc);
     g.m4 = (int)ceil_div(ceil_div(L, S), 4);
     g.ahead = nslot - 1;
@@ -319,7 +329,8 @@ static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc) {
 // q = 21: 3 slots (larger chunks, two in flight) take 1.4-1.8x as long per
 // sweep, 5, 6 or 8 slots (smaller chunks, more steps) 1.5-2.5x.
 static GatherShape gather_shape(int L, int q, int cpb, int lpc) {
-  return gather_shape_n(L, q, cpb, 4, lpc);
+  const GatherShape g = gather_shape_n(L, q, cpb, 4, lpc, true);
+  return g.waves ? g : gather_shape_n(L, q, cpb, 4, lpc, false);  // q = 25, 27 at large L
 }
 
 bool gather_supported(int L, int q) {
@@ -552,25 +563,38 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
       }
     }
 
-    // ---- this lane's sites of the chunk: j = k*jc + S*r + u, r < jc/S.
-    // The rows of j = i (zero block) and of j >= L (past the end of the run,
-    // loaded as zeros) add nothing, so every position is added
-    // unconditionally; positions past the last token dword read any valid
-    // token.  Groups of 16 positions: 4 token loads, 16 row loads, the adds.
+    // ---- this lane's sites of the chunk: j = k*jc + S*r + u, r < jc/S,
+    // token positions m0 + r.  The rows of j = i (zero block) and of j >= L
+    // (past the end of the run, loaded as zeros) add nothing, so every
+    // position is added unconditionally; positions past the last token dword
+    // read any valid token.  Groups of 16 positions: 4 token loads, 16 row
+    // loads, the adds (a tail group loads only its positions).
     if (reader) {
       const float* jb = ring + (size_t)csl * slot + 4 * v;
       const int m0 = k * jcs;  // multiple of 4
       const uint32_t* tw = tokw + (size_t)u * m4 * CPB + cb;
       auto group = [&](int r0, bool tail) {
+        // a tail with several site groups (q <= 16, long chunks) skips the
+        // loads past its positions; with one (q > 16, at most 16 positions
+        // lost) it loads clamped rows, the faster code at protein scale
+        constexpr bool kSkip = S > 1;
         uint32_t tk[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) tk[d] = tw[min(((m0 + r0) >> 2) + d, m4 - 1) * CPB];
+        for (int d = 0; d < 4; ++d)
+          tk[d] = (!(kSkip && tail) || 4 * d < jcs - r0)
+                      ? tw[min(((m0 + r0) >> 2) + d, m4 - 1) * CPB]
+                      : 0u;
         f4 x[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int s = (int)((tk[e >> 2] >> (8 * (e & 3))) & 0xFF);
-          const int r = tail ? min(r0 + e, jcs - 1) : r0 + e;
-          x[e] = *reinterpret_cast<const f4*>(jb + ((S * r + u) * Q + s) * QP);
+          if (kSkip) {
+            if (!tail || r0 + e < jcs)  // wave-uniform
+              x[e] = *reinterpret_cast<const f4*>(jb + ((S * (r0 + e) + u) * Q + s) * QP);
+          } else {
+            const int r = tail ? min(r0 + e, jcs - 1) : r0 + e;
+            x[e] = *reinterpret_cast<const f4*>(jb + ((S * r + u) * Q + s) * QP);
+          }
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e)
