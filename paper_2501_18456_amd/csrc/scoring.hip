@@ -234,11 +234,14 @@ hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int 
 // ---------------------------------------------------------------------------
 // APC Frobenius.  k_frob_rows: a workgroup owns block-row i and one chunk of
 // 16 sites j (only j > i are blocks): the q x 16q tile of rows (i, a) is read
-// coalesced into LDS, and 16 threads per block move it to the zero-sum gauge
-// over all states (FP64 row, column and total means) and sum the squares of
-// the entries with a, b != gap; F_ij = F_ji = sqrt of that sum.  J is read
-// once.  k_apc_rows: S_i = sum_k F_ik (one wave per row); k_apc_total: the
-// total in ascending i; k_apc_out: F_apc = F - S_i S_j / S, diagonals 0.
+// into LDS with each thread owning columns and all q row loads in flight at
+// once (coalesced over the columns; row stride 16q + 1 floats, odd, so that
+// the column walks below hit distinct banks); 16 threads per block then take
+// the block's row and column means over all states (FP64), the total mean,
+// and sum the squares of the gauged entries with a, b != gap; F_ij = F_ji =
+// the square root.  J is read once.  k_apc_rows: S_i = sum_k F_ik (one wave
+// per row); k_apc_total: S = sum_i S_i; k_apc_out: F_apc = F - S_i S_j / S,
+// diagonals 0.
 // ---------------------------------------------------------------------------
 constexpr int kFJC = 16;
 
@@ -246,57 +249,64 @@ size_t apc_ws_bytes(int L) { return align256(sizeof(double) * ((size_t)L * L + L
 
 __global__ __launch_bounds__(256) void k_frob_rows(const float* __restrict__ J, int L, int q,
                                                    int gap, double* __restrict__ F) {
-  extern __shared__ float tile[];  // q x (16 q)
+  extern __shared__ double frob_smem[];  // rmean[16][32], cmean[16][32], then the tile
+  double* rmean = frob_smem;
+  double* cmean = frob_smem + kFJC * 32;
+  float* tile = reinterpret_cast<float*>(frob_smem + 2 * kFJC * 32);  // q x (16 q + 1)
   const int i = blockIdx.y;
   const int j0 = blockIdx.x * kFJC;
   const int Lq = L * q;
-  const int W = kFJC * q;
+  const int W = kFJC * q + 1;
   const int jb = threadIdx.x / 16, t = threadIdx.x % 16;  // block of the chunk, thread in it
   if (j0 == 0 && threadIdx.x == 0) F[(size_t)i * L + i] = 0.0;  // never read as a pair
   if (j0 + kFJC - 1 <= i) return;  // no j > i in this chunk (whole workgroup)
-  {
-    const int nj = min(kFJC, L - j0);
-    for (int e = threadIdx.x; e < q * nj * q; e += blockDim.x) {
-      const int a = e / (nj * q), c = e % (nj * q);
-      tile[a * W + c] = J[(size_t)(i * q + a) * Lq + (size_t)j0 * q + c];
+  const int nj = min(kFJC, L - j0);
+  const float* src = J + (size_t)i * q * Lq + (size_t)j0 * q;
+  for (int c = threadIdx.x; c < nj * q; c += blockDim.x) {
+    float v[32];
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      if (a < q) v[a] = src[(size_t)a * Lq + c];
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      if (a < q) tile[a * W + c] = v[a];
+  }
+  __syncthreads();
+  const bool mine = jb < nj && j0 + jb > i;
+  const float* blk = tile + jb * q;  // element (a, b) at blk[a * W + b]
+  if (mine) {
+    // row sums over b and column sums over a for rows / columns t, t + 16
+    for (int r = t; r < q; r += 16) {
+      double rs = 0.0, cs = 0.0;
+      for (int k = 0; k < q; ++k) {
+        rs += (double)blk[r * W + k];
+        cs += (double)blk[k * W + r];
+      }
+      rmean[jb * 32 + r] = rs / (double)q;
+      cmean[jb * 32 + r] = cs / (double)q;
     }
-    __syncthreads();
-    if (jb < nj && j0 + jb > i) {
-      const float* blk = tile + jb * q;  // element (a, b) at blk[a * W + b]
-      // row means over b and column means over a (t covers rows/cols t, t+16)
-      double rs[2] = {0.0, 0.0}, cs[2] = {0.0, 0.0};
-      for (int u = 0; u < 2; ++u) {
-        const int r = t + 16 * u;
-        if (r < q)
-          for (int k = 0; k < q; ++k) {
-            rs[u] += (double)blk[r * W + k];
-            cs[u] += (double)blk[k * W + r];
-          }
-      }
-      // all threads of the group need every row/column mean: share through
-      // shuffles within the 16-lane group
-      double all = 0.0;
-      for (int u = 0; u < 2; ++u) all += rs[u];
-      for (int o = 8; o > 0; o >>= 1) all += __shfl_xor(all, o, 16);
-      const double mean_all = all / ((double)q * (double)q);
-      double ss = 0.0;
+  }
+  __syncthreads();
+  if (mine) {
+    double all = 0.0;
+    for (int a = 0; a < q; ++a) all += rmean[jb * 32 + a];
+    const double mean_all = all / (double)q;
+    double ss = 0.0;
+    for (int b = t; b < q; b += 16) {
+      if (b == gap) continue;
+      const double cb = cmean[jb * 32 + b];
       for (int a = 0; a < q; ++a) {
-        const double ra = __shfl(rs[a / 16], a % 16, 16) / (double)q;
-        for (int u = 0; u < 2; ++u) {
-          const int b = t + 16 * u;
-          if (b < q && a != gap && b != gap) {
-            const double z = (double)blk[a * W + b] - ra - cs[u] / (double)q + mean_all;
-            ss += z * z;
-          }
-        }
+        if (a == gap) continue;
+        const double z = (double)blk[a * W + b] - rmean[jb * 32 + a] - cb + mean_all;
+        ss += z * z;
       }
-      for (int o = 8; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 16);
-      if (t == 0) {
-        const double f = sqrt(ss);
-        const int j = j0 + jb;
-        F[(size_t)i * L + j] = f;
-        F[(size_t)j * L + i] = f;
-      }
+    }
+    for (int o = 8; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 16);
+    if (t == 0) {
+      const double f = sqrt(ss);
+      const int j = j0 + jb;
+      F[(size_t)i * L + j] = f;
+      F[(size_t)j * L + i] = f;
     }
   }
 }
@@ -312,11 +322,19 @@ __global__ __launch_bounds__(256) void k_apc_rows(const double* __restrict__ F, 
   if (lane == 0) S[i] = s;
 }
 
-__global__ void k_apc_total(double* __restrict__ S, int L) {
-  if (threadIdx.x != 0) return;
+// S = sum_i S_i: thread t adds S_t, S_{t+256}, ... in ascending order, then a
+// fixed tree over the 256 partial sums (one workgroup, deterministic).
+__global__ __launch_bounds__(256) void k_apc_total(double* __restrict__ S, int L) {
+  __shared__ double part[256];
   double tot = 0.0;
-  for (int i = 0; i < L; ++i) tot += S[i];
-  S[L] = tot;
+  for (int i = threadIdx.x; i < L; i += 256) tot += S[i];
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S[L] = part[0];
 }
 
 __global__ void k_apc_out(const double* __restrict__ F, const double* __restrict__ S, int L,
@@ -333,11 +351,14 @@ hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fa
                       hipStream_t s) {
   double* Fd = static_cast<double*>(ws);
   double* S = Fd + (size_t)L * L;
-  const size_t lds = sizeof(float) * (size_t)q * kFJC * q;
+  const size_t lds = sizeof(double) * 2 * kFJC * 32 + sizeof(float) * (size_t)q * (kFJC * q + 1);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_frob_rows),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_frob_rows, dim3((unsigned)ceil_div(L, kFJC), (unsigned)L), dim3(256), lds, s,
                      J, L, q, gap, Fd);
   hipLaunchKernelGGL(k_apc_rows, dim3((unsigned)ceil_div(L, 4)), dim3(256), 0, s, Fd, L, S);
-  hipLaunchKernelGGL(k_apc_total, dim3(1), dim3(64), 0, s, S, L);
+  hipLaunchKernelGGL(k_apc_total, dim3(1), dim3(256), 0, s, S, L);
   hipLaunchKernelGGL(k_apc_out, dim3((unsigned)ceil_div((size_t)L * L, (size_t)256)), dim3(256), 0,
                      s, Fd, S, L, F, Fapc);
   return hipGetLastError();
