@@ -588,12 +588,15 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int s = (int)((tk[e >> 2] >> (8 * (e & 3))) & 0xFF);
+          // row offset s * QP by a 24-bit multiply (full rate; a 32-bit
+          // integer multiply issues at a quarter of the rate)
+          const uint32_t so = __umul24((uint32_t)s, (uint32_t)QP);
           if (kSkip) {
             if (!tail || r0 + e < jcs)  // wave-uniform
-              x[e] = *reinterpret_cast<const f4*>(jb + ((S * (r0 + e) + u) * Q + s) * QP);
+              x[e] = *reinterpret_cast<const f4*>(jb + (S * (r0 + e) + u) * Q * QP + so);
           } else {
             const int r = tail ? min(r0 + e, jcs - 1) : r0 + e;
-            x[e] = *reinterpret_cast<const f4*>(jb + ((S * r + u) * Q + s) * QP);
+            x[e] = *reinterpret_cast<const f4*>(jb + (S * r + u) * Q * QP + so);
           }
         }
 #pragma unroll
