@@ -238,13 +238,10 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 // ---------------------------------------------------------------------------
 constexpr int kGMaxWaves = 16;   // waves per workgroup at most
 constexpr int kGMinWaves = 4;    // and at least
-#ifndef BMDCA_GATHER_SHARE_CHAINS
-#define BMDCA_GATHER_SHARE_CHAINS 64
-#endif
-constexpr int kGShareChains = BMDCA_GATHER_SHARE_CHAINS;  // chains per workgroup on a CU share
-// 1 KB loads per loading wave per chunk: a compile-time count (8, 16 or 31),
-// so that the wait for a chunk is an immediate; 31 keeps two younger chunks
-// within vmcnt's range.
+// Chains per workgroup at most for a launch on a share of the CUs (grouped
+// training of 64 models over 8 lanes: caps of 32, 64 and 128 chains measured
+// 909, 575 and 1163 ms per epoch).
+constexpr int kGShareChains = 64;
 constexpr size_t kGLds = 160 * 1024 - 256;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -266,7 +263,9 @@ struct GatherShape {
   int nchunk;     // chunks per site
   int m4;         // token dwords per (chain, site group)
   int ahead;      // chunks in flight (ring = ahead + 1 slots)
-  int items;      // 1 KB loads per loading wave per chunk
+  int items;      // 1 KB loads per loading wave per chunk: 8, 16 or 31, a template
+                  // parameter so that every wait is an immediate (31 keeps two
+                  // younger chunks within vmcnt's range)
   int nload;      // loading waves (waves 0..nload-1; wave w loads blocks w*items ...)
   int slot;       // floats per ring slot (nload * items KB)
   size_t lds;     // dynamic LDS bytes
@@ -279,8 +278,8 @@ static size_t gather_tok_bytes(int L, int q, int lpc) {
   return (size_t)S * (size_t)ceil_div(ceil_div(L, S), 4) * 4;
 }
 
-// Shape for `cpb` chains per workgroup and a ring of `nslot` slots (3 or 4);
-// waves = 0 if it does not fit.
+// Shape for `cpb` chains per workgroup and a ring of `nslot` slots; waves = 0
+// if it does not fit.  `align` asks for chunks on 256-byte boundaries.
 static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc, bool align) {
   GatherShape g{};
   const int S = gather_s(q, lpc);
