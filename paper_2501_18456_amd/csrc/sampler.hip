@@ -6,6 +6,7 @@
 // vertex (i, a) is one contiguous Lq vector and H can be kept current with two
 // coalesced row reads per accepted change.
 #include "common.hpp"
+#include "gather_plan.hpp"
 #include "internal.hpp"
 
 namespace bmdca {
@@ -236,101 +237,7 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
 // written only by its own lanes (one wave, LDS in order), so token updates
 // need no barrier.
 // ---------------------------------------------------------------------------
-constexpr int kGMaxWaves = 16;   // waves per workgroup at most
-constexpr int kGMinWaves = 4;    // and at least
-// Chains per workgroup at most for a launch on a share of the CUs (grouped
-// training of 64 models over 8 lanes: caps of 32, 64 and 128 chains measured
-// 909, 575 and 1163 ms per epoch).
-constexpr int kGShareChains = 64;
-constexpr size_t kGLds = 160 * 1024 - 256;
-
 typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Row pitch of Jt: q rounded up to a multiple of 4 floats (16-byte quads).
-__host__ __device__ constexpr int gather_qp(int q) { return (q + 3) & ~3; }
-// Lanes per quad group: quads per row rounded up to a power of two.
-__host__ __device__ constexpr int gather_v(int q) {
-  return gather_qp(q) / 4 <= 1 ? 1 : gather_qp(q) / 4 <= 2 ? 2 : gather_qp(q) / 4 <= 4 ? 4 : 8;
-}
-// Site groups per chain of `lpc` lanes (8 or 16).
-__host__ __device__ constexpr int gather_s(int q, int lpc) { return lpc / gather_v(q); }
-
-struct GatherShape {
-  int lpc;        // lanes per chain (8 or 16)
-  int waves;      // waves per workgroup
-  int cpb;        // chains per workgroup
-  int jc;         // sites per chunk (multiple of 4 S)
-  int nchunk;     // chunks per site
-  int m4;         // token dwords per (chain, site group)
-  int ahead;      // chunks in flight (ring = ahead + 1 slots)
-  int items;      // 1 KB loads per loading wave per chunk: 8, 16 or 31, a template
-                  // parameter so that every wait is an immediate (31 keeps two
-                  // younger chunks within vmcnt's range)
-  int nload;      // loading waves (waves 0..nload-1; wave w loads blocks w*items ...)
-  int slot;       // floats per ring slot (nload * items KB)
-  size_t lds;     // dynamic LDS bytes
-  unsigned blocks;
-};
-
-// Token bytes per chain.
-static size_t gather_tok_bytes(int L, int q, int lpc) {
-  const int S = gather_s(q, lpc);
-  return (size_t)S * (size_t)ceil_div(ceil_div(L, S), 4) * 4;
-}
-
-// Shape for `cpb` chains per workgroup and a ring of `nslot` slots; waves = 0
-// if it does not fit.  `align` asks for chunks on 256-byte boundaries.
-static GatherShape gather_shape_n(int L, int q, int cpb, int nslot, int lpc, bool align) {
-  GatherShape g{};
-  const int S = gather_s(q, lpc);
-  const size_t site_row = (size_t)q * gather_qp(q) * sizeof(float);  // bytes per site of a chunk
-  // at least 4 waves, one per SIMD, to spread the chunk loads and barriers
-  g.lpc = lpc;
-  g.waves = std::max<int>(kGMinWaves, (int)ceil_div(cpb, 64 / lpc));
-  if (g.waves < 1 || g.waves > kGMaxWaves) return GatherShape{};
-  const size_t tok = gather_tok_bytes(L, q, lpc) * (size_t)(g.waves * (64 / lpc));
-  if (tok >= kGLds) return GatherShape{};
-  const size_t per_slot = std::min((kGLds - tok) / nslot, (size_t)31 * g.waves * 1024);
-  // Chunks are a multiple of 4 S sites (4 token positions per lane, one
-  // token dword) and of 256 bytes: a chunk that starts off a 256-byte
-  // boundary of the run makes every load of it misaligned (L = 100, q = 21:
-  // 17-site chunks, 34272 bytes, took 1.8x the time per sweep of 16-site
-  // ones).
-  int step = 4 * S;
-  while (align && ((size_t)step * site_row) % 256 != 0) step += 4 * S;
-  const int lcap = (int)ceil_div(L, 4 * S) * 4 * S;
-  // the largest chunk whose padded slots and tokens fit (a chunk of the
-  // whole run needs no alignment)
-  for (int jc = std::min((int)(per_slot / site_row) / (4 * S) * (4 * S), lcap); jc >= 4 * S;
-       jc -= 4 * S) {
-    g.nchunk = (int)ceil_div(L, jc);
-    g.jc = (int)ceil_div(ceil_div(L, g.nchunk), 4 * S) * 4 * S;  // balanced chunks
-    if (g.nchunk > 1) g.jc = (int)ceil_div(g.jc, step) * step;
-    if (g.jc > jc) continue;
-    g.nchunk = (int)ceil_div(L, g.jc);
-    g.m4 = (int)ceil_div(ceil_div(L, S), 4);
-    g.ahead = nslot - 1;
-    g.cpb = cpb;
-    const int nblk = (int)ceil_div((size_t)g.jc * site_row, 1024);
-    for (int it : {8, 16, 31}) {  // the least padding that the waves can load
-      if ((nslot - 2) * it > 63) continue;  // vmcnt range of the younger chunks
-      g.items = it;
-      g.nload = (int)ceil_div(nblk, it);
-      g.slot = g.nload * it * 256;
-      g.lds = (size_t)nslot * g.slot * sizeof(float) + tok;
-      if (g.nload <= g.waves && g.lds <= kGLds) return g;
-    }
-  }
-  return GatherShape{};
-}
-
-// A ring of 4 slots: three chunks in flight.  Measured at L = 100..512,
-// q = 21: 3 slots (larger chunks, two in flight) take 1.4-1.8x as long per
-// sweep, 5, 6 or 8 slots (smaller chunks, more steps) 1.5-2.5x.
-static GatherShape gather_shape(int L, int q, int cpb, int lpc) {
-  const GatherShape g = gather_shape_n(L, q, cpb, 4, lpc, true);
-  return g.waves ? g : gather_shape_n(L, q, cpb, 4, lpc, false);  // q = 25, 27 at large L
-}
 
 bool gather_supported(int L, int q) {
   return L >= 1 && L <= 512 && q >= 2 && q <= 32 && gather_shape(L, q, 1, 8).waves > 0;
@@ -679,24 +586,6 @@ static int device_cus() {
       cus = 256;
   }
   return cus;
-}
-
-// Chains per workgroup: spread the chains over the CUs (one workgroup per CU
-// at a time) in as few rounds as the largest workgroup that fits allows, with
-// 8 lanes per chain.  For q <= 8 (rows of at most two quads) the same chains
-// then get 16 lanes each where that workgroup fits: twice the waves, each
-// with half the positions per step (q = 5, L = 400: 12% less time per sweep;
-// q = 21: 1.9x more, the per-wave step overhead doubles).
-static GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8) {
-  int cmax = std::min(cap, kGMaxWaves * (64 / 8));
-  while (cmax > 64 / 8 && gather_shape(L, q, cmax, 8).waves == 0) cmax -= 64 / 8;
-  const int64_t rounds = ceil_div(N, cus * cmax);
-  const int cpb = (int)std::min<int64_t>(cmax, ceil_div(N, rounds * cus));
-  GatherShape g{};
-  if (gather_v(q) <= 2) g = gather_shape(L, q, cpb, 16);
-  if (g.waves == 0) g = gather_shape(L, q, cpb, 8);
-  g.blocks = (unsigned)ceil_div(N, (int64_t)cpb);
-  return g;
 }
 
 template <int Q>
