@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--cpu-chains", type=int, default=4000,
                     help="chains in the oracle's timed sample epoch")
     ap.add_argument("--workload", default="protein",
-                    choices=["protein", "small", "precision", "scoring", "group", "serve"],
+                    choices=["protein", "small", "precision", "scoring", "group", "serve", "next"],
                     help="protein: one model at protein scale (default); small: the whole "
                          "plain-bmDCA run at CPU-seconds size (L=20) on the GPU and in the "
                          "oracle; precision: BF16 hi+lo "
@@ -55,7 +55,9 @@ def parse():
                          "reweighting at M=1e5 and energies, mutant scans, contact scores of an "
                          "L=512 model; group: 64 "
                          "uneven models trained together in one captured graph per epoch; "
-                         "serve: request loop over 8 resident models at three arrival rates")
+                         "serve: request loop over 8 resident models at three arrival rates; "
+                         "next: equilibrium sampling with the mixing time, Metropolis sweeps "
+                         "and element decimation at protein scale")
     ap.add_argument("--lanes", type=int, default=8, help="group/serve: concurrent lane streams")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
@@ -90,6 +92,8 @@ def main():
         sys.exit(2)
     if args.workload == "small":
         return bench_small(args)
+    if args.workload == "next":
+        return bench_next(args)
     if args.workload == "precision":
         return bench_precision(args)
     if args.workload == "scoring":
@@ -368,6 +372,123 @@ def bench_small(args):
         log(f"oracle: whole run {cpu_s:.2f} s; alignment rows that differ: {rows} of {M}; "
             f"max |J_gpu - J_oracle| = {dJ:.3g} (both are 0 unless a draw fell within 1e-5 of "
             "a CDF step, after which the trajectories part)")
+    print(json.dumps(out), flush=True)
+
+
+def bench_next(args):
+    """The next items at protein scale (L = 100, q = 21, planted sparse model as
+    the trained model, alignment of M = 20 000 drawn by 200 sweeps, 80% identity
+    weights): (1) the mixing time of Sec. 4.1 from 10 000 data-started chains
+    and equilibrium sampling of 10 000 chains for 2 t_mix sweeps; (2)
+    Metropolis sweeps of 10 000 chains (field form: proposal uniform over the
+    other q - 1 states); (3) one edDCA graph update (symmetric KL scores of
+    every element, selection of the smallest 1%) and one masked epoch.  The
+    line's value is the Metropolis sweep rate; its roofline is the field-form
+    kernel's algorithmic HBM traffic."""
+    import numpy as np
+    import torch
+
+    from paper_2501_18456_amd import api, sampling, synth
+    from paper_2501_18456_amd import _lib as B
+
+    torch.cuda.set_device(0)
+    L, q, M, N, sweeps, lr = 100, 21, 20000, 10000, 10, 0.05
+    Lq = L * q
+    h_true, J_true = synth.planted_sparse(L, q, seed=1002, sigma_J=0.5, gap_mass=0.15)
+    h, J = torch.from_numpy(h_true).cuda(), torch.from_numpy(J_true).cuda()
+    msa = api.init_chains(M, L, q, seed=2002)
+    api.gibbs(h, J, msa, sweeps=200, seed=2002)
+    _, w, _ = api.reweight(msa, q, 0.8)
+    f1, f2, _ = api.stats(msa, q, w, -1.0, "bf16x2")
+    torch.cuda.synchronize()
+    log(f"next items: L={L} q={q} M={M} N={N}")
+    extras = {}
+
+    # (1) mixing time and equilibrium sampling
+    sampling.mixing_time(h, J, msa, w, 1000, seed=7, max_sweeps=8)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_mix, rec, _ = sampling.mixing_time(h, J, msa, w, N, seed=7, max_sweeps=4096)
+    torch.cuda.synchronize()
+    mix_s = time.perf_counter() - t0
+    last = rec[-1][0]
+    t0 = time.perf_counter()
+    chains, t_mix2, _ = sampling.sample_equilibrium(h, J, msa, w, N, N, seed=7, nmix=2,
+                                                    max_sweeps=4096)
+    torch.cuda.synchronize()
+    eq_s = time.perf_counter() - t0
+    extras["mixing"] = {"t_mix": t_mix, "checkpoints": len(rec) - 1, "last_sweep": last,
+                        "ms": mix_s * 1e3, "site_updates_per_s": N * L * last / mix_s,
+                        "equilibrium_sample_ms": eq_s * 1e3,
+                        "records": [[r[0], r[1], r[3]] for r in rec]}
+    log(f"mixing time {t_mix} sweeps ({len(rec) - 1} checkpoints, {mix_s * 1e3:.1f} ms, "
+        f"{N * L * last / mix_s:.3e} site-updates/s with the SeqID read-backs); "
+        f"equilibrium sample of {N} chains (mixing time + {2 * (t_mix or 0)} sweeps): "
+        f"{eq_s * 1e3:.1f} ms")
+
+    # (2) Metropolis sweeps (field form)
+    ch = api.init_chains(N, L, q, seed=3002)
+    H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS)
+    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+    api.gibbs(h, J, ch, 1, 3002, H_ws=H, sampler="metropolis")  # builds the fields
+    t = Timer()
+    reps = max(args.steps, 3)
+    t.start()
+    for r in range(reps):
+        api.gibbs(h, J, ch, sweeps, 3002, sweep_offset=1 + r * sweeps, H_ws=H, flips=flips,
+                  keep_fields=True, sampler="metropolis")
+    m_ms = t.stop_ms() / reps
+    acc = float(flips.cpu()[0]) / reps
+    visits = N * L * sweeps
+    m_bytes = visits * 8 + acc * 8 * (Lq - q) + 2 * N * L
+    m_gbs = m_bytes / (m_ms * 1e-3) / 1e9
+    log(f"Metropolis: {m_ms:.2f} ms per {sweeps} sweeps ({visits / (m_ms * 1e-3):.3e} "
+        f"site-updates/s), acceptance {acc / visits:.3f}, algorithmic HBM {m_gbs:.0f} GB/s")
+    g_ch = api.init_chains(N, L, q, seed=3002)
+    t.start()
+    for r in range(reps):
+        api.gibbs(h, J, g_ch, sweeps, 3002, sweep_offset=r * sweeps)
+    g_ms = t.stop_ms() / reps
+    extras["metropolis"] = {"ms_per_launch": m_ms, "acceptance": acc / visits,
+                            "gibbs_ms_per_launch_same_chains": g_ms}
+
+    # (3) element decimation: one graph update and one masked epoch
+    mask = api.full_mask(L, q)
+    J2 = J.clone() * mask.to(J.dtype)
+    h2 = h.clone()
+    ch2 = chains.clone()
+    wsd = api.workspace(B.WS_DECIMATE, N, L, q, 0)
+    n_act = torch.empty(1, dtype=torch.int64, device="cuda")
+    api.decimate(J2.clone(), mask.clone(), ch2, q, 0.01, 0.0, ws=wsd, n_active=n_act)  # warm
+    t.start()
+    api.decimate(J2, mask, ch2, q, 0.01, 0.0, ws=wsd, n_active=n_act)
+    d_ms = t.stop_ms()
+    wst = api.workspace(B.WS_TRAIN_STEP, N, L, q, "bf16x2")
+    api.train_step_masked(h2, J2, mask, ch2, f1, f2, lr, sweeps, 3003, 0, "bf16x2", wst)
+    t.start()
+    for e in range(3):
+        api.train_step_masked(h2, J2, mask, ch2, f1, f2, lr, sweeps, 3003, 1 + e, "bf16x2", wst)
+    me_ms = t.stop_ms() / 3
+    total = L * (L - 1) // 2 * q * q
+    extras["decimation"] = {"graph_update_ms": d_ms, "masked_epoch_ms": me_ms,
+                            "active_after": int(n_act.cpu()[0]), "elements": total}
+    log(f"edDCA: graph update {d_ms:.2f} ms ({total} elements scored, "
+        f"{int(n_act.cpu()[0])} left), masked epoch {me_ms:.2f} ms")
+
+    out = {
+        "metric": METRIC, "value": visits / (m_ms * 1e-3), "unit": "site-updates/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": m_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (planted sparse Potts model; alignment sampled from it)",
+        "config": {"workload": "equilibrium sampling, Metropolis sweeps and element "
+                               "decimation at protein scale", "L": L, "q": q, "chains": N,
+                   "msa_rows": M, "sweeps_per_step": sweeps},
+        "roofline": {"kernel": "k_gibbs_hbm (Metropolis sweeps, field form)", "bound": "hbm",
+                     "achieved": m_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": m_gbs / HBM_PEAK_GBS, "traffic": None, "launch_ms": m_ms,
+                     "alg_bytes_per_launch": m_bytes},
+        "extras": extras,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -98,10 +98,25 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_hist(const unsigned long lo
   for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
   __syncthreads();
   const unsigned long long pm = st->pmask, pf = st->prefix;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const unsigned long long key = keys[e];
-    if (key != kNoKey && (key & pm) == pf) atomicAdd(&h[(key >> shift) & 255], 1u);
+  const int lane = threadIdx.x & 63;
+  // The keys of one pass mostly share a digit (positive doubles in a narrow
+  // range), so the lanes of a wave are grouped by digit with ballots and one
+  // lane per group adds the group's count: one LDS atomic per distinct digit
+  // in the wave instead of one per key.
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e0 = (size_t)blockIdx.x * blockDim.x; e0 < total; e0 += stride) {
+    const size_t e = e0 + threadIdx.x;
+    const unsigned long long key = e < total ? keys[e] : kNoKey;
+    const bool valid = key != kNoKey && (key & pm) == pf;
+    const int bin = valid ? (int)((key >> shift) & 255) : -1;
+    unsigned long long todo = __ballot(valid);  // wave-uniform
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int lb = __shfl(bin, leader, 64);
+      const unsigned long long same = __ballot(bin == lb) & todo;
+      if (lane == leader) atomicAdd(&h[lb], (unsigned int)__popcll(same));
+      todo &= ~same;
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < 256; b += blockDim.x)
@@ -149,11 +164,29 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tie_count(const unsigned lo
   }
 }
 
-// Exclusive scan of the block tie counts in block order (one thread).
-__global__ void k_dec_tie_scan(unsigned long long* __restrict__ blk, int64_t nblk) {
-  if (threadIdx.x != 0) return;
-  unsigned long long run = 0;
-  for (int64_t b = 0; b < nblk; ++b) {
+// Exclusive scan of the block tie counts in block order (one workgroup:
+// each thread sums a contiguous segment, the segment sums are scanned in LDS,
+// then each thread writes its segment's running counts; exact integers).
+constexpr int kDecScanThreads = 1024;
+__global__ __launch_bounds__(kDecScanThreads) void k_dec_tie_scan(unsigned long long* __restrict__ blk,
+                                                                  int64_t nblk) {
+  __shared__ unsigned long long part[kDecScanThreads];
+  const int t = threadIdx.x;
+  const int64_t per = (nblk + kDecScanThreads - 1) / kDecScanThreads;
+  const int64_t b0 = std::min<int64_t>(nblk, (int64_t)t * per);
+  const int64_t b1 = std::min<int64_t>(nblk, b0 + per);
+  unsigned long long sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += blk[b];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < kDecScanThreads; o <<= 1) {  // inclusive scan of the segment sums
+    const unsigned long long v = t >= o ? part[t - o] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned long long run = t > 0 ? part[t - 1] : 0ull;
+  for (int64_t b = b0; b < b1; ++b) {
     const unsigned long long c = blk[b];
     blk[b] = run;
     run += c;
@@ -220,7 +253,10 @@ hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, 
 
   const int64_t n_total = (int64_t)L * (L - 1) / 2 * q * q;
   const int64_t n_target = (int64_t)ceil(density * (double)n_total);
-  const unsigned grid = (unsigned)std::min<size_t>(ceil_div(total, (size_t)kDecThreads), 8192);
+  // grid-stride kernels that end in global atomics on a few shared addresses
+  // (the active count, the hot digits) get at most 512 workgroups: 8192 of
+  // them made each pass wait ~0.1 ms on serialized atomics
+  const unsigned grid = (unsigned)std::min<size_t>(ceil_div(total, (size_t)kDecThreads), 512);
   hipLaunchKernelGGL(k_dec_zero, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<unsigned long long*>(st), (int)(sizeof(DecState) / 8));
   hipLaunchKernelGGL(k_dec_keys, dim3(grid), dim3(kDecThreads), 0, s, J, mask, C, N, L, q, keys,
@@ -234,7 +270,7 @@ hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, 
   hipLaunchKernelGGL(k_dec_finish, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL(k_dec_tie_count, dim3((unsigned)nblk), dim3(kDecThreads), 0, s, keys, total,
                      st, blk);
-  hipLaunchKernelGGL(k_dec_tie_scan, dim3(1), dim3(64), 0, s, blk, nblk);
+  hipLaunchKernelGGL(k_dec_tie_scan, dim3(1), dim3(kDecScanThreads), 0, s, blk, nblk);
   hipLaunchKernelGGL(k_dec_apply, dim3((unsigned)nblk), dim3(kDecThreads), 0, s, keys, total,
                      (int)Lq, st, blk, J, mask);
   if (n_active_out)
