@@ -80,33 +80,56 @@ __global__ void k_seqid_zero(unsigned long long* __restrict__ acc) {
   if (threadIdx.x < 2) acc[threadIdx.x] = 0ull;
 }
 
-// One wave per pair (A[k], B[perm[k]]): identity count n_k over the L
-// positions; the exact integer sums of n_k and n_k^2 go to acc[0], acc[1].
+// Each wave takes pairs (A[k], B[perm[k]]) k = wave, wave + waves, ...:
+// identity count n_k over the L positions; the exact integer sums of n_k and
+// n_k^2 are reduced per workgroup and added to acc[0], acc[1] once per
+// workgroup (a grid of at most kSeqBlocks workgroups, so the two shared
+// counters see few atomics).
 constexpr int kSeqWaves = 4;
+constexpr int kSeqBlocks = 512;
 
 __global__ __launch_bounds__(kSeqWaves * 64) void k_seqid_count(
     const int8_t* __restrict__ A, const int8_t* __restrict__ B, const int32_t* __restrict__ perm,
     int64_t N, int L, unsigned long long* __restrict__ acc, int32_t* dev_err) {
+  __shared__ unsigned long long part[2][kSeqWaves];
   const int lane = threadIdx.x % 64;
-  const int64_t k = (int64_t)blockIdx.x * kSeqWaves + threadIdx.x / 64;
-  if (k >= N) return;  // whole wave
-  int64_t kb = k;
-  if (perm) {
-    kb = perm[k];
-    if (kb < 0 || kb >= N) {
-      if (dev_err && lane == 0) atomicOr(dev_err, 4);
-      return;
+  const int wid = threadIdx.x / 64;
+  const int64_t waves = (int64_t)gridDim.x * kSeqWaves;
+  unsigned long long s1 = 0, s2 = 0;
+  for (int64_t k = (int64_t)blockIdx.x * kSeqWaves + wid; k < N; k += waves) {
+    int64_t kb = k;
+    if (perm) {
+      kb = perm[k];
+      if (kb < 0 || kb >= N) {
+        if (dev_err && lane == 0) atomicOr(dev_err, 4);
+        continue;
+      }
     }
-  }
-  const int8_t* a = A + k * L;
-  const int8_t* b = B + kb * L;
-  int same = 0;
-  for (int i = lane; i < L; i += 64) same += (a[i] == b[i]) ? 1 : 0;
+    const int8_t* a = A + k * L;
+    const int8_t* b = B + kb * L;
+    int same = 0;
+    for (int i = lane; i < L; i += 64) same += (a[i] == b[i]) ? 1 : 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) same += __shfl_xor(same, o, 64);
+    for (int o = 32; o > 0; o >>= 1) same += __shfl_xor(same, o, 64);
+    s1 += (unsigned long long)same;
+    s2 += (unsigned long long)same * (unsigned long long)same;
+  }
   if (lane == 0) {
-    atomicAdd(acc, (unsigned long long)same);
-    atomicAdd(acc + 1, (unsigned long long)same * (unsigned long long)same);
+    part[0][wid] = s1;
+    part[1][wid] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t1 = 0, t2 = 0;
+#pragma unroll
+    for (int w = 0; w < kSeqWaves; ++w) {
+      t1 += part[0][w];
+      t2 += part[1][w];
+    }
+    if (t1 | t2) {
+      atomicAdd(acc, t1);
+      atomicAdd(acc + 1, t2);
+    }
   }
 }
 
@@ -146,7 +169,8 @@ hipError_t launch_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, i
                         double* out, void* ws, int32_t* dev_err, hipStream_t s) {
   unsigned long long* acc = static_cast<unsigned long long*>(ws);
   hipLaunchKernelGGL(k_seqid_zero, dim3(1), dim3(64), 0, s, acc);
-  hipLaunchKernelGGL(k_seqid_count, dim3((unsigned)ceil_div(N, kSeqWaves)), dim3(kSeqWaves * 64), 0,
+  hipLaunchKernelGGL(k_seqid_count, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(N, kSeqWaves), kSeqBlocks))),
+                     dim3(kSeqWaves * 64), 0,
                      s, A, B, perm, N, L, acc, dev_err);
   hipLaunchKernelGGL(k_seqid_finish, dim3(1), dim3(64), 0, s, acc, N, L, out);
   return hipGetLastError();
