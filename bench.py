@@ -35,6 +35,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gather_lds_bytes(N, L, q, sweeps, cus):
+    """LDS traffic of a gather-form sweep launch: every visit reads the
+    q-vector of L-1 coupling rows; every workgroup stages site i's L-1 blocks
+    of q x q once per visit of site i (workgroups as the library sizes them:
+    chains spread over the CUs in as few rounds as workgroups of at most 128
+    chains allow; at L = 100 the tokens never limit that size)."""
+    rounds = -(-N // (cus * 128))
+    cpb = min(128, -(-N // (rounds * cus)))
+    nwg = -(-N // cpb)
+    return N * L * sweeps * (L - 1) * q * 4 + nwg * sweeps * L * (L - 1) * q * q * 4
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,18 +201,8 @@ def main():
         api.gibbs(h, J, ck, 0, seed_chain, H_ws=Wg, sampler="gather")
     g_fix = t.stop_ms() / reps
     g_ms = g_all - g_fix
-    # LDS traffic the gather form needs: every visit reads the q-vector of L-1
-    # coupling rows; every workgroup stages site i's L-1 blocks of q x q once
-    # per visit of site i (workgroup size as chosen by the library: chains
-    # spread over the CUs in as few rounds as workgroups of at most 128
-    # chains allow; at L = 100 the tokens never limit that size)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    rounds = -(-N // (cus * 128))
-    cpb = min(128, -(-N // (rounds * cus)))
-    nwg = -(-N // cpb)
-    lds_gather = visits * (L - 1) * q * 4
-    lds_stage = nwg * sweeps * L * (L - 1) * q * q * 4
-    lds_bytes = lds_gather + lds_stage
+    lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
     lds_gbs = lds_bytes / (g_ms * 1e-3) / 1e9
     lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9  # GB/s at 2.4 GHz
     log(f"gather sweep kernel: {g_ms:.3f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms re-layout), "
@@ -380,11 +382,11 @@ def bench_next(args):
     the trained model, alignment of M = 20 000 drawn by 200 sweeps, 80% identity
     weights): (1) the mixing time of Sec. 4.1 from 10 000 data-started chains
     and equilibrium sampling of 10 000 chains for 2 t_mix sweeps; (2)
-    Metropolis sweeps of 10 000 chains (field form: proposal uniform over the
-    other q - 1 states); (3) one edDCA graph update (symmetric KL scores of
-    every element, selection of the smallest 1%) and one masked epoch.  The
-    line's value is the Metropolis sweep rate; its roofline is the field-form
-    kernel's algorithmic HBM traffic."""
+    Metropolis sweeps of 10 000 chains (proposal uniform over the other q - 1
+    states) in the gather and the field form; (3) one edDCA graph update
+    (symmetric KL scores of every element, selection of the smallest 1%) and
+    one masked epoch.  The line's value is the gather-form Metropolis sweep
+    rate; its roofline is that kernel's LDS traffic."""
     import numpy as np
     import torch
 
@@ -426,30 +428,58 @@ def bench_next(args):
         f"equilibrium sample of {N} chains (mixing time + {2 * (t_mix or 0)} sweeps): "
         f"{eq_s * 1e3:.1f} ms")
 
-    # (2) Metropolis sweeps (field form)
-    ch = api.init_chains(N, L, q, seed=3002)
-    H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS)
-    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
-    api.gibbs(h, J, ch, 1, 3002, H_ws=H, sampler="metropolis")  # builds the fields
+    # (2) Metropolis sweeps: gather form (the default where the model fits)
+    # and field form, on the same start chains
     t = Timer()
     reps = max(args.steps, 3)
+    visits = N * L * sweeps
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    ch = api.init_chains(N, L, q, seed=3002)
+    Wg = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS | B.SAMPLER_GATHER)
+    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+    api.gibbs(h, J, ch, 1, 3002, H_ws=Wg, sampler="metropolis-gather")  # warm
+    flips.zero_()
+    t.start()
+    for r in range(reps):
+        api.gibbs(h, J, ch, sweeps, 3002, sweep_offset=1 + r * sweeps, H_ws=Wg, flips=flips,
+                  sampler="metropolis-gather")
+    mg_all = t.stop_ms() / reps
+    acc_g = float(flips.cpu()[0]) / reps / visits
+    t.start()
+    for r in range(reps):  # the per-call coupling re-layout and token pass alone
+        api.gibbs(h, J, ch, 0, 3002, H_ws=Wg, sampler="metropolis-gather")
+    mg_fix = t.stop_ms() / reps
+    mg_ms = mg_all - mg_fix
+    lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
+    lds_gbs = lds_bytes / (mg_ms * 1e-3) / 1e9
+    lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9
+    log(f"Metropolis, gather form: {mg_ms:.2f} ms per {sweeps} sweeps (+{mg_fix:.3f} ms re-layout; "
+        f"{visits / (mg_ms * 1e-3):.3e} site-updates/s), acceptance {acc_g:.3f}, "
+        f"LDS {lds_gbs:.0f} GB/s of {lds_peak:.0f}")
+
+    ch = api.init_chains(N, L, q, seed=3002)
+    H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS | B.SAMPLER_FIELDS)
+    api.gibbs(h, J, ch, 1, 3002, H_ws=H, sampler="metropolis-fields")  # builds the fields
+    flips.zero_()
     t.start()
     for r in range(reps):
         api.gibbs(h, J, ch, sweeps, 3002, sweep_offset=1 + r * sweeps, H_ws=H, flips=flips,
-                  keep_fields=True, sampler="metropolis")
+                  keep_fields=True, sampler="metropolis-fields")
     m_ms = t.stop_ms() / reps
     acc = float(flips.cpu()[0]) / reps
-    visits = N * L * sweeps
     m_bytes = visits * 8 + acc * 8 * (Lq - q) + 2 * N * L
     m_gbs = m_bytes / (m_ms * 1e-3) / 1e9
-    log(f"Metropolis: {m_ms:.2f} ms per {sweeps} sweeps ({visits / (m_ms * 1e-3):.3e} "
+    log(f"Metropolis, field form: {m_ms:.2f} ms per {sweeps} sweeps ({visits / (m_ms * 1e-3):.3e} "
         f"site-updates/s), acceptance {acc / visits:.3f}, algorithmic HBM {m_gbs:.0f} GB/s")
     g_ch = api.init_chains(N, L, q, seed=3002)
     t.start()
     for r in range(reps):
         api.gibbs(h, J, g_ch, sweeps, 3002, sweep_offset=r * sweeps)
     g_ms = t.stop_ms() / reps
-    extras["metropolis"] = {"ms_per_launch": m_ms, "acceptance": acc / visits,
+    extras["metropolis"] = {"gather_ms_per_launch": mg_ms, "gather_relayout_ms": mg_fix,
+                            "gather_acceptance": acc_g, "gather_lds_GBps": lds_gbs,
+                            "fields_ms_per_launch": m_ms, "fields_acceptance": acc / visits,
+                            "fields_alg_hbm_GBps": m_gbs,
                             "gibbs_ms_per_launch_same_chains": g_ms}
 
     # (3) element decimation: one graph update and one masked epoch
@@ -476,17 +506,17 @@ def bench_next(args):
         f"{int(n_act.cpu()[0])} left), masked epoch {me_ms:.2f} ms")
 
     out = {
-        "metric": METRIC, "value": visits / (m_ms * 1e-3), "unit": "site-updates/s",
-        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": m_ms,
+        "metric": METRIC, "value": visits / (mg_ms * 1e-3), "unit": "site-updates/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": mg_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (planted sparse Potts model; alignment sampled from it)",
         "config": {"workload": "equilibrium sampling, Metropolis sweeps and element "
                                "decimation at protein scale", "L": L, "q": q, "chains": N,
                    "msa_rows": M, "sweeps_per_step": sweeps},
-        "roofline": {"kernel": "k_gibbs_hbm (Metropolis sweeps, field form)", "bound": "hbm",
-                     "achieved": m_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": m_gbs / HBM_PEAK_GBS, "traffic": None, "launch_ms": m_ms,
-                     "alg_bytes_per_launch": m_bytes},
+        "roofline": {"kernel": "k_gibbs_gather (Metropolis sweeps, gather form)",
+                     "bound": "lds", "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",
+                     "frac": lds_gbs / lds_peak, "traffic": None, "launch_ms": mg_ms,
+                     "alg_bytes_per_launch": lds_bytes},
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

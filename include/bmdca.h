@@ -81,8 +81,9 @@ typedef enum {
 #define BMDCA_GIBBS_KEEP_FIELDS 0x40 /* field form only: H_ws already holds
                                         the fields of these chains */
 #define BMDCA_SAMPLER_METROPOLIS 0x80 /* single-site Metropolis instead of the
-                                        heat-bath draw (field form; not with
-                                        BMDCA_SAMPLER_GATHER): at site i in
+                                        heat-bath draw, in either form (with
+                                        BMDCA_SAMPLER_FIELDS or _GATHER, or
+                                        picked as above): at site i in
                                         state a propose a' uniformly among the
                                         q-1 other states, Philox counter
                                         (i/2, sweep, chain, 3), word 2(i%2):
@@ -182,6 +183,8 @@ int bmdca_stats(const int8_t* X, const double* w, int64_t M, int32_t L,
  *    H += J[(i,new),:] - J[(i,old),:];
  *  - gather form: H_i is recomputed at every visit from a copy of the
  *    coupling blocks that the call re-lays out in H_ws.
+ * With BMDCA_SAMPLER_METROPOLIS either form makes Metropolis visits instead
+ * (the rule stated at that flag) in the same site order.
  * chains  int8 [N][L] in/out
  * H_ws    scratch of bmdca_workspace_bytes(BMDCA_WS_GIBBS, N, L, q, flags)
  *         bytes

@@ -17,7 +17,9 @@ PREC_FP32, PREC_BF16X2 = 0, 1
 DEVERR_TOKEN, DEVERR_NONFINITE, DEVERR_INDEX = 1, 2, 4
 SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS, SAMPLER_METROPOLIS = 0x10, 0x20, 0x40, 0x80
 SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER,
-           "metropolis": SAMPLER_METROPOLIS}
+           "metropolis": SAMPLER_METROPOLIS,
+           "metropolis-fields": SAMPLER_METROPOLIS | SAMPLER_FIELDS,
+           "metropolis-gather": SAMPLER_METROPOLIS | SAMPLER_GATHER}
 (WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY, WS_DRAW,
  WS_SEQID, WS_DECIMATE) = range(10)
 

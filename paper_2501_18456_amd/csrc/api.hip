@@ -60,10 +60,9 @@ size_t gibbs_bytes(int64_t N, int L, int q) { return align256(sizeof(float) * (s
 constexpr int kPrecMask = 0x0F;
 constexpr int kSamplerMask = BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER | BMDCA_SAMPLER_METROPOLIS;
 
-// Sampler choice: 1 = gather form, 0 = field form, -1 = invalid request.
+// Sampler choice: 1 = gather form, 0 = field form, -1 = invalid request
+// (the same for the heat-bath draw and for Metropolis).
 int pick_gather(int flags, int L, int q) {
-  if (flags & BMDCA_SAMPLER_METROPOLIS)  // Metropolis runs in the field form
-    return (flags & BMDCA_SAMPLER_GATHER) ? -1 : 0;
   const int sel = flags & (BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER);
   if (sel == (BMDCA_SAMPLER_FIELDS | BMDCA_SAMPLER_GATHER)) return -1;
   if (sel == BMDCA_SAMPLER_FIELDS) return 0;
@@ -117,7 +116,8 @@ int gibbs_impl(const float* h, const float* J, int8_t* chains, int64_t N, int32_
       return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
                   gather_ws_bytes(L, q));
     return hip_status(launch_gibbs_gather(h, J, chains, N, L, q, sweeps, seed, sweep_offset, beta,
-                                          flips_out, nullptr, H_ws, s, ctl),
+                                          flips_out, nullptr, H_ws, s, ctl,
+                                          (flags & BMDCA_SAMPLER_METROPOLIS) != 0),
                       "gibbs/gather");
   }
   if (H_ws_bytes < gibbs_bytes(N, L, q))
@@ -175,7 +175,8 @@ int enqueue_train(const bmdca_train_problem& p, uint64_t epoch, const DevCtl& ct
   const uint64_t sweep0 = ctl.epoch ? 0 : epoch * (uint64_t)p.sweeps;
   if (gather) {
     BMDCA_TRY(hip_status(launch_gibbs_gather(p.h, p.J, p.chains, N, L, q, p.sweeps, p.seed, sweep0,
-                                             1.0f, p.flips_out, p.dev_err, H, s, ctl),
+                                             1.0f, p.flips_out, p.dev_err, H, s, ctl,
+                                             (p.prec & BMDCA_SAMPLER_METROPOLIS) != 0),
                          "train_step/gather"));
   } else {
     BMDCA_TRY(hip_status(launch_local_fields(p.h, p.J, p.chains, N, L, q, H, p.dev_err, s,

@@ -38,13 +38,21 @@ hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t
                                unsigned long long* flips_out, hipStream_t s,
                                const DevCtl& ctl = DevCtl(), bool metropolis = false);
 // Gather form (local fields recomputed per visit from LDS-staged coupling
-// blocks); needs no field workspace.
+// blocks); needs no field workspace.  metropolis = true: single-site
+// Metropolis instead of the heat-bath draw.
 bool gather_supported(int L, int q);
 size_t gather_ws_bytes(int L, int q);  // re-laid-out coupling blocks
 hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, int64_t N, int L,
                                int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, int32_t* dev_err, void* ws,
-                               hipStream_t s, const DevCtl& ctl = DevCtl());
+                               hipStream_t s, const DevCtl& ctl = DevCtl(),
+                               bool metropolis = false);
+// ----- sampler_mh.hip: the Metropolis sweeps over laid-out blocks Jt
+hipError_t launch_gather_metropolis(const float* h, const float* Jt, int8_t* chains, int64_t N,
+                                    int L, int q, int sweeps, uint64_t seed,
+                                    uint64_t sweep_offset, float beta,
+                                    unsigned long long* flips_out, int32_t* dev_err,
+                                    hipStream_t s, const DevCtl& ctl);
 
 // ----- stats.hip
 // Workspace carve-up of the one-hot statistics product for M rows.

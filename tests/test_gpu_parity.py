@@ -408,30 +408,60 @@ def test_gibbs_streams_equal_separate_calls(sampler, cus):
 
 
 # ----------------------------------------------------------------- Metropolis
-def test_metropolis_trajectories_match_oracle():
+MH_FORMS = ["metropolis-fields", "metropolis-gather"]
+
+
+@pytest.mark.parametrize("sampler", MH_FORMS)
+def test_metropolis_trajectories_match_oracle(sampler):
     L, q, N = 30, 21, 300
     h, J = synth.planted_dense(L, q, seed=140, sigma_J=0.3)
     ch0 = O.init_chains(N, L, q, seed=141)
     cg = dev(ch0)
-    api.gibbs(dev(h), dev(J), cg, 1, seed=142, sampler="metropolis")
+    api.gibbs(dev(h), dev(J), cg, 1, seed=142, sampler=sampler)
     ref, mg, _ = O.metropolis(h, J, ch0, q, 1, 142, want_margins=True)
     check_trajectory(host(cg), ref, mg)
     # several sweeps, continued by offset: chains that differ met a boundary event
     cg = dev(ch0)
-    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sampler="metropolis")
-    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sweep_offset=2, sampler="metropolis")
+    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sampler=sampler)
+    api.gibbs(dev(h), dev(J), cg, 2, seed=143, sweep_offset=2, sampler=sampler)
     ref, mg, _ = O.metropolis(h, J, ch0, q, 4, 143, want_margins=True)
     bad = np.nonzero((host(cg) != ref).any(axis=1))[0]
     assert all(mg[c].min() < BOUNDARY for c in bad)
     assert len(bad) <= N // 50
 
 
-def test_metropolis_stationary_marginals_vs_enumeration():
+@pytest.mark.parametrize("L,q,N", [
+    # the lane layouts of the gather form (8 lanes as 8, 4, 2, 1 site groups),
+    # several waves per workgroup, many chunks, largest L and q
+    (30, 2, 2600), (61, 3, 300), (45, 7, 2100), (130, 13, 700),
+    (77, 21, 2300), (200, 17, 120), (300, 32, 16), (512, 21, 10)])
+def test_metropolis_gather_lane_splits(L, q, N):
+    """Gather-form Metropolis over the lane layouts and workgroup shapes:
+    after three sweeps in one call every chain that differs from the oracle
+    went through a boundary event, and with none the flip counts agree."""
+    h, J = synth.planted_dense(L, q, seed=263 + L, sigma_J=0.1)
+    ch = O.init_chains(N, L, q, seed=264)
+    flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chg = dev(ch)
+    api.gibbs(dev(h), dev(J), chg, sweeps=3, seed=265, sweep_offset=5, flips=flips,
+              sampler="metropolis-gather")
+    g = host(chg)
+    orc, mg, oflips = O.metropolis(h, J, ch, q, 3, 265, sweep_offset=5, want_margins=True)
+    bad = np.nonzero((g != orc).any(axis=1))[0]
+    for c in bad:
+        assert mg[c].min() < BOUNDARY
+    assert len(bad) <= max(2, N // 50)
+    if len(bad) == 0:
+        assert int(host(flips)[0]) == oflips
+
+
+@pytest.mark.parametrize("sampler", MH_FORMS)
+def test_metropolis_stationary_marginals_vs_enumeration(sampler):
     L, q, N = 4, 3, 100000
     h, J = synth.planted_dense(L, q, seed=144, sigma_J=1.0)
     p1, p2, _ = O.enumerate_exact(h, J, L, q)
     cg = api.init_chains(N, L, q, seed=145)
-    api.gibbs(dev(h), dev(J), cg, 80, seed=146, sampler="metropolis")
+    api.gibbs(dev(h), dev(J), cg, 80, seed=146, sampler=sampler)
     Y = onehot(host(cg).astype(np.int64), q)
     s1, s2 = Y.mean(0), Y.T @ Y / N
     z = max((np.abs(s1 - p1) / np.sqrt(np.maximum(p1 * (1 - p1), 1e-12) / N)).max(),
@@ -439,7 +469,8 @@ def test_metropolis_stationary_marginals_vs_enumeration():
     assert z < 4.5, z
 
 
-def test_train_step_with_metropolis_sweeps():
+@pytest.mark.parametrize("sampler", MH_FORMS)
+def test_train_step_with_metropolis_sweeps(sampler):
     """train_step's sampler leg with the Metropolis flag is bmdca_gibbs with it."""
     L, q, N = 20, 21, 500
     h, J = synth.planted_dense(L, q, seed=147, sigma_J=0.1)
@@ -447,12 +478,12 @@ def test_train_step_with_metropolis_sweeps():
     f1, f2, _ = api.stats(dev(X), q, None, -1.0, "fp32")
     ch0 = O.init_chains(N, L, q, seed=149)
     hg, Jg, cg = dev(h), dev(J), dev(ch0)
-    api.train_step(hg, Jg, cg, f1, f2, 0.05, 5, 150, 3, "bf16x2", sampler="metropolis")
+    api.train_step(hg, Jg, cg, f1, f2, 0.05, 5, 150, 3, "bf16x2", sampler=sampler)
     c2 = dev(ch0)
-    api.gibbs(dev(h), dev(J), c2, 5, 150, sweep_offset=15, sampler="metropolis")
+    api.gibbs(dev(h), dev(J), c2, 5, 150, sweep_offset=15, sampler=sampler)
     assert torch.equal(cg, c2)
-    # Metropolis has no gather form: rejected (no workspace size, and the call itself)
-    bad = B.SAMPLER_METROPOLIS | B.SAMPLER_GATHER
+    # both forms at once is not a sampler: rejected (no workspace size, and the call)
+    bad = B.SAMPLER_METROPOLIS | B.SAMPLER_GATHER | B.SAMPLER_FIELDS
     assert B.lib().bmdca_workspace_bytes(B.WS_GIBBS, N, L, q, bad) == 0
     ws = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS)
     with pytest.raises(B.BmdcaError):
