@@ -787,6 +787,76 @@ int64_t orc_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, i
     return n_act - kk;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Element activation (eaDCA, Sec. 2.4 "Element activation DCA"): starting   */
+/* from an empty graph, each graph update targets a number of elements equal */
+/* to the fraction factivate of the currently inactive ones and activates,   */
+/* among all elements (i < j, a, b) -- active ones included, which is why    */
+/* fewer may be added -- those whose model pairwise marginal p_ij(a,b) is    */
+/* farthest from the data's f_ij(a,b).  The paper leaves the distance to a   */
+/* citation; the reading here is the Kullback-Leibler divergence between the */
+/* two Bernoulli variables [s_i == a][s_j == b] under the data and under the */
+/* model:  D(f || p) = f log(f/p) + (1-f) log((1-f)/(1-p)),                  */
+/* with 0 log(0/x) = 0 and +inf where the data has mass the model lacks.     */
+/* Count: k = max(1, floor(factivate n_inactive)) (0 when none is inactive); */
+/* the k largest (D, then smallest r1 Lq + r2) are set active.               */
+/* ------------------------------------------------------------------------ */
+double orc_bernoulli_kl(double f, double p)
+{
+    double d = 0.0;
+    if (f > 0.0) d += (p > 0.0) ? f * log(f / p) : INFINITY;
+    if (f < 1.0) d += (p < 1.0) ? (1.0 - f) * log((1.0 - f) / (1.0 - p)) : INFINITY;
+    return d > 0.0 ? d : 0.0;
+}
+
+static int orc_scored_cmp_desc(const void* a, const void* b)
+{
+    const orc_scored* x = (const orc_scored*)a;
+    const orc_scored* y = (const orc_scored*)b;
+    if (x->score > y->score) return -1;
+    if (x->score < y->score) return 1;
+    return (x->key < y->key) ? -1 : (x->key > y->key);
+}
+
+int64_t orc_activate(uint8_t* mask, const int8_t* chains, int64_t N, int32_t L, int32_t q,
+                     const double* f2, double factivate)
+{
+    const int64_t Lq = (int64_t)L * q;
+    double* p1 = (double*)malloc(sizeof(double) * (size_t)Lq);
+    double* p2 = (double*)malloc(sizeof(double) * (size_t)Lq * (size_t)Lq);
+    orc_chain_freqs(chains, N, L, q, p1, p2);
+    const int64_t n_total = (int64_t)L * (L - 1) / 2 * q * q;
+    orc_scored* s = (orc_scored*)malloc(sizeof(orc_scored) * (size_t)n_total);
+    int64_t n = 0, n_act = 0;
+    for (int64_t r1 = 0; r1 < Lq; ++r1)
+        for (int64_t r2 = r1 + 1; r2 < Lq; ++r2) {
+            if (r1 / q == r2 / q) continue;
+            const size_t k = IDX2(r1, r2, Lq);
+            if (mask[k]) ++n_act;
+            s[n].score = orc_bernoulli_kl(f2[k], p2[k]);
+            s[n].key = r1 * Lq + r2;
+            ++n;
+        }
+    const int64_t n_inact = n_total - n_act;
+    int64_t kk = 0;
+    if (n_inact > 0) {
+        kk = (int64_t)floor(factivate * (double)n_inact);
+        if (kk < 1) kk = 1;
+    }
+    qsort(s, (size_t)n, sizeof(orc_scored), orc_scored_cmp_desc);
+    int64_t added = 0;
+    for (int64_t t = 0; t < kk; ++t) {
+        const int64_t r1 = s[t].key / Lq, r2 = s[t].key % Lq;
+        if (!mask[IDX2(r1, r2, Lq)]) ++added;
+        mask[IDX2(r1, r2, Lq)] = 1;
+        mask[IDX2(r2, r1, Lq)] = 1;
+    }
+    free(s);
+    free(p1);
+    free(p2);
+    return n_act + added;
+}
+
 /* Eq. (5) on a sparse graph: as orc_update, with inactive elements (mask 0)
  * held at zero. */
 void orc_update_masked(float* h, float* J, const uint8_t* mask, const double* f1,

@@ -78,6 +78,8 @@ def _declare(L):
         "orc_seqid": (None, [_p, _p, _p, _i64, _i32, _p]),
         "orc_skl_element": (_f64, [_f64, _f64]),
         "orc_decimate": (_i64, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64]),
+        "orc_bernoulli_kl": (_f64, [_f64, _f64]),
+        "orc_activate": (_i64, [_p, _p, _i64, _i32, _i32, _p, _f64]),
         "orc_train_step_masked": (_f64, [_p, _p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32,
                                          _u64, _u64, _p, _p]),
     }
@@ -368,6 +370,21 @@ def decimate(J, mask, chains, q: int, drate: float, density: float):
     N, L = ch.shape
     n = lib().orc_decimate(_ptr(Jc), _ptr(mc), _ptr(ch), N, L, q, float(drate), float(density))
     return Jc, mc, int(n)
+
+
+def bernoulli_kl(f: float, p: float) -> float:
+    """KL divergence of Bernoulli(f) from Bernoulli(p) (element-activation distance)."""
+    return lib().orc_bernoulli_kl(float(f), float(p))
+
+
+def activate(mask, chains, f2, q: int, factivate: float):
+    """One element-activation graph update; returns (mask, active elements after)."""
+    mc = np.ascontiguousarray(mask, dtype=np.uint8).copy()
+    ch = _i8(chains)
+    N, L = ch.shape
+    f2 = np.ascontiguousarray(f2, dtype=np.float64)
+    n = lib().orc_activate(_ptr(mc), _ptr(ch), N, L, q, _ptr(f2), float(factivate))
+    return mc, int(n)
 
 
 def train_step_masked(h, J, mask, chains, f1, f2, q: int, lr: float, sweeps: int, seed: int,

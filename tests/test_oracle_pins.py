@@ -653,6 +653,98 @@ def test_decimation_selects_smallest_scores():
     assert n3 == n and np.array_equal(m3, mask)
 
 
+# ------------------------------------------------- element activation (eaDCA, Sec. 2.4)
+def test_activation_distance_is_bernoulli_kl():
+    """The distance is KL(Bernoulli(f) || Bernoulli(p)) (the reading of "most
+    distant"): scipy's relative entropy of the two two-outcome laws, the
+    closed forms at f = 0 and f = 1, zero iff f = p, +inf where the data has
+    mass the model lacks."""
+    from scipy.special import rel_entr
+    g = np.random.default_rng(41)
+    for f, p in zip(g.random(200), g.random(200)):
+        ref = float(rel_entr(f, p) + rel_entr(1 - f, 1 - p))
+        assert abs(O.bernoulli_kl(f, p) - ref) <= 1e-13 * max(1.0, ref)
+        assert O.bernoulli_kl(f, p) > 0 and O.bernoulli_kl(f, f) == 0.0
+    for p in (0.1, 0.5, 0.9):
+        assert abs(O.bernoulli_kl(0.0, p) + np.log(1 - p)) <= 1e-15
+        assert abs(O.bernoulli_kl(1.0, p) + np.log(p)) <= 1e-15
+    assert O.bernoulli_kl(0.2, 0.0) == np.inf and O.bernoulli_kl(0.2, 1.0) == np.inf
+    assert O.bernoulli_kl(0.0, 0.0) == 0.0 and O.bernoulli_kl(1.0, 1.0) == 0.0
+
+
+def _activate_numpy(mask, chains, f2, q, factivate):
+    """Independent bookkeeping: numpy frequencies, lexicographic (-score, index) order."""
+    N, L = chains.shape
+    Lq = L * q
+    Y = onehot(chains.astype(np.int64), q)
+    p2 = Y.T @ Y / N
+    r1, r2 = np.triu_indices(Lq, 1)
+    keep = r1 // q != r2 // q
+    r1, r2 = r1[keep], r2[keep]
+    sc = np.array([O.bernoulli_kl(f2[a, b], p2[a, b]) for a, b in zip(r1, r2)])
+    n_act = int(mask[r1, r2].sum())
+    n_inact = r1.size - n_act
+    k = 0 if n_inact == 0 else max(1, int(np.floor(factivate * n_inact)))
+    order = np.lexsort((r1 * Lq + r2, -sc))[:k]
+    m2 = mask.copy()
+    m2[r1[order], r2[order]] = m2[r2[order], r1[order]] = 1
+    return m2, int(m2[r1, r2].sum())
+
+
+def test_activation_selects_largest_distances():
+    L, q, N = 7, 4, 300
+    h, J = synth.planted_dense(L, q, seed=42, sigma_J=0.6)
+    X = synth.clustered_msa(400, L, q, seed=43)
+    f2 = O.stats(X, q, None, -1.0)[1]
+    chains = O.gibbs(h, J, O.init_chains(N, L, q, seed=44), q, 5, 45)[0]
+    mask = np.zeros((L * q, L * q), dtype=np.uint8)
+    n_total = L * (L - 1) // 2 * q * q
+    prev = 0
+    for step in range(5):
+        ref = _activate_numpy(mask, chains, f2, q, 0.05)
+        new, n = O.activate(mask, chains, f2, q, 0.05)
+        assert n == ref[1] and np.array_equal(new, ref[0])
+        assert np.array_equal(new, new.T) and np.all(new[mask == 1] == 1)
+        # the k largest may include active elements (fewer are added then):
+        # with the same chains the second update re-selects the first's
+        k = max(1, int(np.floor(0.05 * (n_total - prev))))
+        assert prev <= n <= prev + k and (step > 0 or n == k)
+        mask, prev = new, n
+        chains = O.gibbs(h, J, chains, q, 1, 50 + step)[0]  # new model statistics
+    assert prev > k
+    # a complete graph stays complete
+    full = np.ones((L * q, L * q), dtype=np.uint8)
+    for i in range(L):
+        full[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
+    m, n = O.activate(full, chains, f2, q, 0.05)
+    assert n == n_total and np.array_equal(m, full)
+
+
+def test_activation_with_matched_statistics_takes_index_order():
+    """With f equal to the chains' own frequencies every distance is 0, so the
+    k activated elements are the first k (r1 < r2, other site) in index order;
+    a pair the chains never show but the data does (+inf) comes first."""
+    L, q, N = 5, 3, 50
+    chains = O.init_chains(N, L, q, seed=46)
+    Y = onehot(chains.astype(np.int64), q)
+    f2 = Y.T @ Y / N
+    Lq = L * q
+    r1, r2 = np.triu_indices(Lq, 1)
+    keep = r1 // q != r2 // q
+    r1, r2 = r1[keep], r2[keep]
+    mask = np.zeros((Lq, Lq), dtype=np.uint8)
+    m, n = O.activate(mask, chains, f2, q, 0.1)
+    k = int(np.floor(0.1 * r1.size))
+    assert n == k
+    assert np.array_equal(np.nonzero(m[r1, r2])[0], np.arange(k))
+    zero = np.nonzero(f2[r1, r2] == 0)[0][-1]  # a pair absent from the chains
+    f2b = f2.copy()
+    f2b[r1[zero], r2[zero]] = f2b[r2[zero], r1[zero]] = 0.5
+    m, n = O.activate(mask, chains, f2b, q, 0.1)
+    assert m[r1[zero], r2[zero]] == 1 and n == k
+    assert np.array_equal(np.nonzero(m[r1, r2])[0], np.sort(np.r_[np.arange(k - 1), zero]))
+
+
 def test_masked_update_holds_pruned_couplings_at_zero():
     L, q, N = 6, 3, 200
     h, J = synth.planted_dense(L, q, seed=34, sigma_J=0.5)
