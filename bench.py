@@ -68,8 +68,8 @@ def parse():
                          "L=512 model; group: 64 "
                          "uneven models trained together in one captured graph per epoch; "
                          "serve: request loop over 8 resident models at three arrival rates; "
-                         "next: equilibrium sampling with the mixing time, Metropolis sweeps "
-                         "and element decimation at protein scale")
+                         "next: equilibrium sampling with the mixing time, Metropolis sweeps, "
+                         "element decimation and activation at protein scale")
     ap.add_argument("--lanes", type=int, default=8, help="group/serve: concurrent lane streams")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
@@ -384,8 +384,9 @@ def bench_next(args):
     and equilibrium sampling of 10 000 chains for 2 t_mix sweeps; (2)
     Metropolis sweeps of 10 000 chains (proposal uniform over the other q - 1
     states) in the gather and the field form; (3) one edDCA graph update
-    (symmetric KL scores of every element, selection of the smallest 1%) and
-    one masked epoch.  The line's value is the gather-form Metropolis sweep
+    (symmetric KL scores of every element, selection of the smallest 1%), one
+    masked epoch, and one eaDCA graph update (Bernoulli KL scores of every
+    element, the largest 0.1% of the inactive count activated).  The line's value is the gather-form Metropolis sweep
     rate; its roofline is that kernel's LDS traffic."""
     import numpy as np
     import torch
@@ -504,14 +505,23 @@ def bench_next(args):
                             "active_after": int(n_act.cpu()[0]), "elements": total}
     log(f"edDCA: graph update {d_ms:.2f} ms ({total} elements scored, "
         f"{int(n_act.cpu()[0])} left), masked epoch {me_ms:.2f} ms")
+    # element activation: one graph update from the empty graph (factivate 0.001)
+    empty = torch.zeros((Lq, Lq), dtype=torch.uint8, device="cuda")
+    api.activate(empty.clone(), ch2, f2, q, 0.001, ws=wsd, n_active=n_act)  # warm
+    t.start()
+    api.activate(empty, ch2, f2, q, 0.001, ws=wsd, n_active=n_act)
+    a_ms = t.stop_ms()
+    extras["activation"] = {"graph_update_ms": a_ms, "active_after": int(n_act.cpu()[0])}
+    log(f"eaDCA: graph update {a_ms:.2f} ms ({total} elements scored, "
+        f"{int(n_act.cpu()[0])} active)")
 
     out = {
         "metric": METRIC, "value": visits / (mg_ms * 1e-3), "unit": "site-updates/s",
         "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": mg_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (planted sparse Potts model; alignment sampled from it)",
-        "config": {"workload": "equilibrium sampling, Metropolis sweeps and element "
-                               "decimation at protein scale", "L": L, "q": q, "chains": N,
+        "config": {"workload": "equilibrium sampling, Metropolis sweeps, element "
+                               "decimation and activation at protein scale", "L": L, "q": q, "chains": N,
                    "msa_rows": M, "sweeps_per_step": sweeps},
         "roofline": {"kernel": "k_gibbs_gather (Metropolis sweeps, gather form)",
                      "bound": "lds", "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",

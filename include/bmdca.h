@@ -376,6 +376,31 @@ int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N,
                    long long* n_active, void* ws, size_t ws_bytes,
                    int32_t* dev_err, void* stream);
 
+/* One graph update of element activation (eaDCA, Sec. 2.4): among all
+ * elements (r1, r2), r1 < r2 in different sites, active or not, the ones
+ * whose model marginal p (chain frequency, as above) is farthest from the
+ * data frequency f = f2[r1][r2] are set active.  The paper leaves the
+ * distance to a citation; this library takes the Kullback-Leibler divergence
+ * of the two Bernoulli laws of the element's indicator,
+ *   D = f log(f/p) + (1-f) log((1-f)/(1-p))
+ * (0 log 0 = 0; +inf where f > 0 = p or f < 1 = p).  With n_inactive
+ * elements, the k = max(1, floor(factivate n_inactive)) largest
+ * (D, then smallest r1 Lq + r2) get mask 1 on both triangles (k = 0 when
+ * none is inactive); selected elements already active add nothing, as the
+ * paper notes.  J is not touched: inactive couplings are already 0.
+ * mask      uint8 [Lq][Lq] in/out (device, symmetric)
+ * chains    int8 [N][L], the model's current chains
+ * f2        FP64 [Lq][Lq] data pairwise frequencies (bmdca_stats)
+ * factivate fraction in [0, 1]
+ * n_active  optional device int64 out: active elements after the update
+ * ws        scratch, bmdca_workspace_bytes(BMDCA_WS_DECIMATE, N, L, q, 0)
+ * dev_err   optional; BMDCA_DEVERR_TOKEN on a token outside 0..q-1,
+ *           BMDCA_DEVERR_NONFINITE on an f2 entry outside [0, 1] (scored 0). */
+int bmdca_activate(uint8_t* mask, const int8_t* chains, int64_t N, int32_t L,
+                   int32_t q, const double* f2, double factivate,
+                   long long* n_active, void* ws, size_t ws_bytes,
+                   int32_t* dev_err, void* stream);
+
 /* Single-mutant library (Sec. 4.4): for each of B wild types,
  * dE[b][i*q + a] = E(wild type with site i set to a) - E(wild type)
  *               = -(H_i(a) - H_i(wt_i)),  H_i(a) = h_i(a) + sum_{j!=i} J_ij(a, wt_j);

@@ -296,6 +296,22 @@ def decimate(J, mask, chains, q: int, drate: float, density: float, ws=None, dev
     return n_active
 
 
+def activate(mask, chains, f2, q: int, factivate: float, ws=None, dev_err=None, n_active=None):
+    """One element-activation graph update of the mask (in place); returns
+    the device int64 count of active elements afterwards."""
+    _dev(mask, torch.uint8, "mask", 2)
+    _dev(chains, torch.int8, "chains", 2)
+    _dev(f2, torch.float64, "f2", 2)
+    N, L = chains.shape
+    if ws is None:
+        ws = workspace(B.WS_DECIMATE, N, L, q, 0, chains.device)
+    if n_active is None:
+        n_active = torch.empty(1, dtype=torch.int64, device=chains.device)
+    check(B.lib().bmdca_activate(_ptr(mask), _ptr(chains), N, L, q, _ptr(f2), float(factivate),
+                                 _ptr(n_active), _ptr(ws), _nbytes(ws), _ptr(dev_err), _stream()))
+    return n_active
+
+
 # ------------------------------------------------------------ grouped training
 def train_ctl(device, target_pearson: float = 0.0, epoch: int = 0, active: bool = True):
     """A device control record (bmdca_train_ctl) as a uint8 tensor of its 24 bytes."""

@@ -555,6 +555,30 @@ int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, int
                     "decimate/select");
 }
 
+int bmdca_activate(uint8_t* mask, const int8_t* chains, int64_t N, int32_t L, int32_t q,
+                   const double* f2, double factivate, long long* n_active, void* ws,
+                   size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(L >= 2, "activation needs L >= 2 (got %d)", L);
+  BMDCA_REQUIRE(mask && chains && f2 && ws, "null pointer argument");
+  BMDCA_REQUIRE(N >= 1 && N < ((int64_t)1 << 24), "N=%lld outside 1..2^24-1", (long long)N);
+  BMDCA_REQUIRE(factivate >= 0.0 && factivate <= 1.0, "factivate=%g outside [0, 1]", factivate);
+  const DecimatePlan plan = plan_decimate(N, L, q);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "activate workspace %zu < %zu bytes", ws_bytes, plan.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = static_cast<char*>(ws);
+  void* sws = base + plan.off_stats;
+  double* C = reinterpret_cast<double*>(base + plan.off_C);
+  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, BMDCA_PREC_BF16X2, plan.sp,
+                                              sws, dev_err, s),
+                       "activate/counts"));
+  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, L * q, C, s), "activate/reduce"));
+  return hip_status(launch_activate(mask, C, f2, N, L, q, factivate, n_active,
+                                    base + plan.off_dec, dev_err, s),
+                    "activate/select");
+}
+
 int bmdca_train_group_step(const bmdca_train_problem* probs, int32_t n, int32_t lanes,
                            void* stream) {
   BMDCA_REQUIRE(probs && n >= 1, "group needs at least one problem");

@@ -9,47 +9,25 @@
 
 namespace bmdca {
 
-// Prefix sums C_m = w_0 + ... + w_m in ascending m (the definition's order,
-// so the sums are bit-identical to a plain sequential loop): the block stages
-// kPrefixChunk weights at a time in LDS and one thread adds them, eight at a
-// time through registers so that only the FP64 add chain is serial.
-constexpr int kPrefixThreads = 1024;
-constexpr int kPrefixPer = 4;
-constexpr int kPrefixChunk = kPrefixThreads * kPrefixPer;
-
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix_weights(const double* __restrict__ w,
-                                                                   int64_t M,
-                                                                   double* __restrict__ C) {
-  __shared__ double buf[kPrefixChunk];
+// Prefix sums C_m = w_0 + ... + w_m in ascending m (the definition's order):
+// the block stages 256 weights at a time in LDS and one thread adds them.
+__global__ __launch_bounds__(256) void k_prefix_weights(const double* __restrict__ w, int64_t M,
+                                                        double* __restrict__ C) {
+  __shared__ double buf[256];
   double run = 0.0;
-  for (int64_t m0 = 0; m0 < M; m0 += kPrefixChunk) {
-#pragma unroll
-    for (int j = 0; j < kPrefixPer; ++j) {
-      const int t = threadIdx.x + j * kPrefixThreads;
-      buf[t] = (m0 + t < M) ? w[m0 + t] : 0.0;
-    }
+  for (int64_t m0 = 0; m0 < M; m0 += 256) {
+    const int64_t m = m0 + threadIdx.x;
+    buf[threadIdx.x] = (m < M) ? w[m] : 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const int n = (int)min<int64_t>(kPrefixChunk, M - m0);
-      for (int k0 = 0; k0 < n; k0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = buf[k0 + j];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (k0 + j < n) run += v[j];
-          v[j] = run;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) buf[k0 + j] = v[j];
+      const int n = (int)min<int64_t>(256, M - m0);
+      for (int k = 0; k < n; ++k) {
+        run += buf[k];
+        buf[k] = run;
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPrefixPer; ++j) {
-      const int t = threadIdx.x + j * kPrefixThreads;
-      if (m0 + t < M) C[m0 + t] = buf[t];
-    }
+    if (m < M) C[m] = buf[threadIdx.x];
     __syncthreads();
   }
 }
@@ -172,7 +150,7 @@ size_t seqid_ws_bytes() { return 256; }
 hipError_t launch_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed, int32_t* rows,
                             void* ws, int32_t* dev_err, hipStream_t s) {
   double* C = static_cast<double*>(ws);
-  hipLaunchKernelGGL(k_prefix_weights, dim3(1), dim3(kPrefixThreads), 0, s, w, M, C);
+  hipLaunchKernelGGL(k_prefix_weights, dim3(1), dim3(256), 0, s, w, M, C);
   if (n > 0)
     hipLaunchKernelGGL(k_draw_rows, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, C, M, n,
                        (uint32_t)seed, (uint32_t)(seed >> 32), rows, dev_err);

@@ -134,6 +134,10 @@ size_t dec_ws_bytes(int L, int q);
 hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, int L, int q,
                            double drate, double density, long long* n_active_out, void* ws,
                            hipStream_t s);
+// One eaDCA graph update from the chain counts C and the data frequencies f2.
+hipError_t launch_activate(uint8_t* mask, const double* C, const double* f2, int64_t N, int L,
+                           int q, double factivate, long long* n_active_out, void* ws,
+                           int32_t* dev_err, hipStream_t s);
 
 // ----- equilibrium.hip
 size_t draw_ws_bytes(int64_t M);

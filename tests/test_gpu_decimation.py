@@ -118,3 +118,86 @@ def test_decimation_driver_reaches_density():
     m = host(mask)
     assert np.all(host(Jg)[m == 0] == 0.0) and np.array_equal(m, m.T)
     assert all(a[1] > b[1] for a, b in zip(hist, hist[1:]))
+
+
+# ----------------------------------------------------------------- element activation
+def act_scores(chains, f2, q):
+    N, L = chains.shape
+    Y = np.zeros((N, L * q))
+    Y[np.arange(N)[:, None], np.arange(L)[None, :] * q + chains] = 1.0
+    p2 = Y.T @ Y / N
+    r1, r2 = np.triu_indices(L * q, 1)
+    keep = r1 // q != r2 // q
+    r1, r2 = r1[keep], r2[keep]
+    return r1, r2, np.array([O.bernoulli_kl(f2[a, b], p2[a, b]) for a, b in zip(r1, r2)])
+
+
+@pytest.mark.parametrize("L,q,N,fact", [(9, 21, 400, 0.05), (30, 5, 700, 0.02),
+                                        (12, 3, 300, 0.3)])
+def test_activate_matches_oracle(L, q, N, fact):
+    h, J = synth.planted_dense(L, q, seed=440 + L, sigma_J=0.4)
+    X = synth.clustered_msa(500, L, q, seed=441)
+    f2 = O.stats(X, q, None, -1.0)[1]
+    ch = O.gibbs(h, J, O.init_chains(N, L, q, seed=442), q, 4, 443)[0]
+    mask = np.zeros((L * q, L * q), dtype=np.uint8)
+    n_total = L * (L - 1) // 2 * q * q
+    for rnd in range(3):
+        mg = dev(mask)
+        n = api.activate(mg, dev(ch), dev(f2), q, fact)
+        mn, no = O.activate(mask, ch, f2, q, fact)
+        diff = np.argwhere(host(mg) != mn)
+        if diff.size:  # only elements tied with the threshold to ~1 ulp (log on GPU vs libm)
+            r1, r2, sc = act_scores(ch, f2, q)
+            k = max(1, int(np.floor(fact * (n_total - int(np.triu(mask, 1).sum())))))
+            thr = np.sort(sc)[::-1][k - 1]
+            for a, b in diff:
+                lo, hi = min(a, b), max(a, b)
+                s = sc[(r1 == lo) & (r2 == hi)][0]
+                assert abs(s - thr) <= 1e-12 * max(thr, 1e-300), (a, b, s, thr)
+        else:
+            assert int(host(n)[0]) == no
+        m = host(mg)
+        assert np.array_equal(m, m.T) and np.all(m[mask == 1] == 1)
+        mask = mn
+        ch = O.gibbs(h, J, ch, q, 1, 444 + rnd)[0]  # new model statistics
+
+
+def test_activate_edges():
+    L, q, N = 8, 4, 200
+    h, J = synth.planted_dense(L, q, seed=450, sigma_J=0.4)
+    X = synth.clustered_msa(300, L, q, seed=451)
+    f2 = O.stats(X, q, None, -1.0)[1]
+    ch = O.init_chains(N, L, q, seed=452)
+    n_total = L * (L - 1) // 2 * q * q
+    # a complete graph stays complete
+    full = api.full_mask(L, q)
+    before = full.clone()
+    n = api.activate(full, dev(ch), dev(f2), q, 0.5)
+    assert int(host(n)[0]) == n_total and torch.equal(full, before)
+    # factivate 0 still activates one element (the largest distance)
+    empty = torch.zeros((L * q, L * q), dtype=torch.uint8, device="cuda")
+    n = api.activate(empty, dev(ch), dev(f2), q, 0.0)
+    mo, no = O.activate(np.zeros((L * q, L * q), np.uint8), ch, f2, q, 0.0)
+    assert int(host(n)[0]) == 1 == no and np.array_equal(host(empty), mo)
+    # a frequency outside [0, 1] raises the device flag
+    bad = f2.copy()
+    bad[0, q] = bad[q, 0] = 1.5
+    e = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.activate(torch.zeros_like(empty), dev(ch), dev(bad), q, 0.1, dev_err=e)
+    assert int(host(e)[0]) == 2
+
+
+def test_activation_driver_reaches_target():
+    L, q, N = 10, 5, 800
+    X = synth.clustered_msa(600, L, q, seed=460)
+    f1, f2, _ = api.stats(dev(X), q, None, -1.0, "fp32")
+    hg = torch.log(f1).float().reshape(L, q).contiguous()
+    Jg = torch.zeros((L * q, L * q), dtype=torch.float32, device="cuda")
+    ch = api.init_chains(N, L, q, seed=461)
+    mask, hist, used = sparse.activation(hg, Jg, ch, f1, f2, 0.05, 5, 462, factivate=0.05,
+                                         target=0.8, gsteps=5, max_epochs=600)
+    m = host(mask)
+    assert hist[-1][2] >= 0.8, hist[-5:]
+    assert np.array_equal(m, m.T) and np.all(host(Jg)[m == 0] == 0.0)
+    assert all(a[1] <= b[1] for a, b in zip(hist, hist[1:]))
+    assert 0 < hist[-1][1] < L * (L - 1) // 2 * q * q
