@@ -233,6 +233,12 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   float hq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   unsigned long long nflip = 0;
+  // one Philox call gives the words of 4 consecutive sites (heat-bath draw)
+  // or 2 (Metropolis); sites are drawn in order from i = 0 every sweep.  The
+  // words are kept across sites except with 31 loads per wave, where the four
+  // extra live registers add spills and cost more than the calls they save.
+  constexpr bool kKeepRnd = IT != 31;
+  uint4 rnd = make_uint4(0u, 0u, 0u, 0u);
   const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
   for (int64_t t = 0; t < Tn; ++t) {
@@ -320,7 +326,8 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
       const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
       if constexpr (MH) {
         // proposal a' != a uniform, then the acceptance test (field form's rule)
-        const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 1, sg, cid, 3u), k0, k1);
+        if (!kKeepRnd || (i & 1) == 0)
+          rnd = philox4x32_10(make_uint4((uint32_t)i >> 1, sg, cid, 3u), k0, k1);
         const uint32_t wp = pick_word(rnd, 2 * (i & 1));
         const float uu = word_to_uniform(pick_word(rnd, 2 * (i & 1) + 1));
         const int a_old = (int)*tok_at(i);
@@ -361,7 +368,8 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
         float excl = V > 1 ? dpp_f<kDppShr1>(inc) : 0.0f;
         if (v == 0) excl = 0.0f;
         const float Stot = group_bcast<V, vL>(excl + P[eL], v);  // S_{q-1}
-        const uint4 rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
+        if (!kKeepRnd || (i & 3) == 0)
+          rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
         const float uz = word_to_uniform(pick_word(rnd, i & 3)) * Stot;
         int cnt = 0;
 #pragma unroll
