@@ -41,12 +41,15 @@ namespace bmdca {
 //     stores the new token.
 // Draw rule and Philox counters are those of the field form (the CDF test
 // S_a / S_{q-1} <= u is evaluated as S_a <= u * S_{q-1}).
-//   - MH = true replaces the draw by single-site Metropolis with the field
-//     form's proposal, counters and acceptance test: every lane of the quad
-//     group takes +H_i(a') and -H_i(a) from its own states (at most one of
-//     each in the group), the V lanes sum them, and lane p = 0 accepts iff
-//     u < exp(beta (H_i(a') - H_i(a))).  The fields are gathered in full as
-//     for the heat-bath draw.
+//   - MH = true makes single-site Metropolis visits with the field form's
+//     proposal, counters and acceptance test.  The proposal a' and the
+//     current a are known when the site starts, so only two entries of each
+//     row are needed: the chain's lanes split the chunk's sites (lane p takes
+//     positions p, p + LPC, ...) and add J_ij(a', s_j) - J_ij(a, s_j) (lane 0
+//     starts from h_i(a') - h_i(a)); at the end of the site a DPP sum over
+//     the chain's lanes gives H_i(a') - H_i(a) and lane p = 0 accepts iff
+//     u < exp(beta (H_i(a') - H_i(a))).  The staging of the blocks is the
+//     same as for the heat-bath draw.
 //
 // Synchronisation: one workgroup barrier per chunk-step.  Before it, each
 // wave waits for its share of the current chunk (vmcnt: at most the A - 1
@@ -176,6 +179,11 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     sweep_offset += st.sweep_offset;
   }
   // byte of the token of site j in the chain's token area
+  // byte offset of the token of site j (32-bit arithmetic)
+  auto tok_off = [&](int j) -> uint32_t {
+    const int m = j / S;
+    return (uint32_t)((((j % S) * m4 + (m >> 2)) * CPB + cb) * 4 + (m & 3));
+  };
   auto tok_at = [&](int j) -> unsigned char* {
     const int m = j / S;
     return tokb + ((size_t)((j % S) * m4 + (m >> 2)) * CPB + cb) * 4 + (m & 3);
@@ -239,8 +247,23 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   // extra live registers add spills and cost more than the calls they save.
   constexpr bool kKeepRnd = IT != 31;
   uint4 rnd = make_uint4(0u, 0u, 0u, 0u);
+  // Metropolis visit state: current and proposed state, uniform, and this
+  // lane's part of H_i(a') - H_i(a)
+  int mh_old = 0, mh_prop = 0;
+  float mh_u = 0.0f, mh_d = 0.0f;
+  // tokens of the next chunk-step's first two positions of this lane, read
+  // one step ahead (software pipeline), and their sites
+  uint32_t mh_nsv[2] = {0u, 0u};
+  int mh_nj[2] = {0, 0};
   const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
+  if (MH) {  // tokens of the first chunk-step (written above by this wave)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      mh_nj[e] = min(min(p + LPC * e, jc - 1), L - 1);
+      mh_nsv[e] = (uint32_t)tokb[tok_off(mh_nj[e])];
+    }
+  }
   for (int64_t t = 0; t < Tn; ++t) {
     // chunk t is complete once at most the younger issued chunks (ahead - 1
     // of them, fewer at the end) are pending
@@ -259,7 +282,31 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
       if (loader) issue_chunk(pi, pk, psl);
       advance(pi, pk, psl);
     }
-    if (k == 0) {
+    if (MH && k == 0) {
+      // proposal and uniform of this visit; lane 0 starts the difference
+      // with h_i(a') - h_i(a)
+      const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
+      if (!kKeepRnd || (i & 1) == 0)
+        rnd = philox4x32_10(make_uint4((uint32_t)i >> 1, sg, cid, 3u), k0, k1);
+      const uint32_t wp = pick_word(rnd, 2 * (i & 1));
+      mh_u = word_to_uniform(pick_word(rnd, 2 * (i & 1) + 1));
+      mh_old = (int)*tok_at(i);
+      mh_prop = (mh_old + 1 + (int)(((uint64_t)wp * (uint64_t)(Q - 1)) >> 32)) % Q;
+      // h_i by scalar loads of the whole row (uniform addresses), then a lane
+      // select: a per-lane vector load here would share the counter of the
+      // chunk loads in flight and make the wave wait for all of them
+      float hs[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) hs[a] = h[i * Q + a];
+      float hp = 0.0f, ho = 0.0f;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        hp = a == mh_prop ? hs[a] : hp;
+        ho = a == mh_old ? hs[a] : ho;
+      }
+      mh_d = p == 0 ? hp - ho : 0.0f;
+    }
+    if (!MH && k == 0) {
       // h_i for this lane's quad (scalar loads of the row, lane select)
       float hs[Q];
 #pragma unroll
@@ -280,7 +327,48 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
     // position is added unconditionally; positions past the last token dword
     // read any valid token.  Groups of 16 positions: 4 token loads, 16 row
     // loads, the adds (a tail group loads only its positions).
-    if (reader) {
+    if (MH && has_chain) {
+      // Metropolis needs two entries of each row: the chain's lanes split
+      // the chunk's sites (lane p: positions p, p + LPC, ...) and add
+      // J_ij(a', s_j) - J_ij(a, s_j); the row of j = i is the zero block.
+      // Two positions at a time, without branches: both token reads, then
+      // the four entry reads.  Positions past the chunk are clamped and not
+      // added; sites past the run read a valid token (clamped to L - 1) and
+      // find a zero row (the slot holds zeros past the run end).
+      const float* cb0 = ring + (size_t)csl * slot;
+      const int j0 = k * jc;
+      const int nr = (jc + LPC - 1) / LPC;  // positions per lane, uniform
+      for (int r0 = 0; r0 < nr; r0 += 2) {
+        uint32_t sv[2];
+        int jlv[2];
+        bool ok[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int jl = p + LPC * (r0 + e);
+          ok[e] = jl < jc;
+          jlv[e] = ok[e] ? jl : jc - 1;
+          sv[e] = r0 == 0 ? mh_nsv[e] : (uint32_t)tokb[tok_off(min(j0 + jlv[e], L - 1))];
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float* row = cb0 + __umul24((uint32_t)(jlv[e] * Q) + sv[e], (uint32_t)QP);
+          const float x = row[mh_prop] - row[mh_old];
+          mh_d += ok[e] ? x : 0.0f;
+        }
+      }
+    }
+    if (MH) {
+      // read the tokens the next chunk-step starts with (same site, next
+      // chunk; or the next site's first chunk)
+      const int nk = k + 1 < nchunk ? k + 1 : 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int jl = min(p + LPC * e, jc - 1);
+        mh_nj[e] = min(nk * jc + jl, L - 1);
+        mh_nsv[e] = (uint32_t)tokb[tok_off(mh_nj[e])];
+      }
+    }
+    if (!MH && reader) {
       const float* jb = ring + (size_t)csl * slot + 4 * v;
       const int m0 = k * jcs;  // multiple of 4
       const uint32_t* tw = tokw + (size_t)u * m4 * CPB + cb;
@@ -321,31 +409,24 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
 
     if (k == nchunk - 1) {
       // ---- combine the S site groups, draw, store the token
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] = combine_sites<V, LPC>(acc[e]);
-      const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
       if constexpr (MH) {
-        // proposal a' != a uniform, then the acceptance test (field form's rule)
-        if (!kKeepRnd || (i & 1) == 0)
-          rnd = philox4x32_10(make_uint4((uint32_t)i >> 1, sg, cid, 3u), k0, k1);
-        const uint32_t wp = pick_word(rnd, 2 * (i & 1));
-        const float uu = word_to_uniform(pick_word(rnd, 2 * (i & 1) + 1));
-        const int a_old = (int)*tok_at(i);
-        const int a_prop = (a_old + 1 + (int)(((uint64_t)wp * (uint64_t)(Q - 1)) >> 32)) % Q;
-        float d = 0.0f;
+        float d = group_fsum<8>(mh_d);  // H_i(a') - H_i(a), in every lane of the chain
+        if (LPC == 16) d += dpp_f<kDppRor8>(d);
+        const bool acc_mh = mh_u < expf(beta * d);
+        if (acc_mh) {
+          // the next step's tokens were read before this change
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int a = 4 * v + e;
-          const float f = hq[e] + acc[e];
-          if (a == a_prop) d += f;
-          if (a == a_old) d -= f;
+          for (int e = 0; e < 2; ++e)
+            if (mh_nj[e] == i) mh_nsv[e] = (uint32_t)mh_prop;
         }
-        d = group_fsum<V>(d);  // H_i(a') - H_i(a), one rounding
-        if (p == 0 && has_chain && uu < expf(beta * d)) {
+        if (p == 0 && has_chain && acc_mh) {
           if (active) ++nflip;
-          *tok_at(i) = (unsigned char)a_prop;
+          *tok_at(i) = (unsigned char)mh_prop;
         }
       } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = combine_sites<V, LPC>(acc[e]);
+        const uint32_t sg = (uint32_t)(sweep_offset + (uint64_t)sw);
         float l[4];
         float mx = -INFINITY;
 #pragma unroll
