@@ -35,16 +35,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def gather_lds_bytes(N, L, q, sweeps, cus):
-    """LDS traffic of a gather-form sweep launch: every visit reads the
-    q-vector of L-1 coupling rows; every workgroup stages site i's L-1 blocks
-    of q x q once per visit of site i (workgroups as the library sizes them:
-    chains spread over the CUs in as few rounds as workgroups of at most 128
-    chains allow; at L = 100 the tokens never limit that size)."""
+def gather_lds_bytes(N, L, q, sweeps, cus, row_bytes=None):
+    """LDS traffic of a gather-form sweep launch: every visit reads row_bytes
+    of each of L-1 coupling rows (the q-vector, 4q bytes, for the heat-bath
+    draw; the two entries of a and a', 8 bytes, for Metropolis); every
+    workgroup stages site i's L-1 blocks of q x q once per visit of site i
+    (workgroups as the library sizes them: chains spread over the CUs in as
+    few rounds as workgroups of at most 128 chains allow; at L = 100 the
+    tokens never limit that size)."""
     rounds = -(-N // (cus * 128))
     cpb = min(128, -(-N // (rounds * cus)))
     nwg = -(-N // cpb)
-    return N * L * sweeps * (L - 1) * q * 4 + nwg * sweeps * L * (L - 1) * q * q * 4
+    rb = 4 * q if row_bytes is None else row_bytes
+    return N * L * sweeps * (L - 1) * rb + nwg * sweeps * L * (L - 1) * q * q * 4
 
 
 def parse():
@@ -451,7 +454,7 @@ def bench_next(args):
         api.gibbs(h, J, ch, 0, 3002, H_ws=Wg, sampler="metropolis-gather")
     mg_fix = t.stop_ms() / reps
     mg_ms = mg_all - mg_fix
-    lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
+    lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus, row_bytes=8)
     lds_gbs = lds_bytes / (mg_ms * 1e-3) / 1e9
     lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9
     log(f"Metropolis, gather form: {mg_ms:.2f} ms per {sweeps} sweeps (+{mg_fix:.3f} ms re-layout; "
