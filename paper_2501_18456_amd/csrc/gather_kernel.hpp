@@ -257,6 +257,17 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   int mh_nj[2] = {0, 0};
   const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
+  // heat-bath draw with one site group (q > 16): the four token dwords the
+  // next chunk-step's first group of 16 positions starts with, read one step
+  // ahead (software pipeline).  With several site groups the four live
+  // registers cost more in spills than the pipeline saves.
+  constexpr bool kPipeTok = !MH && S == 1;
+  const uint32_t* twl = tokw + (size_t)u * m4 * CPB + cb;
+  uint32_t g_tok[4] = {0u, 0u, 0u, 0u};
+  if (kPipeTok && reader) {  // first chunk-step (tokens written above by this wave)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) g_tok[d] = twl[min(d, m4 - 1) * CPB];
+  }
   if (MH) {  // tokens of the first chunk-step (written above by this wave)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -380,7 +391,8 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
         uint32_t tk[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d)
-          tk[d] = (!(kSkip && tail) || 4 * d < jcs - r0)
+          tk[d] = (kPipeTok && r0 == 0) ? g_tok[d]  // read one step ahead
+                  : (!(kSkip && tail) || 4 * d < jcs - r0)
                       ? tw[min(((m0 + r0) >> 2) + d, m4 - 1) * CPB]
                       : 0u;
         f4 x[16];
@@ -405,6 +417,13 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
       int r0 = 0;
       for (; r0 + 16 <= jcs; r0 += 16) group(r0, false);
       if (r0 < jcs) group(r0, true);
+      if (kPipeTok) {
+        // the next chunk-step's first token dwords (same site's next chunk,
+        // or the next site's first chunk)
+        const int m0n = (k + 1 < nchunk ? k + 1 : 0) * jcs;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) g_tok[d] = tw[min((m0n >> 2) + d, m4 - 1) * CPB];
+      }
     }
 
     if (k == nchunk - 1) {
@@ -457,6 +476,15 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
         for (int e = 0; e < 4; ++e)
           if (v < NQ && 4 * v + e < Q - 1 && excl + P[e] <= uz) ++cnt;
         cnt = group_sum<V>(cnt);
+        // every lane of the chain drew the same state: patch the token of
+        // site i in the dwords read ahead for the next site's first chunk
+        if (kPipeTok && reader && u == i % S) {
+          const int mi = i / S;
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            if (min(d, m4 - 1) == (mi >> 2))
+              g_tok[d] = (g_tok[d] & ~(0xFFu << (8 * (mi & 3)))) | ((uint32_t)cnt << (8 * (mi & 3)));
+        }
         if (p == 0 && has_chain) {
           unsigned char* tp = tok_at(i);
           if (active && cnt != (int)*tp) ++nflip;
