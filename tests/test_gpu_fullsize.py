@@ -137,6 +137,91 @@ def test_protein_epoch(sampler):
     assert abs(host(pr)[0] - O.pearson(f1, f2, P1, P2, L, q)) < 1e-10
 
 
+def test_protein_metropolis_gather_sampled_chains():
+    """Gather-form Metropolis at full size (10 sweeps of 10 000 chains):
+    sampled slices follow the oracle's trajectories, boundary events excused."""
+    h_true, J_true, _ = protein_problem()
+    L, q, N = 100, 21, 10000
+    ch0 = O.init_chains(N, L, q, seed=3012)
+    cg = dev(ch0)
+    api.gibbs(dev(h_true), dev(J_true), cg, 10, seed=3013, sweep_offset=4,
+              sampler="metropolis-gather")
+    g = host(cg)
+    for c0 in (0, 5000, N - 37):
+        sl = slice(c0, c0 + 37)
+        ref, mg, _ = O.metropolis(h_true, J_true, ch0[sl], q, 10, 3013, sweep_offset=4,
+                                  want_margins=True, c0=c0)
+        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
+        for c in bad:
+            assert mg[c].min() < BOUNDARY
+        assert len(bad) <= 2
+
+
+def _tied(sc, r1, r2, pairs, thr):
+    for a, b in pairs:
+        lo, hi = min(a, b), max(a, b)
+        s = sc[(r1 == lo) & (r2 == hi)][0]
+        assert abs(s - thr) <= 1e-12 * max(abs(thr), 1e-300), (a, b, s, thr)
+
+
+def test_protein_graph_updates():
+    """One edDCA and one eaDCA graph update over the 2.18e6 elements of the
+    protein-scale model, from 10 000 chains: masks equal to the oracle's
+    except elements tied with the threshold to ~1 ulp (exp and log on the
+    GPU vs libm), same active counts when equal."""
+    h_true, J_true, X = protein_problem()
+    L, q, N = 100, 21, 10000
+    Lq = L * q
+    ch = O.init_chains(N, L, q, seed=3022)
+    ch = host(api.gibbs(dev(h_true), dev(J_true), dev(ch), 3, seed=3023))
+    full = np.ones((Lq, Lq), np.uint8)
+    for i in range(L):
+        full[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
+    Y = np.zeros((N, Lq), np.float32)
+    Y[np.arange(N)[:, None], np.arange(L)[None, :] * q + ch] = 1.0
+    Cg = torch.from_numpy(Y).cuda()
+    p2 = ((Cg.T @ Cg).double() / N).cpu().numpy()  # exact counts / N
+    r1, r2 = np.triu_indices(Lq, 1)
+    keep = r1 // q != r2 // q
+    r1, r2 = r1[keep], r2[keep]
+    # decimation of 1% of the full graph
+    J0 = (J_true * full).astype(np.float32)
+    Jg, mg = dev(J0), dev(full)
+    n = api.decimate(Jg, mg, dev(ch), q, 0.01, 0.0)
+    Jn, mn, no = O.decimate(J0, full, ch, q, 0.01, 0.0)
+    diff = np.argwhere(host(mg) != mn)
+    if diff.size:
+        sc = np.array([O.skl_element(J0[a, b], p2[a, b]) for a, b in zip(r1, r2)])
+        _tied(sc, r1, r2, diff, np.sort(sc)[len(sc) - no - 1])
+    else:
+        assert int(host(n)[0]) == no and np.array_equal(host(Jg), Jn)
+    # activation of 0.1% of the empty graph's inactive count
+    f2 = O.stats(X, q, None, -1.0)[1]
+    empty = np.zeros((Lq, Lq), np.uint8)
+    mg = dev(empty)
+    n = api.activate(mg, dev(ch), dev(f2), q, 0.001)
+    mo, no = O.activate(empty, ch, f2, q, 0.001)
+    diff = np.argwhere(host(mg) != mo)
+    if diff.size:
+        sc = np.array([O.bernoulli_kl(f2[a, b], p2[a, b]) for a, b in zip(r1, r2)])
+        _tied(sc, r1, r2, diff, np.sort(sc)[::-1][no - 1])
+    else:
+        assert int(host(n)[0]) == no
+
+
+def test_protein_seqid_sums():
+    """SeqID of 10 000 chain pairs at L = 100: exact integer sums."""
+    L, q, N = 100, 21, 10000
+    A = O.init_chains(N, L, q, seed=3031)
+    Bm = np.where(np.random.default_rng(3032).random((N, L)) < 0.3, A,
+                  O.init_chains(N, L, q, seed=3033)).astype(np.int8)
+    perm = np.random.default_rng(3034).permutation(N).astype(np.int32)
+    for pm in (None, perm):
+        got = host(api.seqid(dev(A), dev(Bm), None if pm is None else dev(pm)))
+        m, sd = O.seqid(A, Bm, pm)
+        assert got[0] == m and abs(got[1] - sd) <= 1e-15 * max(1.0, sd)
+
+
 # ---------------------------------------------------------------- precision form
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp32", 1e-6)])
 def test_precision_stats_sampled_entries(prec, tol):
