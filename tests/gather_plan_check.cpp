@@ -71,9 +71,9 @@ static void check(int64_t N, int L, int q, int64_t cus, int cap) {
       }
   }
   for (int j = 0; j < L; ++j) CHECK(seen[j] == 1, "site %d read %d times", j, seen[j]);
-  // chunks start on 256-byte boundaries of the run unless no aligned shape fits
+  // chunks start on kGAlign-byte boundaries of the run unless no aligned shape fits
   const size_t site_row = (size_t)q * QP * 4;
-  if (g.nchunk > 1 && (g.jc * site_row) % 256 != 0)
+  if (g.nchunk > 1 && (g.jc * site_row) % kGAlign != 0)
     CHECK(gather_shape_n(L, q, g.cpb, 4, g.lpc, true).waves == 0, "misaligned chunk");
 }
 
