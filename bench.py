@@ -30,6 +30,28 @@ HBM_PEAK_GBS = 8000.0
 # CU, sustains 213 B/clk on MI355X)
 LDS_BYTES_PER_CLK = 256
 
+# HBM bytes per 10-sweep launch of the gather sweep kernel at the protein-scale
+# workload: rocprofv3 FETCH_SIZE and WRITE_SIZE of that launch (KiB per
+# dispatch), scaled by what the same counters read for a 512 MiB device copy
+# (x2.0 and x1.0).  Valid only for the sources they were taken with (the
+# SHA-256 of the files below); for other sources the line reports null.
+GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
+                          "paper_2501_18456_amd/csrc/gather_plan.hpp",
+                          "paper_2501_18456_amd/csrc/sampler.hip",
+                          "paper_2501_18456_amd/csrc/common.hpp")
+GATHER_TRAFFIC = {"sha256": "547bb8a65ffe4193cf15408f8ec628f395d9a9d8520bf977e9ad9497274818fb",
+                  "bytes": 1.61632e+09}  # 1.6146e9 read + 1.68e6 written
+
+
+def gather_traffic():
+    """The profiled HBM bytes per launch if the kernel sources are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in GATHER_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return GATHER_TRAFFIC["bytes"] if h.hexdigest() == GATHER_TRAFFIC["sha256"] else None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -266,7 +288,7 @@ def main():
                    "stats_precision": args.prec, "reweight_identity": 0.8},
         "roofline": {"kernel": "k_gibbs_gather (Gibbs sweeps, gather form)", "bound": "lds",
                      "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",
-                     "frac": lds_gbs / lds_peak, "traffic": None,
+                     "frac": lds_gbs / lds_peak, "traffic": gather_traffic(),
                      "launch_ms": g_ms, "alg_bytes_per_launch": lds_bytes},
         "extras": extras,
     }
