@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--cpu-chains", type=int, default=4000,
+    ap.add_argument("--cpu-chains", type=int, default=10000,
                     help="chains in the oracle's timed sample epoch")
     ap.add_argument("--workload", default="protein",
                     choices=["protein", "small", "precision", "scoring", "group", "serve", "next"],
@@ -296,7 +296,7 @@ def main():
     # ---------------- oracle on the host cores (bounded sample)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        n_s = args.cpu_chains
+        n_s = min(args.cpu_chains, N)
         hh, JJ = h0.cpu().numpy(), J0.cpu().numpy()
         cc = c0[:n_s].cpu().numpy()
         F1, F2 = f1.cpu().numpy(), f2.cpu().numpy()
