@@ -319,8 +319,10 @@ def bench_small(args):
     epochs, lr 0.05, FP32 statistics.  The whole run (alignment draw,
     reweighting, statistics, 20 epochs) is timed on the GPU and, with the same
     seeds, in the oracle on one host core; the trained parameters of the two
-    are compared.  Launch-bound: each kernel takes microseconds, so there is no
-    roofline line."""
+    are compared.  The epochs are also replayed from one captured graph: that
+    takes as long as the eager calls, so the epoch is not launch-bound; at this
+    size each site is one chunk and a sweep launch is 200 dependent chunk-steps
+    of a few microseconds.  No roofline line at this size."""
     import numpy as np
     import torch
 
@@ -362,6 +364,23 @@ def bench_small(args):
     visits = N * L * sweeps
     log(f"GPU: preprocessing {t_pre * 1e3:.2f} ms, epoch {ep_ms:.3f} ms "
         f"({visits / (ep_ms * 1e-3):.3e} site-updates/s), whole run {t_all * 1e3:.1f} ms")
+    # the same 20 epochs as replays of one captured epoch (a graph of one
+    # model): the launch overhead of the small kernels goes away; the trained
+    # parameters must equal the eager run's bit for bit
+    hg, Jg, chg, f1g, f2g, wsg, _ = gpu_run()
+    model = api.TrainModel(hg, Jg, chg, f1g, f2g, lr, sweeps, 3001, "fp32", ws=wsg)
+    graph = api.TrainGroupGraph([model], lanes=1)
+    torch.cuda.synchronize()
+    t.start()
+    for e in range(epochs):
+        graph.launch()
+    gep_ms = t.stop_ms() / epochs
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Jg, J) and torch.equal(hg, h) and torch.equal(chg, ch))
+    graph.close()
+    log(f"GPU, graph-replayed epochs: {gep_ms:.3f} ms per epoch "
+        f"({visits / (gep_ms * 1e-3):.3e} site-updates/s); parameters equal to the eager run: "
+        f"{same}")
     out = {
         "metric": METRIC, "value": visits / (ep_ms * 1e-3), "unit": "site-updates/s",
         "n_gpus": 1, "steps": epochs, "warmup": max(args.warmup, 1), "ms_per_step": ep_ms,
@@ -372,7 +391,8 @@ def bench_small(args):
                    "stats_precision": "fp32", "reweight_identity": 0.8},
         "roofline": None,
         "extras": {"gpu_whole_run_ms": t_all * 1e3, "gpu_preprocessing_ms": t_pre * 1e3,
-                   "pearson_after": float(pr.cpu()[0])},
+                   "pearson_after": float(pr.cpu()[0]), "graph_epoch_ms": gep_ms,
+                   "graph_run_equals_eager": same},
     }
     if not args.no_cpu_baseline:
         t1 = time.perf_counter()
