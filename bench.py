@@ -125,7 +125,8 @@ class Timer:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the "
+                                   "library has no multi-GPU path)"}))
         sys.exit(2)
     if args.workload == "small":
         return bench_small(args)
