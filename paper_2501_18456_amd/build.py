@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbmdca.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "sampler.hip", "sampler_mh.hip", "stats.hip", "learn.hip", "reweight.hip",
-           "scoring.hip", "equilibrium.hip", "decimation.hip"]
+SOURCES = ["api.hip", "sampler.hip", "sampler_mh.hip", "sampler_w8.hip", "stats.hip", "learn.hip",
+           "reweight.hip", "scoring.hip", "equilibrium.hip", "decimation.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -144,8 +144,10 @@ __device__ __forceinline__ float combine_sites(float x) {
   return x;
 }
 
-template <int Q, int IT, int LPC, bool MH>
-__global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
+// MAXW: the most waves a workgroup of this instantiation may have (16, or 8
+// for plans of at most 8 waves: twice the registers per lane, 256).
+template <int Q, int IT, int LPC, bool MH, int MAXW>
+__global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
     int64_t N, int L, int jc, int nchunk, int m4, int ahead, int nload, int slot, int cpb,
     int sweeps, uint32_t k0, uint32_t k1, uint64_t sweep_offset, float beta,
@@ -257,11 +259,12 @@ __global__ __launch_bounds__(kGMaxWaves * 64) void k_gibbs_gather(
   int mh_nj[2] = {0, 0};
   const int jcs = jc / S;  // positions per lane per chunk (multiple of 4)
   int i = 0, k = 0, sw = 0, csl = 0;
-  // heat-bath draw with one site group (q > 16): the four token dwords the
-  // next chunk-step's first group of 16 positions starts with, read one step
-  // ahead (software pipeline).  With several site groups the four live
-  // registers cost more in spills than the pipeline saves.
-  constexpr bool kPipeTok = !MH && S == 1;
+  // heat-bath draw: the four token dwords the next chunk-step's first group
+  // of 16 positions starts with, read one step ahead (software pipeline).
+  // In the 16-wave instantiation (128 VGPRs) only with one site group
+  // (q > 16): with several, the four live registers cost more in spills than
+  // the pipeline saves.
+  constexpr bool kPipeTok = !MH && (S == 1 || MAXW <= 8);
   const uint32_t* twl = tokw + (size_t)u * m4 * CPB + cb;
   uint32_t g_tok[4] = {0u, 0u, 0u, 0u};
   if (kPipeTok && reader) {  // first chunk-step (tokens written above by this wave)
@@ -526,45 +529,47 @@ inline int device_cus() {
   return cus;
 }
 
-template <int Q, bool MH>
-hipError_t launch_gather_q(const float* h, const float* Jt, int8_t* chains, int64_t N,
-                                  int L, int sweeps, uint64_t seed, uint64_t sweep_offset,
-                                  float beta, unsigned long long* flips_out, int32_t* dev_err,
-                                  hipStream_t s, const DevCtl& ctl) {
-  // A launch on a share of the CUs (one of several models running at once)
-  // takes workgroups of at most kGShareChains chains: more, smaller
-  // workgroups let the largest models spread onto CUs the others free.
-  const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
-  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, Q, cus, kGShareChains)
-                                          : gather_plan(N, L, Q, cus);
-  if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
-  auto kern = gs.lpc == 16 ? (gs.items == 31   ? k_gibbs_gather<Q, 31, 16, MH>
-                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 16, MH>
-                                               : k_gibbs_gather<Q, 8, 16, MH>)
-                           : (gs.items == 31   ? k_gibbs_gather<Q, 31, 8, MH>
-                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 8, MH>
-                                               : k_gibbs_gather<Q, 8, 8, MH>);
+// Launch arguments of a gather-form call.
+struct GatherArgs {
+  const float* h;
+  const float* Jt;
+  int8_t* chains;
+  int64_t N;
+  int L;
+  int sweeps;
+  uint64_t seed, sweep_offset;
+  float beta;
+  unsigned long long* flips_out;
+  int32_t* dev_err;
+  hipStream_t s;
+  const DevCtl* ctl;
+};
+
+template <int Q, bool MH, int MAXW>
+hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
+  auto kern = gs.lpc == 16 ? (gs.items == 31   ? k_gibbs_gather<Q, 31, 16, MH, MAXW>
+                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 16, MH, MAXW>
+                                               : k_gibbs_gather<Q, 8, 16, MH, MAXW>)
+                           : (gs.items == 31   ? k_gibbs_gather<Q, 31, 8, MH, MAXW>
+                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 8, MH, MAXW>
+                                               : k_gibbs_gather<Q, 8, 8, MH, MAXW>);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(gs.blocks), dim3(gs.waves * 64), gs.lds, s, h, Jt, chains, N, L,
-                     gs.jc, gs.nchunk, gs.m4, gs.ahead, gs.nload, gs.slot, gs.cpb, sweeps,
-                     (uint32_t)seed, (uint32_t)(seed >> 32), sweep_offset, beta, flips_out, dev_err,
-                     ctl.epoch, ctl.active, ctl.streams);
+  const DevCtl& ctl = *a.ctl;
+  hipLaunchKernelGGL(kern, dim3(gs.blocks), dim3(gs.waves * 64), gs.lds, a.s, a.h, a.Jt, a.chains,
+                     a.N, a.L, gs.jc, gs.nchunk, gs.m4, gs.ahead, gs.nload, gs.slot, gs.cpb,
+                     a.sweeps, (uint32_t)a.seed, (uint32_t)(a.seed >> 32), a.sweep_offset, a.beta,
+                     a.flips_out, a.dev_err, ctl.epoch, ctl.active, ctl.streams);
   return hipGetLastError();
 }
 
-// Sweeps of the gather form over the laid-out blocks Jt (q = 2..32).
-template <bool MH>
-hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, int64_t N, int L,
-                              int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
-                              unsigned long long* flips_out, int32_t* dev_err, hipStream_t s,
-                              const DevCtl& ctl) {
+template <bool MH, int MAXW>
+hipError_t launch_gather_switch(int q, const GatherShape& gs, const GatherArgs& a) {
   switch (q) {
 #define BMDCA_GQ(n) \
   case n:           \
-    return launch_gather_q<n, MH>(h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, \
-                                  flips_out, dev_err, s, ctl);
+    return launch_gather_shape<n, MH, MAXW>(gs, a);
     BMDCA_GQ(2) BMDCA_GQ(3) BMDCA_GQ(4) BMDCA_GQ(5) BMDCA_GQ(6) BMDCA_GQ(7) BMDCA_GQ(8)
     BMDCA_GQ(9) BMDCA_GQ(10) BMDCA_GQ(11) BMDCA_GQ(12) BMDCA_GQ(13) BMDCA_GQ(14) BMDCA_GQ(15)
     BMDCA_GQ(16) BMDCA_GQ(17) BMDCA_GQ(18) BMDCA_GQ(19) BMDCA_GQ(20) BMDCA_GQ(21) BMDCA_GQ(22)
@@ -574,6 +579,31 @@ hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, i
     default:
       return hipErrorInvalidValue;
   }
+}
+
+// ----- sampler_w8.hip: heat-bath sweeps with MAXW = 8 (q <= 16, plans of at
+// most kGSmallWaves waves)
+hipError_t launch_gather_heat_w8(int q, const GatherShape& gs, const GatherArgs& a);
+
+// Sweeps of the gather form over the laid-out blocks Jt (q = 2..32).
+template <bool MH>
+hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, int64_t N, int L,
+                              int q, int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
+                              unsigned long long* flips_out, int32_t* dev_err, hipStream_t s,
+                              const DevCtl& ctl) {
+  // A launch on a share of the CUs (one of several models running at once)
+  // takes workgroups of at most kGShareChains chains: more, smaller
+  // workgroups let the largest models spread onto CUs the others free.
+  const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
+  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, q, cus, kGShareChains)
+                                          : gather_plan(N, L, q, cus);
+  if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
+  const GatherArgs a{h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, dev_err,
+                     s, &ctl};
+  if constexpr (!MH) {
+    if (q <= 16 && gs.waves <= kGSmallWaves) return launch_gather_heat_w8(q, gs, a);
+  }
+  return launch_gather_switch<MH, kGMaxWaves>(q, gs, a);
 }
 
 }  // namespace bmdca

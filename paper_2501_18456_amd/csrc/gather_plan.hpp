@@ -13,6 +13,8 @@ namespace bmdca {
 constexpr int64_t gp_ceil(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr int kGMaxWaves = 16;   // waves per workgroup at most
+constexpr int kGSmallWaves = 8;  // plans with q <= 16 and at most this many waves run a
+                                 // kernel bound to 8 waves (256 VGPRs)
 constexpr int kGMinWaves = 4;    // and at least
 // Chains per workgroup at most for a launch on a share of the CUs (grouped
 // training of 64 models over 8 lanes: caps of 32, 64 and 128 chains measured
@@ -123,7 +125,17 @@ inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = k
   const int64_t rounds = gp_ceil(N, cus * cmax);
   const int cpb = (int)std::min<int64_t>(cmax, gp_ceil(N, rounds * cus));
   GatherShape g{};
-  if (gather_v(q) <= 2) g = gather_shape(L, q, cpb, 16);
+  if (gather_v(q) <= 2) {
+    // 16 lanes unless that needs more than kGSmallWaves waves where 8 lanes
+    // fit in them: the 8-wave kernel reads its tokens a step ahead, which
+    // outweighs the halved lanes (q = 5, L = 400, 10 000 chains: 23.6 against
+    // 28.2 ms per 10 sweeps; q = 8, L = 60: 0.78 against 1.16), while with few
+    // chains (4096: 4 waves either way) 16 lanes stay ahead by 13%
+    g = gather_shape(L, q, cpb, 16);
+    const GatherShape g8 = gather_shape(L, q, cpb, 8);
+    if ((g.waves == 0 || g.waves > kGSmallWaves) && g8.waves > 0 && g8.waves <= kGSmallWaves)
+      g = g8;
+  }
   if (g.waves == 0) g = gather_shape(L, q, cpb, 8);
   g.blocks = (unsigned)gp_ceil(N, (int64_t)cpb);
   return g;
