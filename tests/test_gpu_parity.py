@@ -141,7 +141,10 @@ def test_gibbs_gather_multi_sweep_states(L, q, N):
     # a chain's 8 lanes as 8, 4, 2 and 1 site groups (q <= 4, <= 8, <= 16, > 16)
     (30, 2, 2600), (61, 3, 300), (45, 7, 2100), (130, 13, 700),
     # several waves per workgroup, one chunk per site, many chunks, largest L and q
-    (77, 21, 2300), (24, 9, 3000), (200, 17, 120), (300, 32, 16), (512, 21, 10)])
+    (77, 21, 2300), (24, 9, 3000), (200, 17, 120), (300, 32, 16), (512, 21, 10),
+    # q <= 16 with more than 8 waves (the 16-wave instantiation), and q <= 8
+    # where 8 lanes per chain replace 16 (the 8-wave instantiation)
+    (40, 5, 20000), (30, 13, 20000), (60, 8, 10000)])
 def test_gibbs_gather_lane_splits(L, q, N):
     """Gather form over the lane layouts and workgroup shapes it picks from
     (L, q, N): after three sweeps in one call every chain that differs from
