@@ -116,9 +116,9 @@ inline GatherShape gather_shape(int L, int q, int cpb, int lpc) {
 // Chains per workgroup: spread the chains over the CUs (one workgroup per CU
 // at a time) in as few rounds as the largest workgroup that fits allows, with
 // 8 lanes per chain.  For q <= 8 (rows of at most two quads) the same chains
-// then get 16 lanes each where that workgroup fits: twice the waves, each
-// with half the positions per step (q = 5, L = 400: 12% less time per sweep;
-// q = 21: 1.9x more, the per-wave step overhead doubles).
+// get 16 lanes each (twice the waves, each with half the positions per step;
+// at q = 21 that costs 1.9x, the per-wave step overhead doubles), unless 16
+// lanes need more than kGSmallWaves waves where 8 lanes fit in them (below).
 inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8) {
   int cmax = std::min(cap, kGMaxWaves * (64 / 8));
   while (cmax > 64 / 8 && gather_shape(L, q, cmax, 8).waves == 0) cmax -= 64 / 8;
