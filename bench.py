@@ -39,7 +39,7 @@ GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
                           "paper_2501_18456_amd/csrc/gather_plan.hpp",
                           "paper_2501_18456_amd/csrc/sampler.hip",
                           "paper_2501_18456_amd/csrc/common.hpp")
-GATHER_TRAFFIC = {"sha256": "6914c0183cae0d26aaca1ceaf287f6347ea310f8eedeb69ec321baef5a58e4ad",
+GATHER_TRAFFIC = {"sha256": "ffc7c3ecc2781b215e1aaa41b640f232263ef01c4dd53a1ccc4a5fe0dda56327",
                   "bytes": 1.61628e+09}  # 1.6146e9 read + 1.68e6 written
 
 

@@ -595,8 +595,8 @@ hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, i
   // takes workgroups of at most kGShareChains chains: more, smaller
   // workgroups let the largest models spread onto CUs the others free.
   const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
-  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, q, cus, kGShareChains)
-                                          : gather_plan(N, L, q, cus);
+  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, q, cus, kGShareChains, !MH)
+                                          : gather_plan(N, L, q, cus, kGMaxWaves * 8, !MH);
   if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
   const GatherArgs a{h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, dev_err,
                      s, &ctl};

@@ -117,9 +117,13 @@ inline GatherShape gather_shape(int L, int q, int cpb, int lpc) {
 // at a time) in as few rounds as the largest workgroup that fits allows, with
 // 8 lanes per chain.  For q <= 8 (rows of at most two quads) the same chains
 // get 16 lanes each (twice the waves, each with half the positions per step;
-// at q = 21 that costs 1.9x, the per-wave step overhead doubles), unless 16
-// lanes need more than kGSmallWaves waves where 8 lanes fit in them (below).
-inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8) {
+// at q = 21 that costs 1.9x, the per-wave step overhead doubles), unless, for
+// the heat-bath draw (`small`), 16 lanes need more than kGSmallWaves waves
+// where 8 lanes fit in them (below).  Metropolis always runs the 16-wave
+// kernel and keeps 16 lanes (q = 5, L = 400, 10 000 chains: 24.0 against
+// 27.2 ms per 10 sweeps with 8).
+inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8,
+                               bool small = true) {
   int cmax = std::min(cap, kGMaxWaves * (64 / 8));
   while (cmax > 64 / 8 && gather_shape(L, q, cmax, 8).waves == 0) cmax -= 64 / 8;
   const int64_t rounds = gp_ceil(N, cus * cmax);
@@ -133,7 +137,8 @@ inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = k
     // chains (4096: 4 waves either way) 16 lanes stay ahead by 13%
     g = gather_shape(L, q, cpb, 16);
     const GatherShape g8 = gather_shape(L, q, cpb, 8);
-    if ((g.waves == 0 || g.waves > kGSmallWaves) && g8.waves > 0 && g8.waves <= kGSmallWaves)
+    if (small && (g.waves == 0 || g.waves > kGSmallWaves) && g8.waves > 0 &&
+        g8.waves <= kGSmallWaves)
       g = g8;
   }
   if (g.waves == 0) g = gather_shape(L, q, cpb, 8);

@@ -25,8 +25,8 @@ static int failures = 0;
     }                                                                 \
   } while (0)
 
-static void check(int64_t N, int L, int q, int64_t cus, int cap) {
-  const GatherShape g = gather_plan(N, L, q, cus, cap);
+static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
+  const GatherShape g = gather_plan(N, L, q, cus, cap, small);
   CHECK(g.waves >= kGMinWaves && g.waves <= kGMaxWaves, "waves %d", g.waves);
   CHECK(g.lpc == 8 || g.lpc == 16, "lpc %d", g.lpc);
   const int S = gather_s(q, g.lpc), QP = gather_qp(q), NQ = QP / 4;
@@ -92,10 +92,11 @@ int main() {
       }
       for (int64_t n : {1, 7, 100, 1000, 4096, 10000, 20000, 40000, 100000})
         for (int64_t c : {256, 32})
-          for (int cp : {128, kGShareChains}) {
-            check(n, L, q, c, cp);
-            ++shapes;
-          }
+          for (int cp : {128, kGShareChains})
+            for (bool small : {true, false}) {  // heat-bath and Metropolis plans
+              check(n, L, q, c, cp, small);
+              ++shapes;
+            }
     }
   std::printf("%d shapes checked, %d failures\n", shapes, failures);
   return failures == 0 ? 0 : 1;
