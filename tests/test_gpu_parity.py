@@ -389,7 +389,7 @@ def test_train_step_nonfinite_flag():
     assert int(host(e)[0]) & B.DEVERR_NONFINITE
 
 
-@pytest.mark.parametrize("sampler", ["gather", "fields"])
+@pytest.mark.parametrize("sampler", ["gather", "fields", "metropolis-gather", "metropolis-fields"])
 @pytest.mark.parametrize("cus", [0, 8])
 def test_gibbs_streams_equal_separate_calls(sampler, cus):
     """Chains of two callers swept in one launch through a stream table make
@@ -456,6 +456,22 @@ def test_metropolis_gather_lane_splits(L, q, N):
     assert len(bad) <= max(2, N // 50)
     if len(bad) == 0:
         assert int(host(flips)[0]) == oflips
+
+
+@pytest.mark.parametrize("sampler", MH_FORMS)
+@pytest.mark.parametrize("beta", [0.5, 1.7])
+def test_metropolis_at_other_temperatures(sampler, beta):
+    """beta != 1 (the sampling temperature of the sampling routine): both
+    forms follow the oracle's trajectories, boundary events excused."""
+    L, q, N = 40, 21, 400
+    h, J = synth.planted_dense(L, q, seed=151, sigma_J=0.3)
+    ch0 = O.init_chains(N, L, q, seed=152)
+    cg = dev(ch0)
+    api.gibbs(dev(h), dev(J), cg, 3, seed=153, sweep_offset=2, beta=beta, sampler=sampler)
+    ref, mg, _ = O.metropolis(h, J, ch0, q, 3, 153, sweep_offset=2, beta=beta, want_margins=True)
+    bad = np.nonzero((host(cg) != ref).any(axis=1))[0]
+    assert all(mg[c].min() < BOUNDARY for c in bad)
+    assert len(bad) <= N // 50
 
 
 @pytest.mark.parametrize("sampler", MH_FORMS)
