@@ -212,7 +212,16 @@ typedef struct bmdca_chain_stream {
  * exactly the draws of chain streams[c].chain in a bmdca_gibbs call with
  * seed streams[c].seed and sweep_offset streams[c].sweep_offset, so chains
  * of several callers can be swept in one launch with the results each would
- * get alone (same sampler form).  All chains run `sweeps` sweeps.
+ * get alone (same sampler form).  All chains run `sweeps` sweeps.  The
+ * random words and draw rules are those of the alone call; the FP32 local
+ * fields of the gather form are summed in an order fixed by L, q and the
+ * lanes per chain, and for Metropolis also by the chunk length of the
+ * launch.  Both follow the chains per workgroup where q <= 8 (lanes: 8 or
+ * 16) and, for Metropolis, where the tokens limit the chunk; where the two
+ * launches differ in them a chain can part from its alone trajectory at a
+ * draw within FP32 rounding of a boundary (as between the two sampler
+ * forms).  Otherwise, and always in the field form, the chains are
+ * bit-identical.
  * streams  device array [N], caller-owned
  * cus      compute units the launch is sized for (0 = the whole device): a
  *          smaller share packs more chains into each workgroup and streams
