@@ -213,15 +213,15 @@ typedef struct bmdca_chain_stream {
  * seed streams[c].seed and sweep_offset streams[c].sweep_offset, so chains
  * of several callers can be swept in one launch with the results each would
  * get alone (same sampler form).  All chains run `sweeps` sweeps.  The
- * random words and draw rules are those of the alone call; the FP32 local
- * fields of the gather form are summed in an order fixed by L, q and the
- * lanes per chain, and for Metropolis also by the chunk length of the
- * launch.  Both follow the chains per workgroup where q <= 8 (lanes: 8 or
- * 16) and, for Metropolis, where the tokens limit the chunk; where the two
- * launches differ in them a chain can part from its alone trajectory at a
- * draw within FP32 rounding of a boundary (as between the two sampler
- * forms).  Otherwise, and always in the field form, the chains are
- * bit-identical.
+ * random words and draw rules are those of the alone call.  The FP32 local
+ * fields of the gather form are summed in an order fixed by L, q and the draw
+ * (the lanes per chain are a function of q and the draw alone), so heat-bath
+ * chains are bit-identical to their alone call in any launch.  For
+ * Metropolis the order also follows the chunk length, which the chains per
+ * workgroup bound where their tokens fill the LDS; where two launches differ
+ * in it a chain can part from its alone trajectory at a draw within FP32
+ * rounding of the acceptance threshold (as between the two sampler forms).
+ * The field form is always bit-identical.
  * streams  device array [N], caller-owned
  * cus      compute units the launch is sized for (0 = the whole device): a
  *          smaller share packs more chains into each workgroup and streams
@@ -272,6 +272,16 @@ int bmdca_train_step(float* h, float* J, int8_t* chains, int64_t N, int32_t L,
                      int32_t prec, double* pearson,
                      unsigned long long* flips_out, void* ws, size_t ws_bytes,
                      int32_t* dev_err, void* stream);
+
+/* Fields of the independent-site (profile) model, the starting point of
+ * training (eaDCA starts from a profile model, Sec. 2.2; bmDCA here too):
+ * h[(i,a)] = log f1[(i,a)] in FP64, rounded once to float32.  With J = 0
+ * its one-site marginals are f_i(a) (each f_i sums to 1).
+ * f1 double [Lq] (bmdca_stats); h float32 [Lq] out.
+ * dev_err optional; BMDCA_DEVERR_NONFINITE where f1 is not positive and
+ * finite (that field is not finite). */
+int bmdca_profile_fields(const double* f1, int32_t L, int32_t q, float* h, int32_t* dev_err,
+                         void* stream);
 
 /* ---- Grouped training (many independent models, one replayable epoch) ----
  *
@@ -327,7 +337,9 @@ typedef struct bmdca_train_problem {
  * models run side by side.  Each model runs bmdca_train_step with its epoch
  * read from ctl->epoch, then advances its record: if active, epoch += 1 and
  * the target test above.  Every model's results are the same as its own
- * bmdca_train_step calls with the same epochs (bit for bit).
+ * bmdca_train_step calls with the same epochs (bit for bit; a model with the
+ * Metropolis flag in the gather form is subject to the chunk-length
+ * exception stated at bmdca_gibbs_streams).
  * The call may be captured into a HIP graph (it allocates no device memory
  * and enqueues no memset); bmdca_train_group_graph does exactly that.  The
  * lane streams are created once per device (default priority) and kept;
@@ -349,7 +361,7 @@ int bmdca_graph_launch(bmdca_graph g, void* stream);
 /* Frees the graph (NULL is accepted). */
 int bmdca_graph_destroy(bmdca_graph g);
 
-/* ---- Sparse models by element decimation (edDCA, Sec. 2.4) ----
+/* ---- Sparse models by element decimation (edDCA, Sec. 2.2 and Sec. 3.2) ----
  *
  * A coupling graph is a mask uint8 [Lq][Lq] (device, caller-owned,
  * symmetric; 1 = active element, diagonal blocks ignored). */
@@ -364,6 +376,19 @@ int bmdca_train_step_masked(float* h, float* J, const uint8_t* mask, int8_t* cha
                             double* pearson, unsigned long long* flips_out,
                             void* ws, size_t ws_bytes, int32_t* dev_err,
                             void* stream);
+
+/* Coupling graph of a model (Sec. 2.2): bmDCA uses the fully connected
+ * graph, eaDCA starts from the empty one.  mask uint8 [Lq][Lq] out: with
+ * full != 0, 1 for every element of two different sites and 0 on the
+ * diagonal blocks; with full == 0, all 0. */
+int bmdca_mask_init(uint8_t* mask, int32_t L, int32_t q, int32_t full, void* stream);
+
+/* Restricts couplings to a graph (Sec. 2.2: couplings off the graph are 0):
+ * J[r1][r2] = 0 wherever mask is 0 or r1, r2 lie on the same site; J may be
+ * NULL to count only.  n_active: optional device int64, set to the number of
+ * active elements r1 < r2 of different sites (exact integer count). */
+int bmdca_mask_apply(float* J, const uint8_t* mask, int32_t L, int32_t q, long long* n_active,
+                     void* stream);
 
 /* One graph update of element decimation: for every active element
  * (r1, r2), r1 < r2 in different sites, with p = (count of chains with
@@ -385,7 +410,7 @@ int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N,
                    long long* n_active, void* ws, size_t ws_bytes,
                    int32_t* dev_err, void* stream);
 
-/* One graph update of element activation (eaDCA, Sec. 2.4): among all
+/* One graph update of element activation (eaDCA, Sec. 2.2 and Sec. 3.1): among all
  * elements (r1, r2), r1 < r2 in different sites, active or not, the ones
  * whose model marginal p (chain frequency, as above) is farthest from the
  * data frequency f = f2[r1][r2] are set active.  The paper leaves the

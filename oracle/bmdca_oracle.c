@@ -250,6 +250,46 @@ void orc_local_fields_all(const float* h, const float* J, const int8_t* s,
 /* Chains chains[0..N) carry the global chain indices c0 .. c0+N-1 (the
  * chain index is part of the Philox counter), so any contiguous slice of a
  * large set of chains can be advanced on its own. */
+/* Draw of one visit from the local fields Hi by the rule above; returns
+ * a_new and the visit's margin.  When n_lo / n_hi are given they receive the
+ * number of CDF steps a <= q-2 within tol of u at or below u (each of them
+ * read the other way lowers a_new by one) and above u (raises it by one). */
+static int32_t gibbs_draw(const double* Hi, int32_t q, double beta, double u,
+                          double* e, double* cdf, double tol, double* margin,
+                          int32_t* n_lo, int32_t* n_hi)
+{
+    double mx = -INFINITY;
+    for (int32_t a = 0; a < q; ++a) {
+        double l = beta * Hi[a];
+        if (l > mx) mx = l;
+    }
+    double S = 0.0;
+    for (int32_t a = 0; a < q; ++a) {
+        e[a] = exp(beta * Hi[a] - mx);
+        S += e[a];
+        cdf[a] = S; /* running sum, normalised below */
+    }
+    for (int32_t a = 0; a < q; ++a) cdf[a] = cdf[a] / S;
+    int32_t anew = 0, lo = 0, hi = 0;
+    double mg = INFINITY;
+    for (int32_t a = 0; a < q - 1; ++a) {
+        if (cdf[a] <= u) anew += 1;
+        double d = fabs(u - cdf[a]);
+        if (d < mg) mg = d;
+        if (d < tol) {
+            if (cdf[a] <= u) lo += 1;
+            else hi += 1;
+        }
+    }
+    *margin = mg;
+    if (n_lo) *n_lo = lo;
+    if (n_hi) *n_hi = hi;
+    return anew;
+}
+
+/* Chains chains[0..N) carry the global chain indices c0 .. c0+N-1 (the
+ * chain index is part of the Philox counter), so any contiguous slice of a
+ * large set of chains can be advanced on its own. */
 void orc_gibbs_range(const float* h, const float* J, int8_t* chains, int64_t N,
                      int64_t c0, int32_t L, int32_t q, int32_t sweeps,
                      uint64_t seed, uint64_t sweep_offset, double beta,
@@ -265,26 +305,9 @@ void orc_gibbs_range(const float* h, const float* J, int8_t* chains, int64_t N,
             uint64_t sg = sweep_offset + (uint64_t)sw;
             for (int32_t i = 0; i < L; ++i) {
                 orc_local_field(h, J, s, L, q, i, Hi);
-                double mx = -INFINITY;
-                for (int32_t a = 0; a < q; ++a) {
-                    double l = beta * Hi[a];
-                    if (l > mx) mx = l;
-                }
-                double S = 0.0;
-                for (int32_t a = 0; a < q; ++a) {
-                    e[a] = exp(beta * Hi[a] - mx);
-                    S += e[a];
-                    cdf[a] = S; /* running sum, normalised below */
-                }
-                for (int32_t a = 0; a < q; ++a) cdf[a] = cdf[a] / S;
                 double u = orc_gibbs_uniform(seed, (uint64_t)(c0 + c), sg, i);
-                int32_t anew = 0;
-                double margin = INFINITY;
-                for (int32_t a = 0; a < q - 1; ++a) {
-                    if (cdf[a] <= u) anew += 1;
-                    double d = fabs(u - cdf[a]);
-                    if (d < margin) margin = d;
-                }
+                double margin;
+                int32_t anew = gibbs_draw(Hi, q, beta, u, e, cdf, 0.0, &margin, NULL, NULL);
                 if (margins) margins[((size_t)c * sweeps + sw) * L + i] = margin;
                 if (anew != s[i]) nflip += 1;
                 s[i] = (int8_t)anew;
@@ -669,6 +692,28 @@ void orc_seqid(const int8_t* A, const int8_t* B, const int32_t* perm, int64_t N,
 /* u = (word >> 8) 2^-24, accept iff u < exp(beta (H_i(a') - H_i(a))).  The   */
 /* margin of a visit is |u - min(1, exp(beta (H_i(a') - H_i(a))))|.           */
 /* ------------------------------------------------------------------------ */
+/* One Metropolis visit of site i (rule above) for chain index c in global
+ * sweep sg; returns the state after the visit and its margin. */
+static int32_t metropolis_visit(const float* h, const float* J, const int8_t* s,
+                                int32_t L, int32_t q, int32_t i, uint64_t c,
+                                uint64_t sg, uint64_t seed, double beta, double* Hi,
+                                double* margin, int32_t* proposal)
+{
+    orc_local_field(h, J, s, L, q, i, Hi);
+    const uint32_t wp = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg, (uint32_t)c, 3u,
+                                    2 * (i & 1));
+    const uint32_t wa = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg, (uint32_t)c, 3u,
+                                    2 * (i & 1) + 1);
+    const int32_t a = s[i];
+    const int32_t ap = (a + 1 + (int32_t)(((uint64_t)wp * (uint64_t)(q - 1)) >> 32)) % q;
+    const double u = (double)(wa >> 8) * (1.0 / 16777216.0);
+    const double p = exp(beta * (Hi[ap] - Hi[a]));
+    const double pc = p < 1.0 ? p : 1.0;
+    *margin = fabs(u - pc);
+    *proposal = ap;
+    return u < p ? ap : a;
+}
+
 void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_t N,
                           int64_t c0, int32_t L, int32_t q, int32_t sweeps,
                           uint64_t seed, uint64_t sweep_offset, double beta,
@@ -681,22 +726,13 @@ void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_
         for (int32_t sw = 0; sw < sweeps; ++sw) {
             uint64_t sg = sweep_offset + (uint64_t)sw;
             for (int32_t i = 0; i < L; ++i) {
-                orc_local_field(h, J, s, L, q, i, Hi);
-                const uint32_t wp = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg,
-                                                (uint32_t)(c0 + c), 3u, 2 * (i & 1));
-                const uint32_t wa = philox_word(seed, (uint32_t)i >> 1, (uint32_t)sg,
-                                                (uint32_t)(c0 + c), 3u, 2 * (i & 1) + 1);
-                const int32_t a = s[i];
-                const int32_t ap = (a + 1 + (int32_t)(((uint64_t)wp * (uint64_t)(q - 1)) >> 32)) % q;
-                const double u = (double)(wa >> 8) * (1.0 / 16777216.0);
-                const double p = exp(beta * (Hi[ap] - Hi[a]));
-                const int accept = u < p;
-                if (margins) {
-                    const double pc = p < 1.0 ? p : 1.0;
-                    margins[((size_t)c * sweeps + sw) * L + i] = fabs(u - pc);
-                }
-                if (accept) {
-                    s[i] = (int8_t)ap;
+                double margin;
+                int32_t ap;
+                const int32_t anew = metropolis_visit(h, J, s, L, q, i, (uint64_t)(c0 + c), sg,
+                                                      seed, beta, Hi, &margin, &ap);
+                if (margins) margins[((size_t)c * sweeps + sw) * L + i] = margin;
+                if (anew != s[i]) {
+                    s[i] = (int8_t)anew;
                     nflip += 1;
                 }
             }
@@ -707,7 +743,59 @@ void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_
 }
 
 /* ------------------------------------------------------------------------ */
-/* Element decimation (edDCA, Sec. 2.4 "Element decimation DCA"): prune the   */
+/* Replay of one chain with forced outcomes (Gibbs when metropolis == 0,      */
+/* Metropolis otherwise), for parity tests that must tell a boundary event   */
+/* (a draw whose uniform lies within tol of its threshold, which FP32 fields */
+/* may resolve the other way) from an error.  Visit v = sw*L + i records the */
+/* drawn state drawn[v] and the states alt_lo[v]..alt_hi[v] the visit could */
+/* take if every comparison within tol of u went the other way (for          */
+/* Metropolis: the other outcome of the acceptance test); where nothing is   */
+/* that close both equal drawn[v].  force (may be NULL): where force[v] >= 0 */
+/* the chain takes that state at visit v instead of the drawn one.  With no  */
+/* forced visit the result is exactly that of orc_gibbs_range /              */
+/* orc_metropolis_range for the chain with global index c.                   */
+/* ------------------------------------------------------------------------ */
+void orc_chain_forced(const float* h, const float* J, int8_t* s, uint64_t c, int32_t L,
+                      int32_t q, int32_t sweeps, uint64_t seed, uint64_t sweep_offset,
+                      double beta, int32_t metropolis, double tol, const int8_t* force,
+                      int8_t* drawn, int8_t* alt_lo, int8_t* alt_hi)
+{
+    double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
+    double* e = (double*)malloc(sizeof(double) * (size_t)q);
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)q);
+    for (int32_t sw = 0; sw < sweeps; ++sw) {
+        uint64_t sg = sweep_offset + (uint64_t)sw;
+        for (int32_t i = 0; i < L; ++i) {
+            const size_t v = (size_t)sw * L + i;
+            double margin;
+            int32_t anew, lo, hi;
+            if (metropolis) {
+                int32_t ap;
+                const int32_t a = s[i];
+                anew = metropolis_visit(h, J, s, L, q, i, c, sg, seed, beta, Hi, &margin, &ap);
+                lo = hi = anew;
+                if (margin < tol) lo = hi = (anew == ap) ? a : ap;
+            } else {
+                orc_local_field(h, J, s, L, q, i, Hi);
+                const double u = orc_gibbs_uniform(seed, c, sg, i);
+                int32_t nlo, nhi;
+                anew = gibbs_draw(Hi, q, beta, u, e, cdf, tol, &margin, &nlo, &nhi);
+                lo = anew - nlo;
+                hi = anew + nhi;
+            }
+            drawn[v] = (int8_t)anew;
+            alt_lo[v] = (int8_t)lo;
+            alt_hi[v] = (int8_t)hi;
+            s[i] = (int8_t)((force && force[v] >= 0) ? force[v] : anew);
+        }
+    }
+    free(Hi);
+    free(e);
+    free(cdf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element decimation (edDCA, Sec. 2.2 "Element decimation DCA"): prune the   */
 /* active coupling elements whose removal perturbs the model least, measured  */
 /* by the symmetric Kullback-Leibler distance between the current model P and */
 /* P' = P with the single element J_ij(a,b) set to zero.                     */
@@ -788,7 +876,7 @@ int64_t orc_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, i
 }
 
 /* ------------------------------------------------------------------------ */
-/* Element activation (eaDCA, Sec. 2.4 "Element activation DCA"): starting   */
+/* Element activation (eaDCA, Sec. 2.2 "Element activation DCA"): starting   */
 /* from an empty graph, each graph update targets a number of elements equal */
 /* to the fraction factivate of the currently inactive ones and activates,   */
 /* among all elements (i < j, a, b) -- active ones included, which is why    */
@@ -886,4 +974,31 @@ double orc_train_step_masked(float* h, float* J, const uint8_t* mask, int8_t* ch
     free(p1);
     free(p2);
     return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Starting point and coupling graphs.                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Independent-site (profile) model: h[(i,a)] = (float) log f1[(i,a)]; with
+ * J = 0 its one-site marginals are f_i(a) when each f_i sums to 1. */
+void orc_profile_fields(const double* f1, int32_t L, int32_t q, float* h)
+{
+    for (int64_t r = 0; r < (int64_t)L * q; ++r) h[r] = (float)log(f1[r]);
+}
+
+/* Couplings restricted to a graph (Sec. 2.2): J = 0 wherever the mask is 0
+ * or both indices lie on one site; returns the number of active elements
+ * r1 < r2 of different sites. */
+int64_t orc_mask_apply(float* J, const uint8_t* mask, int32_t L, int32_t q)
+{
+    const int64_t Lq = (int64_t)L * q;
+    int64_t n = 0;
+    for (int64_t r1 = 0; r1 < Lq; ++r1)
+        for (int64_t r2 = 0; r2 < Lq; ++r2) {
+            const int on = mask[IDX2(r1, r2, Lq)] != 0 && r1 / q != r2 / q;
+            if (!on && J) J[IDX2(r1, r2, Lq)] = 0.0f;
+            if (on && r1 < r2) n += 1;
+        }
+    return n;
 }

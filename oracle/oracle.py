@@ -80,6 +80,10 @@ def _declare(L):
         "orc_decimate": (_i64, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64]),
         "orc_bernoulli_kl": (_f64, [_f64, _f64]),
         "orc_activate": (_i64, [_p, _p, _i64, _i32, _i32, _p, _f64]),
+        "orc_chain_forced": (None, [_p, _p, _p, _u64, _i32, _i32, _i32, _u64, _u64, _f64, _i32,
+                                    _f64, _p, _p, _p, _p]),
+        "orc_profile_fields": (None, [_p, _i32, _i32, _p]),
+        "orc_mask_apply": (_i64, [_p, _p, _i32, _i32]),
         "orc_train_step_masked": (_f64, [_p, _p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32,
                                          _u64, _u64, _p, _p]),
     }
@@ -236,6 +240,26 @@ def metropolis(h, J, chains, q: int, sweeps: int, seed: int, sweep_offset: int =
     return ch, mg, int(flips[0])
 
 
+def chain_forced(h, J, s0, c: int, q: int, sweeps: int, seed: int, sweep_offset: int = 0,
+                 beta: float = 1.0, metropolis: bool = False, tol: float = 0.0, force=None):
+    """One chain (global index c) replayed with forced outcomes: force[v] >= 0
+    replaces the drawn state at visit v = sweep*L + site.  Returns (end state,
+    drawn [sweeps*L], alt_lo, alt_hi): the states each visit could take had
+    every comparison within tol of its threshold gone the other way."""
+    h, J = _f32(h), _f32(J)
+    s = _i8(s0).copy()
+    L = s.shape[0]
+    nv = sweeps * L
+    drawn = np.zeros(nv, dtype=np.int8)
+    lo = np.zeros(nv, dtype=np.int8)
+    hi = np.zeros(nv, dtype=np.int8)
+    fv = None if force is None else np.ascontiguousarray(force, dtype=np.int8)
+    lib().orc_chain_forced(_ptr(h), _ptr(J), _ptr(s), c, L, q, sweeps, seed, sweep_offset,
+                           float(beta), int(bool(metropolis)), float(tol), _ptr(fv), _ptr(drawn),
+                           _ptr(lo), _ptr(hi))
+    return s, drawn, lo, hi
+
+
 def chain_freqs(chains, q: int):
     ch = _i8(chains)
     N, L = ch.shape
@@ -355,7 +379,7 @@ def mixing_time(h, J, msa, w, q: int, nmeasure: int, seed: int, perm, max_sweeps
 
 
 # --------------------------------------------------------------------------
-# Element decimation (edDCA, Sec. 2.4)
+# Element decimation (edDCA, Sec. 2.2 and Sec. 3.2)
 # --------------------------------------------------------------------------
 def skl_element(J: float, p: float) -> float:
     """Symmetric KL between the model and the model without one coupling element."""
@@ -400,3 +424,23 @@ def train_step_masked(h, J, mask, chains, f1, f2, q: int, lr: float, sweeps: int
                                     _ptr(f2), float(lr), sweeps, seed, epoch, None, None)
     return h2, J2, ch, r
 
+
+
+# --------------------------------------------------------------------------
+# Starting point and coupling graphs
+# --------------------------------------------------------------------------
+def profile_fields(f1, L: int, q: int):
+    """h = (float) log f1 of the independent-site model, float32 [L, q]."""
+    f1 = np.ascontiguousarray(f1, dtype=np.float64)
+    h = np.zeros((L, q), dtype=np.float32)
+    lib().orc_profile_fields(_ptr(f1), L, q, _ptr(h))
+    return h
+
+
+def mask_apply(J, mask, q: int):
+    """Returns (J with couplings off the graph set to 0, active elements r1 < r2)."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    L = m.shape[0] // q
+    Jc = None if J is None else _f32(J).copy()
+    n = lib().orc_mask_apply(_ptr(Jc), _ptr(m), L, q)
+    return Jc, int(n)

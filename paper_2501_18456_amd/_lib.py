@@ -73,6 +73,9 @@ SIGNATURES = {
                                           _u64, _u64, _i32, _p, _p, _p, _sz, _p, _p]),
     "bmdca_decimate": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64, _p, _p, _sz, _p, _p]),
     "bmdca_activate": (C.c_int, [_p, _p, _i64, _i32, _i32, _p, _f64, _p, _p, _sz, _p, _p]),
+    "bmdca_profile_fields": (C.c_int, [_p, _i32, _i32, _p, _p, _p]),
+    "bmdca_mask_init": (C.c_int, [_p, _i32, _i32, _i32, _p]),
+    "bmdca_mask_apply": (C.c_int, [_p, _p, _i32, _i32, _p, _p]),
     "bmdca_train_group_step": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p]),
     "bmdca_train_group_graph": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p,
                                           C.POINTER(_p)]),

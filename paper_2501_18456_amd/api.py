@@ -250,12 +250,42 @@ def seqid(A, Bm, perm=None, dev_err=None, ws=None, out=None):
 
 
 # ----------------------------------------------------- sparse models (edDCA)
+def mask_init(L: int, q: int, full: bool = True, device="cuda", out=None):
+    """bmdca_mask_init: the fully connected coupling graph (1 off the diagonal
+    blocks) or the empty one, as a uint8 [Lq, Lq] mask."""
+    if out is None:
+        out = torch.empty((L * q, L * q), dtype=torch.uint8, device=device)
+    _dev(out, torch.uint8, "mask", 2)
+    check(B.lib().bmdca_mask_init(_ptr(out), L, q, 1 if full else 0, _stream()))
+    return out
+
+
 def full_mask(L: int, q: int, device="cuda"):
     """The fully connected coupling graph: 1 off the diagonal blocks."""
-    m = torch.ones((L * q, L * q), dtype=torch.uint8, device=device)
-    for i in range(L):
-        m[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
-    return m
+    return mask_init(L, q, True, device)
+
+
+def mask_apply(J, mask, q: int, n_active=None):
+    """bmdca_mask_apply: J = 0 off the graph (J may be None to count only);
+    returns the device int64 count of active elements r1 < r2."""
+    _dev(mask, torch.uint8, "mask", 2)
+    L = mask.shape[0] // q
+    if J is not None:
+        _dev(J, torch.float32, "J", 2)
+    if n_active is None:
+        n_active = torch.empty(1, dtype=torch.int64, device=mask.device)
+    check(B.lib().bmdca_mask_apply(_ptr(J), _ptr(mask), L, q, _ptr(n_active), _stream()))
+    return n_active
+
+
+def profile_fields(f1, L: int, q: int, dev_err=None, out=None):
+    """bmdca_profile_fields: h = (float) log f1, the independent-site model's
+    fields, as float32 [L, q]."""
+    _dev(f1, torch.float64, "f1")
+    if out is None:
+        out = torch.empty((L, q), dtype=torch.float32, device=f1.device)
+    check(B.lib().bmdca_profile_fields(_ptr(f1), L, q, _ptr(out), _ptr(dev_err), _stream()))
+    return out
 
 
 def train_step_masked(h, J, mask, chains, f1, f2, lr: float, sweeps: int, seed: int, epoch: int,

@@ -579,6 +579,28 @@ int bmdca_activate(uint8_t* mask, const int8_t* chains, int64_t N, int32_t L, in
                     "activate/select");
 }
 
+int bmdca_profile_fields(const double* f1, int32_t L, int32_t q, float* h, int32_t* dev_err,
+                         void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(f1 && h, "null pointer argument");
+  return hip_status(launch_profile_fields(f1, L, q, h, dev_err, (hipStream_t)stream),
+                    "profile_fields");
+}
+
+int bmdca_mask_init(uint8_t* mask, int32_t L, int32_t q, int32_t full, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(mask, "null pointer argument");
+  return hip_status(launch_mask_init(mask, L, q, full != 0, (hipStream_t)stream), "mask_init");
+}
+
+int bmdca_mask_apply(float* J, const uint8_t* mask, int32_t L, int32_t q, long long* n_active,
+                     void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(mask, "null pointer argument");
+  return hip_status(launch_mask_apply(J, mask, L, q, n_active, (hipStream_t)stream),
+                    "mask_apply");
+}
+
 int bmdca_train_group_step(const bmdca_train_problem* probs, int32_t n, int32_t lanes,
                            void* stream) {
   BMDCA_REQUIRE(probs && n >= 1, "group needs at least one problem");

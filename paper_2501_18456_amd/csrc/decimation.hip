@@ -1,4 +1,4 @@
-// Element decimation (edDCA; adabmDCA 2.0, Sec. 2.4): one graph update
+// Element decimation (edDCA; adabmDCA 2.0, Sec. 2.2, options in Sec. 3.2): one graph update
 // removes the active coupling elements whose removal changes the model least.
 // For the element J_ij(a,b) with pairwise model marginal p (chain frequency),
 // the symmetric Kullback-Leibler distance between the model and the model
@@ -14,7 +14,7 @@
 // order with a block-level scan.  Everything after the counts stays on the
 // device.
 //
-// Element activation (eaDCA; Sec. 2.4) shares the selection: every element
+// Element activation (eaDCA; Sec. 2.2, options in Sec. 3.1) shares the selection: every element
 // (r1 < r2, different sites), active or not, is scored by how far the model
 // marginal p is from the data's f, taken as the Kullback-Leibler divergence
 // of the two Bernoulli laws of [s_i == a][s_j == b],
@@ -413,6 +413,82 @@ hipError_t launch_activate(uint8_t* mask, const double* C, const double* f2, int
                      b.total, L * q, b.st, b.blk, nullptr, mask);
   if (n_active_out)
     hipLaunchKernelGGL(k_act_out, dim3(1), dim3(64), 0, s, b.st, n_active_out);
+  return hipGetLastError();
+}
+
+}  // namespace bmdca
+
+namespace bmdca {
+
+// ----- coupling graphs as masks (Sec. 2.2): the fully connected graph of
+// bmDCA, the empty graph eaDCA starts from, and the couplings of a graph.
+
+// mask[r1][r2] = full && site(r1) != site(r2).
+__global__ __launch_bounds__(kDecThreads) void k_mask_init(uint8_t* __restrict__ mask, int L,
+                                                           int q, int full) {
+  const int Lq = L * q;
+  const size_t total = (size_t)Lq * Lq;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int r1 = (int)(e / Lq), r2 = (int)(e % Lq);
+    mask[e] = (uint8_t)(full && r1 / q != r2 / q);
+  }
+}
+
+__global__ void k_count_zero(unsigned long long* n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *n = 0;
+}
+
+// J = 0 where the element is inactive (mask 0 or a diagonal block); the
+// active elements r1 < r2 are counted (integer atomics: exact in any order).
+__global__ __launch_bounds__(kDecThreads) void k_mask_apply(float* __restrict__ J,
+                                                            const uint8_t* __restrict__ mask,
+                                                            int L, int q,
+                                                            unsigned long long* __restrict__ n) {
+  __shared__ unsigned long long sh[kDecThreads / 64];
+  const int Lq = L * q;
+  const size_t total = (size_t)Lq * Lq;
+  unsigned long long cnt = 0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int r1 = (int)(e / Lq), r2 = (int)(e % Lq);
+    const bool on = mask[e] != 0 && r1 / q != r2 / q;
+    if (!on && J) J[e] = 0.0f;
+    cnt += (on && r1 < r2) ? 1ull : 0ull;
+  }
+  if (!n) return;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kDecThreads / 64; ++w) s += sh[w];
+    if (s) atomicAdd(n, s);
+  }
+}
+
+static unsigned mask_blocks(int L, int q) {
+  const size_t total = (size_t)L * q * (size_t)L * q;
+  return (unsigned)std::min<size_t>(ceil_div(total, kDecThreads), 2048);
+}
+
+hipError_t launch_mask_init(uint8_t* mask, int L, int q, int full, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_init, dim3(mask_blocks(L, q)), dim3(kDecThreads), 0, s, mask, L, q,
+                     full);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_apply(float* J, const uint8_t* mask, int L, int q, long long* n_active,
+                             hipStream_t s) {
+  auto* n = reinterpret_cast<unsigned long long*>(n_active);
+  if (n) {
+    hipLaunchKernelGGL(k_count_zero, dim3(1), dim3(64), 0, s, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_mask_apply, dim3(mask_blocks(L, q)), dim3(kDecThreads), 0, s, J, mask, L,
+                     q, n);
   return hipGetLastError();
 }
 

@@ -113,35 +113,31 @@ inline GatherShape gather_shape(int L, int q, int cpb, int lpc) {
   return g.waves ? g : gather_shape_n(L, q, cpb, 4, lpc, false);
 }
 
+// Lanes per chain: a function of q and the draw alone, never of the chain
+// count or the CU share, because the FP32 summation order of a chain's local
+// fields follows its lanes -- with this rule a chain draws the same bits in
+// bmdca_gibbs, in a grouped epoch on a CU share and in a merged
+// bmdca_gibbs_streams launch.  8 lanes for q > 8 (16 cost 1.9x at q = 21:
+// the per-wave step overhead doubles).  For q <= 8 (rows of at most two
+// quads) the heat-bath draw also takes 8: its 8-wave kernel reads tokens a
+// step ahead, which outweighs the halved lanes (q = 5, L = 400, 10 000
+// chains: 23.6 against 28.2 ms per 10 sweeps; q = 8, L = 60: 0.78 against
+// 1.16; with 4096 chains on the whole device 16 lanes were 13% faster, the
+// price of the fixed rule).  Metropolis, which runs the 16-wave kernel,
+// takes 16 (q = 5, L = 400, 10 000 chains: 24.0 against 27.2 ms).
+constexpr int gather_lanes(int q, bool small) { return (gather_v(q) <= 2 && !small) ? 16 : 8; }
+
 // Chains per workgroup: spread the chains over the CUs (one workgroup per CU
-// at a time) in as few rounds as the largest workgroup that fits allows, with
-// 8 lanes per chain.  For q <= 8 (rows of at most two quads) the same chains
-// get 16 lanes each (twice the waves, each with half the positions per step;
-// at q = 21 that costs 1.9x, the per-wave step overhead doubles), unless, for
-// the heat-bath draw (`small`), 16 lanes need more than kGSmallWaves waves
-// where 8 lanes fit in them (below).  Metropolis always runs the 16-wave
-// kernel and keeps 16 lanes (q = 5, L = 400, 10 000 chains: 24.0 against
-// 27.2 ms per 10 sweeps with 8).
+// at a time) in as few rounds as the largest workgroup that fits allows.
 inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8,
                                bool small = true) {
-  int cmax = std::min(cap, kGMaxWaves * (64 / 8));
-  while (cmax > 64 / 8 && gather_shape(L, q, cmax, 8).waves == 0) cmax -= 64 / 8;
+  const int lpc = gather_lanes(q, small);
+  const int cpw = 64 / lpc;  // chains per wave
+  int cmax = std::min(cap, kGMaxWaves * cpw);
+  while (cmax > cpw && gather_shape(L, q, cmax, lpc).waves == 0) cmax -= cpw;
   const int64_t rounds = gp_ceil(N, cus * cmax);
   const int cpb = (int)std::min<int64_t>(cmax, gp_ceil(N, rounds * cus));
-  GatherShape g{};
-  if (gather_v(q) <= 2) {
-    // 16 lanes unless that needs more than kGSmallWaves waves where 8 lanes
-    // fit in them: the 8-wave kernel reads its tokens a step ahead, which
-    // outweighs the halved lanes (q = 5, L = 400, 10 000 chains: 23.6 against
-    // 28.2 ms per 10 sweeps; q = 8, L = 60: 0.78 against 1.16), while with few
-    // chains (4096: 4 waves either way) 16 lanes stay ahead by 13%
-    g = gather_shape(L, q, cpb, 16);
-    const GatherShape g8 = gather_shape(L, q, cpb, 8);
-    if (small && (g.waves == 0 || g.waves > kGSmallWaves) && g8.waves > 0 &&
-        g8.waves <= kGSmallWaves)
-      g = g8;
-  }
-  if (g.waves == 0) g = gather_shape(L, q, cpb, 8);
+  GatherShape g = gather_shape(L, q, cpb, lpc);
   g.blocks = (unsigned)gp_ceil(N, (int64_t)cpb);
   return g;
 }

@@ -98,6 +98,9 @@ hipError_t launch_update(float* h, float* J, const double* f1, const double* f2,
 // Group epoch epilogue of one model: if active, epoch += 1 and, with a
 // positive target, active = 0 once the Pearson coefficient reaches it.
 hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s);
+// h = (float) log f1 (the profile model's fields).
+hipError_t launch_profile_fields(const double* f1, int L, int q, float* h, int32_t* dev_err,
+                                 hipStream_t s);
 
 // ----- reweight.hip
 struct ReweightPlan {
@@ -138,6 +141,13 @@ hipError_t launch_decimate(float* J, uint8_t* mask, const double* C, int64_t N, 
 hipError_t launch_activate(uint8_t* mask, const double* C, const double* f2, int64_t N, int L,
                            int q, double factivate, long long* n_active_out, void* ws,
                            int32_t* dev_err, hipStream_t s);
+
+// Coupling graphs: mask = the full graph (full != 0, 1 off the diagonal
+// blocks) or the empty one; J = 0 off the graph, active elements r1 < r2
+// counted into *n_active (optional).
+hipError_t launch_mask_init(uint8_t* mask, int L, int q, int full, hipStream_t s);
+hipError_t launch_mask_apply(float* J, const uint8_t* mask, int L, int q, long long* n_active,
+                             hipStream_t s);
 
 // ----- equilibrium.hip
 size_t draw_ws_bytes(int64_t M);

@@ -162,4 +162,26 @@ hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Independent-site (profile) model: h_i(a) = log f_i(a) in FP64, rounded
+// once to float32.  With J = 0 its one-site marginals are
+// exp(h_i(a)) / sum_b exp(h_i(b)) = f_i(a), since each f_i sums to 1.  A
+// frequency that is not positive and finite gives a non-finite field and
+// raises BMDCA_DEVERR_NONFINITE.
+__global__ void k_profile_fields(const double* __restrict__ f1, int Lq, float* __restrict__ h,
+                                 int32_t* dev_err) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < Lq; r += gridDim.x * blockDim.x) {
+    const float v = (float)log(f1[r]);
+    h[r] = v;
+    if (!isfinite(v) && dev_err) atomicOr(dev_err, 2);
+  }
+}
+
+hipError_t launch_profile_fields(const double* f1, int L, int q, float* h, int32_t* dev_err,
+                                 hipStream_t s) {
+  const int Lq = L * q;
+  hipLaunchKernelGGL(k_profile_fields, dim3((unsigned)ceil_div(Lq, 256)), dim3(256), 0, s, f1, Lq,
+                     h, dev_err);
+  return hipGetLastError();
+}
+
 }  // namespace bmdca

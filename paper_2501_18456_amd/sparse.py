@@ -1,4 +1,4 @@
-"""Sparse models (Sec. 2.4 of the paper): element decimation (edDCA) and
+"""Sparse models (Sec. 2.2 of the paper, options in Sec. 3.1 and 3.2): element decimation (edDCA) and
 element activation (eaDCA).
 
 edDCA starts from a trained fully connected model and its chains and
@@ -45,15 +45,14 @@ def decimation(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, drate: f
     dev = chains.device
     if mask is None:
         mask = api.full_mask(L, q, dev)
-        J.mul_(mask.to(J.dtype))
+    n_act_d = api.mask_apply(J, mask, q)  # couplings off the graph are 0
     n_total = L * (L - 1) // 2 * q * q
     n_target = math.ceil(density * n_total)
     ws_t = api.workspace(B.WS_TRAIN_STEP, N, L, q, api._prec(prec) | api._sampler(sampler), dev)
     ws_d = api.workspace(B.WS_DECIMATE, N, L, q, 0, dev)
     pearson = torch.empty(1, dtype=torch.float64, device=dev)
-    n_act_d = torch.empty(1, dtype=torch.int64, device=dev)
     epoch = epoch0
-    n_act = int((torch.triu(mask, 1) != 0).sum().item())
+    n_act = int(n_act_d.item())
     history = []
     while True:
         r = -1.0
@@ -76,14 +75,14 @@ def activation(h, J, chains, f1, f2, lr: float, sweeps: int, seed: int, factivat
                target: float = 0.95, gsteps: int = 10, max_epochs: int = 10000, prec="bf16x2",
                sampler="auto", mask=None, epoch0: int = 0):
     """eaDCA in place on (h, J, chains, mask); without a mask the graph starts
-    empty and J is zeroed.  Returns (mask, history of (epoch, active
+    empty (J is zero off the graph).  Returns (mask, history of (epoch, active
     elements, Pearson), epochs used)."""
     L, q = api._model(h, J)
     N = chains.shape[0]
     dev = chains.device
     if mask is None:
-        mask = torch.zeros((L * q, L * q), dtype=torch.uint8, device=dev)
-        J.zero_()
+        mask = api.mask_init(L, q, full=False, device=dev)
+    api.mask_apply(J, mask, q)  # couplings off the graph are 0
     ws_t = api.workspace(B.WS_TRAIN_STEP, N, L, q, api._prec(prec) | api._sampler(sampler), dev)
     ws_a = api.workspace(B.WS_DECIMATE, N, L, q, 0, dev)
     pearson = torch.empty(1, dtype=torch.float64, device=dev)

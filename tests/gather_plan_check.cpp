@@ -27,20 +27,11 @@ static int failures = 0;
 
 static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
   const GatherShape g = gather_plan(N, L, q, cus, cap, small);
-  // lanes per chain: 8 for q > 8; for q <= 8, 16 where that shape fits, except
-  // (heat-bath plans only) where 16 lanes need more than kGSmallWaves waves
-  // and 8 lanes fit in them
-  if (gather_v(q) > 2) {
-    CHECK(g.lpc == 8, "lpc %d for q %d", g.lpc, q);
-  } else {
-    const GatherShape g16 = gather_shape(L, q, g.cpb, 16);
-    const GatherShape g8 = gather_shape(L, q, g.cpb, 8);
-    const bool rule = small && (g16.waves == 0 || g16.waves > kGSmallWaves) && g8.waves > 0 &&
-                      g8.waves <= kGSmallWaves;
-    const int want = (g16.waves > 0 && !rule) ? 16 : 8;
-    CHECK(g.lpc == want, "lpc %d, expected %d (q %d, cpb %d, small %d)", g.lpc, want, q, g.cpb,
-          (int)small);
-  }
+  // lanes per chain: fixed by q and the draw (8; 16 for Metropolis at q <= 8),
+  // whatever the chain count, CU share and cap
+  const int want = (gather_v(q) <= 2 && !small) ? 16 : 8;
+  CHECK(g.lpc == want, "lpc %d, expected %d (q %d, cpb %d, small %d)", g.lpc, want, q, g.cpb,
+        (int)small);
   CHECK(g.waves >= kGMinWaves && g.waves <= kGMaxWaves, "waves %d", g.waves);
   CHECK(g.lpc == 8 || g.lpc == 16, "lpc %d", g.lpc);
   const int S = gather_s(q, g.lpc), QP = gather_qp(q), NQ = QP / 4;

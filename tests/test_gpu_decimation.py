@@ -1,4 +1,4 @@
-"""Element decimation (edDCA, Sec. 2.4) and masked training through the C ABI
+"""Element decimation (edDCA, Sec. 2.2 and Sec. 3.2) and masked training through the C ABI
 against the oracle."""
 import numpy as np
 import pytest
@@ -201,3 +201,23 @@ def test_activation_driver_reaches_target():
     assert np.array_equal(m, m.T) and np.all(host(Jg)[m == 0] == 0.0)
     assert all(a[1] <= b[1] for a, b in zip(hist, hist[1:]))
     assert 0 < hist[-1][1] < L * (L - 1) // 2 * q * q
+
+
+@pytest.mark.parametrize("L,q", [(9, 21), (30, 5), (2, 2)])
+def test_mask_init_and_apply(L, q):
+    """bmdca_mask_init (full and empty graphs) and bmdca_mask_apply (couplings
+    off the graph zeroed, active elements counted) against the oracle."""
+    Lq = L * q
+    assert np.array_equal(host(api.mask_init(L, q, True)), full_mask(L, q))
+    assert not host(api.mask_init(L, q, False)).any()
+    g = np.random.default_rng(60 + L)
+    J = g.normal(size=(Lq, Lq)).astype(np.float32)
+    m = (g.random((Lq, Lq)) < 0.4).astype(np.uint8)
+    m = np.triu(m, 1) | np.triu(m, 1).T
+    m[0, 0] = 1  # a diagonal-block entry set in the mask is still inactive
+    Jg = dev(J)
+    n = api.mask_apply(Jg, dev(m), q)
+    Jo, no = O.mask_apply(J, m, q)
+    assert np.array_equal(host(Jg), Jo) and int(host(n)[0]) == no
+    n = api.mask_apply(None, dev(full_mask(L, q)), q)
+    assert int(host(n)[0]) == L * (L - 1) * q * q // 2

@@ -15,9 +15,9 @@ import torch
 from oracle import oracle as O
 from paper_2501_18456_amd import api, synth
 from paper_2501_18456_amd import _lib as B
+from tests.trajectory_check import check_chains
 
 pytestmark = pytest.mark.gpu
-BOUNDARY = 1e-5
 
 
 def dev(x):
@@ -92,7 +92,9 @@ def test_protein_stats_sampled_entries(prec, tol):
 @pytest.mark.parametrize("sampler", ["gather", "fields"])
 def test_protein_epoch(sampler):
     """One epoch at full size: sampled chains follow the oracle's trajectories
-    (boundary events excused); h, J satisfy the update's invariants."""
+    (boundary events excused by replay); h and J equal the oracle's update
+    (Eq. 5) on the chain frequencies of the GPU's own chains, bit for bit, and
+    the Pearson value matches the oracle's on those chains."""
     h_true, J_true, X = protein_problem()
     L, q, N, lr = 100, 21, 10000, 0.05
     _, w, _ = O.reweight(X[:2000], 0.8)  # weights of a block; any weights will do here
@@ -109,31 +111,14 @@ def test_protein_epoch(sampler):
     # sampled slices of chains against the oracle
     for c0 in (0, 4321, N - 37):
         sl = slice(c0, c0 + 37)
-        ref, mg, _ = O.gibbs_range(h0, J0, ch0[sl], c0, q, 10, 3002, sweep_offset=30,
-                                   want_margins=True)
-        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
-        for c in bad:
-            assert mg[c].min() < BOUNDARY
+        ref, _, _ = O.gibbs_range(h0, J0, ch0[sl], c0, q, 10, 3002, sweep_offset=30)
+        bad = check_chains(h0, J0, ch0[sl], g[sl], ref, q, 10, 3002, sweep_offset=30, c0=c0)
         assert len(bad) <= 2
-    # invariants of the update (Eq. 5) relating the two outputs
-    h1, J1 = host(hg).astype(np.float64), host(Jg)
-    assert np.array_equal(J1, J1.T)
-    J4 = J1.reshape(L, q, L, q)
-    assert all(np.all(J4[i, :, i, :] == 0) for i in range(L))
-    dJ = (J1.astype(np.float64) - J0.astype(np.float64)).reshape(L, q, L, q) / lr
-    dh = (h1 - h0.astype(np.float64)).reshape(L, q) / lr
-    # sum_b (f_ij - p_ij)(a, b) = f_i(a) - p_i(a) for every j != i
-    s = dJ.sum(axis=3)  # [i, a, j]
-    for i in (0, 17, 99):
-        for j in (3, 50, 98):
-            if i != j:
-                assert np.abs(s[i, :, j] - dh[i]).max() < 2e-3  # fp32 rounding of q entries / lr
-    # Pearson against the chains the epoch produced
-    Y = np.zeros((N, L * q), np.float32)
-    Y[np.arange(N)[:, None], np.arange(L)[None, :] * q + g] = 1.0
-    C = torch.from_numpy(Y).cuda()
-    P2 = (C.T @ C).double().cpu().numpy() / N
-    P1 = np.diag(P2).copy()
+    # the update of Eq. (5) on the GPU's own chains: bit for bit
+    P1, P2 = O.chain_freqs(g, q)
+    h1o, J1o = O.update(h0, J0, f1, f2, P1, P2, L, q, lr)
+    assert np.array_equal(host(hg).reshape(-1), h1o.reshape(-1))
+    assert np.array_equal(host(Jg), J1o)
     assert abs(host(pr)[0] - O.pearson(f1, f2, P1, P2, L, q)) < 1e-10
 
 
@@ -149,11 +134,9 @@ def test_protein_metropolis_gather_sampled_chains():
     g = host(cg)
     for c0 in (0, 5000, N - 37):
         sl = slice(c0, c0 + 37)
-        ref, mg, _ = O.metropolis(h_true, J_true, ch0[sl], q, 10, 3013, sweep_offset=4,
-                                  want_margins=True, c0=c0)
-        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
-        for c in bad:
-            assert mg[c].min() < BOUNDARY
+        ref, _, _ = O.metropolis(h_true, J_true, ch0[sl], q, 10, 3013, sweep_offset=4, c0=c0)
+        bad = check_chains(h_true, J_true, ch0[sl], g[sl], ref, q, 10, 3013, sweep_offset=4,
+                           metropolis=True, c0=c0)
         assert len(bad) <= 2
 
 
@@ -250,11 +233,8 @@ def test_precision_gibbs_sampled_chains():
     g = host(cg)
     for c0 in (0, 12345, N - 20):
         sl = slice(c0, c0 + 20)
-        ref, mg, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 2, 3003, sweep_offset=7,
-                                   want_margins=True)
-        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
-        for c in bad:
-            assert mg[c].min() < BOUNDARY
+        ref, _, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 2, 3003, sweep_offset=7)
+        bad = check_chains(h, J, ch0[sl], g[sl], ref, q, 2, 3003, sweep_offset=7, c0=c0)
         assert len(bad) <= 1
 
 
@@ -268,10 +248,8 @@ def test_rna_gibbs_and_counts():
     g = host(cg)
     for c0 in (0, 2000):
         sl = slice(c0, c0 + 16)
-        ref, mg, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 1, 3004, want_margins=True)
-        bad = np.nonzero((g[sl] != ref).any(axis=1))[0]
-        for c in bad:
-            assert mg[c].min() < BOUNDARY
+        ref, _, _ = O.gibbs_range(h, J, ch0[sl], c0, q, 1, 3004)
+        check_chains(h, J, ch0[sl], g[sl], ref, q, 1, 3004, c0=c0)
     # unit-weight statistics of these chains: bit-exact sampled entries
     f1, f2, _ = api.stats(cg, q, None, 0.0, "bf16x2")
     r1, r2 = sample_pairs(L * q, 500, 9)
@@ -302,6 +280,30 @@ def test_largest_model_scores():
     assert np.abs(host(Fa) - Fao).max() <= 1e-5 * np.abs(Fo).max()
 
 
+def test_served_sampling_shape_streams():
+    """The largest served model's sampling shape: 10 000 chains of three
+    requests (own keys, chain indices and sweep offsets) at L = 512, q = 21 in
+    one bmdca_gibbs_streams launch sized for a 32-CU share, 2 sweeps; sampled
+    chains of every request follow the oracle's trajectories."""
+    L, q = 512, 21
+    h, J = synth.planted_dense(L, q, seed=1006, sigma_J=0.02)
+    sizes, seeds, offs = [6000, 3000, 1000], [5001, 5002, 5003], [0, 17, 40]
+    ch0 = O.init_chains(sum(sizes), L, q, seed=3040)
+    sd = np.repeat(seeds, sizes).astype(np.uint64)
+    of = np.repeat(offs, sizes).astype(np.uint64)
+    ids = np.concatenate([np.arange(n) for n in sizes]).astype(np.uint32)
+    cg = dev(ch0)
+    api.gibbs_streams(dev(h), dev(J), cg, 2, api.chain_streams(sd, of, ids), cus=32)
+    g = host(cg)
+    pick = np.concatenate([np.arange(0, 8), np.arange(5995, 6005), np.arange(7490, 7498),
+                           np.arange(9992, 10000)])
+    ref = np.stack([O.gibbs_range(h, J, ch0[k:k + 1], int(ids[k]), q, 2, int(sd[k]),
+                                  sweep_offset=int(of[k]))[0][0] for k in pick])
+    bad = check_chains(h, J, ch0[pick], g[pick], ref, q, 2, 0, ids=ids[pick], seeds=sd[pick],
+                       offsets=of[pick])
+    assert len(bad) <= 2
+
+
 # ---------------------------------------------------------------- edge cases
 def test_edge_single_chain_two_sites():
     L, q = 2, 2
@@ -310,9 +312,8 @@ def test_edge_single_chain_two_sites():
     for sampler in ("gather", "fields"):
         cg = dev(ch0)
         api.gibbs(dev(h), dev(J), cg, 5, seed=14, sampler=sampler)
-        ref, mg, _ = O.gibbs(h, J, ch0, q, 5, 14, want_margins=True)
-        if not np.array_equal(host(cg), ref):
-            assert mg.min() < BOUNDARY
+        ref, _, _ = O.gibbs(h, J, ch0, q, 5, 14)
+        check_chains(h, J, ch0, host(cg), ref, q, 5, 14)
     X = ch0
     f1, f2, _ = api.stats(dev(X), q, None, -1.0)
     o1, o2, _ = O.stats(X, q, None, -1.0)

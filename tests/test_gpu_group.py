@@ -143,3 +143,69 @@ def test_pearson_target_stops_a_model(problems, solo):
     assert torch.equal(ms[2].chains, after1[2])
     ps, _ = solo[3]
     assert same(ms[3], ps)
+
+
+def test_group_q5_many_chains_equal_solo():
+    """RNA-like models (q = 5) with 4096 chains on 8 lanes (a 32-CU share each):
+    the share plan takes the lanes per chain of the solo plan (fixed by q and
+    the draw), so the grouped epochs equal solo bmdca_train_step calls."""
+    ps = []
+    for k, L in enumerate((100, 61)):
+        h, J = synth.planted_dense(L, 5, seed=720 + k, sigma_J=0.3)
+        hg, Jg = torch.from_numpy(h).cuda(), torch.from_numpy(J).cuda()
+        msa = api.init_chains(600, L, 5, seed=820 + k)
+        api.gibbs(hg, Jg, msa, 20, 820 + k)
+        f1, f2, _ = api.stats(msa, 5, None, -1.0, "fp32")
+        ps.append(dict(h=torch.log(f1).float().reshape(L, 5).contiguous(),
+                       J=torch.zeros((L * 5, L * 5), dtype=torch.float32, device="cuda"),
+                       chains=api.init_chains(4096, L, 5, seed=920 + k), f1=f1, f2=f2,
+                       seed=920 + k, prec="bf16x2", sampler="auto"))
+    torch.cuda.synchronize()
+    solo = [solo_run(p, EPOCHS) for p in ps]
+    ms = models_of(ps)
+    for e in range(EPOCHS):
+        api.train_group_step(ms, lanes=8)
+    torch.cuda.synchronize()
+    for k, m in enumerate(ms):
+        assert same(m, solo[k][0]), f"q=5 model {k} differs from its solo run"
+
+
+def test_group_epochs_follow_the_oracle(problems):
+    """Two models of the group (gather form and field form, BF16 and FP32
+    counts) against the oracle's train_step, epoch by epoch: chains follow the
+    oracle's trajectories (boundary events excused by replay, then both sides
+    continue from the oracle's state); h, J bit-exact and Pearson within 1e-12
+    after every epoch without a boundary event."""
+    from oracle import oracle as O
+    from tests.trajectory_check import check_chains
+
+    picks = [0, 2]  # (12, 21, 300, bf16x2, auto -> gather), (9, 21, 128, fp32, fields)
+    ms = models_of([problems[k] for k in picks])
+    state = []
+    for m in ms:
+        state.append([m.h.cpu().numpy().copy(), m.J.cpu().numpy().copy(),
+                      m.chains.cpu().numpy().copy()])
+    f = [(problems[k]["f1"].cpu().numpy(), problems[k]["f2"].cpu().numpy()) for k in picks]
+    events = 0
+    for e in range(EPOCHS):
+        api.train_group_step(ms, lanes=2)
+        torch.cuda.synchronize()
+        for i, m in enumerate(ms):
+            L, q = SHAPES[picks[i]][:2]
+            h, J, ch = state[i]
+            h2, J2, ch2, r, _, _ = O.train_step(h, J, ch, f[i][0], f[i][1], q, LR, SWEEPS,
+                                                problems[picks[i]]["seed"], e)
+            g = m.chains.cpu().numpy()
+            bad = check_chains(h, J, ch, g, ch2, q, SWEEPS, problems[picks[i]]["seed"],
+                               sweep_offset=e * SWEEPS)
+            if len(bad):
+                events += len(bad)
+                m.h.copy_(torch.from_numpy(h2.reshape(m.h.shape)))
+                m.J.copy_(torch.from_numpy(J2))
+                m.chains.copy_(torch.from_numpy(ch2))
+            else:
+                assert np.array_equal(m.h.cpu().numpy().reshape(-1), h2.reshape(-1))
+                assert np.array_equal(m.J.cpu().numpy(), J2)
+                assert abs(float(m.pearson.item()) - r) <= 1e-12
+            state[i] = [h2, J2, ch2]
+    assert events <= 3

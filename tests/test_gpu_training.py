@@ -27,7 +27,7 @@ def test_driver_equals_eager_epochs(prec, sampler):
     assert used == 12 and [e for e, _ in hist] == [5, 10, 12]
     _, w, _ = api.reweight(msa, q, 0.8)
     f1, f2, _ = api.stats(msa, q, w, -1.0, prec)
-    he = torch.log(f1).float().reshape(L, q).contiguous()
+    he = api.profile_fields(f1, L, q)
     Je = torch.zeros((L * q, L * q), dtype=torch.float32, device="cuda")
     ce = api.init_chains(N, L, q, seed)
     for e in range(12):
@@ -48,3 +48,19 @@ def test_driver_stops_at_target():
     assert all(r < 0.6 for _, r in hist[:-1])
     assert np.isfinite(h.cpu().numpy()).all() and np.array_equal(J.cpu().numpy(),
                                                                   J.cpu().numpy().T)
+
+
+def test_driver_raises_on_device_flags():
+    """A huge learning rate overflows the float32 parameters: the driver reads
+    the device flag with the first batch of epochs and raises, instead of
+    replaying a diverged model to max_epochs; a token outside 0..q-1 in the
+    alignment is caught at pre-processing."""
+    L, q = 20, 21
+    msa = alignment(L, q, 300, 90)
+    with pytest.raises(training.DeviceError, match="non-finite"):
+        training.bmdca(msa, q, chains=200, sweeps=2, lr=1e300, target=0.99, max_epochs=50,
+                       seed=91, check_every=5)
+    bad = msa.clone()
+    bad[3, 4] = q + 2
+    with pytest.raises(training.DeviceError, match="token"):
+        training.bmdca(bad, q, chains=200, sweeps=2, max_epochs=5, seed=92)

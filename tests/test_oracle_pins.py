@@ -82,6 +82,127 @@ def test_init_chains_uniform_tokens():
     assert np.array_equal(ch, O.init_chains(4000, 30, q, seed=11))
 
 
+def _word(seed, ctr, k):
+    """Word k of Philox4x32-10 (pinned by the KATs above) under key = seed
+    (low 32 bits first) and the given counter."""
+    return int(O.philox4x32_10(ctr, [seed & 0xFFFFFFFF, seed >> 32])[k])
+
+
+SEED64 = 0x9E3779B97F4A7C15  # both key halves non-zero, so a swapped key half shows
+
+
+def test_gibbs_uniform_counter_map():
+    """The Gibbs uniform of chain c, global sweep sg, site i is
+    (word >> 8) 2^-24 of counter (i/4, sg, c, 0), word i%4 (reading R6)."""
+    g = np.random.default_rng(21)
+    for _ in range(400):
+        c, sg, i = int(g.integers(0, 2 ** 20)), int(g.integers(0, 2 ** 31)), int(g.integers(0, 600))
+        w = _word(SEED64, [i >> 2, sg, c, 0], i & 3)
+        assert O.gibbs_uniform(SEED64, c, sg, i) == (w >> 8) / 16777216.0
+
+
+def test_init_token_counter_map():
+    """Initial token of chain c at site i: (w q) >> 32 for the word i%4 of
+    counter (i/4, 0, c, 1) (reading R5)."""
+    N, L = 37, 23
+    for q in (2, 5, 21, 32):
+        ch = O.init_chains(N, L, q, SEED64 + q)
+        ref = np.array([[(_word(SEED64 + q, [i >> 2, 0, c, 1], i & 3) * q) >> 32
+                         for i in range(L)] for c in range(N)])
+        assert np.array_equal(ch, ref)
+
+
+def test_gibbs_sweep_uses_the_counter_map():
+    """With J = 0 the sites are independent and one sweep draws site i of chain c
+    from softmax(beta h_i) by the inverse CDF at the uniform of counter
+    (i/4, offset, c, 0): recomputed here from the KAT-pinned generator and a
+    numpy softmax (visits within 1e-12 of a CDF step are skipped: libm and numpy
+    exp may differ in the last bit)."""
+    L, q, N, off, beta = 19, 21, 60, 123456, 0.8
+    g = np.random.default_rng(22)
+    h = g.normal(size=(L, q)).astype(np.float32)
+    J = np.zeros((L * q, L * q), np.float32)
+    ch0 = O.init_chains(N, L, q, 5)
+    c0 = 1000
+    out, _, _ = O.gibbs_range(h, J, ch0, c0, q, 1, SEED64, sweep_offset=off, beta=beta)
+    checked = 0
+    for c in range(N):
+        for i in range(L):
+            l = beta * h[i].astype(np.float64)
+            e = np.exp(l - l.max())
+            cdf = np.cumsum(e) / e.sum()
+            u = (_word(SEED64, [i >> 2, off, c0 + c, 0], i & 3) >> 8) / 16777216.0
+            if np.abs(u - cdf[:-1]).min() < 1e-12:
+                continue
+            assert out[c, i] == int((cdf[:-1] <= u).sum())
+            checked += 1
+    assert checked >= N * L - 2
+
+
+def test_metropolis_counter_map():
+    """With J = 0 one Metropolis sweep at site i proposes
+    a' = (a + 1 + ((w (q-1)) >> 32)) mod q from word 2(i%2) of counter
+    (i/2, offset, c, 3) and accepts iff u < exp(beta (h_i(a') - h_i(a))) with u
+    from word 2(i%2)+1 (reading R21); recomputed from the generator."""
+    L, q, N, off = 17, 21, 80, 77
+    g = np.random.default_rng(23)
+    h = g.normal(size=(L, q)).astype(np.float32)
+    J = np.zeros((L * q, L * q), np.float32)
+    ch0 = O.init_chains(N, L, q, 6)
+    for beta in (0.0, 1.3):
+        out, _, _ = O.metropolis(h, J, ch0, q, 1, SEED64, sweep_offset=off, beta=beta, c0=50)
+        for c in range(N):
+            for i in range(L):
+                a = int(ch0[c, i])
+                ctr = [i >> 1, off, 50 + c, 3]
+                ap = (a + 1 + ((_word(SEED64, ctr, 2 * (i & 1)) * (q - 1)) >> 32)) % q
+                u = (_word(SEED64, ctr, 2 * (i & 1) + 1) >> 8) / 16777216.0
+                p = np.exp(beta * (float(h[i, ap]) - float(h[i, a])))
+                if abs(u - min(1.0, p)) < 1e-12:
+                    continue
+                assert out[c, i] == (ap if u < p else a), (beta, c, i)
+
+
+def test_boundary_replay_excuses_only_boundary_events():
+    """The parity tests' excusal: a chain that took the other outcome at a
+    visit within 1e-5 of its threshold is reproduced by the replay search;
+    a chain with one site changed anywhere else is not (planted error)."""
+    from tests.trajectory_check import BOUNDARY, check_chains, reproduces
+    L, q, N, sweeps = 20, 21, 400, 4
+    h, J = synth.planted_dense(L, q, seed=24, sigma_J=0.3)
+    ch0 = O.init_chains(N, L, q, 7)
+    ref, mg, _ = O.gibbs(h, J, ch0, q, sweeps, 8, sweep_offset=3, want_margins=True)
+    close = [c for c in range(N) if mg[c].min() < BOUNDARY]
+    assert close, "no near-boundary visit among the chains; pick another seed"
+    moved = 0
+    for c in close:
+        end, drawn, lo, hi = O.chain_forced(h, J, ch0[c], c, q, sweeps, 8, 3, tol=BOUNDARY)
+        assert np.array_equal(end, ref[c])
+        v = int(np.nonzero((lo != drawn) | (hi != drawn))[0][0])
+        alt = int(lo[v]) if lo[v] != drawn[v] else int(hi[v])
+        f = np.full(sweeps * L, -1, np.int8)
+        f[v] = alt
+        end2, _, _, _ = O.chain_forced(h, J, ch0[c], c, q, sweeps, 8, 3, force=f)
+        if not np.array_equal(end2, ref[c]):
+            moved += 1
+            assert reproduces(h, J, ch0[c], end2, c, q, sweeps, 8, 3)
+    assert moved > 0
+    # a planted error: one site of one chain changed away from every boundary branch
+    far = [c for c in range(N) if mg[c].min() > 1e-3]
+    bad = ref.copy()
+    bad[far[0], 5] = (bad[far[0], 5] + 1) % q
+    with pytest.raises(AssertionError):
+        check_chains(h, J, ch0, bad, ref, q, sweeps, 8, sweep_offset=3)
+    # and the same chains with no change pass
+    assert len(check_chains(h, J, ch0, ref, ref, q, sweeps, 8, sweep_offset=3)) == 0
+    # Metropolis replays equal the sampler
+    mref, _, _ = O.metropolis(h, J, ch0[:20], q, sweeps, 9, sweep_offset=2, beta=0.7)
+    for c in range(20):
+        end, _, _, _ = O.chain_forced(h, J, ch0[c], c, q, sweeps, 9, 2, beta=0.7,
+                                      metropolis=True)
+        assert np.array_equal(end, mref[c])
+
+
 # ---------------------------------------------------------------- reweighting (Eq. 7)
 def test_identity_threshold_reading():
     assert O.identity_threshold(0.8, 35) == 28  # 0.8*35 rounds above 28 in FP64
@@ -594,7 +715,7 @@ def test_metropolis_beta_zero_always_moves_uniformly():
     assert np.all(np.abs(cnt[1:] - e) < 5 * np.sqrt(e))
 
 
-# ------------------------------------------------- element decimation (edDCA, Sec. 2.4)
+# ------------------------------------------------- element decimation (edDCA, Sec. 2.2 and Sec. 3.2)
 def test_decimation_score_is_symmetric_kl_by_enumeration():
     L, q = 3, 3
     h, J = tiny_model(30, L=L, q=q, sJ=0.8)
@@ -653,7 +774,7 @@ def test_decimation_selects_smallest_scores():
     assert n3 == n and np.array_equal(m3, mask)
 
 
-# ------------------------------------------------- element activation (eaDCA, Sec. 2.4)
+# ------------------------------------------------- element activation (eaDCA, Sec. 2.2 and Sec. 3.1)
 def test_activation_distance_is_bernoulli_kl():
     """The distance is KL(Bernoulli(f) || Bernoulli(p)) (the reading of "most
     distant"): scipy's relative entropy of the two two-outcome laws, the
@@ -761,3 +882,42 @@ def test_masked_update_holds_pruned_couplings_at_zero():
     assert np.array_equal(chm, chu) and rm == ru and np.array_equal(hm, hu)
     assert np.all(Jm2[mask == 0] == 0.0)
     assert np.array_equal(Jm2[mask == 1], Ju[mask == 1])
+
+
+# ------------------------------------------------- profile start and coupling graphs (Sec. 2.2)
+def test_profile_fields_reproduce_the_one_site_frequencies():
+    """The independent-site model h = log f1, J = 0: its exactly enumerated
+    one-site marginals equal f1 (to the float32 rounding of h), and its
+    pairwise marginals factorise."""
+    L, q = 3, 4
+    g = np.random.default_rng(31)
+    f1 = g.random((L, q)) + 0.05
+    f1 /= f1.sum(axis=1, keepdims=True)
+    h = O.profile_fields(f1.reshape(-1), L, q)
+    assert h.dtype == np.float32 and h.shape == (L, q)
+    p1, p2 = enumerate_numpy(h, np.zeros((L * q, L * q), np.float32), L, q)[:2]
+    assert np.abs(p1 - f1.reshape(-1)).max() < 1e-6
+    assert np.abs(p2[:q, q:2 * q] - np.outer(f1[0], f1[1])).max() < 1e-6
+    # a zero frequency gives a non-finite field (raised as a device flag by the library)
+    f1[1, 2] = 0.0
+    assert np.isneginf(O.profile_fields(f1.reshape(-1), L, q)[1, 2])
+
+
+def test_mask_apply_counts_and_zeroes():
+    L, q = 7, 3
+    Lq = L * q
+    full = np.ones((Lq, Lq), np.uint8)
+    for i in range(L):
+        full[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0
+    # the fully connected graph has L (L-1) q^2 / 2 elements (Sec. 2.2)
+    assert O.mask_apply(None, full, q)[1] == L * (L - 1) * q * q // 2
+    assert O.mask_apply(None, np.ones((Lq, Lq), np.uint8), q)[1] == L * (L - 1) * q * q // 2
+    assert O.mask_apply(None, np.zeros((Lq, Lq), np.uint8), q)[1] == 0
+    g = np.random.default_rng(32)
+    J = g.normal(size=(Lq, Lq)).astype(np.float32)
+    m = (g.random((Lq, Lq)) < 0.3).astype(np.uint8)
+    m = np.triu(m, 1) | np.triu(m, 1).T
+    Jm, n = O.mask_apply(J, m, q)
+    keep = (m != 0) & full.astype(bool)
+    assert np.array_equal(Jm[keep], J[keep]) and np.all(Jm[~keep] == 0)
+    assert n == int(np.triu(keep, 1).sum())
