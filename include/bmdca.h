@@ -246,6 +246,29 @@ int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B,
                  int32_t L, int32_t q, float* E, void* ws, size_t ws_bytes,
                  int32_t* dev_err, void* stream);
 
+/* Bytes of the library's static per-GPU scratch array for
+ * bmdca_energy_noalloc (64 MiB). */
+#define BMDCA_ENERGY_SCRATCH_BYTES (64u << 20)
+
+/* bmdca_energy with no workspace argument and no device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Results are those of bmdca_energy
+ * bit for bit.  Its scratch (the site-major token copy and the FP64 partial
+ * pair sums, align256(L Bp) + align256(8 P Bp) bytes with Bp = B rounded up
+ * to 64 and P <= 128 pair ranges fixed by L) lives in one static device array
+ * of BMDCA_ENERGY_SCRATCH_BYTES per GPU, held from library load to process
+ * end; nothing in it needs clearing between calls.  A batch whose scratch
+ * exceeds the array returns BMDCA_EINVAL before anything is enqueued (up
+ * to 43 648 sequences fit at L = 512, 84 672 at L = 256, 328 960 at
+ * L = 100): split it, or call bmdca_energy.  Every call on one GPU uses the
+ * same array, so calls
+ * that may overlap on that GPU (different streams, or host threads) race and
+ * must be serialised by the caller.  The first call on a device looks up the
+ * array's device address (not a stream operation); later calls only enqueue
+ * kernels.  Other arguments as bmdca_energy. */
+int bmdca_energy_noalloc(const float* h, const float* J, const int8_t* seqs, int64_t B,
+                         int32_t L, int32_t q, float* E, int32_t* dev_err, void* stream);
+
 /* One epoch of persistent-chain Boltzmann learning (Sec. 2.1):
  *   1. `sweeps` Gibbs sweeps of the chains at beta = 1, global sweep index
  *      epoch*sweeps + s (as bmdca_gibbs);

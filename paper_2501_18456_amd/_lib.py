@@ -20,6 +20,7 @@ SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER,
            "metropolis": SAMPLER_METROPOLIS,
            "metropolis-fields": SAMPLER_METROPOLIS | SAMPLER_FIELDS,
            "metropolis-gather": SAMPLER_METROPOLIS | SAMPLER_GATHER}
+ENERGY_SCRATCH_BYTES = 64 << 20  # BMDCA_ENERGY_SCRATCH_BYTES
 (WS_REWEIGHT, WS_STATS, WS_GIBBS, WS_TRAIN_STEP, WS_APC, WS_MUTANT, WS_ENERGY, WS_DRAW,
  WS_SEQID, WS_DECIMATE) = range(10)
 
@@ -62,6 +63,7 @@ SIGNATURES = {
     "bmdca_gibbs_streams": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _i32, _p, _f32, _p, _sz,
                                       _i32, _i32, _p, _p]),
     "bmdca_energy": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p, _p]),
+    "bmdca_energy_noalloc": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _p]),
     "bmdca_train_step": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _f64, _i32, _u64, _u64,
                                    _i32, _p, _p, _p, _sz, _p, _p]),
     "bmdca_single_mutant_scan": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _p, _p, _sz, _p]),

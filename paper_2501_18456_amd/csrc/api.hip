@@ -316,6 +316,37 @@ DecimatePlan plan_decimate(int64_t N, int L, int q) {
 
 }  // namespace
 
+// ----- Allocation-free energies: the scratch of bmdca_energy_noalloc lives in
+// a file-scope device array (each GPU holds its own copy from module load to
+// process end).  Host code never passes the array's name to a kernel: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kEnergyScratchBytes = (size_t)BMDCA_ENERGY_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kEnergyScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+static int scratch_address(void** out) {
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "energy_noalloc: current device");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(BMDCA_EINVAL, "energy_noalloc: device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t g = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g != hipSuccess) return hip_status(g, "energy_noalloc: scratch address");
+    if (!p) return fail(BMDCA_EHIP, "energy_noalloc: scratch address is NULL");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return BMDCA_OK;
+}
+
 struct bmdca_graph_s {
   hipGraphExec_t exec = nullptr;
 };
@@ -441,6 +472,24 @@ int bmdca_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, 
     return fail(BMDCA_EWORKSPACE, "energy workspace %zu < %zu bytes", ws_bytes, plan.total);
   return hip_status(launch_energy(h, J, seqs, B, L, q, E, plan, ws, dev_err, (hipStream_t)stream),
                     "energy");
+}
+
+int bmdca_energy_noalloc(const float* h, const float* J, const int8_t* seqs, int64_t B,
+                         int32_t L, int32_t q, float* E, int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(B >= 0 && B <= (int64_t)1 << 31, "B=%lld outside 0..2^31", (long long)B);
+  if (B == 0) return BMDCA_OK;  // nothing to score; seqs and E may be NULL
+  BMDCA_REQUIRE(h && J && seqs && E, "null pointer argument");
+  const EnergyPlan plan = plan_energy(B, L, q);
+  if (plan.total > kEnergyScratchBytes)
+    return fail(BMDCA_EINVAL,
+                "energy_noalloc: B=%lld at L=%d needs %zu bytes of scratch, more than the "
+                "%zu-byte static array; split the batch or use bmdca_energy",
+                (long long)B, L, plan.total, kEnergyScratchBytes);
+  void* ws = nullptr;
+  BMDCA_TRY(scratch_address(&ws));
+  return hip_status(launch_energy(h, J, seqs, B, L, q, E, plan, ws, dev_err, (hipStream_t)stream),
+                    "energy_noalloc");
 }
 
 int bmdca_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed, int32_t* rows,
