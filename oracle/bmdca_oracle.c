@@ -295,11 +295,15 @@ void orc_gibbs_range(const float* h, const float* J, int8_t* chains, int64_t N,
                      uint64_t seed, uint64_t sweep_offset, double beta,
                      double* margins, int64_t* flips)
 {
-    double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
-    double* e = (double*)malloc(sizeof(double) * (size_t)q);
-    double* cdf = (double*)malloc(sizeof(double) * (size_t)q);
     int64_t nflip = 0;
+    /* Chains are independent.  Built with -fopenmp (the timing build of the
+     * CPU baseline) they are spread over threads; every chain's draws are the
+     * same in either build. */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nflip)
     for (int64_t c = 0; c < N; ++c) {
+        double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
+        double* e = (double*)malloc(sizeof(double) * (size_t)q);
+        double* cdf = (double*)malloc(sizeof(double) * (size_t)q);
         int8_t* s = chains + c * L;
         for (int32_t sw = 0; sw < sweeps; ++sw) {
             uint64_t sg = sweep_offset + (uint64_t)sw;
@@ -313,11 +317,11 @@ void orc_gibbs_range(const float* h, const float* J, int8_t* chains, int64_t N,
                 s[i] = (int8_t)anew;
             }
         }
+        free(Hi);
+        free(e);
+        free(cdf);
     }
     if (flips) *flips = nflip;
-    free(Hi);
-    free(e);
-    free(cdf);
 }
 
 void orc_gibbs(const float* h, const float* J, int8_t* chains, int64_t N,
@@ -719,9 +723,10 @@ void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_
                           uint64_t seed, uint64_t sweep_offset, double beta,
                           double* margins, int64_t* flips)
 {
-    double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
     int64_t nflip = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nflip)
     for (int64_t c = 0; c < N; ++c) {
+        double* Hi = (double*)malloc(sizeof(double) * (size_t)q);
         int8_t* s = chains + c * L;
         for (int32_t sw = 0; sw < sweeps; ++sw) {
             uint64_t sg = sweep_offset + (uint64_t)sw;
@@ -737,9 +742,9 @@ void orc_metropolis_range(const float* h, const float* J, int8_t* chains, int64_
                 }
             }
         }
+        free(Hi);
     }
     if (flips) *flips = nflip;
-    free(Hi);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -20,19 +20,29 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bmdca_oracle.c")
 _LIB = os.path.join(_HERE, "libbmdca_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libbmdca_oracle_omp.so")
+
+
+def _compile(out: str, extra, force: bool) -> str:
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               *extra, "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, contraction off) into oracle/."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (-O2, contraction off) into oracle/: the
+    single-threaded library the tests use, and an OpenMP build (chains spread
+    over threads, same results) used only to time the oracle on all host
+    cores."""
+    _compile(_LIB_OMP, ["-fopenmp"], force)
+    return _compile(_LIB, [], force)
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -41,6 +51,16 @@ def lib():
         _lib = C.CDLL(build())
         _declare(_lib)
     return _lib
+
+
+def lib_threads():
+    """The OpenMP build (OMP_NUM_THREADS threads): the CPU-baseline timing leg."""
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        _lib_omp = C.CDLL(_LIB_OMP)
+        _declare(_lib_omp)
+    return _lib_omp
 
 
 _p = C.c_void_p
@@ -284,8 +304,9 @@ def update(h, J, f1, f2, p1, p2, L: int, q: int, lr: float):
 
 
 def train_step(h, J, chains, f1, f2, q: int, lr: float, sweeps: int, seed: int,
-               epoch: int, want_margins: bool = False):
-    """One epoch. Returns (h', J', chains', pearson, margins, flips)."""
+               epoch: int, want_margins: bool = False, threads: bool = False):
+    """One epoch. Returns (h', J', chains', pearson, margins, flips).
+    threads=True runs the OpenMP build (the same results)."""
     h = _f32(h).copy()
     J = _f32(J).copy()
     ch = _i8(chains).copy()
@@ -294,8 +315,9 @@ def train_step(h, J, chains, f1, f2, q: int, lr: float, sweeps: int, seed: int,
     f2 = np.ascontiguousarray(f2, dtype=np.float64)
     mg = np.zeros((N, sweeps, L), dtype=np.float64) if want_margins else None
     flips = np.zeros(1, dtype=np.int64)
-    r = lib().orc_train_step(_ptr(h), _ptr(J), _ptr(ch), N, L, q, _ptr(f1), _ptr(f2), lr,
-                             sweeps, seed, epoch, _ptr(mg), _ptr(flips))
+    lb = lib_threads() if threads else lib()
+    r = lb.orc_train_step(_ptr(h), _ptr(J), _ptr(ch), N, L, q, _ptr(f1), _ptr(f2), lr,
+                          sweeps, seed, epoch, _ptr(mg), _ptr(flips))
     return h, J, ch, r, mg, int(flips[0])
 
 

@@ -921,3 +921,18 @@ def test_mask_apply_counts_and_zeroes():
     keep = (m != 0) & full.astype(bool)
     assert np.array_equal(Jm[keep], J[keep]) and np.all(Jm[~keep] == 0)
     assert n == int(np.triu(keep, 1).sum())
+
+
+def test_openmp_build_gives_the_same_epoch():
+    """The OpenMP build of the oracle (timing leg of the CPU baseline) spreads
+    chains over threads; every output equals the single-threaded build's."""
+    L, q, N = 30, 21, 97
+    h, J = synth.planted_dense(L, q, seed=33, sigma_J=0.3)
+    X = synth.clustered_msa(200, L, q, seed=34)
+    f1, f2, _ = O.stats(X, q, None, -1.0)
+    ch = O.init_chains(N, L, q, 35)
+    a = O.train_step(h, J, ch, f1, f2, q, 0.05, 4, 36, 2)
+    b = O.train_step(h, J, ch, f1, f2, q, 0.05, 4, 36, 2, threads=True)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3] == b[3] and a[5] == b[5]
