@@ -1,13 +1,16 @@
 """Benchmark of the bmDCA training hot path on one MI355X.
 
-One step = one training epoch through bmdca_train_step: 10 Gibbs sweeps of all
-persistent chains (gather form), one-hot chain statistics on the matrix
-cores, FP64 Pearson check and FP64 update.  Workload (protein scale): L = 100 sites,
-q = 21 states, N = 10 000 chains, planted sparse-contact Potts model (3L random
-pairs with N(0, 0.5) blocks, gap holding 15% of the independent-site mass),
-M = 20 000 sequences drawn from it by 200 Gibbs sweeps and reweighted at 80%
-identity, FP32 statistics.  Inputs are synthetic and resident in HBM before
-the timed region.
+Default workload (the precision form): L = 256 sites, q = 21 states, an
+alignment of M = 100 000 synthetic sequences (phylogeny-like, seeded) with
+non-uniform weights w = 1 - U[0, 1) in (0, 1], N = 20 000 persistent chains,
+10 Gibbs sweeps per epoch, lr 0.05.  One step = one training epoch through
+bmdca_train_step (sweeps in the gather form, chain counts on the matrix
+cores, FP64 Pearson check and FP64 update), timed in the plain FP32 form
+(`value`); beside it the mixed (BF16 hi+lo) epoch, the weighted two-site
+statistics in both forms with their maximum error against the FP64 oracle on
+sampled entries, the sweep kernels alone, and the protein-scale workload
+(L = 100, N = 10 000) as context.  Inputs are synthetic and resident in HBM
+before the timed region.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -30,27 +33,49 @@ HBM_PEAK_GBS = 8000.0
 # CU, sustains 213 B/clk on MI355X)
 LDS_BYTES_PER_CLK = 256
 
-# HBM bytes per 10-sweep launch of the gather sweep kernel at the protein-scale
-# workload: rocprofv3 FETCH_SIZE and WRITE_SIZE of that launch (KiB per
-# dispatch), scaled by what the same counters read for a 512 MiB device copy
-# (x2.0 and x1.0).  Valid only for the sources they were taken with (the
-# SHA-256 of the files below); for other sources the line reports null.
+# HBM bytes per 10-sweep launch of the gather sweep kernel: rocprofv3
+# FETCH_SIZE and WRITE_SIZE of that launch (KiB per dispatch), each scaled by
+# what the same counter reads for a 512 MiB device copy in the same run.
+# Valid only for the sources they were taken with (the SHA-256 of the files
+# below); for other sources the line reports null.
 GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
                           "paper_2501_18456_amd/csrc/gather_plan.hpp",
                           "paper_2501_18456_amd/csrc/sampler.hip",
                           "paper_2501_18456_amd/csrc/common.hpp")
-GATHER_TRAFFIC = {"sha256": "ffc7c3ecc2781b215e1aaa41b640f232263ef01c4dd53a1ccc4a5fe0dda56327",
-                  "bytes": 1.61628e+09}  # 1.6146e9 read + 1.68e6 written
+GATHER_TRAFFIC = {"sha256": None, "bytes": {}}  # workload name -> bytes per launch
 
 
-def gather_traffic():
-    """The profiled HBM bytes per launch if the kernel sources are unchanged."""
+def sources_digest():
     import hashlib
     h = hashlib.sha256()
     for f in GATHER_TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return GATHER_TRAFFIC["bytes"] if h.hexdigest() == GATHER_TRAFFIC["sha256"] else None
+    return h.hexdigest()
+
+
+def gather_traffic(workload):
+    """The profiled HBM bytes per launch if the kernel sources are unchanged."""
+    if GATHER_TRAFFIC["sha256"] != sources_digest():
+        return None
+    return GATHER_TRAFFIC["bytes"].get(workload)
+
+
+def cpu_info():
+    """Host cores this process may use, nproc and the CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", usable) or usable)
+    return {"nproc": os.cpu_count(), "usable": usable, "omp_threads": min(threads, usable),
+            "model": model}
 
 
 def log(msg):
@@ -81,14 +106,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--cpu-chains", type=int, default=10000,
+    ap.add_argument("--cpu-chains", type=int, default=1000,
                     help="chains in the oracle's timed sample epoch")
-    ap.add_argument("--workload", default="protein",
+    ap.add_argument("--no-oracle-errors", action="store_true",
+                    help="precision: skip the FP64 oracle entries of the statistics errors")
+    ap.add_argument("--no-protein", action="store_true",
+                    help="precision: skip the protein-scale context figures")
+    ap.add_argument("--workload", default="precision",
                     choices=["protein", "small", "precision", "scoring", "group", "serve", "next"],
-                    help="protein: one model at protein scale (default); small: the whole "
+                    help="precision (default): training epochs at L=256, M=1e5 weighted rows, "
+                         "N=2e4 chains, FP32 form timed, BF16 hi+lo beside it, statistics "
+                         "errors vs the FP64 oracle; protein: one model at protein scale; "
+                         "small: the whole "
                          "plain-bmDCA run at CPU-seconds size (L=20) on the GPU and in the "
-                         "oracle; precision: BF16 hi+lo "
-                         "vs FP32 statistics at L=256, M=1e5 and the epoch at N=2e4; scoring: "
+                         "oracle; scoring: "
                          "reweighting at M=1e5 and energies, mutant scans, contact scores of an "
                          "L=512 model; group: 64 "
                          "uneven models trained together in one captured graph per epoch; "
@@ -128,18 +159,19 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the "
                                    "library has no multi-GPU path)"}))
         sys.exit(2)
-    if args.workload == "small":
-        return bench_small(args)
-    if args.workload == "next":
-        return bench_next(args)
-    if args.workload == "precision":
-        return bench_precision(args)
-    if args.workload == "scoring":
-        return bench_scoring(args)
-    if args.workload == "group":
-        return bench_group(args)
-    if args.workload == "serve":
-        return bench_serve(args)
+    fn = {"precision": bench_precision_epoch, "protein": bench_protein, "small": bench_small,
+          "next": bench_next, "scoring": bench_scoring, "group": bench_group,
+          "serve": bench_serve}[args.workload]
+    return fn(args)
+
+
+def bench_protein(args, emit=True):
+    """Protein scale: L = 100, q = 21, N = 10 000 chains, planted sparse-contact
+    model (3L random pairs with N(0, 0.5) blocks, gap holding 15% of the
+    independent-site mass), M = 20 000 sequences drawn from it by 200 Gibbs
+    sweeps and reweighted at 80% identity, FP32 statistics.  One step = one
+    epoch.  With emit=False returns the line's dict (the default workload
+    reports it as context)."""
     import numpy as np
     import torch
 
@@ -147,14 +179,8 @@ def main():
     from paper_2501_18456_amd import _lib as B
 
     torch.cuda.set_device(0)
-    if args.profile_copy_mib:
-        # a copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the others
-        n = args.profile_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    if emit:
+        calibration_copy(args)
     L, q, N, M, sweeps, lr = 100, 21, 10000, 20000, 10, 0.05
     Lq = L * q
     seed_model, seed_msa, seed_chain = 1002, 2002, 3002
@@ -178,7 +204,7 @@ def main():
     log(f"reweight {rw_ms:.2f} ms, M_eff={float(meff.cpu()[0]):.1f}; stats {st_ms:.2f} ms")
 
     # initial model: independent-site fields log f_i(a), no couplings
-    h = torch.log(f1).to(torch.float32).reshape(L, q).contiguous()
+    h = api.profile_fields(f1, L, q)
     J = torch.zeros((Lq, Lq), dtype=torch.float32, device="cuda")
     chains = api.init_chains(N, L, q, seed=seed_chain)
     h0, J0, c0 = h.clone(), J.clone(), chains.clone()
@@ -289,13 +315,13 @@ def main():
                    "stats_precision": args.prec, "reweight_identity": 0.8},
         "roofline": {"kernel": "k_gibbs_gather (Gibbs sweeps, gather form)", "bound": "lds",
                      "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",
-                     "frac": lds_gbs / lds_peak, "traffic": gather_traffic(),
+                     "frac": lds_gbs / lds_peak, "traffic": gather_traffic("protein"),
                      "launch_ms": g_ms, "alg_bytes_per_launch": lds_bytes},
         "extras": extras,
     }
 
     # ---------------- oracle on the host cores (bounded sample)
-    if not args.no_cpu_baseline:
+    if emit and not args.no_cpu_baseline:
         from oracle import oracle as O
         n_s = min(args.cpu_chains, N)
         hh, JJ = h0.cpu().numpy(), J0.cpu().numpy()
@@ -310,7 +336,9 @@ def main():
                                "sample": f"one epoch of the same workload with {n_s} of the "
                                          f"{N} chains ({cpu_s:.1f} s, single thread)"}
         log(f"oracle: {cpu_s:.1f} s")
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_small(args):
@@ -578,10 +606,35 @@ def bench_next(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_precision(args):
-    """Precision form: the weighted two-site statistics product in BF16 hi+lo
-    against FP32 (L = 256, q = 21, M = 100 000 rows with weights in (0, 1]),
-    and the training epoch in both forms at N = 20 000 chains."""
+def calibration_copy(args):
+    """A plain device copy of known size first, when asked: its FETCH_SIZE /
+    WRITE_SIZE counters scale the sweep kernel's in the same profiled run."""
+    import torch
+    if args.profile_copy_mib:
+        n = args.profile_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
+def stats_product_flops(M, Lq, prec):
+    """Dense MFMA work of the statistics product: 128-wide output tiles on or
+    above the diagonal (64 x 128 for BF16 hi+lo, two products), K = M rows
+    padded to 64."""
+    Mpad = -(-M // 64) * 64
+    if prec == "bf16x2":
+        tiles64 = sum(-(-Lq // 128) - (ti * 64) // 128 for ti in range(-(-Lq // 64)))
+        return 2.0 * 2 * Mpad * 64 * 128 * tiles64
+    tiles128 = (-(-Lq // 128)) * (-(-Lq // 128) + 1) // 2
+    return 2.0 * Mpad * 128 * 128 * tiles128
+
+
+def bench_precision_epoch(args):
+    """The precision form (the default line): training epochs at L = 256,
+    q = 21, N = 20 000 chains on an alignment of M = 100 000 weighted
+    sequences; FP32 form timed for `value`, BF16 hi+lo beside it."""
     import numpy as np
     import torch
 
@@ -589,117 +642,223 @@ def bench_precision(args):
     from paper_2501_18456_amd import _lib as B
 
     torch.cuda.set_device(0)
+    calibration_copy(args)
     L, q, M, N, sweeps, lr = 256, 21, 100000, 20000, 10, 0.05
     Lq = L * q
-    h_true, J_true = synth.planted_dense(L, q, seed=1003, sigma_J=0.05)
-    ht, Jt = torch.from_numpy(h_true).cuda(), torch.from_numpy(J_true).cuda()
-    msa = api.init_chains(M, L, q, seed=2003)
-    api.gibbs(ht, Jt, msa, sweeps=50, seed=2003)
-    w = torch.from_numpy(synth.weights_open_unit(M, 4003)).cuda()
+    seed_chain = 3003
+    t_in = time.perf_counter()
+    X_h = synth.clustered_msa(M, L, q, seed=2003, n_families=200, mut_rate=0.3)
+    w_h = synth.weights_open_unit(M, 4003)
+    msa = torch.from_numpy(X_h).cuda()
+    w = torch.from_numpy(w_h).cuda()
     torch.cuda.synchronize()
-    log(f"precision form: L={L} q={q} M={M} (50 sweeps of a planted model), weights in (0, 1]")
+    log(f"precision form: L={L} q={q} M={M} (phylogeny-like alignment, weights 1 - U[0,1)) "
+        f"N={N} sweeps={sweeps}; inputs {time.perf_counter() - t_in:.1f} s")
     t = Timer()
-    res, ms = {}, {}
+    extras = {}
+
+    # ---------------- weighted two-site statistics, both forms (run once per training)
+    stats, st_ms, st_tf, st_frac = {}, {}, {}, {}
+    peaks = {"bf16x2": 2500.0, "fp32": 157.3}
     for prec in ("bf16x2", "fp32"):
         ws = api.workspace(B.WS_STATS, M, L, q, prec)
         out = (torch.empty(Lq, dtype=torch.float64, device="cuda"),
                torch.empty((Lq, Lq), dtype=torch.float64, device="cuda"),
                torch.empty(1, dtype=torch.float64, device="cuda"))
         api.stats(msa, q, w, -1.0, prec, ws=ws, out=out)
+        reps = max(3, min(args.steps, 10))
         t.start()
-        for _ in range(args.steps):
+        for _ in range(reps):
             api.stats(msa, q, w, -1.0, prec, ws=ws, out=out)
-        ms[prec] = t.stop_ms() / args.steps
-        res[prec] = (out[0].clone(), out[1].clone())
-        del ws, out
+        st_ms[prec] = t.stop_ms() / reps
+        st_tf[prec] = stats_product_flops(M, Lq, prec) / (st_ms[prec] * 1e-3) / 1e12
+        st_frac[prec] = st_tf[prec] / peaks[prec]
+        stats[prec] = out
+        del ws
         torch.cuda.empty_cache()
-    d1 = float((res["bf16x2"][0] - res["fp32"][0]).abs().max())
-    d2 = float((res["bf16x2"][1] - res["fp32"][1]).abs().max())
-    # dense MFMA work of the product: 128-wide (64 x 128 for hi+lo) tiles on or
-    # above the diagonal, K = M rows padded to 64, hi and lo products
-    Mpad = -(-M // 64) * 64
-    tiles64 = sum(-(-Lq // 128) - (ti * 64) // 128 for ti in range(-(-Lq // 64)))
-    flops_bf16 = 2.0 * 2 * Mpad * 64 * 128 * tiles64
-    tiles128 = (-(-Lq // 128)) * (-(-Lq // 128) + 1) // 2
-    flops_fp32 = 2.0 * Mpad * 128 * 128 * tiles128
-    tf_bf16 = flops_bf16 / (ms["bf16x2"] * 1e-3) / 1e12
-    tf_fp32 = flops_fp32 / (ms["fp32"] * 1e-3) / 1e12
-    log(f"stats bf16x2 {ms['bf16x2']:.2f} ms ({tf_bf16:.0f} TFLOP/s tile-level), fp32 "
-        f"{ms['fp32']:.2f} ms ({tf_fp32:.0f} TFLOP/s); max |bf16x2 - fp32| f1 {d1:.2e} f2 {d2:.2e}")
-    f1, f2 = res["bf16x2"]
-    del res
-    torch.cuda.empty_cache()
-    epoch_ms = {}
+    # error against the FP64 oracle: every f1 entry and 2000 sampled f2 entries
+    err = {}
+    if not args.no_oracle_errors:
+        from oracle import oracle as O
+        g = np.random.default_rng(8)
+        r1, r2 = g.integers(0, Lq, 2000), g.integers(0, Lq, 2000)
+        d = np.arange(Lq)
+        t1 = time.perf_counter()
+        ref1 = O.stats_entries(X_h, q, d, d, w_h, -1.0)
+        ref2 = O.stats_entries(X_h, q, r1, r2, w_h, -1.0)
+        sel = torch.from_numpy(r1 * Lq + r2).cuda()
+        for prec, (f1p, f2p, _) in stats.items():
+            g1 = f1p.cpu().numpy()
+            g2 = f2p.reshape(-1)[sel].cpu().numpy()
+            nz1, nz2 = ref1 != 0, ref2 != 0
+            err[prec] = {"f1_maxabs": float(np.abs(g1 - ref1).max()),
+                         "f1_maxrel": float((np.abs(g1 - ref1)[nz1] / np.abs(ref1[nz1])).max()),
+                         "f2_maxabs": float(np.abs(g2 - ref2).max()),
+                         "f2_maxrel": float((np.abs(g2 - ref2)[nz2] / np.abs(ref2[nz2])).max()),
+                         "entries": {"f1": int(Lq), "f2": 2000},
+                         "f2_zero_entries_exact": bool((g2[~nz2] == 0).all())}
+        log(f"oracle entries for the statistics errors: {time.perf_counter() - t1:.1f} s")
     for prec in ("bf16x2", "fp32"):
-        h = torch.log(f1).to(torch.float32).reshape(L, q).contiguous()
+        e = err.get(prec, {})
+        log(f"stats {prec}: {st_ms[prec]:.2f} ms, {st_tf[prec]:.0f} TFLOP/s dense tile work "
+            f"({100 * st_frac[prec]:.0f}% of {peaks[prec]:.0f}); max |f - f_FP64| "
+            f"f1 {e.get('f1_maxabs', float('nan')):.2e} f2 {e.get('f2_maxabs', float('nan')):.2e}")
+    extras["stats"] = {"ms": st_ms, "tflops": st_tf, "mfma_frac": st_frac,
+                       "peak_tflops": peaks, "error_vs_fp64_oracle": err,
+                       "alg_flops_per_call": {p: stats_product_flops(M, Lq, p) for p in peaks}}
+
+    # ---------------- training epochs: FP32 form timed for `value`, then BF16 hi+lo
+    epoch_ms, pear, flipf = {}, {}, {}
+    for prec in ("fp32", "bf16x2"):
+        f1, f2, _ = stats[prec]
+        h = api.profile_fields(f1, L, q)
         J = torch.zeros((Lq, Lq), dtype=torch.float32, device="cuda")
-        ch = api.init_chains(N, L, q, seed=3003)
+        ch = api.init_chains(N, L, q, seed=seed_chain)
         wst = api.workspace(B.WS_TRAIN_STEP, N, L, q, prec)
+        pearson = torch.zeros(1, dtype=torch.float64, device="cuda")
+        flips = torch.zeros(1, dtype=torch.int64, device="cuda")
+        derr = torch.zeros(1, dtype=torch.int32, device="cuda")
         for ep in range(args.warmup):
-            api.train_step(h, J, ch, f1, f2, lr, sweeps, 3003, ep, prec, wst)
+            api.train_step(h, J, ch, f1, f2, lr, sweeps, seed_chain, ep, prec, wst, pearson,
+                           flips, derr)
+        flips.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            api.train_step(h, J, ch, f1, f2, lr, sweeps, 3003, args.warmup + k, prec, wst)
+            api.train_step(h, J, ch, f1, f2, lr, sweeps, seed_chain, args.warmup + k, prec, wst,
+                           pearson, flips, derr)
         torch.cuda.synchronize()
         epoch_ms[prec] = (time.perf_counter() - t0) * 1e3 / args.steps
+        pear[prec] = float(pearson.item())
+        flipf[prec] = float(flips.item()) / (N * L * sweeps * args.steps)
+        assert int(derr.item()) == 0, "device error flag raised"
+        log(f"epoch {prec}: {epoch_ms[prec]:.2f} ms ({N * L * sweeps / (epoch_ms[prec] * 1e-3):.3e} "
+            f"site-updates/s), flip fraction {flipf[prec]:.3f}, pearson {pear[prec]:.4f}")
+        if prec == "fp32":
+            h_run, J_run, ch_run = h, J, ch
+        else:
+            del h, J, ch
         del wst
         torch.cuda.empty_cache()
-    value = N * L * sweeps / (epoch_ms["bf16x2"] * 1e-3)
-    log(f"epoch bf16x2 {epoch_ms['bf16x2']:.1f} ms, fp32 {epoch_ms['fp32']:.1f} ms")
-    # the two sweep kernels at this size: H = N Lq 4 bytes = 430 MB, beyond the
-    # 256 MB last-level cache, so the field form's H traffic is HBM traffic
-    h = torch.log(f1).to(torch.float32).reshape(L, q).contiguous()
-    J = (0.05 * torch.randn((Lq, Lq), device="cuda", generator=torch.Generator("cuda").manual_seed(5)))
-    J = ((J + J.T) * 0.5).contiguous()
-    for i in range(L):
-        J[i * q:(i + 1) * q, i * q:(i + 1) * q] = 0.0
-    ch = api.init_chains(N, L, q, seed=3005)
-    Hf = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
-    api.gibbs(h, J, ch, 1, 3005, H_ws=Hf, sampler="fields")
+    value = N * L * sweeps / (epoch_ms["fp32"] * 1e-3)
+    extras["epoch_ms"] = epoch_ms
+    extras["site_updates_per_s"] = {p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()}
+    extras["mixed_speedup_over_fp32"] = epoch_ms["fp32"] / epoch_ms["bf16x2"]
+    extras["pearson_after"] = pear
+    extras["flip_fraction"] = flipf
+
+    # ---------------- the sweep kernels alone on the trained model and its chains
+    reps = 5
+    visits = N * L * sweeps
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    ck = ch_run.clone()
+    Wg = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_GATHER)
+    api.gibbs(h_run, J_run, ck, 1, seed_chain, sweep_offset=10**6 - 1, H_ws=Wg, sampler="gather")
+    t.start()
+    for r in range(reps):
+        api.gibbs(h_run, J_run, ck, sweeps, seed_chain, sweep_offset=10**6 + r * sweeps, H_ws=Wg,
+                  sampler="gather")
+    g_all = t.stop_ms() / reps
+    t.start()
+    for r in range(reps):  # the per-call coupling re-layout alone
+        api.gibbs(h_run, J_run, ck, 0, seed_chain, H_ws=Wg, sampler="gather")
+    g_fix = t.stop_ms() / reps
+    g_ms = g_all - g_fix
+    lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
+    lds_gbs = lds_bytes / (g_ms * 1e-3) / 1e9
+    lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9
+    log(f"gather sweep kernel: {g_ms:.2f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms "
+        f"re-layout), {visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of "
+        f"{lds_peak:.0f}")
+    del Wg
+    ck = ch_run.clone()
+    H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
+    api.gibbs(h_run, J_run, ck, 0, seed_chain, H_ws=H, sampler="fields")
     kfl = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ks = 5
+    fs = 5  # sweeps
     t.start()
-    api.gibbs(h, J, ch, ks, 3005, sweep_offset=1, H_ws=Hf, flips=kfl, keep_fields=True,
-              sampler="fields")
+    api.gibbs(h_run, J_run, ck, fs, seed_chain, sweep_offset=2 * 10**6, H_ws=H, flips=kfl,
+              keep_fields=True, sampler="fields")
     f_ms = t.stop_ms()
-    flips = float(kfl.item())
-    visits = N * L * ks
-    fbytes = visits * 4 * q + flips * 8 * (Lq - q) + 2 * N * L
-    f_gbs = fbytes / (f_ms * 1e-3) / 1e9
-    Hg = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_GATHER)
-    api.gibbs(h, J, ch, 1, 3005, sweep_offset=100, H_ws=Hg, sampler="gather")
-    t.start()
-    api.gibbs(h, J, ch, ks, 3005, sweep_offset=101, H_ws=Hg, sampler="gather")
-    g_ms = t.stop_ms()
-    log(f"field form {ks} sweeps: {f_ms:.1f} ms, flip fraction {flips / visits:.3f}, "
-        f"{f_gbs:.0f} GB/s algorithmic HBM ({100 * f_gbs / HBM_PEAK_GBS:.0f}% of peak); "
-        f"gather form {g_ms:.1f} ms")
-    del Hf, Hg, ch, J
+    fv = N * L * fs
+    fl = float(kfl.item())
+    f_bytes = fv * 4 * q + fl * 8 * (Lq - q) + 2 * N * L
+    f_gbs = f_bytes / (f_ms * 1e-3) / 1e9
+    log(f"field sweep kernel: {f_ms:.1f} ms per {fs} sweeps, flip fraction {fl / fv:.3f}, "
+        f"algorithmic HBM {f_gbs:.0f} GB/s ({100 * f_gbs / HBM_PEAK_GBS:.0f}% of peak; H = "
+        f"{N * Lq * 4 / 1e6:.0f} MB, beyond the 256 MB last-level cache)")
+    del H
     torch.cuda.empty_cache()
+    extras["gather_kernel"] = {"ms_per_launch": g_ms, "sweeps_per_launch": sweeps,
+                               "relayout_ms": g_fix,
+                               "site_updates_per_s": visits / (g_ms * 1e-3),
+                               "alg_lds_bytes_per_launch": lds_bytes, "lds_GBps": lds_gbs,
+                               "lds_frac": lds_gbs / lds_peak}
+    extras["field_kernel"] = {"ms_per_launch": f_ms, "sweeps_per_launch": fs,
+                              "flip_fraction": fl / fv, "alg_hbm_bytes_per_launch": f_bytes,
+                              "alg_hbm_GBps": f_gbs, "hbm_frac": f_gbs / HBM_PEAK_GBS,
+                              "site_updates_per_s": fv / (f_ms * 1e-3),
+                              "traffic": gather_traffic("precision-fields")}
+
+    # ---------------- protein scale as context
+    if not args.no_protein:
+        del ch_run, J_run, h_run
+        torch.cuda.empty_cache()
+        pa = argparse.Namespace(**vars(args))
+        pa.steps, pa.warmup = 10, 2
+        po = bench_protein(pa, emit=False)
+        extras["protein_scale"] = {"config": po["config"], "ms_per_step": po["ms_per_step"],
+                                   "site_updates_per_s": po["value"],
+                                   "gather_kernel": po["extras"]["gather_kernel"],
+                                   "field_kernel": po["extras"]["field_kernel"],
+                                   "gather_traffic": po["roofline"]["traffic"]}
+
     out = {
         "metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": epoch_ms["bf16x2"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-        "data": "synthetic (planted dense Potts model; alignment sampled from it; "
-                "weights 1 - U[0,1))",
-        "config": {"workload": "precision form: weighted statistics at L=256, q=21, M=100000; "
-                               "epoch at N=20000", "L": L, "q": q, "msa_rows": M, "chains": N,
-                   "sweeps_per_step": sweeps},
-        "roofline": {"kernel": "bmdca_stats BF16 hi+lo (one-hot product and its epilogue)",
-                     "bound": "mfma", "achieved": tf_bf16, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": tf_bf16 / 2500.0, "traffic": None,
-                     "call_ms": ms["bf16x2"], "alg_flops_per_call": flops_bf16},
-        "extras": {"stats_ms": ms, "stats_fp32_tflops": tf_fp32,
-                   "stats_fp32_frac_of_157": tf_fp32 / 157.3,
-                   "bf16x2_vs_fp32_maxabs": {"f1": d1, "f2": d2},
-                   "epoch_ms": epoch_ms, "site_updates_per_s": {
-                       p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()},
-                   "field_kernel_5_sweeps": {"ms": f_ms, "flip_fraction": flips / visits,
-                                             "alg_hbm_GBps": f_gbs,
-                                             "hbm_frac": f_gbs / HBM_PEAK_GBS},
-                   "gather_kernel_5_sweeps_ms": g_ms},
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": epoch_ms["fp32"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (phylogeny-like alignment of seeded ancestors and mutations; "
+                "weights 1 - U[0,1); model trained from the profile start)",
+        "config": {"workload": "precision form: bmDCA training epoch at L=256, q=21, "
+                               "M=100000 weighted rows, N=20000 chains",
+                   "L": L, "q": q, "msa_rows": M, "chains": N, "sweeps_per_step": sweeps,
+                   "lr": lr, "step_form": "fp32 (BF16 hi+lo epoch in extras)"},
+        "roofline": {"kernel": "k_gibbs_gather (Gibbs sweeps, gather form)", "bound": "lds",
+                     "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",
+                     "frac": lds_gbs / lds_peak, "traffic": gather_traffic("precision"),
+                     "launch_ms": g_ms, "alg_bytes_per_launch": lds_bytes},
+        "extras": extras,
     }
+
+    # ---------------- oracle on the host cores (bounded sample, extrapolated)
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        info = cpu_info()
+        n_s = min(args.cpu_chains, N)
+        f1, f2, _ = stats["fp32"]
+        F1, F2 = f1.cpu().numpy(), f2.cpu().numpy()
+        hh = np.log(F1).astype(np.float32).reshape(L, q)
+        JJ = np.zeros((Lq, Lq), np.float32)
+        cc = O.init_chains(n_s, L, q, seed_chain)
+        res = {}
+        for label, threads in (("single_thread", False), ("all_cores", True)):
+            log(f"oracle sample epoch ({label}): {n_s} of {N} chains ...")
+            t1 = time.perf_counter()
+            O.train_step(hh, JJ, cc, F1, F2, q, lr, sweeps, seed_chain, 0, threads=threads)
+            cpu_s = time.perf_counter() - t1
+            res[label] = {"value": n_s * L * sweeps / cpu_s, "seconds": cpu_s,
+                          "cores": info["omp_threads"] if threads else 1}
+            log(f"oracle ({label}): {cpu_s:.1f} s")
+        allc = res["all_cores"]
+        out["cpu_baseline"] = {
+            "value": allc["value"], "unit": "site-updates/s", "cores": allc["cores"],
+            "kind": "oracle",
+            "sample": f"one epoch (10 sweeps, chain statistics, Pearson, update) of {n_s} of the "
+                      f"{N} chains at L={L}, q={q}, timed and extrapolated per site-update "
+                      f"({allc['seconds']:.1f} s on {allc['cores']} threads; single thread "
+                      f"{res['single_thread']['seconds']:.1f} s)",
+            "extrapolated": True, "single_thread": res["single_thread"],
+            "nproc": info["nproc"], "usable_cores": info["usable"], "cpu_model": info["model"]}
     print(json.dumps(out), flush=True)
 
 

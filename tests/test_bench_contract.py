@@ -24,7 +24,15 @@ def test_traffic_follows_the_source_digest(monkeypatch):
     for f in bench.GATHER_TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    monkeypatch.setattr(bench, "GATHER_TRAFFIC", {"sha256": h.hexdigest(), "bytes": 123.0})
-    assert bench.gather_traffic() == 123.0
-    monkeypatch.setattr(bench, "GATHER_TRAFFIC", {"sha256": "0" * 64, "bytes": 123.0})
-    assert bench.gather_traffic() is None
+    monkeypatch.setattr(bench, "GATHER_TRAFFIC", {"sha256": h.hexdigest(),
+                                                  "bytes": {"precision": 123.0}})
+    assert bench.gather_traffic("precision") == 123.0
+    assert bench.gather_traffic("protein") is None
+    monkeypatch.setattr(bench, "GATHER_TRAFFIC", {"sha256": "0" * 64,
+                                                  "bytes": {"precision": 123.0}})
+    assert bench.gather_traffic("precision") is None
+
+
+def test_cpu_info_names_the_host():
+    info = bench.cpu_info()
+    assert info["nproc"] >= 1 and 1 <= info["omp_threads"] <= info["usable"]
