@@ -1047,7 +1047,8 @@ def bench_group(args):
 
 def bench_serve(args):
     """Poisson request streams against 8 resident models at three rates: light
-    (0.3x), knee (0.8x) and saturating (1.3x) of the measured capacity."""
+    (0.3x), knee (0.8x) and saturating (1.3x) of the measured capacity.  Every
+    batch is one replay of its engine's captured graph."""
     import numpy as np
     import torch
 
@@ -1058,7 +1059,11 @@ def bench_serve(args):
     models = serve.resident_models(Ls, q)
     budget = int(args.serve_budget_gib * 2**30)
     mix = (0.4, 0.4, 0.2)
+    t0 = time.perf_counter()
     srv = serve.Server(models, budget, lanes=args.lanes, chunk_sweeps=args.serve_chunk)
+    log(f"engines: {len(srv.engines)} captured graphs, arenas {srv.stats.arena_bytes / 2**30:.2f} "
+        f"GiB of the {args.serve_budget_gib:.0f} GiB budget, built in "
+        f"{time.perf_counter() - t0:.1f} s")
     # warmup: every kind on every model once
     warm = serve.poisson_requests(48, 1e6, Ls, q, seed=7, mix=(1, 1, 1),
                                   energy_range=(1000, 2000), chain_range=(100, 200))
@@ -1067,7 +1072,7 @@ def bench_serve(args):
     # capacity: a burst of requests all present at once
     n_cap = max(100, args.serve_requests // 10)
     burst = serve.poisson_requests(n_cap, 1e6, Ls, q, seed=8, mix=mix)
-    srv = serve.Server(models, budget, lanes=args.lanes, chunk_sweeps=args.serve_chunk)
+    srv.reset_stats()
     t0 = time.perf_counter()
     srv.run(burst, realtime=False)
     cap = n_cap / (time.perf_counter() - t0)
@@ -1077,18 +1082,24 @@ def bench_serve(args):
     results = {}
     for k, (name, rate) in enumerate(rates.items()):
         reqs = serve.poisson_requests(args.serve_requests, rate, Ls, q, seed=100 + k, mix=mix)
-        srv = serve.Server(models, budget, lanes=args.lanes, chunk_sweeps=args.serve_chunk)
+        srv.reset_stats()
         t0 = time.perf_counter()
         srv.run(reqs, realtime=True)
         wall = time.perf_counter() - t0
         sm = serve.summarize(reqs)
+        st = srv.stats
+        n_req = len(reqs)
         sm.update({"offered_per_s": rate, "wall_s": wall,
-                   "peak_admitted_GiB": srv.stats.peak_bytes / 2**30,
-                   "launches": dict(srv.stats.launches), "batched": dict(srv.stats.batched)})
+                   "peak_admitted_GiB": st.peak_bytes / 2**30,
+                   "graph_launches": dict(st.launches), "eager_launches": dict(st.eager),
+                   "request_launches": dict(st.batched),
+                   "launches_per_request": (sum(st.launches.values()) +
+                                            sum(st.eager.values())) / n_req})
         results[name] = sm
         log(f"{name}: offered {rate:.1f}/s served {sm['requests_per_s']:.1f}/s; " + "; ".join(
             f"{kd} p50 {sm[kd]['p50_ms']:.1f} p99 {sm[kd]['p99_ms']:.1f} ms"
-            for kd in serve.KINDS if kd in sm))
+            for kd in serve.KINDS if kd in sm) +
+            f"; {sm['launches_per_request']:.2f} launches per request")
         del reqs
     sat = results["saturating"]
     out = {
@@ -1103,7 +1114,8 @@ def bench_serve(args):
                    "budget_GiB": args.serve_budget_gib, "lanes": args.lanes,
                    "chunk_sweeps": args.serve_chunk, "requests_per_rate": args.serve_requests},
         "roofline": None,
-        "extras": {"capacity_per_s": cap, "rates": results},
+        "extras": {"capacity_per_s": cap, "arena_GiB": srv.stats.arena_bytes / 2**30,
+                   "rates": results},
     }
     print(json.dumps(out), flush=True)
 

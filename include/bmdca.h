@@ -80,6 +80,11 @@ typedef enum {
                                      chains of a workgroup in lockstep */
 #define BMDCA_GIBBS_KEEP_FIELDS 0x40 /* field form only: H_ws already holds
                                         the fields of these chains */
+#define BMDCA_GIBBS_KEEP_LAYOUT 0x100 /* gather form only: H_ws already holds
+                                        the re-laid-out couplings of this J (left
+                                        by a previous call on the same buffers),
+                                        so the per-call copy is skipped -- for
+                                        repeated sampling of a fixed model */
 #define BMDCA_SAMPLER_METROPOLIS 0x80 /* single-site Metropolis instead of the
                                         heat-bath draw, in either form (with
                                         BMDCA_SAMPLER_FIELDS or _GATHER, or
@@ -479,6 +484,48 @@ int bmdca_single_mutant_scan(const float* h, const float* J, const int8_t* wt,
 int bmdca_apc_frobenius(const float* J, int32_t L, int32_t q, int32_t gap,
                         float* F, float* F_apc, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* ---- Serving forms: one launch shape, replayed as a HIP graph ----
+ *
+ * Sampling, scoring and mutant scans of resident trained models (Sec. 4.1,
+ * 4.3, 4.4) served to a stream of requests.  Each call below is sized once
+ * for a capacity `cap` of items in caller-owned arenas; the number of live
+ * items is read at run time from the device int64 *n_live (0 <= *n_live <=
+ * cap), which the caller writes before each launch.  Nothing else in the
+ * call changes between launches, so a call captured into a HIP graph can be
+ * replayed for every batch.  Items past *n_live are not touched; workgroups
+ * past it leave at once.  Every live item gets exactly the bits of the plain
+ * call (bmdca_energy, bmdca_single_mutant_scan, bmdca_gibbs), whatever else
+ * shares the batch. */
+
+/* bmdca_energy over seqs [cap][L] (first *n_live rows live); ws sized by
+ * bmdca_workspace_bytes(BMDCA_WS_ENERGY, cap, L, q, 0). */
+int bmdca_energy_batch(const float* h, const float* J, const int8_t* seqs, int64_t cap,
+                       const int64_t* n_live, int32_t L, int32_t q, float* E, void* ws,
+                       size_t ws_bytes, int32_t* dev_err, void* stream);
+
+/* bmdca_single_mutant_scan over wild types wt [cap][L] (first *n_live live);
+ * ws sized by bmdca_workspace_bytes(BMDCA_WS_MUTANT, cap, L, q, 0). */
+int bmdca_mutant_scan_batch(const float* h, const float* J, const int8_t* wt, int64_t cap,
+                            const int64_t* n_live, int32_t L, int32_t q, float* dE, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* One tick of continuous-batching sampling: the chains [0, *n_live) of the
+ * arena chains [cap][L] make `sweeps` sweeps in the gather form (heat-bath,
+ * or Metropolis with BMDCA_SAMPLER_METROPOLIS), chain c drawing exactly as
+ * chain streams[c].chain of a bmdca_gibbs call with key streams[c].seed and
+ * sweep offset streams[c].sweep_offset + (*tick) * sweeps; then *tick += 1
+ * (device uint64, caller-owned).  A request that joins the arena at tick T0
+ * with its own first sweep 0 therefore stores sweep_offset = -T0 * sweeps
+ * (mod 2^64), and after k ticks its chains equal its plain bmdca_gibbs call
+ * of k * sweeps sweeps.  With BMDCA_GIBBS_KEEP_LAYOUT the couplings are not
+ * re-laid out (ws holds them from a previous call with this J).  Needs the
+ * gather form (L <= 512, q <= 32); ws as bmdca_gibbs with
+ * BMDCA_SAMPLER_GATHER.  cus as bmdca_gibbs_streams. */
+int bmdca_sample_tick(const float* h, const float* J, int8_t* chains, int64_t cap,
+                      const int64_t* n_live, int32_t L, int32_t q, int32_t sweeps,
+                      const bmdca_chain_stream* streams, uint64_t* tick, float beta,
+                      float* ws, size_t ws_bytes, int32_t flags, int32_t cus, void* stream);
 
 /* ---- Equilibrium sampling (Sec. 4.1: sampling from a trained model) ----
  *

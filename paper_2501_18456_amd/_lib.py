@@ -16,6 +16,7 @@ OK, EINVAL, ETOKEN, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_BF16X2 = 0, 1
 DEVERR_TOKEN, DEVERR_NONFINITE, DEVERR_INDEX = 1, 2, 4
 SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS, SAMPLER_METROPOLIS = 0x10, 0x20, 0x40, 0x80
+GIBBS_KEEP_LAYOUT = 0x100
 SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER,
            "metropolis": SAMPLER_METROPOLIS,
            "metropolis-fields": SAMPLER_METROPOLIS | SAMPLER_FIELDS,
@@ -76,6 +77,10 @@ SIGNATURES = {
     "bmdca_decimate": (C.c_int, [_p, _p, _p, _i64, _i32, _i32, _f64, _f64, _p, _p, _sz, _p, _p]),
     "bmdca_activate": (C.c_int, [_p, _p, _i64, _i32, _i32, _p, _f64, _p, _p, _sz, _p, _p]),
     "bmdca_profile_fields": (C.c_int, [_p, _i32, _i32, _p, _p, _p]),
+    "bmdca_energy_batch": (C.c_int, [_p, _p, _p, _i64, _p, _i32, _i32, _p, _p, _sz, _p, _p]),
+    "bmdca_mutant_scan_batch": (C.c_int, [_p, _p, _p, _i64, _p, _i32, _i32, _p, _p, _sz, _p]),
+    "bmdca_sample_tick": (C.c_int, [_p, _p, _p, _i64, _p, _i32, _i32, _i32, _p, _p, _f32, _p,
+                                    _sz, _i32, _i32, _p]),
     "bmdca_mask_init": (C.c_int, [_p, _i32, _i32, _i32, _p]),
     "bmdca_mask_apply": (C.c_int, [_p, _p, _i32, _i32, _p, _p]),
     "bmdca_train_group_step": (C.c_int, [C.POINTER(TrainProblem), _i32, _i32, _p]),

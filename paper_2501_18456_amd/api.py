@@ -171,6 +171,48 @@ def gibbs_streams(h, J, chains, sweeps: int, streams, beta: float = 1.0, H_ws=No
     return chains
 
 
+# ------------------------------------------------------------ serving forms
+def energy_batch(h, J, seqs, n_live, E, ws, dev_err=None):
+    """bmdca_energy_batch: energies of the first *n_live rows of the arena
+    seqs [cap, L] into E [cap] (n_live: device int64 [1])."""
+    L, q = _model(h, J)
+    _dev(seqs, torch.int8, "seqs", 2)
+    _dev(n_live, torch.int64, "n_live")
+    check(B.lib().bmdca_energy_batch(_ptr(h), _ptr(J), _ptr(seqs), seqs.shape[0], _ptr(n_live),
+                                     L, q, _ptr(E), _ptr(ws), _nbytes(ws), _ptr(dev_err),
+                                     _stream()))
+    return E
+
+
+def mutant_scan_batch(h, J, wt, n_live, dE, ws):
+    """bmdca_mutant_scan_batch over the first *n_live wild types of wt [cap, L]."""
+    L, q = _model(h, J)
+    _dev(wt, torch.int8, "wt", 2)
+    _dev(n_live, torch.int64, "n_live")
+    check(B.lib().bmdca_mutant_scan_batch(_ptr(h), _ptr(J), _ptr(wt), wt.shape[0], _ptr(n_live),
+                                          L, q, _ptr(dE), _ptr(ws), _nbytes(ws), _stream()))
+    return dE
+
+
+def sample_tick(h, J, chains, n_live, sweeps: int, streams, tick, ws, beta: float = 1.0,
+                keep_layout: bool = True, cus: int = 0):
+    """bmdca_sample_tick: `sweeps` sweeps of the first *n_live chains of the
+    arena chains [cap, L] with per-chain streams, then tick += 1."""
+    L, q = _model(h, J)
+    _dev(chains, torch.int8, "chains", 2)
+    _dev(n_live, torch.int64, "n_live")
+    _dev(streams, torch.uint8, "streams", 1)
+    _dev(tick, torch.int64, "tick")
+    cap = chains.shape[0]
+    if streams.numel() != 24 * cap:
+        raise ValueError("streams must hold one 24-byte record per arena chain")
+    flags = B.GIBBS_KEEP_LAYOUT if keep_layout else 0
+    check(B.lib().bmdca_sample_tick(_ptr(h), _ptr(J), _ptr(chains), cap, _ptr(n_live), L, q,
+                                    sweeps, _ptr(streams), _ptr(tick), beta, _ptr(ws),
+                                    _nbytes(ws), flags, cus, _stream()))
+    return chains
+
+
 def energy(h, J, seqs, dev_err=None, out=None, ws=None):
     """Eq. (1) energies: float32 [B]."""
     L, q = _model(h, J)

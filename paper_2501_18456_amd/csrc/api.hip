@@ -102,7 +102,9 @@ TrainPlan plan_train(int64_t N, int L, int q, int prec) {
 int gibbs_impl(const float* h, const float* J, int8_t* chains, int64_t N, int32_t L, int32_t q,
                int32_t sweeps, uint64_t seed, uint64_t sweep_offset, float beta, float* H_ws,
                size_t H_ws_bytes, int32_t flags, unsigned long long* flips_out,
-               const DevCtl& ctl, hipStream_t s) {
+               const DevCtl& ctl_in, hipStream_t s) {
+  DevCtl ctl = ctl_in;
+  ctl.keep_layout = (flags & BMDCA_GIBBS_KEEP_LAYOUT) != 0;
   BMDCA_TRY(check_model(L, q));
   BMDCA_REQUIRE(h && J && chains, "null pointer argument");
   BMDCA_REQUIRE(N >= 1 && N <= (int64_t)1 << 31, "N=%lld outside 1..2^31", (long long)N);
@@ -111,6 +113,8 @@ int gibbs_impl(const float* h, const float* J, int8_t* chains, int64_t N, int32_
   const int gather = pick_gather(flags, L, q);
   BMDCA_REQUIRE(gather >= 0, "sampler flags 0x%x not usable for L=%d q=%d", flags, L, q);
   BMDCA_REQUIRE(H_ws, "H_ws is NULL");
+  BMDCA_REQUIRE(gather || !(flags & BMDCA_GIBBS_KEEP_LAYOUT),
+                "BMDCA_GIBBS_KEEP_LAYOUT needs the gather form");
   if (gather) {
     if (H_ws_bytes < gather_ws_bytes(L, q))
       return fail(BMDCA_EWORKSPACE, "gibbs workspace %zu < %zu bytes", H_ws_bytes,
@@ -490,6 +494,58 @@ int bmdca_energy_noalloc(const float* h, const float* J, const int8_t* seqs, int
   BMDCA_TRY(scratch_address(&ws));
   return hip_status(launch_energy(h, J, seqs, B, L, q, E, plan, ws, dev_err, (hipStream_t)stream),
                     "energy_noalloc");
+}
+
+int bmdca_energy_batch(const float* h, const float* J, const int8_t* seqs, int64_t cap,
+                       const int64_t* n_live, int32_t L, int32_t q, float* E, void* ws,
+                       size_t ws_bytes, int32_t* dev_err, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(cap >= 1 && cap <= (int64_t)1 << 31, "cap=%lld outside 1..2^31", (long long)cap);
+  BMDCA_REQUIRE(h && J && seqs && E && ws && n_live, "null pointer argument");
+  const EnergyPlan plan = plan_energy(cap, L, q);
+  if (ws_bytes < plan.total)
+    return fail(BMDCA_EWORKSPACE, "energy workspace %zu < %zu bytes", ws_bytes, plan.total);
+  return hip_status(launch_energy(h, J, seqs, cap, L, q, E, plan, ws, dev_err,
+                                  (hipStream_t)stream, n_live),
+                    "energy_batch");
+}
+
+int bmdca_mutant_scan_batch(const float* h, const float* J, const int8_t* wt, int64_t cap,
+                            const int64_t* n_live, int32_t L, int32_t q, float* dE, void* ws,
+                            size_t ws_bytes, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(cap >= 1 && cap <= (int64_t)1 << 31, "cap=%lld outside 1..2^31", (long long)cap);
+  BMDCA_REQUIRE(h && J && wt && dE && ws && n_live, "null pointer argument");
+  if (ws_bytes < gibbs_bytes(cap, L, q))
+    return fail(BMDCA_EWORKSPACE, "mutant workspace %zu < %zu bytes", ws_bytes,
+                gibbs_bytes(cap, L, q));
+  hipStream_t s = (hipStream_t)stream;
+  float* H = static_cast<float*>(ws);
+  BMDCA_TRY(hip_status(launch_local_fields(h, J, wt, cap, L, q, H, nullptr, s, nullptr, n_live),
+                       "mutant_batch/fields"));
+  return hip_status(launch_mutant_delta(H, wt, cap, L, q, dE, s, n_live), "mutant_batch/delta");
+}
+
+int bmdca_sample_tick(const float* h, const float* J, int8_t* chains, int64_t cap,
+                      const int64_t* n_live, int32_t L, int32_t q, int32_t sweeps,
+                      const bmdca_chain_stream* streams, uint64_t* tick, float beta,
+                      float* ws, size_t ws_bytes, int32_t flags, int32_t cus, void* stream) {
+  BMDCA_TRY(check_model(L, q));
+  BMDCA_REQUIRE(streams && tick && n_live, "null pointer argument");
+  BMDCA_REQUIRE(cus >= 0, "cus=%d negative", cus);
+  BMDCA_REQUIRE(gather_supported(L, q), "sample_tick needs the gather form (L=%d q=%d)", L, q);
+  BMDCA_REQUIRE((flags & ~(BMDCA_GIBBS_KEEP_LAYOUT | BMDCA_SAMPLER_METROPOLIS |
+                           BMDCA_SAMPLER_GATHER)) == 0,
+                "sample_tick flags 0x%x: only KEEP_LAYOUT, METROPOLIS, GATHER", flags);
+  DevCtl ctl;
+  ctl.streams = reinterpret_cast<const ChainStream*>(streams);
+  ctl.cu_share = cus;
+  ctl.epoch = tick;
+  ctl.count = n_live;
+  hipStream_t s = (hipStream_t)stream;
+  BMDCA_TRY(gibbs_impl(h, J, chains, cap, L, q, sweeps, 0, 0, beta, ws, ws_bytes,
+                       flags | BMDCA_SAMPLER_GATHER, nullptr, ctl, s));
+  return hip_status(launch_tick_advance(tick, s), "sample_tick/advance");
 }
 
 int bmdca_draw_rows(const double* w, int64_t M, int64_t n, uint64_t seed, int32_t* rows,

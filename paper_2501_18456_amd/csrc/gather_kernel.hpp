@@ -152,8 +152,14 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     int64_t N, int L, int jc, int nchunk, int m4, int ahead, int nload, int slot, int cpb,
     int sweeps, uint32_t k0, uint32_t k1, uint64_t sweep_offset, float beta,
     unsigned long long* flips_out, int32_t* dev_err, const uint64_t* __restrict__ epoch,
-    const int32_t* __restrict__ run, const ChainStream* __restrict__ streams) {
+    const int32_t* __restrict__ run, const ChainStream* __restrict__ streams,
+    const int64_t* __restrict__ count) {
   if (run && *run == 0) return;  // whole grid leaves before any barrier
+  if (count) {  // live chains of a launch sized for N
+    const int64_t live = *count;
+    if (live < N) N = live;
+  }
+  if ((int64_t)blockIdx.x * cpb >= N) return;  // whole workgroup, before any barrier
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   constexpr int QP = gather_qp(Q), NQ = QP / 4, V = gather_v(Q), S = gather_s(Q, LPC);
   constexpr int vL = (Q - 1) / 4, eL = (Q - 1) % 4;  // lane and slot of state q-1
@@ -560,7 +566,7 @@ hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
   hipLaunchKernelGGL(kern, dim3(gs.blocks), dim3(gs.waves * 64), gs.lds, a.s, a.h, a.Jt, a.chains,
                      a.N, a.L, gs.jc, gs.nchunk, gs.m4, gs.ahead, gs.nload, gs.slot, gs.cpb,
                      a.sweeps, (uint32_t)a.seed, (uint32_t)(a.seed >> 32), a.sweep_offset, a.beta,
-                     a.flips_out, a.dev_err, ctl.epoch, ctl.active, ctl.streams);
+                     a.flips_out, a.dev_err, ctl.epoch, ctl.active, ctl.streams, ctl.count);
   return hipGetLastError();
 }
 

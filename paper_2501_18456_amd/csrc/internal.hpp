@@ -24,15 +24,19 @@ struct DevCtl {
   const int32_t* active = nullptr;  // *active == 0: the kernel returns at once
   int cu_share = 0;                 // CUs the sampler grid is sized for (0: all)
   const ChainStream* streams = nullptr;  // per-chain random streams (sampler)
+  const int64_t* count = nullptr;   // live chains: only chains < min(N, *count) are swept
+  bool keep_layout = false;         // gather form: the workspace already holds the
+                                    // re-laid-out couplings of this J
 };
 
 // ----- sampler.hip
 hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t seed,
                               hipStream_t s);
 // H[c][r] = h[r] + sum_{k != r/q} J[(k, chains[c][k])][r] for c < N.
+// count (optional, device): only chains < min(N, *count).
 hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
                                int L, int q, float* H, int32_t* dev_err, hipStream_t s,
-                               const int32_t* active = nullptr);
+                               const int32_t* active = nullptr, const int64_t* count = nullptr);
 hipError_t launch_gibbs_sweeps(const float* J, int8_t* chains, float* H, int64_t N, int L, int q,
                                int sweeps, uint64_t seed, uint64_t sweep_offset, float beta,
                                unsigned long long* flips_out, hipStream_t s,
@@ -68,8 +72,10 @@ StatsPlan plan_stats(int64_t M, int L, int q, int prec);
 
 // X [M][L] -> XT [L][Mpad] (Mpad a multiple of 64); padding rows and invalid
 // tokens become -1, invalid tokens also raise BMDCA_DEVERR_TOKEN.
+// count (optional, device): rows >= min(M, *count) are treated as padding.
 hipError_t launch_transpose_tokens(const int8_t* X, int64_t M, int L, int q, int8_t* XT,
-                                  int64_t Mpad, int32_t* dev_err, hipStream_t s);
+                                  int64_t Mpad, int32_t* dev_err, hipStream_t s,
+                                  const int64_t* count = nullptr);
 
 // Statistics product: partial planes P[s][Lq][Lq] (upper tiles only) of
 // sum_m w_m [x_mi == a][x_mj == b].  w == nullptr: unit weights.
@@ -98,6 +104,8 @@ hipError_t launch_update(float* h, float* J, const double* f1, const double* f2,
 // Group epoch epilogue of one model: if active, epoch += 1 and, with a
 // positive target, active = 0 once the Pearson coefficient reaches it.
 hipError_t launch_ctl_advance(void* ctl, const double* pearson, hipStream_t s);
+// *tick += 1 (one thread): the sweep counter of a replayed sampling launch.
+hipError_t launch_tick_advance(uint64_t* tick, hipStream_t s);
 // h = (float) log f1 (the profile model's fields).
 hipError_t launch_profile_fields(const double* f1, int L, int q, float* h, int32_t* dev_err,
                                  hipStream_t s);
@@ -122,11 +130,13 @@ struct EnergyPlan {
   size_t off_xt, off_part, total;
 };
 EnergyPlan plan_energy(int64_t B, int L, int q);
+// count (optional, device): only sequences < min(B, *count) are scored (the
+// launch is sized for B; E past the count is left as it is).
 hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int L,
                          int q, float* E, const EnergyPlan& plan, void* ws, int32_t* dev_err,
-                         hipStream_t s);
+                         hipStream_t s, const int64_t* count = nullptr);
 hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int L, int q,
-                               float* dE, hipStream_t s);
+                               float* dE, hipStream_t s, const int64_t* count = nullptr);
 size_t apc_ws_bytes(int L);
 hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fapc, void* ws,
                       hipStream_t s);

@@ -184,4 +184,13 @@ hipError_t launch_profile_fields(const double* f1, int L, int q, float* h, int32
   return hipGetLastError();
 }
 
+__global__ void k_tick_advance(uint64_t* __restrict__ tick) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *tick += 1;
+}
+
+hipError_t launch_tick_advance(uint64_t* tick, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick_advance, dim3(1), dim3(64), 0, s, tick);
+  return hipGetLastError();
+}
+
 }  // namespace bmdca

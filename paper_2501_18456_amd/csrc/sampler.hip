@@ -46,10 +46,12 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
                                                       const int8_t* __restrict__ chains, int64_t N,
                                                       int L, int q, float* __restrict__ H,
                                                       int32_t* dev_err,
-                                                      const int32_t* __restrict__ active) {
+                                                      const int32_t* __restrict__ active,
+                                                      const int64_t* __restrict__ count) {
   if (active && *active == 0) return;
-  extern __shared__ int rowbase[];  // L entries: (k*q + s_k)
   const int64_t c = blockIdx.x;
+  if (count && c >= *count) return;  // whole workgroup, before any barrier
+  extern __shared__ int rowbase[];  // L entries: (k*q + s_k)
   const int Lq = L * q;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     const int t = checked_token(chains[c * L + k], q, dev_err);
@@ -69,12 +71,12 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
 
 hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
                                int L, int q, float* H, int32_t* dev_err, hipStream_t s,
-                               const int32_t* active) {
+                               const int32_t* active, const int64_t* count) {
   const int Lq = L * q;
   const int bs = 256;
   dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, bs));
   hipLaunchKernelGGL(k_local_fields, grid, dim3(bs), sizeof(int) * L, s, h, J, chains, N, L, q, H,
-                     dev_err, active);
+                     dev_err, active, count);
   return hipGetLastError();
 }
 
@@ -231,7 +233,7 @@ hipError_t launch_gibbs_gather(const float* h, const float* J, int8_t* chains, i
                                unsigned long long* flips_out, int32_t* dev_err, void* ws,
                                hipStream_t s, const DevCtl& ctl, bool metropolis) {
   float* Jt = static_cast<float*>(ws);
-  {
+  if (!ctl.keep_layout) {
     const size_t total = (size_t)L * L * q * gather_qp(q);
     const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 65536);
     hipLaunchKernelGGL(k_gather_layout, dim3(nb), dim3(256), 0, s, J, L, q, Jt, ctl.active);

@@ -52,7 +52,10 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
                                                             const int8_t* __restrict__ XT,
                                                             int64_t Bpad, int64_t B, int L,
                                                             int64_t steps, int parts,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part,
+                                                            const int64_t* __restrict__ count) {
+  if (count && *count < B) B = *count;  // live sequences of a launch sized for B
+  if ((int64_t)blockIdx.x * kESeqBlock >= B) return;  // whole workgroup, before any barrier
   constexpr int kW = kEJC * Q;                                 // tile row length
   constexpr int kNV = (Q * kW + kEThreads - 1) / kEThreads;    // tile floats per thread
   __shared__ float tile[2][Q * kW];
@@ -153,7 +156,9 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
 
 __global__ void k_energy_finish(const float* __restrict__ h, const int8_t* __restrict__ XT,
                                 int64_t Bpad, int64_t B, int L, int q, int parts,
-                                const double* __restrict__ part, float* __restrict__ E) {
+                                const double* __restrict__ part, float* __restrict__ E,
+                                const int64_t* __restrict__ count) {
+  if (count && *count < B) B = *count;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   double acc = 0.0;
@@ -168,25 +173,26 @@ __global__ void k_energy_finish(const float* __restrict__ h, const int8_t* __res
 
 template <int Q>
 static void launch_energy_q(const float* J, const int8_t* XT, int64_t B, int L,
-                            const EnergyPlan& plan, double* part, hipStream_t s) {
+                            const EnergyPlan& plan, double* part, hipStream_t s,
+                            const int64_t* count) {
   const dim3 grid((unsigned)ceil_div(B, kESeqBlock), (unsigned)plan.parts);
   hipLaunchKernelGGL(k_energy_pairs<Q>, grid, dim3(kEThreads), 0, s, J, XT, plan.Bpad, B, L,
-                     plan.steps, plan.parts, part);
+                     plan.steps, plan.parts, part, count);
 }
 
 hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int64_t B, int L,
                          int q, float* E, const EnergyPlan& plan, void* ws, int32_t* dev_err,
-                         hipStream_t s) {
+                         hipStream_t s, const int64_t* count) {
   char* base = static_cast<char*>(ws);
   int8_t* XT = reinterpret_cast<int8_t*>(base + plan.off_xt);
   double* part = reinterpret_cast<double*>(base + plan.off_part);
-  hipError_t e = launch_transpose_tokens(seqs, B, L, q, XT, plan.Bpad, dev_err, s);
+  hipError_t e = launch_transpose_tokens(seqs, B, L, q, XT, plan.Bpad, dev_err, s, count);
   if (e != hipSuccess) return e;
   if (plan.parts > 0) {
     switch (q) {
 #define BMDCA_EQ(n)                                        \
   case n:                                                  \
-    launch_energy_q<n>(J, XT, B, L, plan, part, s); \
+    launch_energy_q<n>(J, XT, B, L, plan, part, s, count); \
     break;
       BMDCA_EQ(2) BMDCA_EQ(3) BMDCA_EQ(4) BMDCA_EQ(5) BMDCA_EQ(6) BMDCA_EQ(7) BMDCA_EQ(8)
       BMDCA_EQ(9) BMDCA_EQ(10) BMDCA_EQ(11) BMDCA_EQ(12) BMDCA_EQ(13) BMDCA_EQ(14) BMDCA_EQ(15)
@@ -201,7 +207,7 @@ hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_energy_finish, dim3((unsigned)ceil_div(B, 256)), dim3(256), 0, s, h, XT,
-                     plan.Bpad, B, L, q, plan.parts, part, E);
+                     plan.Bpad, B, L, q, plan.parts, part, E, count);
   return hipGetLastError();
 }
 
@@ -210,7 +216,9 @@ hipError_t launch_energy(const float* h, const float* J, const int8_t* seqs, int
 // wild type's local fields (h + sum_{j != i} J_ij(., wt_j)).
 // ---------------------------------------------------------------------------
 __global__ void k_mutant_delta(const float* __restrict__ H, const int8_t* __restrict__ wt,
-                               int64_t B, int L, int q, float* __restrict__ dE) {
+                               int64_t B, int L, int q, float* __restrict__ dE,
+                               const int64_t* __restrict__ count) {
+  if (count && *count < B) B = *count;
   const int64_t Lq = (int64_t)L * q;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * Lq) return;
@@ -224,10 +232,10 @@ __global__ void k_mutant_delta(const float* __restrict__ H, const int8_t* __rest
 }
 
 hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int L, int q,
-                               float* dE, hipStream_t s) {
+                               float* dE, hipStream_t s, const int64_t* count) {
   const int64_t total = B * (int64_t)L * q;
   hipLaunchKernelGGL(k_mutant_delta, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, H, wt,
-                     B, L, q, dE);
+                     B, L, q, dE, count);
   return hipGetLastError();
 }
 

@@ -101,9 +101,12 @@ StatsPlan plan_stats(int64_t M, int L, int q, int prec) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_transpose_tokens(const int8_t* __restrict__ X, int64_t M,
                                                           int L, int q, int8_t* __restrict__ XT,
-                                                          int64_t Mpad, int32_t* dev_err) {
+                                                          int64_t Mpad, int32_t* dev_err,
+                                                          const int64_t* __restrict__ count) {
   __shared__ int8_t t[64][65];
+  if (count && *count < M) M = *count;
   const int64_t m0 = (int64_t)blockIdx.x * 64;
+  if (m0 >= M) return;  // whole workgroup (its rows are not read), before the barrier
   const int i0 = blockIdx.y * 64;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
   for (int r = ty; r < 64; r += 4) {
@@ -128,9 +131,10 @@ __global__ __launch_bounds__(256) void k_transpose_tokens(const int8_t* __restri
 }
 
 hipError_t launch_transpose_tokens(const int8_t* X, int64_t M, int L, int q, int8_t* XT,
-                                  int64_t Mpad, int32_t* dev_err, hipStream_t s) {
+                                  int64_t Mpad, int32_t* dev_err, hipStream_t s,
+                                  const int64_t* count) {
   hipLaunchKernelGGL(k_transpose_tokens, dim3((unsigned)(Mpad / 64), (unsigned)ceil_div(L, 64)),
-                     dim3(256), 0, s, X, M, L, q, XT, Mpad, dev_err);
+                     dim3(256), 0, s, X, M, L, q, XT, Mpad, dev_err, count);
   return hipGetLastError();
 }
 
@@ -498,7 +502,7 @@ hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, i
   double* P = reinterpret_cast<double*>(base + plan.off_part);
 
   hipLaunchKernelGGL(k_transpose_tokens, dim3((unsigned)(plan.Mpad / 64), (unsigned)ceil_div(L, 64)),
-                     dim3(256), 0, s, X, M, L, q, XT, plan.Mpad, dev_err);
+                     dim3(256), 0, s, X, M, L, q, XT, plan.Mpad, dev_err, nullptr);
   hipLaunchKernelGGL(k_prep_weights, dim3((unsigned)ceil_div(plan.Mpad, 256)), dim3(256), 0, s, w,
                      M, plan.Mpad, whi, wlo, wf);
   switch (mode_of(prec, w != nullptr)) {

@@ -1,31 +1,38 @@
 """Request loop over resident trained models (scoring, mutant scans, sampling).
 
 Uses of a trained Potts model from Sec. 4 of the paper (energies of a sequence
-set, the single-mutant library, sampling) served to a stream of requests:
+set, Sec. 4.3; the single-mutant library, Sec. 4.4; sampling, Sec. 4.1)
+served to a stream of requests:
 
   - models stay resident in HBM (h, J as float32);
-  - admission by HBM footprint: a request is admitted, in arrival order, once
-    the memory its inputs, outputs and workspace need fits the budget beside
-    everything in flight; a request that can never fit is refused at once;
-  - continuous batching (iteration-level): each (kind, model) pair has at most
-    one launch in flight; when it is free, everything of that pair that is
-    ready goes out as one launch -- the admitted energy requests of the model
-    as one bmdca_energy call, its mutant scans as one
-    bmdca_single_mutant_scan call, and its sampling requests as one
-    bmdca_gibbs_streams call over all their chains for the next
-    `chunk_sweeps` sweeps (each chain keeps its own request's key, chain
-    index and sweep count).  Requests that arrive while a launch runs join
-    the next one, at the next chunk boundary for sampling;
-  - launches go to `lanes` streams (default priority) and overlap on the GPU;
-    every (kind, model) pair has a fixed lane, so a batch never waits on
-    another lane's work; completion is seen by polling events, results are
-    copied back on the lane that made them.
+  - every (kind, model) pair owns an engine: fixed device arenas (inputs,
+    outputs, workspace, a device work table) sized once from the HBM budget,
+    and ONE captured HIP graph of the library's serving call over the whole
+    arena (bmdca_energy_batch, bmdca_mutant_scan_batch, bmdca_sample_tick).
+    The live item count, and for sampling each chain's random stream, are
+    device data the host writes before a replay, so the same graph serves
+    every batch: one graph launch per batch;
+  - admission by HBM footprint: a request is admitted, in arrival order, into
+    its engine's arena once its items fit beside the ones in flight; a
+    request larger than its arena is refused at once;
+  - continuous batching (iteration-level): each engine has at most one
+    replay in flight; when it is free, every admitted request of that engine
+    that fits goes into the next replay.  Sampling runs in ticks of
+    `chunk_sweeps` sweeps over all live chains of the model: requests join at
+    the next tick, leave when their sweeps are done (their chains are copied
+    out and the arena compacted), and each chain draws with its own request's
+    key, chain index and sweep offset from the work table;
+  - engines run on `lanes` streams (default priority) and overlap on the GPU;
+    completion is seen by polling events, results come back through pinned
+    host buffers on the engine's stream.
 
 A request's result does not depend on what else is in flight: energies of a
-sequence are independent of the batch (fixed pair order per L), mutant scans
-are per wild type, and chunked sampling uses the counter-based draws of the
-whole request.  Every computation runs in the HIP library; this module only
-moves data and decides what to launch when.
+sequence are independent of the batch (pair order fixed by L), mutant scans
+are per wild type, and the gather-form sampler's draws depend only on the
+chain's stream record (its lanes per chain are fixed by q and the draw), so
+every result equals the plain library call made alone, bit for bit.  Every
+computation runs in the HIP library; this module moves data and decides
+what to launch when.
 """
 from __future__ import annotations
 
@@ -40,6 +47,9 @@ from . import _lib as B
 from . import api
 
 KINDS = ("energy", "mutant", "sample")
+# default arena capacities (items): two of the largest energy batches, a
+# batch of mutant scans, and the chains of several sampling requests
+DEFAULT_CAPS = {"energy": 200000, "mutant": 64, "sample": 65536}
 
 
 @dataclass
@@ -64,166 +74,289 @@ class Request:
     def latency(self) -> float:
         return self.t_done - self.arrival
 
+    @property
+    def items(self) -> int:
+        if self.kind == "energy":
+            return int(self.seqs.shape[0])
+        return 1 if self.kind == "mutant" else int(self.n_chains)
+
 
 @dataclass
 class _Live:
-    """An admitted request and its device buffers."""
+    """An admitted request: its pinned input and output, and its arena slot."""
     req: Request
-    lane: int
-    inp: torch.Tensor | None = None       # device input (sequences, wild type, chains)
-    host_in: torch.Tensor | None = None   # pinned input, alive until uploaded
-    host_out: torch.Tensor | None = None  # pinned result
-    dev_out: torch.Tensor | None = None   # device result, alive until copied
+    host_in: torch.Tensor | None = None
+    host_out: torch.Tensor | None = None
+    off: int = -1          # first arena item (sampling: while in the arena)
     done_sweeps: int = 0
-    busy: bool = False
-
-
-@dataclass
-class _Launch:
-    event: torch.cuda.Event
-    lives: list
-    kind: str
-    model: int
+    base: int = 0          # sampling: stream-record sweep offset (mod 2^64)
 
 
 @dataclass
 class Stats:
     peak_bytes: int = 0
-    launches: dict = field(default_factory=lambda: {k: 0 for k in KINDS})
-    batched: dict = field(default_factory=lambda: {k: 0 for k in KINDS})
+    arena_bytes: int = 0
+    launches: dict = field(default_factory=lambda: {k: 0 for k in KINDS})  # graph replays
+    batched: dict = field(default_factory=lambda: {k: 0 for k in KINDS})   # request-launches
+    eager: dict = field(default_factory=lambda: {k: 0 for k in KINDS})     # launches outside graphs
+
+
+class _Engine:
+    """Arena, work table and captured graph of one (kind, model)."""
+
+    def __init__(self, kind, h, J, cap, stream, chunk, cus, device):
+        self.kind, self.h, self.J, self.cap, self.stream = kind, h, J, int(cap), stream
+        L, q = api._model(h, J)
+        self.L, self.q, self.chunk = L, q, chunk
+        dev = device
+        self.n_live = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.n_host = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+        self.pending: list[_Live] = []   # admitted, waiting for the next replay
+        self.flight: list[_Live] = []    # in the replay in flight (sampling: the live set)
+        self.event = None
+        self.busy = False
+        if kind == "energy":
+            self.inp = torch.zeros((cap, L), dtype=torch.int8, device=dev)
+            self.out = torch.zeros(cap, dtype=torch.float32, device=dev)
+            self.ws = api.workspace(B.WS_ENERGY, cap, L, q, 0, dev)
+            call = lambda: api.energy_batch(h, J, self.inp, self.n_live, self.out, self.ws)
+        elif kind == "mutant":
+            self.inp = torch.zeros((cap, L), dtype=torch.int8, device=dev)
+            self.out = torch.zeros((cap, L * q), dtype=torch.float32, device=dev)
+            self.ws = api.workspace(B.WS_MUTANT, cap, L, q, 0, dev)
+            call = lambda: api.mutant_scan_batch(h, J, self.inp, self.n_live, self.out, self.ws)
+        else:
+            self.inp = torch.zeros((cap, L), dtype=torch.int8, device=dev)
+            self.scratch = torch.zeros((cap, L), dtype=torch.int8, device=dev)
+            self.table = torch.zeros(24 * cap, dtype=torch.uint8, device=dev)
+            self.rec_host = np.zeros(cap, dtype=[("seed", "<u8"), ("sweep_offset", "<u8"),
+                                                 ("chain", "<u4"), ("reserved", "<u4")])
+            self.table_host = torch.zeros(24 * cap, dtype=torch.uint8, pin_memory=True)
+            self.tick = torch.zeros(1, dtype=torch.int64, device=dev)
+            self.ticks = 0  # host mirror of the device tick
+            self.ws = api.workspace(B.WS_GIBBS, cap, L, q, B.SAMPLER_GATHER, dev)
+            self.dirty = 0  # first table record that changed since the last upload
+            with torch.cuda.stream(stream):
+                # lay the couplings out once; the graph then only sweeps
+                api.gibbs(h, J, self.inp[:1], 0, 0, H_ws=self.ws, sampler="gather")
+            call = lambda: api.sample_tick(h, J, self.inp, self.n_live, chunk, self.table,
+                                           self.tick, self.ws, keep_layout=True, cus=cus)
+        # one eager call (kernel loading, attributes), then the capture
+        stream.synchronize()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            call()
+            if kind == "sample":
+                self.tick.zero_()
+        stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=stream, capture_error_mode="thread_local"):
+            call()
+        torch.cuda.synchronize()
+
+    def item_bytes(self) -> int:
+        """Device bytes per arena item (the footprint unit of admission)."""
+        L, q = self.L, self.q
+        if self.kind == "energy":
+            return L + 4 + api.workspace_bytes(B.WS_ENERGY, 64, L, q, 0) // 64
+        if self.kind == "mutant":
+            return L + 8 * L * q
+        return 2 * L + 24
+
+    def arena_bytes(self) -> int:
+        tot = self.inp.numel() + self.ws.numel() * self.ws.element_size() + 16
+        if self.kind in ("energy", "mutant"):
+            tot += self.out.numel() * 4
+        else:
+            tot += self.scratch.numel() + self.table.numel()
+        return tot
+
+    def used(self) -> int:
+        return sum(lv.req.items for lv in self.pending + self.flight)
 
 
 class Server:
-    def __init__(self, models, budget_bytes: int, lanes: int = 4, chunk_sweeps: int = 5,
-                 sample_cus: int = 0, device="cuda"):
+    def reset_stats(self) -> None:
+        """Fresh counters for a new run on the same engines."""
+        arena = self.stats.arena_bytes
+        self.stats = Stats()
+        self.stats.arena_bytes = arena
+
+    def __init__(self, models, budget_bytes: int, lanes: int = 4, chunk_sweeps: int = 1,
+                 sample_cus: int = 0, caps=None, device="cuda"):
         """models: list of (h float32 [L, q], J float32 [Lq, Lq]) device tensors.
-        sample_cus: compute units a sampling launch is sized for (0: all)."""
+        Arenas of `caps` items per kind and model (scaled down to fit
+        `budget_bytes` in total); sample_cus: compute units a sampling tick
+        is sized for (0: all)."""
         self.models = []
         for h, J in models:
             L, q = api._model(h, J)
             self.models.append((h, J, L, q))
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_sweeps)
-        self.sample_cus = int(sample_cus)
         self.device = device
         self.lanes = [torch.cuda.Stream(device=device) for _ in range(lanes)]
         self.stats = Stats()
+        caps = dict(DEFAULT_CAPS, **(caps or {}))
+        # arena capacities: the requested ones, scaled down until every
+        # arena (inputs, outputs, workspace, work table) fits the budget
+        scale = 1.0
+        while True:
+            plan = {(k, m): self._cap(k, caps[k] * scale) for m in range(len(self.models))
+                    for k in KINDS}
+            total = sum(self._arena_bytes(k, m, c) for (k, m), c in plan.items())
+            if total <= self.budget or scale < 1e-4:
+                break
+            scale *= 0.9
+        self.engines = {}
+        for (k, m), cap in plan.items():
+            h, J = self.models[m][:2]
+            s = self.lanes[(len(KINDS) * m + KINDS.index(k)) % len(self.lanes)]
+            self.engines[(k, m)] = _Engine(k, h, J, cap, s, self.chunk, sample_cus, device)
+        self.stats.arena_bytes = sum(e.arena_bytes() for e in self.engines.values())
+
+    @staticmethod
+    def _cap(kind: str, c: float) -> int:
+        c = max(1, int(c))
+        return max(64, c // 64 * 64) if kind == "energy" else c
+
+    def _arena_bytes(self, kind: str, m: int, cap: int) -> int:
+        """Device bytes of one engine's arena (as _Engine allocates it)."""
+        L, q = self.models[m][2:]
+        if kind == "energy":
+            return cap * L + 4 * cap + api.workspace_bytes(B.WS_ENERGY, cap, L, q, 0) + 16
+        if kind == "mutant":
+            return cap * L + 4 * cap * L * q + api.workspace_bytes(B.WS_MUTANT, cap, L, q, 0) + 16
+        return (2 * cap * L + 24 * cap + 16 +
+                api.workspace_bytes(B.WS_GIBBS, cap, L, q, B.SAMPLER_GATHER))
 
     # ------------------------------------------------------------ footprints
     def footprint(self, r: Request) -> int:
-        h, J, L, q = self.models[r.model]
-        if r.kind == "energy":
-            n = r.seqs.shape[0]
-            return n * L + 4 * n + api.workspace_bytes(B.WS_ENERGY, n, L, q, 0)
-        if r.kind == "mutant":
-            return L + 4 * L * q + api.workspace_bytes(B.WS_MUTANT, 1, L, q, 0)
-        if r.kind == "sample":
-            return r.n_chains * L + api.workspace_bytes(B.WS_GIBBS, r.n_chains, L, q,
-                                                       B.SAMPLER_GATHER if L <= 512 else 0)
-        raise ValueError(f"unknown request kind {r.kind}")
+        return r.items * self.engines[(r.kind, r.model)].item_bytes()
 
-    # ------------------------------------------------------------ admission
-    def lane_of(self, kind: str, model: int) -> int:
-        return (len(KINDS) * model + KINDS.index(kind)) % len(self.lanes)
-
-    def _admit(self, r: Request, now: float) -> _Live:
-        h, J, L, q = self.models[r.model]
-        lane = self.lane_of(r.kind, r.model)
-        lv = _Live(r, lane)
-        s = self.lanes[lane]
-        with torch.cuda.stream(s):
-            if r.kind in ("energy", "mutant"):
-                x = r.seqs if r.kind == "energy" else r.wt[None]
-                lv.host_in = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).pin_memory()
-                lv.inp = lv.host_in.to(self.device, non_blocking=True)
-            else:
-                lv.inp = api.init_chains(r.n_chains, L, q, r.seed, device=self.device)
-        r.t_admit = now
-        return lv
+    def fits_ever(self, r: Request) -> bool:
+        return r.items <= self.engines[(r.kind, r.model)].cap
 
     # ------------------------------------------------------------ launches
-    def _launch_group(self, kind: str, model: int, lives: list) -> _Launch:
-        """One batched launch for several admitted requests of one model."""
-        h, J, L, q = self.models[model]
-        s = self.lanes[lives[0].lane]  # the lane of (kind, model): inputs were uploaded there
-        with torch.cuda.stream(s):
-            if kind == "energy":
-                seqs = lives[0].inp if len(lives) == 1 else torch.cat([lv.inp for lv in lives])
-                n = seqs.shape[0]
-                ws = api.workspace(B.WS_ENERGY, n, L, q, 0, self.device)
-                out = api.energy(h, J, seqs, ws=ws)
-                o = 0
-                for lv in lives:
-                    k = lv.inp.shape[0]
-                    lv.host_out = torch.empty(k, dtype=torch.float32, pin_memory=True)
-                    lv.host_out.copy_(out[o:o + k], non_blocking=True)
-                    o += k
-            else:
-                wts = lives[0].inp if len(lives) == 1 else torch.cat([lv.inp for lv in lives])
-                out = api.single_mutant_scan(h, J, wts)
-                for k, lv in enumerate(lives):
-                    lv.host_out = torch.empty((L * q,), dtype=torch.float32, pin_memory=True)
-                    lv.host_out.copy_(out[k], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        for lv in lives:
-            lv.busy = True
-            lv.dev_out = out
-        self.stats.launches[kind] += 1
-        self.stats.batched[kind] += len(lives)
-        return _Launch(ev, lives, kind, model)
+    def _launch_scores(self, e: _Engine) -> None:
+        """Energies or mutant scans: the admitted requests that fit, in
+        arrival order, packed into the arena, one graph replay."""
+        batch, n = [], 0
+        while e.pending and n + e.pending[0].req.items <= e.cap:
+            lv = e.pending.pop(0)
+            lv.off = n
+            n += lv.req.items
+            batch.append(lv)
+        if not batch:
+            return
+        with torch.cuda.stream(e.stream):
+            for lv in batch:
+                k = lv.req.items
+                e.inp[lv.off:lv.off + k].copy_(lv.host_in.view(k, e.L), non_blocking=True)
+            e.n_host[0] = n
+            e.n_live.copy_(e.n_host, non_blocking=True)
+            e.graph.replay()
+            for lv in batch:
+                k = lv.req.items
+                shape = (k,) if e.kind == "energy" else (e.L * e.q,)
+                lv.host_out = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+                src = e.out[lv.off:lv.off + k]
+                lv.host_out.copy_(src if e.kind == "energy" else src[0], non_blocking=True)
+            e.event = torch.cuda.Event()
+            e.event.record(e.stream)
+        e.flight = batch
+        e.busy = True
+        self.stats.launches[e.kind] += 1
+        self.stats.batched[e.kind] += len(batch)
 
-    def _launch_samples(self, model: int, lives: list) -> _Launch:
-        """The next chunk of every listed sampling request of one model, as one
-        launch over all their chains."""
-        h, J, L, q = self.models[model]
-        s = self.lanes[lives[0].lane]  # the lane of (sample, model)
-        n = min(self.chunk, min(lv.req.sweeps - lv.done_sweeps for lv in lives))
-        counts = [lv.req.n_chains for lv in lives]
-        seeds = np.concatenate([np.full(k, lv.req.seed, dtype=np.uint64)
-                                for k, lv in zip(counts, lives)])
-        offs = np.concatenate([np.full(k, lv.done_sweeps, dtype=np.uint64)
-                               for k, lv in zip(counts, lives)])
-        ids = np.concatenate([np.arange(k, dtype=np.uint32) for k in counts])
-        sampler = "gather" if L <= 512 else "fields"
-        with torch.cuda.stream(s):
-            chains = lives[0].inp if len(lives) == 1 else torch.cat([lv.inp for lv in lives])
-            table = api.chain_streams(seeds, offs, ids, self.device)
-            api.gibbs_streams(h, J, chains, n, table, sampler=sampler, cus=self.sample_cus)
-            o = 0
-            for k, lv in zip(counts, lives):
-                if len(lives) > 1:
-                    lv.inp.copy_(chains[o:o + k])
-                o += k
-                lv.done_sweeps += n
+    def _launch_tick(self, e: _Engine) -> None:
+        """One sampling tick over every live chain of the model: compaction of
+        the requests that left, new requests joined at the end, the work
+        table's changed records and the live count uploaded, one replay."""
+        L, q, chunk = e.L, e.q, self.chunk
+        with torch.cuda.stream(e.stream):
+            # compaction: requests that finished in the previous tick left holes
+            live = [lv for lv in e.flight if lv.done_sweeps < lv.req.sweeps]
+            n = 0
+            moved = None
+            for lv in live:
+                k = lv.req.items
+                if lv.off != n:
+                    e.scratch[n:n + k].copy_(e.inp[lv.off:lv.off + k], non_blocking=True)
+                    moved = n if moved is None else moved
+                    lv.off = n
+                    self._records(e, lv)
+                elif moved is not None:
+                    e.scratch[n:n + k].copy_(e.inp[n:n + k], non_blocking=True)
+                n += k
+            if moved is not None:
+                e.inp[moved:n].copy_(e.scratch[moved:n], non_blocking=True)
+                e.dirty = min(e.dirty, moved)
+            # new requests join at this tick: their first sweep is sweep 0
+            while e.pending and n + e.pending[0].req.items <= e.cap:
+                lv = e.pending.pop(0)
+                k = lv.req.items
+                lv.off = n
+                lv.base = (-e.ticks * chunk) % (1 << 64)
+                api.init_chains(k, L, q, lv.req.seed, out=e.inp[n:n + k])
+                self.stats.eager["sample"] += 1
+                self._records(e, lv)
+                e.dirty = min(e.dirty, n)
+                live.append(lv)
+                n += k
+            if not live:
+                e.flight = []
+                return
+            if e.dirty < n:
+                a, b = 24 * e.dirty, 24 * n
+                e.table_host.numpy()[a:b] = e.rec_host[e.dirty:n].view(np.uint8)
+                e.table[a:b].copy_(e.table_host[a:b], non_blocking=True)
+            e.dirty = e.cap
+            e.n_host[0] = n
+            e.n_live.copy_(e.n_host, non_blocking=True)
+            e.graph.replay()
+            e.ticks += 1
+            for lv in live:
+                lv.done_sweeps += chunk
                 if lv.done_sweeps == lv.req.sweeps:
-                    lv.host_out = torch.empty(tuple(lv.inp.shape), dtype=torch.int8,
-                                              pin_memory=True)
-                    lv.host_out.copy_(lv.inp, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        for lv in lives:
-            lv.busy = True
+                    k = lv.req.items
+                    lv.host_out = torch.empty((k, L), dtype=torch.int8, pin_memory=True)
+                    lv.host_out.copy_(e.inp[lv.off:lv.off + k], non_blocking=True)
+            e.event = torch.cuda.Event()
+            e.event.record(e.stream)
+        e.flight = live
+        e.busy = True
         self.stats.launches["sample"] += 1
-        self.stats.batched["sample"] += len(lives)
-        return _Launch(ev, lives, "sample", model)
+        self.stats.batched["sample"] += len(live)
+
+    @staticmethod
+    def _records(e: _Engine, lv: _Live) -> None:
+        k, o = lv.req.items, lv.off
+        rec = e.rec_host[o:o + k]
+        rec["seed"] = lv.req.seed
+        rec["sweep_offset"] = lv.base
+        rec["chain"] = np.arange(k, dtype=np.uint32)
+        rec["reserved"] = 0
 
     # ------------------------------------------------------------ main loop
     def run(self, requests, realtime: bool = True, idle_sleep: float = 20e-6):
         """Serves `requests` (sorted by arrival).  With realtime=False every
         request counts as arrived at once (throughput mode)."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in reqs:
+            if r.kind == "sample" and r.sweeps % self.chunk:
+                raise ValueError(f"request {r.rid}: sweeps {r.sweeps} not a multiple of the "
+                                 f"tick's {self.chunk}")
         waiting: list[Request] = []
-        ready: list[_Live] = []      # admitted, not in flight
-        inflight: list[_Launch] = []
         in_use = 0
         nxt = 0
+        live_count = 0
         t0 = time.perf_counter()
 
         def clock():
             return time.perf_counter() - t0
 
-        while nxt < len(reqs) or waiting or ready or inflight:
+        while nxt < len(reqs) or waiting or live_count:
             now = clock()
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
                 r = reqs[nxt]
@@ -231,49 +364,58 @@ class Server:
                 if not realtime:
                     r.arrival = now
                 r.footprint = self.footprint(r)
-                if r.footprint > self.budget:
-                    r.refused = f"needs {r.footprint} bytes, budget {self.budget}"
+                if not self.fits_ever(r):
+                    e = self.engines[(r.kind, r.model)]
+                    r.refused = (f"{r.items} items, the {r.kind} arena of model {r.model} "
+                                 f"holds {e.cap}")
                     r.t_done = now
                     continue
                 waiting.append(r)
-            # admission in arrival order while the head fits
-            while waiting and in_use + waiting[0].footprint <= self.budget:
-                r = waiting.pop(0)
-                ready.append(self._admit(r, now))
+            # admission in arrival order while the head fits its arena
+            while waiting:
+                r = waiting[0]
+                e = self.engines[(r.kind, r.model)]
+                if e.used() + r.items > e.cap:
+                    break
+                waiting.pop(0)
+                lv = _Live(r)
+                if r.kind != "sample":
+                    x = r.seqs if r.kind == "energy" else r.wt[None]
+                    lv.host_in = torch.from_numpy(
+                        np.ascontiguousarray(x, dtype=np.int8).reshape(-1)).pin_memory()
+                r.t_admit = now
+                e.pending.append(lv)
+                live_count += 1
                 in_use += r.footprint
                 self.stats.peak_bytes = max(self.stats.peak_bytes, in_use)
-            # batched launches of everything ready
-            groups: dict = {}
-            busy_keys = {(ln.kind, ln.model) for ln in inflight}
-            for lv in ready:
-                key = (lv.req.kind, lv.req.model)
-                if not lv.busy and key not in busy_keys:
-                    groups.setdefault(key, []).append(lv)
-            for (kind, model), lives in groups.items():
-                if kind == "sample":
-                    inflight.append(self._launch_samples(model, lives))
-                else:
-                    inflight.append(self._launch_group(kind, model, lives))
+            # one replay per free engine with work
+            for e in self.engines.values():
+                if e.busy:
+                    continue
+                if e.kind == "sample":
+                    if e.pending or e.flight:
+                        self._launch_tick(e)
+                elif e.pending:
+                    self._launch_scores(e)
             # completions
             progressed = False
-            still = []
-            for ln in inflight:
-                if not ln.event.query():
-                    still.append(ln)
+            for e in self.engines.values():
+                if not e.busy or not e.event.query():
                     continue
                 progressed = True
+                e.busy = False
                 t = clock()
-                for lv in ln.lives:
-                    lv.busy = False
+                for lv in e.flight:
                     r = lv.req
-                    if ln.kind == "sample" and lv.done_sweeps < r.sweeps:
-                        continue  # next chunk at the next tick
+                    if r.kind == "sample" and lv.done_sweeps < r.sweeps:
+                        continue  # next tick
                     r.result = lv.host_out.numpy()
                     r.t_done = t
-                    lv.dev_out = lv.host_in = None
-                    ready.remove(lv)
+                    lv.host_in = None
+                    live_count -= 1
                     in_use -= r.footprint
-            inflight = still
+                if e.kind != "sample":
+                    e.flight = []
             if not progressed and idle_sleep > 0:
                 time.sleep(idle_sleep)
         return reqs
