@@ -1084,7 +1084,8 @@ def bench_serve(args):
         reqs = serve.poisson_requests(args.serve_requests, rate, Ls, q, seed=100 + k, mix=mix)
         srv.reset_stats()
         t0 = time.perf_counter()
-        srv.run(reqs, realtime=True)
+        srv.run(reqs, realtime=True,
+                progress=lambda d, n: log(f"{name}: {d} of {n} requests done"))
         wall = time.perf_counter() - t0
         sm = serve.summarize(reqs)
         st = srv.stats

@@ -172,7 +172,10 @@ class _Engine:
         return tot
 
     def used(self) -> int:
-        return sum(lv.req.items for lv in self.pending + self.flight)
+        """Arena items held by admitted requests; finished sampling requests
+        leave at the next tick's compaction, before any joiner is placed."""
+        return sum(lv.req.items for lv in self.pending + self.flight
+                   if lv.req.kind != "sample" or lv.done_sweeps < lv.req.sweeps)
 
 
 class Server:
@@ -339,9 +342,11 @@ class Server:
         rec["reserved"] = 0
 
     # ------------------------------------------------------------ main loop
-    def run(self, requests, realtime: bool = True, idle_sleep: float = 20e-6):
+    def run(self, requests, realtime: bool = True, idle_sleep: float = 20e-6, progress=None,
+            every: float = 15.0):
         """Serves `requests` (sorted by arrival).  With realtime=False every
-        request counts as arrived at once (throughput mode)."""
+        request counts as arrived at once (throughput mode).  progress(done,
+        total), if given, is called every `every` seconds."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in reqs:
             if r.kind == "sample" and r.sweeps % self.chunk:
@@ -356,8 +361,12 @@ class Server:
         def clock():
             return time.perf_counter() - t0
 
+        t_report = every
         while nxt < len(reqs) or waiting or live_count:
             now = clock()
+            if progress is not None and now >= t_report:
+                progress(sum(r.t_done == r.t_done for r in reqs), len(reqs))
+                t_report = now + every
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
                 r = reqs[nxt]
                 nxt += 1

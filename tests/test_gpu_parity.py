@@ -517,3 +517,51 @@ def test_train_step_with_metropolis_sweeps(sampler):
     ws = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_METROPOLIS)
     with pytest.raises(B.BmdcaError):
         api.gibbs(dev(h), dev(J), dev(ch0), 1, 1, H_ws=ws, sampler=bad)
+
+
+# ----------------------------------------------------------------- serving forms
+def test_serving_forms_equal_plain_calls():
+    """bmdca_energy_batch, bmdca_mutant_scan_batch and bmdca_sample_tick over
+    arenas larger than the live count: live items equal the plain calls bit
+    for bit, items past the count are untouched, and a request joining the
+    sampling arena at a later tick draws as its own bmdca_gibbs call."""
+    L, q = 57, 21
+    h, J = synth.planted_dense(L, q, seed=160, sigma_J=0.3)
+    hg, Jg = dev(h), dev(J)
+    S = dev(synth.random_sequences(3000, L, q, 161))
+    n = torch.tensor([1234], dtype=torch.int64, device="cuda")
+    E = torch.full((3000,), float("nan"), dtype=torch.float32, device="cuda")
+    ws = api.workspace(B.WS_ENERGY, 3000, L, q, 0)
+    api.energy_batch(hg, Jg, S, n, E, ws)
+    assert torch.equal(E[:1234], api.energy(hg, Jg, S[:1234]))
+    assert bool(torch.isnan(E[1234:]).all())
+    W = dev(synth.random_sequences(5, L, q, 162))
+    dE = torch.full((5, L * q), float("nan"), dtype=torch.float32, device="cuda")
+    n3 = torch.tensor([3], dtype=torch.int64, device="cuda")
+    api.mutant_scan_batch(hg, Jg, W, n3, dE, api.workspace(B.WS_MUTANT, 5, L, q, 0))
+    assert torch.equal(dE[:3], api.single_mutant_scan(hg, Jg, W[:3]))
+    assert bool(torch.isnan(dE[3:]).all())
+    # sampling arena of 500 chains: request A (300 chains) from tick 0,
+    # request B (150 chains) joins at tick 2; 2 sweeps a tick, 5 ticks
+    cap, sw = 500, 2
+    arena = torch.zeros((cap, L), dtype=torch.int8, device="cuda")
+    api.init_chains(300, L, q, 11, out=arena[:300])
+    tick = torch.zeros(1, dtype=torch.int64, device="cuda")
+    live = torch.tensor([300], dtype=torch.int64, device="cuda")
+    seeds = np.array([11] * 300 + [22] * 150 + [0] * 50, dtype=np.uint64)
+    offs = np.array([0] * 300 + [(-2 * sw) % (1 << 64)] * 150 + [0] * 50, dtype=np.uint64)
+    ids = np.concatenate([np.arange(300), np.arange(150), np.zeros(50)]).astype(np.uint32)
+    table = api.chain_streams(seeds, offs, ids)
+    wsg = api.workspace(B.WS_GIBBS, cap, L, q, B.SAMPLER_GATHER)
+    api.gibbs(hg, Jg, arena[:1].clone(), 0, 0, H_ws=wsg, sampler="gather")  # lays J out
+    tail = arena[450:].clone()
+    for t in range(5):
+        if t == 2:
+            api.init_chains(150, L, q, 22, out=arena[300:450])
+            live.fill_(450)
+        api.sample_tick(hg, Jg, arena, live, sw, table, tick, wsg, keep_layout=True)
+    assert int(tick.item()) == 5
+    a = api.gibbs(hg, Jg, api.init_chains(300, L, q, 11), 10, 11, sampler="gather")
+    b = api.gibbs(hg, Jg, api.init_chains(150, L, q, 22), 6, 22, sampler="gather")
+    assert torch.equal(arena[:300], a) and torch.equal(arena[300:450], b)
+    assert torch.equal(arena[450:], tail)

@@ -98,6 +98,6 @@ def test_admission_follows_the_arenas(models):
 
 def test_tiny_budget_scales_the_arenas(models):
     """A budget below the default arenas scales every arena down to fit."""
-    srv = serve.Server(models, budget_bytes=700 << 20, lanes=1, chunk_sweeps=4)
-    assert srv.stats.arena_bytes <= 700 << 20
+    srv = serve.Server(models, budget_bytes=100 << 20, lanes=1, chunk_sweeps=4)
+    assert srv.stats.arena_bytes <= 100 << 20
     assert srv.engines[("energy", 0)].cap < serve.DEFAULT_CAPS["energy"]
