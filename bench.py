@@ -131,7 +131,9 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0,
                     help="serve: HBM budget for requests in flight")
     ap.add_argument("--serve-chunk", type=int, default=1,
-                    help="serve: sweeps per sampling chunk (the batching boundary)")
+                    help="serve: sweeps per sampling tick (the batching boundary)")
+    ap.add_argument("--serve-cus", type=int, default=64,
+                    help="serve: compute units a sampling tick is sized for (0: all)")
     return ap.parse_args()
 
 
@@ -1060,7 +1062,8 @@ def bench_serve(args):
     budget = int(args.serve_budget_gib * 2**30)
     mix = (0.4, 0.4, 0.2)
     t0 = time.perf_counter()
-    srv = serve.Server(models, budget, lanes=args.lanes, chunk_sweeps=args.serve_chunk)
+    srv = serve.Server(models, budget, lanes=args.lanes, chunk_sweeps=args.serve_chunk,
+                       sample_cus=args.serve_cus)
     log(f"engines: {len(srv.engines)} captured graphs, arenas {srv.stats.arena_bytes / 2**30:.2f} "
         f"GiB of the {args.serve_budget_gib:.0f} GiB budget, built in "
         f"{time.perf_counter() - t0:.1f} s")
@@ -1113,7 +1116,8 @@ def bench_serve(args):
                                "energy 1k-100k sequences, full single-mutant scans, sampling "
                                "100-10000 chains x 50 sweeps (mix 0.4/0.4/0.2)",
                    "budget_GiB": args.serve_budget_gib, "lanes": args.lanes,
-                   "chunk_sweeps": args.serve_chunk, "requests_per_rate": args.serve_requests},
+                   "chunk_sweeps": args.serve_chunk, "sample_cus": args.serve_cus,
+                   "requests_per_rate": args.serve_requests},
         "roofline": None,
         "extras": {"capacity_per_s": cap, "arena_GiB": srv.stats.arena_bytes / 2**30,
                    "rates": results},

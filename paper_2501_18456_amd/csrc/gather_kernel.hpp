@@ -155,11 +155,16 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     const int32_t* __restrict__ run, const ChainStream* __restrict__ streams,
     const int64_t* __restrict__ count) {
   if (run && *run == 0) return;  // whole grid leaves before any barrier
-  if (count) {  // live chains of a launch sized for N
+  // With a live count (a launch sized for N chains of which the first *count
+  // are live) the workgroups take chains strided by the grid, chain
+  // cb * gridDim.x + blockIdx.x, so a partly filled arena still spreads its
+  // live chains over every workgroup; otherwise each takes a contiguous range.
+  if (count) {
     const int64_t live = *count;
     if (live < N) N = live;
   }
-  if ((int64_t)blockIdx.x * cpb >= N) return;  // whole workgroup, before any barrier
+  if ((count ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * cpb) >= N)
+    return;  // no live chain: whole workgroup, before any barrier
   if (epoch) sweep_offset += *epoch * (uint64_t)sweeps;
   constexpr int QP = gather_qp(Q), NQ = QP / 4, V = gather_v(Q), S = gather_s(Q, LPC);
   constexpr int vL = (Q - 1) / 4, eL = (Q - 1) % 4;  // lane and slot of state q-1
@@ -174,7 +179,8 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
   float* ring = reinterpret_cast<float*>(g_smem);                             // [nslot][slot]
   uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [S][m4][CPB]
   unsigned char* tokb = reinterpret_cast<unsigned char*>(tokw);
-  const int64_t c = (int64_t)blockIdx.x * cpb + cb;
+  const int64_t c =
+      count ? (int64_t)cb * gridDim.x + blockIdx.x : (int64_t)blockIdx.x * cpb + cb;
   const bool has_chain = cb < cpb;
   const bool active = has_chain && (c < N);
   const bool reader = has_chain && v < NQ;

@@ -12,9 +12,10 @@ served to a stream of requests:
     The live item count, and for sampling each chain's random stream, are
     device data the host writes before a replay, so the same graph serves
     every batch: one graph launch per batch;
-  - admission by HBM footprint: a request is admitted, in arrival order, into
-    its engine's arena once its items fit beside the ones in flight; a
-    request larger than its arena is refused at once;
+  - admission by HBM footprint: a request is admitted into its engine's
+    arena, in arrival order among that engine's requests, once its items fit
+    beside the ones in flight (a full arena holds back only its own
+    requests); a request larger than its arena is refused at once;
   - continuous batching (iteration-level): each engine has at most one
     replay in flight; when it is free, every admitted request of that engine
     that fits goes into the next replay.  Sampling runs in ticks of
@@ -22,9 +23,10 @@ served to a stream of requests:
     the next tick, leave when their sweeps are done (their chains are copied
     out and the arena compacted), and each chain draws with its own request's
     key, chain index and sweep offset from the work table;
-  - engines run on `lanes` streams (default priority) and overlap on the GPU;
-    completion is seen by polling events, results come back through pinned
-    host buffers on the engine's stream.
+  - engines run on `lanes` streams (default priority), sampling and scoring
+    on disjoint ones, and overlap on the GPU; completion is seen by polling
+    events, results come back through pinned host buffers on the engine's
+    stream.
 
 A request's result does not depend on what else is in flight: energies of a
 sequence are independent of the batch (pair order fixed by L), mutant scans
@@ -137,22 +139,49 @@ class _Engine:
             self.ws = api.workspace(B.WS_GIBBS, cap, L, q, B.SAMPLER_GATHER, dev)
             self.dirty = 0  # first table record that changed since the last upload
             with torch.cuda.stream(stream):
-                # lay the couplings out once; the graph then only sweeps
+                # lay the couplings out once; the graphs then only sweep
                 api.gibbs(h, J, self.inp[:1], 0, 0, H_ws=self.ws, sampler="gather")
-            call = lambda: api.sample_tick(h, J, self.inp, self.n_live, chunk, self.table,
-                                           self.tick, self.ws, keep_layout=True, cus=cus)
-        # one eager call (kernel loading, attributes), then the capture
+            # one graph per capacity bucket (powers of two up to cap): a tick
+            # replays the smallest bucket that holds the live chains, so the
+            # launch shape (chains per workgroup) follows the live count
+            self.buckets = []
+            b = min(256, cap)
+            while True:  # ratio sqrt(2): at most ~1.4x the live chains per launch
+                self.buckets.append(b)
+                if b >= cap:
+                    break
+                b = min(max(b + 1, int(b * 1.4142)), cap)
+            self.graphs = {}
+            for b in self.buckets:
+                call = (lambda b=b: api.sample_tick(
+                    h, J, self.inp[:b], self.n_live, chunk, self.table[:24 * b], self.tick,
+                    self.ws, keep_layout=True, cus=cus))
+                self.graphs[b] = self._capture(call, stream)
+            self.tick.zero_()
+            torch.cuda.synchronize()
+            return
+        self.graph = self._capture(call, stream)
+
+    @staticmethod
+    def _capture(call, stream):
+        """One eager call (kernel loading, attributes), then the capture."""
         stream.synchronize()
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             call()
-            if kind == "sample":
-                self.tick.zero_()
         stream.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph, stream=stream, capture_error_mode="thread_local"):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream, capture_error_mode="thread_local"):
             call()
         torch.cuda.synchronize()
+        return g
+
+    def sample_graph(self, n: int):
+        """The graph of the smallest capacity bucket that holds n live chains."""
+        for b in self.buckets:
+            if n <= b:
+                return self.graphs[b]
+        raise ValueError(f"{n} live chains exceed the arena of {self.cap}")
 
     def item_bytes(self) -> int:
         """Device bytes per arena item (the footprint unit of admission)."""
@@ -214,9 +243,21 @@ class Server:
         self.engines = {}
         for (k, m), cap in plan.items():
             h, J = self.models[m][:2]
-            s = self.lanes[(len(KINDS) * m + KINDS.index(k)) % len(self.lanes)]
+            s = self.lanes[self.lane_of(k, m)]
             self.engines[(k, m)] = _Engine(k, h, J, cap, s, self.chunk, sample_cus, device)
         self.stats.arena_bytes = sum(e.arena_bytes() for e in self.engines.values())
+
+    def lane_of(self, kind: str, model: int) -> int:
+        """Sampling engines and scoring engines use disjoint lanes (with two or
+        more), so a scoring batch never queues behind a sampling tick in
+        stream order."""
+        n = len(self.lanes)
+        if n == 1:
+            return 0
+        ns = n // 2  # lanes for sampling ticks
+        if kind == "sample":
+            return model % ns
+        return ns + (model + (n - ns) // 2 * (kind == "mutant")) % (n - ns)
 
     @staticmethod
     def _cap(kind: str, c: float) -> int:
@@ -317,7 +358,7 @@ class Server:
             e.dirty = e.cap
             e.n_host[0] = n
             e.n_live.copy_(e.n_host, non_blocking=True)
-            e.graph.replay()
+            e.sample_graph(n).replay()
             e.ticks += 1
             for lv in live:
                 lv.done_sweeps += chunk
@@ -380,13 +421,17 @@ class Server:
                     r.t_done = now
                     continue
                 waiting.append(r)
-            # admission in arrival order while the head fits its arena
-            while waiting:
-                r = waiting[0]
-                e = self.engines[(r.kind, r.model)]
-                if e.used() + r.items > e.cap:
-                    break
-                waiting.pop(0)
+            # admission in arrival order per engine: a request waits only for
+            # room in its own arena (no head-of-line blocking across engines)
+            full = set()
+            still = []
+            for r in waiting:
+                key = (r.kind, r.model)
+                e = self.engines[key]
+                if key in full or e.used() + r.items > e.cap:
+                    full.add(key)
+                    still.append(r)
+                    continue
                 lv = _Live(r)
                 if r.kind != "sample":
                     x = r.seqs if r.kind == "energy" else r.wt[None]
@@ -397,6 +442,7 @@ class Server:
                 live_count += 1
                 in_use += r.footprint
                 self.stats.peak_bytes = max(self.stats.peak_bytes, in_use)
+            waiting = still
             # one replay per free engine with work
             for e in self.engines.values():
                 if e.busy:
