@@ -889,17 +889,29 @@ def bench_scoring(args):
         n_sim, w, meff = api.reweight(msa, q, 0.8, ws=ws)
     rw_ms = t.stop_ms() / args.steps
     P, W = 5, -(-L // 32)
-    # per pair: one three-input bit operation per plane word ((a ^ b) | c, the
-    # first plane a plain XOR), one popcount-accumulate per word, threshold
-    # test, count and loop step
-    ops_pair = W * P + W + 3
-    rw_ops = float(M) * M * ops_pair
-    # 32-bit VALU lane operations per second: 256 CUs x 128 lanes/clk x 2.4 GHz
-    # (the FP32 vector peak 157.3 TFLOP/s over 2 flops per FMA)
-    int_peak = 256 * 128 * 2.4e9
-    log(f"reweight M={M} L={L}: {rw_ms:.1f} ms, {M * M / (rw_ms * 1e-3):.3e} pairs/s, "
+    # every unordered pair is compared once: M(M-1)/2 pairs (plus the M self
+    # pairs); per pair one three-input bit operation per plane word ((a ^ b) |
+    # c, the first plane a plain XOR), one popcount-accumulate per word,
+    # threshold test and count, and the column side's ballot and popcount
+    ops_pair = W * P + W + 4
+    rw_pairs = M * (M - 1) / 2 + M
+    rw_ops = rw_pairs * ops_pair
+    # integer VALU peak measured on this device by a probe of the same
+    # operation mix (8 independent chains per lane, 1M lanes)
+    import ctypes
+    pk = ctypes.CDLL(os.path.join(ROOT, "paper_2501_18456_amd", "libbmdca_peaks.so"))
+    pk.bmdca_probe_int_valu.restype = ctypes.c_double
+    pk.bmdca_probe_int_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    int_peak = pk.bmdca_probe_int_valu(1, 20000, 4096)
+    int_peak_bitop = pk.bmdca_probe_int_valu(0, 20000, 4096)
+    nominal = 256 * 64 * 2.4e9  # one wave64 instruction per CU and clock
+    log(f"integer VALU probe: {int_peak / 1e12:.1f} T lane-ops/s (pair-count mix), "
+        f"{int_peak_bitop / 1e12:.1f} T (bit operations only); 256 CU x 64 lanes x 2.4 GHz = "
+        f"{nominal / 1e12:.1f} T")
+    log(f"reweight M={M} L={L}: {rw_ms:.1f} ms, {rw_pairs / (rw_ms * 1e-3):.3e} unordered pairs/s, "
         f"{rw_ops / (rw_ms * 1e-3) / 1e12:.2f} Tops/s ({100 * rw_ops / (rw_ms * 1e-3) / int_peak:.1f}% "
-        f"of integer VALU peak); max n_sim {int(n_sim.max())}, M_eff {float(meff.item()):.1f}")
+        f"of the probed integer VALU rate); max n_sim {int(n_sim.max())}, "
+        f"M_eff {float(meff.item()):.1f}")
     del msa, ws, n_sim, w
     torch.cuda.empty_cache()
     # ---- scoring of a resident L = 512 model
@@ -954,8 +966,10 @@ def bench_scoring(args):
                      "unit": "GB/s", "frac": lds_bytes / (en_ms * 1e-3) / lds_peak,
                      "traffic": None, "call_ms": en_ms, "alg_bytes_per_call": lds_bytes},
         "extras": {
-            "reweight": {"ms": rw_ms, "pairs_per_s": M * M / (rw_ms * 1e-3),
-                         "int_ops_per_s": rw_ops / (rw_ms * 1e-3),
+            "reweight": {"ms": rw_ms, "unordered_pairs_per_s": rw_pairs / (rw_ms * 1e-3),
+                         "ops_per_pair": ops_pair, "int_ops_per_s": rw_ops / (rw_ms * 1e-3),
+                         "alu_probe_ops_per_s": int_peak, "alu_probe_bitop_ops_per_s":
+                         int_peak_bitop, "alu_nominal_ops_per_s": nominal,
                          "alu_frac": rw_ops / (rw_ms * 1e-3) / int_peak, "M": M, "L": 256},
             "mutant_scan": {"ms": mu_ms, "wild_types": nw, "GBps": mu_bytes / (mu_ms * 1e-3) / 1e9,
                             "hbm_frac": mu_bytes / (mu_ms * 1e-3) / 8e12},

@@ -13,6 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbmdca.so")
+PEAKS = os.path.join(HERE, "libbmdca_peaks.so")  # measurement aid of bench.py only
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "sampler.hip", "sampler_mh.hip", "sampler_w8.hip", "stats.hip", "learn.hip",
            "reweight.hip", "scoring.hip", "equilibrium.hip", "decimation.hip"]
@@ -53,6 +54,10 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, OUT)
+    # the benchmark's device throughput probe: a library of its own
+    tmp = PEAKS + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC, *FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, "peaks.hip")])
+    os.replace(tmp, PEAKS)
     return OUT
 
 

@@ -8,7 +8,8 @@
 // and identical positions = L - mismatches (padding bits are 0 in both rows).
 // A thread owns one or two rows m and keeps their planes in registers; a
 // workgroup stages 256 rows n at a time in LDS and every lane reads the same
-// n (broadcast).  Counts are exact integers.
+// n (broadcast).  Each unordered pair is compared once (M(M-1)/2 pairs) and
+// counted for both rows.  Counts are exact integers.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -16,6 +17,8 @@ namespace bmdca {
 
 constexpr int kRwThreads = 256;
 constexpr int kMaxPlanes = 5;  // q <= 32
+// 256-column stages per work item of the pair count (balance over the CUs)
+constexpr int kRwChunk = 16;
 // Truth table of (a ^ b) | c for v_bitop3_b32(a, b, c): bit (4a + 2b + c).
 #ifndef BMDCA_XOR_OR_TABLE
 #define BMDCA_XOR_OR_TABLE 0xBE
@@ -60,18 +63,37 @@ __global__ void k_encode_planes(const int8_t* __restrict__ msa, int64_t M, int L
   for (int p = 0; p < P; ++p) planes[((size_t)m * kMaxPlanes + p) * W + w] = bits[p];
 }
 
-// Pair counts.  Grid (row blocks, column splits): a workgroup compares its
-// 256*R rows (R per thread, planes in registers) with one contiguous range
-// of columns, staged 256 rows at a time in LDS (every lane reads the same
-// column: broadcast), and adds its counts to n_sim with integer atomics
-// (exact in any order).
+// Pair counts over unordered pairs.  A work item is (row block, column
+// chunk): 256*R rows (R per thread, planes in registers) against a chunk of
+// later columns staged 256 at a time in LDS (every lane reads the same
+// column: broadcast).  Each row block starts with its own rows: those R
+// stages count every ordered pair inside the block (self included) for the
+// rows only.  Every later column n is compared once with the block's rows m
+// and the pair counts for both: for m in the thread's counter, for n by a
+// wave ballot and popcount per column, summed over the waves in LDS and added
+// to N^(n) with one integer atomic per column and stage.  Integer atomics are
+// exact in any order, so the counts are bit-exact.
 template <int P, int W, int R>
 __global__ __launch_bounds__(kRwThreads) void k_count_similar(const uint32_t* __restrict__ planes,
                                                               int64_t M, int L, int T,
-                                                              int64_t cols_per_split,
                                                               int32_t* __restrict__ n_sim) {
+  constexpr int kRows = kRwThreads * R;  // rows per block
   __shared__ uint32_t sh[kRwThreads * P * W];
-  const int64_t m0 = (int64_t)blockIdx.x * kRwThreads * R + threadIdx.x;
+  __shared__ int colpart[kRwThreads / 64][kRwThreads];
+  // work item -> (row block rb, its stages s0 .. s1-1): row blocks in turn,
+  // each cut into chunks of kRwChunk stages (the launch counts them alike)
+  const int64_t stages = ceil_div(M, kRwThreads);
+  int64_t t = blockIdx.x, rb = 0;
+  for (;;) {
+    const int64_t nch = ceil_div(stages - rb * R, kRwChunk);
+    if (t < nch) break;
+    t -= nch;
+    ++rb;
+  }
+  const int s0 = (int)(t * kRwChunk);
+  const int s1 = (int)std::min<int64_t>(stages - rb * R, (int64_t)s0 + kRwChunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t m0 = rb * kRows + threadIdx.x;
   uint32_t mine[R][P][W];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -82,14 +104,15 @@ __global__ __launch_bounds__(kRwThreads) void k_count_similar(const uint32_t* __
       for (int w = 0; w < W; ++w)
         mine[r][p][w] = (m < M) ? planes[((size_t)m * kMaxPlanes + p) * W + w] : 0u;
   }
+  const int maxmis = L - T;  // similar iff mismatches <= L - T
   int count[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) count[r] = 0;
-  const int64_t c0 = (int64_t)blockIdx.y * cols_per_split;
-  const int64_t c1 = std::min<int64_t>(c0 + cols_per_split, M);
-  for (int64_t n0 = c0; n0 < c1; n0 += kRwThreads) {
+  for (int st = s0; st < s1; ++st) {
+    const int64_t n0 = rb * kRows + (int64_t)st * kRwThreads;
+    const bool own = st < R;  // the block's own rows: ordered pairs, rows only
     __syncthreads();
-    const int nload = (int)std::min<int64_t>(kRwThreads, c1 - n0);
+    const int nload = (int)std::min<int64_t>(kRwThreads, M - n0);
     for (int k = threadIdx.x; k < nload * P * W; k += kRwThreads) {
       const int nl = k / (P * W), pw = k % (P * W);
       sh[k] = planes[(size_t)(n0 + nl) * kMaxPlanes * W + pw];
@@ -114,8 +137,23 @@ __global__ __launch_bounds__(kRwThreads) void k_count_similar(const uint32_t* __
           mism[r] += __popc(d);
         }
       }
+      int wc = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) count[r] += (L - mism[r] >= T) ? 1 : 0;
+      for (int r = 0; r < R; ++r) {
+        const bool sim = (m0 + (int64_t)kRwThreads * r < M) && mism[r] <= maxmis;
+        count[r] += sim ? 1 : 0;
+        if (!own) wc += __popcll(__ballot(sim));
+      }
+      if (!own && lane == 0) colpart[wid][nl] = wc;
+    }
+    if (!own) {
+      __syncthreads();
+      if (threadIdx.x < nload) {
+        int c = 0;
+#pragma unroll
+        for (int v = 0; v < kRwThreads / 64; ++v) c += colpart[v][threadIdx.x];
+        if (c > 0) atomicAdd(n_sim + n0 + threadIdx.x, c);
+      }
     }
   }
 #pragma unroll
@@ -149,14 +187,12 @@ static void launch_count_pw(const uint32_t* planes, int64_t M, int L, int T, int
                             hipStream_t s) {
   // two rows per thread while the planes fit comfortably in registers
   constexpr int R = (P * W <= 40) ? 2 : 1;
+  const int64_t stages = ceil_div(M, kRwThreads);
   const int64_t rowblocks = ceil_div(M, (int64_t)kRwThreads * R);
-  // column splits: about 2048 workgroups in all, every split >= 256 columns
-  const int64_t colblocks = ceil_div(M, (int64_t)kRwThreads);
-  const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(colblocks, ceil_div(2048, rowblocks)));
-  const int64_t per = ceil_div(colblocks, splits) * kRwThreads;
-  const int64_t used = ceil_div(M, per);
-  hipLaunchKernelGGL((k_count_similar<P, W, R>), dim3((unsigned)rowblocks, (unsigned)used),
-                     dim3(kRwThreads), 0, s, planes, M, L, T, per, n_sim);
+  int64_t items = 0;
+  for (int64_t rb = 0; rb < rowblocks; ++rb) items += ceil_div(stages - rb * R, kRwChunk);
+  hipLaunchKernelGGL((k_count_similar<P, W, R>), dim3((unsigned)items), dim3(kRwThreads), 0, s,
+                     planes, M, L, T, n_sim);
 }
 
 template <int W>
