@@ -42,7 +42,11 @@ GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
                           "paper_2501_18456_amd/csrc/gather_plan.hpp",
                           "paper_2501_18456_amd/csrc/sampler.hip",
                           "paper_2501_18456_amd/csrc/common.hpp")
-GATHER_TRAFFIC = {"sha256": None, "bytes": {}}  # workload name -> bytes per launch
+# workload -> bytes per launch: the gather kernel's 10-sweep launch and the
+# field kernel's 5-sweep launch of the precision form (L = 256, N = 20 000)
+GATHER_TRAFFIC = {"sha256": "635894c5e8205fb826e2d108b6dce4d6afb7a86c3babdcde73cab52949928123",
+                  "bytes": {"precision": 3.8304e10,           # 3.8297e10 read + 6.5e6 written
+                            "precision-fields": 1.98279e12}}  # 1.4609e12 read + 5.2185e11
 
 
 def sources_digest():
@@ -876,6 +880,7 @@ def bench_scoring(args):
     from paper_2501_18456_amd import _lib as B
 
     torch.cuda.set_device(0)
+    calibration_copy(args)
     t = Timer()
     # ---- reweighting: L = 256, q = 21, M = 100 000 rows drawn from a planted model
     L, q, M = 256, 21, 100000
