@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbmdca.so")
 PEAKS = os.path.join(HERE, "libbmdca_peaks.so")  # measurement aid of bench.py only
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "sampler.hip", "sampler_mh.hip", "sampler_w8.hip", "stats.hip", "learn.hip",
+SOURCES = ["api.hip", "sampler.hip", "sampler_mh.hip", "sampler_w8.hip", "sampler_w12.hip", "stats.hip", "learn.hip",
            "reweight.hip", "scoring.hip", "equilibrium.hip", "decimation.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

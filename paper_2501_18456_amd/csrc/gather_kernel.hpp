@@ -559,12 +559,19 @@ struct GatherArgs {
 
 template <int Q, bool MH, int MAXW>
 hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
-  auto kern = gs.lpc == 16 ? (gs.items == 31   ? k_gibbs_gather<Q, 31, 16, MH, MAXW>
-                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 16, MH, MAXW>
-                                               : k_gibbs_gather<Q, 8, 16, MH, MAXW>)
-                           : (gs.items == 31   ? k_gibbs_gather<Q, 31, 8, MH, MAXW>
-                              : gs.items == 16 ? k_gibbs_gather<Q, 16, 8, MH, MAXW>
-                                               : k_gibbs_gather<Q, 8, 8, MH, MAXW>);
+  // 16 lanes per chain only for Metropolis at q <= 8 (the planner's lane
+  // rule), so only that draw instantiates them
+  constexpr bool k16 = MH && gather_v(Q) <= 2;
+  if (gs.lpc != gather_lanes(Q, !MH)) return hipErrorInvalidValue;
+  decltype(&k_gibbs_gather<Q, 8, 8, MH, MAXW>) kern;
+  if constexpr (k16)
+    kern = gs.items == 31   ? k_gibbs_gather<Q, 31, 16, MH, MAXW>
+           : gs.items == 16 ? k_gibbs_gather<Q, 16, 16, MH, MAXW>
+                            : k_gibbs_gather<Q, 8, 16, MH, MAXW>;
+  else
+    kern = gs.items == 31   ? k_gibbs_gather<Q, 31, 8, MH, MAXW>
+           : gs.items == 16 ? k_gibbs_gather<Q, 16, 8, MH, MAXW>
+                            : k_gibbs_gather<Q, 8, 8, MH, MAXW>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
   if (e != hipSuccess) return e;
@@ -596,6 +603,9 @@ hipError_t launch_gather_switch(int q, const GatherShape& gs, const GatherArgs& 
 // ----- sampler_w8.hip: heat-bath sweeps with MAXW = 8 (q <= 16, plans of at
 // most kGSmallWaves waves)
 hipError_t launch_gather_heat_w8(int q, const GatherShape& gs, const GatherArgs& a);
+// ----- sampler_w12.hip: heat-bath sweeps with MAXW = 12 (q > 16, plans of at
+// most kGMidWaves waves)
+hipError_t launch_gather_heat_w12(int q, const GatherShape& gs, const GatherArgs& a);
 
 // Sweeps of the gather form over the laid-out blocks Jt (q = 2..32).
 template <bool MH>
@@ -614,6 +624,7 @@ hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, i
                      s, &ctl};
   if constexpr (!MH) {
     if (q <= 16 && gs.waves <= kGSmallWaves) return launch_gather_heat_w8(q, gs, a);
+    if (q > 16 && gs.waves <= kGMidWaves) return launch_gather_heat_w12(q, gs, a);
   }
   return launch_gather_switch<MH, kGMaxWaves>(q, gs, a);
 }

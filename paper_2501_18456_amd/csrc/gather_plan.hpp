@@ -15,6 +15,9 @@ constexpr int64_t gp_ceil(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int kGMaxWaves = 16;   // waves per workgroup at most
 constexpr int kGSmallWaves = 8;  // plans with q <= 16 and at most this many waves run a
                                  // kernel bound to 8 waves (256 VGPRs)
+constexpr int kGMidWaves = 12;   // heat-bath plans with q > 16 and at most this many waves
+                                 // run a kernel bound to 12 waves (168 VGPRs: the 16-wave
+                                 // bound of 128 spills two of them to scratch)
 constexpr int kGMinWaves = 4;    // and at least
 // Chains per workgroup at most for a launch on a share of the CUs (grouped
 // training of 64 models over 8 lanes: caps of 32, 64 and 128 chains measured
