@@ -41,12 +41,13 @@ LDS_BYTES_PER_CLK = 256
 GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
                           "paper_2501_18456_amd/csrc/gather_plan.hpp",
                           "paper_2501_18456_amd/csrc/sampler.hip",
+                          "paper_2501_18456_amd/csrc/sampler_w12.hip",
                           "paper_2501_18456_amd/csrc/common.hpp")
 # workload -> bytes per launch: the gather kernel's 10-sweep launch and the
 # field kernel's 5-sweep launch of the precision form (L = 256, N = 20 000)
-GATHER_TRAFFIC = {"sha256": "635894c5e8205fb826e2d108b6dce4d6afb7a86c3babdcde73cab52949928123",
-                  "bytes": {"precision": 3.8304e10,           # 3.8297e10 read + 6.5e6 written
-                            "precision-fields": 1.98279e12}}  # 1.4609e12 read + 5.2185e11
+GATHER_TRAFFIC = {"sha256": "ad35b051ea59d567a4f5c75ce52d9829270ce6c726e091a4646fac824fb1023b",
+                  "bytes": {"precision": 1.87078e10,           # 1.87026e10 read + 5.2e6 written
+                            "precision-fields": 1.98356e12}}  # 1.4617e12 read + 5.2185e11
 
 
 def sources_digest():
