@@ -19,6 +19,11 @@
 //     parts (two products into the same FP32 accumulator); FP32 partial sums
 //     are flushed into FP64 registers every 1024 rows.  Unit weights give
 //     integer counts, exact in FP32 below 2^24 rows.
+//   - the stage loop of the BF16 forms is unrolled four times so that the
+//     token registers of the previous, current, next and after-next stage
+//     rotate by name: a load issued two stages ahead is first read when its
+//     entries are set, one stage later, and no register copy waits for it
+//     (the FP32 form and q <= 3 rotate by copies: fewer live registers).
 //   - FP32: 32x32x2 FP32 MFMAs on FP32 operands (the comparator form).
 // K may be split across workgroups; every split writes its own FP64 plane
 // and the planes are summed in split order (deterministic).
@@ -38,9 +43,10 @@ constexpr int kRowF = kKT + 1;         // FP32 tile row stride in floats (padded
 enum { MODE_UNIT_BF16 = 0, MODE_HILO_BF16 = 1, MODE_F32 = 2 };
 
 // K stages per FP32 partial sum before it is added into FP64: 1024 rows in
-// the BF16 hi+lo form (one FP32 rounding per 16-row MFMA step: at most 64
-// roundings, <= 3.8e-6 relative, beside the <= 2^-18 of the hi+lo split),
-// 512 rows in the FP32 form (2-row MFMA steps).
+// the BF16 hi+lo form (two FP32 roundings per 16-row MFMA step, hi then lo:
+// at most 128 roundings of a sum of nonnegative terms, <= 7.7e-6 relative,
+// beside the <= 2^-18 of the hi+lo split), 512 rows in the FP32 form (2-row
+// MFMA steps).
 template <int MODE>
 constexpr int flush_stages() { return MODE == MODE_HILO_BF16 ? 16 : 8; }
 
@@ -196,15 +202,15 @@ __device__ __forceinline__ void load_tokens(const int8_t* __restrict__ XT, int64
   for (int p = 0; p < NP; ++p) {
     const int s = wid + NW * p;
     // padding (-1) reads as 255: past every tile row for any site base; a
-    // site beyond the tile reads a valid site and is replaced by 255
+    // site beyond the tile reads a valid site, replaced by 255 when the
+    // entry is written (not here: the load stays in flight until then)
     const int site = o.i_lo + min(s, o.nsites - 1);
-    const int t = (int)(uint8_t)XT[(size_t)site * Mpad + m0 + lane];
-    tok[p] = (s < o.nsites) ? t : 255;
+    tok[p] = (int)(uint8_t)XT[(size_t)site * Mpad + m0 + lane];
   }
 }
 
-// Writes value(s) at this thread's entries; a padding token or a row outside
-// the tile goes to the trash row ROWS.
+// Writes value(s) at this thread's entries; a padding token, a site past the
+// tile or a row outside the tile goes to the trash row ROWS.
 template <int MODE, int NW, int NP, int ROWS>
 __device__ __forceinline__ void put_entries(const Operand& o, int q, int wid, int lane,
                                             const int (&tok)[NP], unsigned char* t0,
@@ -216,7 +222,8 @@ __device__ __forceinline__ void put_entries(const Operand& o, int q, int wid, in
     // base is wave-uniform and > -q; tokens are in [0, q) or 255, and 255
     // (padding, or a site past the tile) always lands in the trash row
     const int base = (o.i_lo + s) * q - o.R0;
-    const int r = (int)min((unsigned)(tok[p] + base), (unsigned)ROWS);
+    const int tk = (s < o.nsites) ? tok[p] : 255;
+    const int r = (int)min((unsigned)(tk + base), (unsigned)ROWS);
     if (MODE == MODE_F32) {
       *reinterpret_cast<float*>(t0 + r * (kRowF * 4) + 4 * lane) = vf;
     } else {
@@ -228,8 +235,8 @@ __device__ __forceinline__ void put_entries(const Operand& o, int q, int wid, in
 }
 
 // Output tile kTR x 128 per workgroup of four waves (2 x 2 wave tiles).  The
-// hi+lo form takes 64-row tiles: its waves hold 32x64 (FP32 hi and lo sums
-// plus FP64 sums) and two workgroups share a CU, so one's barrier is
+// hi+lo form takes 64-row tiles: its waves hold 32x64 (FP32 sums of the hi
+// and lo products plus FP64 sums) and two workgroups share a CU, so one's barrier is
 // covered by the other's matrix work.  The other forms take 128 x 128.
 template <int MODE>
 struct ProductShape {
@@ -281,17 +288,14 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
   const int lrow = lane % 32, lhalf = lane / 32;
   constexpr uint16_t kOne = 0x3F80;  // BF16 1.0
 
-  // acc[rb][cb]: hi (or only) products; lacc: lo products (hi+lo form).
-  f32x16 acc[RB][2], lacc[kLo ? RB : 1][2];
+  // acc[rb][cb]: FP32 partial sums (hi then lo product in the hi+lo form)
+  f32x16 acc[RB][2];
 #pragma unroll
   for (int b = 0; b < RB; ++b)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[b][c][v] = 0.0f;
-        if (kLo) lacc[b][c][v] = 0.0f;
-      }
+      for (int v = 0; v < 16; ++v) acc[b][c][v] = 0.0f;
   constexpr int kD = kWeighted ? RB * 2 : 1;  // FP64 sums only for weighted forms
   double dacc[kD][16];
 #pragma unroll
@@ -299,13 +303,6 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
 #pragma unroll
     for (int v = 0; v < 16; ++v) dacc[b][v] = 0.0;
 
-  // Tokens of the previous, current, next and after-next stage (previous:
-  // none yet, so its clears go to the trash row).
-  int aP[NP], bP[NP], aC[NP], bC[NP], aN[NP], bN[NP], aNN[NP], bNN[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) aP[p] = bP[p] = 255;
-  uint16_t hiN = 0, loN = 0, hiNN = 0, loNN = 0;
-  float fN = 0.0f, fNN = 0.0f;
   auto load_w = [&](int64_t m, uint16_t& hi, uint16_t& lo, float& f) {
     if (MODE == MODE_HILO_BF16) {
       hi = whi[m + lane];
@@ -325,26 +322,42 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
                               clear ? (uint16_t)0 : kOne, 0, clear ? 0.0f : 1.0f);
   };
 
-  load_tokens<NW, NP>(XT, Mpad, oa, kbeg, wid, lane, aC);
-  load_tokens<NW, NP>(XT, Mpad, ob, kbeg, wid, lane, bC);
-  uint16_t hi0 = 0, lo0 = 0;
-  float f0 = 0.0f;
-  load_w(kbeg, hi0, lo0, f0);
-  {  // stage after the first (the last stage again when there is none)
+  // Token sets T0..T3 (A and B operand) and weight sets W0, W1.  Stage st
+  // holds its own tokens in T[st % 4]; the tokens of stage st - 1 (cleared
+  // at st) in T[(st + 3) % 4], of st + 1 (set at st) in T[(st + 1) % 4], and
+  // loads those of st + 2 into T[(st + 2) % 4]; the weights of st + 1 are in
+  // W[(st + 1) % 2], those of st + 2 go to W[st % 2].  Before the first stage
+  // the "previous" tokens are 255, so their clears go to the trash row.
+  int T0a[NP], T0b[NP], T1a[NP], T1b[NP], T2a[NP], T2b[NP], T3a[NP], T3b[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) T3a[p] = T3b[p] = 255;
+  uint16_t W0h = 0, W0l = 0, W1h = 0, W1l = 0;
+  float W0f = 0.0f, W1f = 0.0f;
+  load_tokens<NW, NP>(XT, Mpad, oa, kbeg, wid, lane, T0a);
+  load_tokens<NW, NP>(XT, Mpad, ob, kbeg, wid, lane, T0b);
+  {
+    uint16_t hi0 = 0, lo0 = 0;
+    float f0 = 0.0f;
+    load_w(kbeg, hi0, lo0, f0);
+    // stage after the first (the last stage again when there is none)
     const int64_t m1 = min(kbeg + kKT, kend - kKT);
-    load_tokens<NW, NP>(XT, Mpad, oa, m1, wid, lane, aN);
-    load_tokens<NW, NP>(XT, Mpad, ob, m1, wid, lane, bN);
-    load_w(m1, hiN, loN, fN);
+    load_tokens<NW, NP>(XT, Mpad, oa, m1, wid, lane, T1a);
+    load_tokens<NW, NP>(XT, Mpad, ob, m1, wid, lane, T1b);
+    load_w(m1, W1h, W1l, W1f);
+    __syncthreads();
+    put_a(T0a, smem, false, hi0, lo0, f0);
+    put_b(T0b, smem, false);
+    __syncthreads();
   }
-  __syncthreads();
-  put_a(aC, smem, false, hi0, lo0, f0);
-  put_b(bC, smem, false);
-  __syncthreads();
 
   const int arow0 = 32 * RB * wr + lrow;  // first A row of this lane
   const int brow0 = 64 * wc + lrow;       // first B row of this lane
-  int st = 0;
-  for (int64_t m0 = kbeg; m0 < kend; m0 += kKT, ++st) {
+  // One stage: matrix work on the buffer of stage st, then the other buffer
+  // gets the clears of stage st - 1 and the entries of stage st + 1.
+  auto stage = [&](int64_t m0, int st, const int(&aP)[NP], const int(&bP)[NP],
+                   const int(&aN)[NP], const int(&bN)[NP], int(&aNN)[NP], int(&bNN)[NP],
+                   uint16_t hiN, uint16_t loN, float fN, uint16_t& hiNN, uint16_t& loNN,
+                   float& fNN) {
     const bool has1 = m0 + kKT < kend;
     {  // loads two stages ahead (clamped to the last stage: used only if it exists)
       const int64_t m2 = min(m0 + 2 * kKT, kend - kKT);
@@ -391,16 +404,12 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
+          for (int cb = 0; cb < 2; ++cb) {
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-        if (kLo) {
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-              lacc[rb][cb] =
-                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(c[rb], b[cb], lacc[rb][cb], 0, 0, 0);
-        }
+            if (kLo)
+              acc[rb][cb] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(c[rb], b[cb], acc[rb][cb], 0, 0, 0);
+          }
       }
     }
     // ---- other buffer: clear stage m0 - kKT, set stage m0 + kKT.  Nobody
@@ -420,27 +429,55 @@ __global__ __launch_bounds__(64 * ProductShape<MODE>::kWaves, (MODE == MODE_HILO
           for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              float part = acc[rb][cb][v];
-              if (kLo) part += lacc[rb][cb][v];  // lo <= 2^-8 hi: one FP32 rounding
-              dacc[rb * 2 + cb][v] += (double)part;
+              dacc[rb * 2 + cb][v] += (double)acc[rb][cb][v];
               acc[rb][cb][v] = 0.0f;
-              if (kLo) lacc[rb][cb][v] = 0.0f;
             }
       }
     }
     __syncthreads();
+  };
+
+  const int nst = (int)((kend - kbeg) / kKT);
+  int st = 0;
+  if constexpr (MODE == MODE_F32 || NP > 9) {
+    // register-heavy forms: the sets keep their roles and rotate by copies
+    // (each copy waits for its load; fewer registers stay live)
+    for (; st < nst; ++st) {
+      stage(kbeg + (int64_t)st * kKT, st, T3a, T3b, T1a, T1b, T2a, T2b, W1h, W1l, W1f, W0h, W0l,
+            W0f);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      aP[p] = aC[p];
-      bP[p] = bC[p];
-      aC[p] = aN[p];
-      bC[p] = bN[p];
-      aN[p] = aNN[p];
-      bN[p] = bNN[p];
+      for (int p = 0; p < NP; ++p) {
+        T3a[p] = T0a[p];
+        T3b[p] = T0b[p];
+        T0a[p] = T1a[p];
+        T0b[p] = T1b[p];
+        T1a[p] = T2a[p];
+        T1b[p] = T2b[p];
+      }
+      W1h = W0h;
+      W1l = W0l;
+      W1f = W0f;
     }
-    hiN = hiNN;
-    loN = loNN;
-    fN = fNN;
+  } else {
+    // groups of four stages (one loop exit keeps every accumulator in its
+    // registers), then the last 0-3 stages
+    for (; st + 4 <= nst; st += 4) {
+      const int64_t m0 = kbeg + (int64_t)st * kKT;
+      stage(m0, st, T3a, T3b, T1a, T1b, T2a, T2b, W1h, W1l, W1f, W0h, W0l, W0f);
+      stage(m0 + kKT, st + 1, T0a, T0b, T2a, T2b, T3a, T3b, W0h, W0l, W0f, W1h, W1l, W1f);
+      stage(m0 + 2 * kKT, st + 2, T1a, T1b, T3a, T3b, T0a, T0b, W1h, W1l, W1f, W0h, W0l, W0f);
+      stage(m0 + 3 * kKT, st + 3, T2a, T2b, T0a, T0b, T1a, T1b, W0h, W0l, W0f, W1h, W1l, W1f);
+    }
+    if (st < nst) {
+      const int64_t m0 = kbeg + (int64_t)st * kKT;
+      stage(m0, st, T3a, T3b, T1a, T1b, T2a, T2b, W1h, W1l, W1f, W0h, W0l, W0f);
+      if (st + 1 < nst) {
+        stage(m0 + kKT, st + 1, T0a, T0b, T2a, T2b, T3a, T3b, W0h, W0l, W0f, W1h, W1l, W1f);
+        if (st + 2 < nst)
+          stage(m0 + 2 * kKT, st + 2, T1a, T1b, T3a, T3b, T0a, T0b, W1h, W1l, W1f, W0h, W0l,
+                W0f);
+      }
+    }
   }
 
   // ---- write this split's plane.  Accumulator element v of lane l in a

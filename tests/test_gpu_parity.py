@@ -196,7 +196,8 @@ def test_gibbs_beta_zero_is_uniform_and_two_state(sampler):
 
 # ----------------------------------------------------------------- statistics
 @pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
-@pytest.mark.parametrize("L,q,M", [(20, 21, 700), (37, 5, 300), (7, 2, 129)])
+@pytest.mark.parametrize("L,q,M", [(20, 21, 700), (37, 5, 300), (7, 2, 129), (11, 21, 50),
+                                   (11, 21, 100), (6, 4, 257)])
 def test_stats_unit_weights_bitexact(prec, L, q, M):
     X = synth.clustered_msa(M, L, q, seed=80 + L)
     f1g, f2g, mg = api.stats(dev(X), q, None, -1.0, prec)
@@ -207,7 +208,8 @@ def test_stats_unit_weights_bitexact(prec, L, q, M):
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp32", 1e-6)])
-@pytest.mark.parametrize("L,q,M", [(20, 21, 1500), (37, 5, 700), (9, 2, 500), (13, 3, 400)])
+@pytest.mark.parametrize("L,q,M", [(20, 21, 1500), (37, 5, 700), (9, 2, 500), (13, 3, 400),
+                                   (15, 21, 40), (15, 21, 170), (8, 5, 1090)])
 def test_stats_weighted(L, q, M, prec, tol):
     X = synth.clustered_msa(M, L, q, seed=90 + q)
     w = synth.weights_open_unit(M, 91)
