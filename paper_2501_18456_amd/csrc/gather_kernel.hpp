@@ -25,8 +25,9 @@ namespace bmdca {
 //     buffer->LDS loads, A = 3 chunks ahead of use, into a ring of A + 1
 //     slots.  JC is chosen per (L, q) to fill the LDS left over by the
 //     tokens.
-//   - Each chain owns LPC = 8 or 16 consecutive lanes (16 for q <= 8 when
-//     the chains per workgroup are few enough), lane p = u * V + v
+//   - Each chain owns LPC = 8 or 16 consecutive lanes (16 for Metropolis at
+//     q <= 8; heat-bath chains with 5..7 quads per row may be narrow, one
+//     lane per quad, the lanes of the row group only), lane p = u * V + v
 //     (V = QP/4 rounded up to a power of two, S = LPC / V site groups): lane
 //     (u, v) adds quad v of the rows of the sites j = u, u + S, u + 2S, ...
 //     of every chunk.  For q > 16 each 8 lanes of a chain read one row as
@@ -144,6 +145,35 @@ __device__ __forceinline__ float combine_sites(float x) {
   return x;
 }
 
+// Narrow chains (LPC = quads per row, 5..7, one chain per LPC consecutive
+// lanes): the draw's cross-lane steps by lane shuffles inside the chain,
+// base = first lane of the chain, v = lane - base.  The prefix sum keeps the
+// association order of group_scan<8> (add lane v-1, then v-2, then v-4), the
+// other steps are exact in any order.
+template <int LPC>
+__device__ __forceinline__ float narrow_max(float x, int base) {
+  float m = __shfl(x, base, kWave);
+#pragma unroll
+  for (int k = 1; k < LPC; ++k) m = fmaxf(m, __shfl(x, base + k, kWave));
+  return m;
+}
+__device__ __forceinline__ float narrow_scan(float x, int lane, int v) {
+  float y = __shfl(x, lane - 1, kWave);
+  if (v >= 1) x += y;
+  y = __shfl(x, lane - 2, kWave);
+  if (v >= 2) x += y;
+  y = __shfl(x, lane - 4, kWave);
+  if (v >= 4) x += y;
+  return x;
+}
+template <int LPC>
+__device__ __forceinline__ int narrow_sum(int x, int base) {
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < LPC; ++k) t += __shfl(x, base + k, kWave);
+  return t;
+}
+
 // MAXW: the most waves a workgroup of this instantiation may have (16, or 8
 // for plans of at most 8 waves: twice the registers per lane, 256).
 template <int Q, int IT, int LPC, bool MH, int MAXW>
@@ -170,18 +200,25 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
   constexpr int vL = (Q - 1) / 4, eL = (Q - 1) % 4;  // lane and slot of state q-1
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ __attribute__((aligned(16))) unsigned char g_smem[];
-  const int T = blockDim.x, CPB = T / LPC;
+  // chains per wave: 64 / LPC (narrow chains: the last 64 % LPC lanes of a
+  // wave hold no chain)
+  constexpr int CPW = 64 / LPC;
+  constexpr bool kNarrow = LPC < 8;
+  const int T = blockDim.x, CPB = kNarrow ? (T / 64) * CPW : T / LPC;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int p = lane & (LPC - 1), u = p / V, v = p % V;
-  const int cb = tid / LPC;  // chain slot in the workgroup
+  const int p = kNarrow ? lane % LPC : lane & (LPC - 1), u = p / V, v = p % V;
+  const bool lane_ok = !kNarrow || lane < CPW * LPC;
+  // chain slot in the workgroup (the wide form keeps the plain expression:
+  // the per-wave one costs scalar registers that the wide kernels spill)
+  const int cb = kNarrow ? wid * CPW + lane / LPC : tid / LPC;
   const int nslot = ahead + 1;
   float* ring = reinterpret_cast<float*>(g_smem);                             // [nslot][slot]
   uint32_t* tokw = reinterpret_cast<uint32_t*>(ring + (size_t)nslot * slot);  // [S][m4][CPB]
   unsigned char* tokb = reinterpret_cast<unsigned char*>(tokw);
   const int64_t c =
       count ? (int64_t)cb * gridDim.x + blockIdx.x : (int64_t)blockIdx.x * cpb + cb;
-  const bool has_chain = cb < cpb;
+  const bool has_chain = lane_ok && cb < cpb;
   const bool active = has_chain && (c < N);
   const bool reader = has_chain && v < NQ;
   uint32_t cid = (uint32_t)c;
@@ -203,7 +240,7 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     return tokb + ((size_t)((j % S) * m4 + (m >> 2)) * CPB + cb) * 4 + (m & 3);
   };
 
-  for (int k = p; k < S * m4; k += LPC) {  // dword k = (site group, 4 positions)
+  for (int k = lane_ok ? p : S * m4; k < S * m4; k += LPC) {  // dword k = (site group, 4 positions)
     const int uu = k / m4, mq = k % m4;
     uint32_t w = 0;
     for (int e = 0; e < 4; ++e) {
@@ -469,7 +506,11 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
           l[e] = ok ? beta * (hq[e] + acc[e]) : -INFINITY;
           mx = fmaxf(mx, l[e]);
         }
-        mx = group_max<V>(mx);
+        const int nbase = lane - p;  // first lane of the chain (narrow chains)
+        if constexpr (kNarrow)
+          mx = narrow_max<LPC>(mx, nbase);
+        else
+          mx = group_max<V>(mx);
         float P[4];
         float run_sum = 0.0f;
 #pragma unroll
@@ -479,10 +520,18 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
           P[e] = run_sum;
         }
         // inclusive scan of the quad sums over v; exclusive = shifted by one
-        const float inc = group_scan<V>(run_sum, v);
-        float excl = V > 1 ? dpp_f<kDppShr1>(inc) : 0.0f;
-        if (v == 0) excl = 0.0f;
-        const float Stot = group_bcast<V, vL>(excl + P[eL], v);  // S_{q-1}
+        float inc, excl, Stot;
+        if constexpr (kNarrow) {
+          inc = narrow_scan(run_sum, lane, v);
+          excl = __shfl(inc, lane - 1, kWave);
+          if (v == 0) excl = 0.0f;
+          Stot = __shfl(excl + P[eL], nbase + vL, kWave);  // S_{q-1}
+        } else {
+          inc = group_scan<V>(run_sum, v);
+          excl = V > 1 ? dpp_f<kDppShr1>(inc) : 0.0f;
+          if (v == 0) excl = 0.0f;
+          Stot = group_bcast<V, vL>(excl + P[eL], v);  // S_{q-1}
+        }
         if (!kKeepRnd || (i & 3) == 0)
           rnd = philox4x32_10(make_uint4((uint32_t)i >> 2, sg, cid, 0u), k0, k1);
         const float uz = word_to_uniform(pick_word(rnd, i & 3)) * Stot;
@@ -490,7 +539,10 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (v < NQ && 4 * v + e < Q - 1 && excl + P[e] <= uz) ++cnt;
-        cnt = group_sum<V>(cnt);
+        if constexpr (kNarrow)
+          cnt = narrow_sum<LPC>(cnt, nbase);
+        else
+          cnt = group_sum<V>(cnt);
         // every lane of the chain drew the same state: patch the token of
         // site i in the dwords read ahead for the next site's first chunk
         if (kPipeTok && reader && u == i % S) {
@@ -559,19 +611,20 @@ struct GatherArgs {
 
 template <int Q, bool MH, int MAXW>
 hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
-  // 16 lanes per chain only for Metropolis at q <= 8 (the planner's lane
-  // rule), so only that draw instantiates them
-  constexpr bool k16 = MH && gather_v(Q) <= 2;
-  if (gs.lpc != gather_lanes(Q, !MH)) return hipErrorInvalidValue;
-  decltype(&k_gibbs_gather<Q, 8, 8, MH, MAXW>) kern;
-  if constexpr (k16)
-    kern = gs.items == 31   ? k_gibbs_gather<Q, 31, 16, MH, MAXW>
-           : gs.items == 16 ? k_gibbs_gather<Q, 16, 16, MH, MAXW>
-                            : k_gibbs_gather<Q, 8, 16, MH, MAXW>;
-  else
-    kern = gs.items == 31   ? k_gibbs_gather<Q, 31, 8, MH, MAXW>
-           : gs.items == 16 ? k_gibbs_gather<Q, 16, 8, MH, MAXW>
-                            : k_gibbs_gather<Q, 8, 8, MH, MAXW>;
+  // lanes per chain: the planner's rule for (q, draw), or narrow chains
+  // (heat-bath, 5..7 quads per row) where the planner takes them
+  constexpr int LP = gather_lanes(Q, !MH), LN = gather_narrow_lanes(Q, !MH);
+  if (gs.lpc != LP && (LN == 0 || gs.lpc != LN)) return hipErrorInvalidValue;
+  decltype(&k_gibbs_gather<Q, 8, LP, MH, MAXW>) kern =
+      gs.items == 31   ? k_gibbs_gather<Q, 31, LP, MH, MAXW>
+      : gs.items == 16 ? k_gibbs_gather<Q, 16, LP, MH, MAXW>
+                       : k_gibbs_gather<Q, 8, LP, MH, MAXW>;
+  if constexpr (LN > 0) {
+    if (gs.lpc == LN)
+      kern = gs.items == 31   ? k_gibbs_gather<Q, 31, LN, MH, MAXW>
+             : gs.items == 16 ? k_gibbs_gather<Q, 16, LN, MH, MAXW>
+                              : k_gibbs_gather<Q, 8, LN, MH, MAXW>;
+  }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);
   if (e != hipSuccess) return e;

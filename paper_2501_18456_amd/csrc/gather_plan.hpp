@@ -32,8 +32,9 @@ constexpr int gather_qp(int q) { return (q + 3) & ~3; }
 constexpr int gather_v(int q) {
   return gather_qp(q) / 4 <= 1 ? 1 : gather_qp(q) / 4 <= 2 ? 2 : gather_qp(q) / 4 <= 4 ? 4 : 8;
 }
-// Site groups per chain of `lpc` lanes (8 or 16).
-constexpr int gather_s(int q, int lpc) { return lpc / gather_v(q); }
+// Site groups per chain of `lpc` lanes (8 or 16; a narrow chain, one lane
+// per quad of its row, has one).
+constexpr int gather_s(int q, int lpc) { return lpc >= gather_v(q) ? lpc / gather_v(q) : 1; }
 
 struct GatherShape {
   int lpc;        // lanes per chain (8 or 16)
@@ -116,10 +117,10 @@ inline GatherShape gather_shape(int L, int q, int cpb, int lpc) {
   return g.waves ? g : gather_shape_n(L, q, cpb, 4, lpc, false);
 }
 
-// Lanes per chain: a function of q and the draw alone, never of the chain
-// count or the CU share, because the FP32 summation order of a chain's local
-// fields follows its lanes -- with this rule a chain draws the same bits in
-// bmdca_gibbs, in a grouped epoch on a CU share and in a merged
+// Lanes per chain (8 or 16): a function of q and the draw alone, never of
+// the chain count or the CU share, because the FP32 summation order of a
+// chain's local fields follows its lanes -- with this rule a chain draws the
+// same bits in bmdca_gibbs, in a grouped epoch on a CU share and in a merged
 // bmdca_gibbs_streams launch.  8 lanes for q > 8 (16 cost 1.9x at q = 21:
 // the per-wave step overhead doubles).  For q <= 8 (rows of at most two
 // quads) the heat-bath draw also takes 8: its 8-wave kernel reads tokens a
@@ -130,11 +131,26 @@ inline GatherShape gather_shape(int L, int q, int cpb, int lpc) {
 // takes 16 (q = 5, L = 400, 10 000 chains: 24.0 against 27.2 ms).
 constexpr int gather_lanes(int q, bool small) { return (gather_v(q) <= 2 && !small) ? 16 : 8; }
 
-// Chains per workgroup: spread the chains over the CUs (one workgroup per CU
-// at a time) in as few rounds as the largest workgroup that fits allows.
-inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8,
-                               bool small = true) {
-  const int lpc = gather_lanes(q, small);
+// Narrow heat-bath chains: rows of 5, 6 or 7 quads (q = 17..28) can also run
+// with one lane per quad, 12, 10 or 9 chains per wave instead of 8, so no
+// lane of the row gathers idles (q = 21: 6 of 8 lanes would).  Each lane adds
+// its quad over the positions in the same order as in an 8-lane chain, and
+// the draw's cross-lane steps keep the 8-lane association order, so a narrow
+// chain draws the same bits as an 8-lane one (checked over whole runs): the
+// choice may follow the launch shape.  The planner takes it where it saves
+// waves and still leaves at least kGNarrowWaves, two per SIMD (L = 256,
+// q = 21, 20 000 chains: 8 waves instead of 10, 33.5 against 39.6 ms per 10
+// sweeps; with one wave per SIMD it lost: L = 100, 10 000 chains, 4 instead
+// of 5 waves, 5.71 against 5.45 ms).
+constexpr int kGNarrowWaves = 8;
+constexpr int gather_narrow_lanes(int q, bool small) {
+  return (small && gather_v(q) == 8 && gather_qp(q) / 4 < 8) ? gather_qp(q) / 4 : 0;
+}
+
+// Chains per workgroup for chains of `lpc` lanes: spread the chains over the
+// CUs (one workgroup per CU at a time) in as few rounds as the largest
+// workgroup that fits allows.
+inline GatherShape gather_plan_lanes(int64_t N, int L, int q, int64_t cus, int cap, int lpc) {
   const int cpw = 64 / lpc;  // chains per wave
   int cmax = std::min(cap, kGMaxWaves * cpw);
   while (cmax > cpw && gather_shape(L, q, cmax, lpc).waves == 0) cmax -= cpw;
@@ -142,6 +158,17 @@ inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = k
   const int cpb = (int)std::min<int64_t>(cmax, gp_ceil(N, rounds * cus));
   GatherShape g = gather_shape(L, q, cpb, lpc);
   g.blocks = (unsigned)gp_ceil(N, (int64_t)cpb);
+  return g;
+}
+
+inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8,
+                               bool small = true) {
+  const GatherShape g = gather_plan_lanes(N, L, q, cus, cap, gather_lanes(q, small));
+  const int nl = gather_narrow_lanes(q, small);
+  if (nl > 0 && g.waves > kGNarrowWaves) {
+    const GatherShape n = gather_plan_lanes(N, L, q, cus, cap, nl);
+    if (n.waves >= kGNarrowWaves && n.waves < g.waves && n.blocks <= g.blocks) return n;
+  }
   return g;
 }
 

@@ -29,13 +29,20 @@ static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
   const GatherShape g = gather_plan(N, L, q, cus, cap, small);
   // lanes per chain: fixed by q and the draw (8; 16 for Metropolis at q <= 8),
   // whatever the chain count, CU share and cap
+  // or narrow heat-bath chains (one lane per quad, q = 17..28) in plans of at
+  // least kGNarrowWaves waves
+  const int nq = gather_qp(q) / 4;
   const int want = (gather_v(q) <= 2 && !small) ? 16 : 8;
-  CHECK(g.lpc == want, "lpc %d, expected %d (q %d, cpb %d, small %d)", g.lpc, want, q, g.cpb,
-        (int)small);
+  const bool narrow_ok = small && gather_v(q) == 8 && nq < 8;
+  CHECK(g.lpc == want || (narrow_ok && g.lpc == nq && g.waves >= kGNarrowWaves),
+        "lpc %d, expected %d (q %d, cpb %d, small %d)", g.lpc, want, q, g.cpb, (int)small);
   CHECK(g.waves >= kGMinWaves && g.waves <= kGMaxWaves, "waves %d", g.waves);
-  CHECK(g.lpc == 8 || g.lpc == 16, "lpc %d", g.lpc);
+  CHECK(g.lpc == 8 || g.lpc == 16 || (g.lpc >= 5 && g.lpc <= 7 && g.lpc == nq && small),
+        "lpc %d", g.lpc);
   const int S = gather_s(q, g.lpc), QP = gather_qp(q), NQ = QP / 4;
-  const int T = 64 * g.waves, CPB = T / g.lpc;
+  const int CPW = 64 / g.lpc, CPB = g.waves * CPW;  // chains per wave, per workgroup
+  // a narrow chain has one lane per quad and one site group
+  if (g.lpc < 8) CHECK(S == 1 && NQ == g.lpc && CPW * g.lpc <= 64, "narrow S %d NQ %d", S, NQ);
   CHECK(g.cpb >= 1 && g.cpb <= CPB && g.cpb <= cap, "cpb %d of %d", g.cpb, CPB);
   CHECK((int64_t)g.blocks * g.cpb >= N && (int64_t)(g.blocks - 1) * g.cpb < N, "blocks %u", g.blocks);
   CHECK(g.ahead == 3, "ahead %d", g.ahead);

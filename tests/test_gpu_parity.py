@@ -139,7 +139,10 @@ def test_gibbs_gather_multi_sweep_states(L, q, N):
     (77, 21, 2300), (24, 9, 3000), (200, 17, 120), (300, 32, 16), (512, 21, 10),
     # q <= 16 with more than 8 waves (the 16-wave instantiation), and q <= 8
     # where 8 lanes per chain replace 16 (the 8-wave instantiation)
-    (40, 5, 20000), (30, 13, 20000), (60, 8, 10000)])
+    (40, 5, 20000), (30, 13, 20000), (60, 8, 10000),
+    # narrow chains (one lane per quad: 5, 6, 7 lanes) in the 12-wave
+    # instantiation, and 6-lane chains with 13 waves (the 16-wave one)
+    (40, 17, 22000), (60, 21, 19000), (50, 25, 19000), (20, 21, 32768)])
 def test_gibbs_gather_lane_splits(L, q, N):
     """Gather form over the lane layouts and workgroup shapes it picks from
     (L, q, N): after three sweeps in one call every chain that differs from
