@@ -220,7 +220,9 @@ typedef struct bmdca_chain_stream {
  * get alone (same sampler form).  All chains run `sweeps` sweeps.  The
  * random words and draw rules are those of the alone call.  The FP32 local
  * fields of the gather form are summed in an order fixed by L, q and the draw
- * (the lanes per chain are a function of q and the draw alone), so heat-bath
+ * (the lanes per chain are a function of q and the draw alone; heat-bath
+ * chains with 5..7 quads per row may run narrow, one lane per quad, where a
+ * launch has many chains per CU, and draw the same bits), so heat-bath
  * chains are bit-identical to their alone call in any launch.  For
  * Metropolis the order also follows the chunk length, which the chains per
  * workgroup bound where their tokens fill the LDS; where two launches differ

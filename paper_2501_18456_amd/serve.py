@@ -31,7 +31,8 @@ served to a stream of requests:
 A request's result does not depend on what else is in flight: energies of a
 sequence are independent of the batch (pair order fixed by L), mutant scans
 are per wild type, and the gather-form sampler's draws depend only on the
-chain's stream record (its lanes per chain are fixed by q and the draw), so
+chain's stream record (its field sums follow lanes per chain fixed by q and
+the draw, or narrow lanes that give the same bits), so
 every result equals the plain library call made alone, bit for bit.  Every
 computation runs in the HIP library; this module moves data and decides
 what to launch when.
