@@ -17,9 +17,10 @@ namespace bmdca {
 // (i, a) and columns (j, b), j in the chunk.  A workgroup owns 1024
 // sequences (four per thread) and one contiguous range of steps; it stages
 // each tile in LDS once (double-buffered through registers) and every
-// sequence picks J[(i, s_i), (j, s_j)] for its own tokens.  The FP32 terms
-// are summed in FP64 in step order, one FP64 partial sum per (range,
-// sequence); the finish adds the fields and the partials in range order.
+// sequence picks J[(i, s_i), (j, s_j)] for its own tokens.  A step's 16
+// terms are summed in FP32 in column order and the step sums in FP64 in step
+// order, one FP64 partial sum per (range, sequence); the finish adds the
+// fields and the partials in range order.
 // The ranges depend on L only, so a sequence's energy does not depend on the
 // rest of the batch.
 // ---------------------------------------------------------------------------
@@ -56,16 +57,20 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
                                                             const int64_t* __restrict__ count) {
   if (count && *count < B) B = *count;  // live sequences of a launch sized for B
   if ((int64_t)blockIdx.x * kESeqBlock >= B) return;  // whole workgroup, before any barrier
-  constexpr int kW = kEJC * Q;                                 // tile row length
-  constexpr int kNV = (Q * kW + kEThreads - 1) / kEThreads;    // tile floats per thread
-  __shared__ float tile[2][Q * kW];
+  constexpr int kW = kEJC * Q;                                 // tile row length (16 Q floats)
+  constexpr int kRowQ = kW / 4;                                // 16-byte quads per tile row
+  constexpr int kQuads = Q * kRowQ;                            // quads per tile
+  constexpr int kNQ = (kQuads + kEThreads - 1) / kEThreads;    // tile quads per thread
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) float tile[2][Q * kW];
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int64_t t0 = steps * p / parts, t1 = steps * (p + 1) / parts;
   const int Lq = L * Q;
+  const int64_t b0 = (int64_t)blockIdx.x * kESeqBlock;  // first sequence of the workgroup
   int64_t bs[kESeq];
 #pragma unroll
-  for (int k = 0; k < kESeq; ++k) bs[k] = (int64_t)blockIdx.x * kESeqBlock + tid + kEThreads * k;
+  for (int k = 0; k < kESeq; ++k) bs[k] = b0 + tid + kEThreads * k;
 
   // (jc, i) of step t0
   int jc = 0;
@@ -76,25 +81,53 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
   }
   int i = (int)r;
 
+  // Tokens through a buffer resource over XT [L][Bpad]: the workgroup's rows
+  // of a site start at the scalar offset site Bpad + b0; reads past the
+  // array (sequences beyond Bpad) return 0, padding rows hold -1 (read as 0).
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)XT, (short)0, (int)((size_t)L * Bpad), 0x00020000);
   auto tok = [&](int site, int k) -> int {
-    const int t = (bs[k] < B) ? (int)XT[(size_t)site * Bpad + bs[k]] : 0;
+    const int t = (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(
+        rx, tid + kEThreads * k, (int)((size_t)site * Bpad + b0), 0);
     return t < 0 ? 0 : t;  // invalid tokens were flagged by the transpose
   };
-  float v[kNV];
-  auto load_tile = [&](int ti, int tjc) {
-    const int w = min(kEJC, L - tjc * kEJC) * Q;  // valid columns
+  // Tile (ti, tjc): rows (ti Q + a), columns tjc kW + c of J, as 16-byte
+  // quads; quad e = a kRowQ + c4 of the tile comes from float
+  // a Lq + 4 c4 past the tile's corner (32-bit offsets fixed per thread).
+  // Columns past the last site (partial last chunk) bring values of the next
+  // row, or zeros past the end of J: lookups never read them.
+  uint32_t qoff[kNQ];
 #pragma unroll
-    for (int n = 0; n < kNV; ++n) {
-      const int e = tid + kEThreads * n;
-      const int a = e / kW, c = e % kW;
-      v[n] = (a < Q && c < w) ? J[(size_t)(ti * Q + a) * Lq + tjc * kW + c] : 0.0f;
+  for (int n = 0; n < kNQ; ++n) {
+    const int e = tid + kEThreads * n;
+    qoff[n] = (uint32_t)((e / kRowQ) * Lq + 4 * (e % kRowQ)) * 4u;
+  }
+  const uint32_t jbytes = (uint32_t)((size_t)Lq * Lq * sizeof(float));
+  auto load_tile = [&](f4(&v)[kNQ], int ti, int tjc) {
+    const uint32_t corner = (uint32_t)(((size_t)ti * Q * Lq + (size_t)tjc * kW) * sizeof(float));
+    const __amdgpu_buffer_rsrc_t rj = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const char*>(J) + corner), (short)0, (int)(jbytes - corner),
+        0x00020000);
+#pragma unroll
+    for (int n = 0; n < kNQ; ++n) {
+      if (tid + kEThreads * n < kQuads) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rj, (int)qoff[n], 0, 0);
+        v[n] = f4{__uint_as_float(w[0]), __uint_as_float(w[1]), __uint_as_float(w[2]),
+                  __uint_as_float(w[3])};
+      }
     }
   };
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](const f4(&v)[kNQ], int buf) {
 #pragma unroll
-    for (int n = 0; n < kNV; ++n) {
+    for (int n = 0; n < kNQ; ++n) {
       const int e = tid + kEThreads * n;
-      if (e < Q * kW) tile[buf][e] = v[n];
+      if (e < kQuads) *reinterpret_cast<f4*>(&tile[buf][4 * e]) = v[n];
+    }
+  };
+  auto advance = [&](int& ii, int& jj) {
+    if (++ii >= energy_rows(jj, L)) {
+      ii = 0;
+      ++jj;
     }
   };
 
@@ -111,43 +144,80 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
         sj[k][jj] = (j < L) ? tok(j, k) : 0;
       }
   };
-
-  if (t0 < t1) {
-    load_tile(i, jc);
-    store_tile(0);
-    load_chunk(jc);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int64_t t = t0; t < t1; ++t) {
-    // next step's coordinates and tile (in flight during this step)
-    int ni = i + 1, njc = jc;
-    if (ni >= energy_rows(jc, L)) {
-      ni = 0;
-      ++njc;
-    }
-    const bool more = t + 1 < t1;
-    if (more) load_tile(ni, njc);
-    int si[kESeq];
-#pragma unroll
-    for (int k = 0; k < kESeq; ++k) si[k] = tok(i, k) * kW;
+  // The lookups of one step (row site si_, chunk cjc, LDS buffer buf): the
+  // step's terms summed in FP32 in column order, then added to the FP64 sum.
+  auto lookups = [&](int si_, int cjc, const int(&srow)[kESeq], int buf) {
     const float* tb = tile[buf];
+    float sf[kESeq];
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) sf[k] = 0.0f;
 #pragma unroll
     for (int jj = 0; jj < kEJC; ++jj) {
-      const int j = jc * kEJC + jj;
-      if (j > i && j < L) {  // uniform over the workgroup
+      const int j = cjc * kEJC + jj;
+      if (j > si_ && j < L) {  // uniform over the workgroup
 #pragma unroll
-        for (int k = 0; k < kESeq; ++k) acc[k] += (double)tb[si[k] + jj * Q + sj[k][jj]];
+        for (int k = 0; k < kESeq; ++k) sf[k] += tb[srow[k] + jj * Q + sj[k][jj]];
       }
     }
-    if (more) {
-      store_tile(buf ^ 1);
-      if (njc != jc) load_chunk(njc);
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) acc[k] += (double)sf[k];
+  };
+
+  // The tile of step t + 1 is fetched into registers during step t and
+  // stored to LDS buffer (t + 1 - t0) % 2 at its end; the row tokens of step
+  // t + 2 are fetched during step t into the registers of t's parity (A: even
+  // offsets from t0, B: odd), so the lookups never wait on a load issued in
+  // their own step and no register copy waits for one.
+  f4 v[kNQ];
+  int sA[kESeq], sB[kESeq];
+  int iA = i, jA = jc, iB = i, jB = jc;
+  advance(iB, jB);
+  if (t0 < t1) {
+    load_tile(v, iA, jA);
+    store_tile(v, 0);
+    load_chunk(jA);
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) sA[k] = tok(iA, k) * kW;
+  }
+  if (t0 + 1 < t1) {
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) sB[k] = tok(iB, k) * kW;
+  }
+  __syncthreads();
+  for (int64_t t = t0; t < t1; t += 2) {
+    // ---- step t (A)
+    int iC = iB, jC = jB;  // step t + 2
+    advance(iC, jC);
+    if (t + 1 < t1) load_tile(v, iB, jB);
+    lookups(iA, jA, sA, 0);
+    if (t + 2 < t1) {
+#pragma unroll
+      for (int k = 0; k < kESeq; ++k) sA[k] = tok(iC, k) * kW;
+    }
+    if (t + 1 < t1) {
+      store_tile(v, 1);
+      if (jB != jA) load_chunk(jB);
     }
     __syncthreads();
-    buf ^= 1;
-    i = ni;
-    jc = njc;
+    if (t + 1 >= t1) break;
+    // ---- step t + 1 (B)
+    int iD = iC, jD = jC;  // step t + 3
+    advance(iD, jD);
+    if (t + 2 < t1) load_tile(v, iC, jC);
+    lookups(iB, jB, sB, 1);
+    if (t + 3 < t1) {
+#pragma unroll
+      for (int k = 0; k < kESeq; ++k) sB[k] = tok(iD, k) * kW;
+    }
+    if (t + 2 < t1) {
+      store_tile(v, 0);
+      if (jC != jB) load_chunk(jC);
+    }
+    __syncthreads();
+    iA = iC;
+    jA = jC;
+    iB = iD;
+    jB = jD;
   }
 #pragma unroll
   for (int k = 0; k < kESeq; ++k)
