@@ -81,14 +81,18 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
   }
   int i = (int)r;
 
-  // Tokens through a buffer resource over XT [L][Bpad]: the workgroup's rows
-  // of a site start at the scalar offset site Bpad + b0; reads past the
-  // array (sequences beyond Bpad) return 0, padding rows hold -1 (read as 0).
-  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)XT, (short)0, (int)((size_t)L * Bpad), 0x00020000);
-  auto tok = [&](int site, int k) -> int {
-    const int t = (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(
-        rx, tid + kEThreads * k, (int)((size_t)site * Bpad + b0), 0);
+  // Tokens of a site through a buffer resource over the workgroup's part of
+  // that site's row of XT [L][Bpad] (64-bit base, at most Bpad - b0 bytes,
+  // under 2^31): reads past the row (sequences beyond Bpad) return 0,
+  // padding rows hold -1 (read as 0).
+  auto site_rsrc = [&](int site) {
+    const int64_t left = Bpad - b0;  // > 0: b0 < B <= Bpad
+    return __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(XT + (size_t)site * Bpad + b0), (short)0,
+        (int)std::min<int64_t>(left, 0x7FFFFFFF), 0x00020000);
+  };
+  auto tok_in = [&](__amdgpu_buffer_rsrc_t rs, int k) -> int {
+    const int t = (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(rs, tid + kEThreads * k, 0, 0);
     return t < 0 ? 0 : t;  // invalid tokens were flagged by the transpose
   };
   // Tile (ti, tjc): rows (ti Q + a), columns tjc kW + c of J, as 16-byte
@@ -102,12 +106,14 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
     const int e = tid + kEThreads * n;
     qoff[n] = (uint32_t)((e / kRowQ) * Lq + 4 * (e % kRowQ)) * 4u;
   }
-  const uint32_t jbytes = (uint32_t)((size_t)Lq * Lq * sizeof(float));
+  const size_t jbytes = (size_t)Lq * Lq * sizeof(float);  // up to 2^32 (L 1024, q 32)
   auto load_tile = [&](f4(&v)[kNQ], int ti, int tjc) {
-    const uint32_t corner = (uint32_t)(((size_t)ti * Q * Lq + (size_t)tjc * kW) * sizeof(float));
+    // a resource from the tile's corner to the end of J, at most 2^31 - 1
+    // bytes (a tile spans under q Lq 4 + 16 q 4 bytes, far less)
+    const size_t corner = ((size_t)ti * Q * Lq + (size_t)tjc * kW) * sizeof(float);
     const __amdgpu_buffer_rsrc_t rj = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(reinterpret_cast<const char*>(J) + corner), (short)0, (int)(jbytes - corner),
-        0x00020000);
+        (void*)(reinterpret_cast<const char*>(J) + corner), (short)0,
+        (int)std::min<size_t>(jbytes - corner, 0x7FFFFFFF), 0x00020000);
 #pragma unroll
     for (int n = 0; n < kNQ; ++n) {
       if (tid + kEThreads * n < kQuads) {
@@ -137,12 +143,17 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
   int sj[kESeq][kEJC];
   auto load_chunk = [&](int cjc) {
 #pragma unroll
-    for (int k = 0; k < kESeq; ++k)
+    for (int jj = 0; jj < kEJC; ++jj) {
+      const int j = cjc * kEJC + jj;
+      const __amdgpu_buffer_rsrc_t rs = site_rsrc(min(j, L - 1));
 #pragma unroll
-      for (int jj = 0; jj < kEJC; ++jj) {
-        const int j = cjc * kEJC + jj;
-        sj[k][jj] = (j < L) ? tok(j, k) : 0;
-      }
+      for (int k = 0; k < kESeq; ++k) sj[k][jj] = (j < L) ? tok_in(rs, k) : 0;
+    }
+  };
+  auto row_tokens = [&](int(&s)[kESeq], int site) {
+    const __amdgpu_buffer_rsrc_t rs = site_rsrc(site);
+#pragma unroll
+    for (int k = 0; k < kESeq; ++k) s[k] = tok_in(rs, k) * kW;
   };
   // The lookups of one step (row site si_, chunk cjc, LDS buffer buf): the
   // step's terms summed in FP32 in column order, then added to the FP64 sum.
@@ -176,12 +187,10 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
     load_tile(v, iA, jA);
     store_tile(v, 0);
     load_chunk(jA);
-#pragma unroll
-    for (int k = 0; k < kESeq; ++k) sA[k] = tok(iA, k) * kW;
+    row_tokens(sA, iA);
   }
   if (t0 + 1 < t1) {
-#pragma unroll
-    for (int k = 0; k < kESeq; ++k) sB[k] = tok(iB, k) * kW;
+    row_tokens(sB, iB);
   }
   __syncthreads();
   for (int64_t t = t0; t < t1; t += 2) {
@@ -191,8 +200,7 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
     if (t + 1 < t1) load_tile(v, iB, jB);
     lookups(iA, jA, sA, 0);
     if (t + 2 < t1) {
-#pragma unroll
-      for (int k = 0; k < kESeq; ++k) sA[k] = tok(iC, k) * kW;
+      row_tokens(sA, iC);
     }
     if (t + 1 < t1) {
       store_tile(v, 1);
@@ -206,8 +214,7 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
     if (t + 2 < t1) load_tile(v, iC, jC);
     lookups(iB, jB, sB, 1);
     if (t + 3 < t1) {
-#pragma unroll
-      for (int k = 0; k < kESeq; ++k) sB[k] = tok(iD, k) * kW;
+      row_tokens(sB, iD);
     }
     if (t + 2 < t1) {
       store_tile(v, 0);

@@ -256,6 +256,27 @@ def test_rna_gibbs_and_counts():
     assert np.array_equal(host(f2)[r1, r2], O.stats_entries(g, q, r1, r2, None, 0.0))
 
 
+# ---------------------------------------------------------------- batches past 2^31 bytes
+def test_energy_batch_beyond_2gib_of_tokens():
+    """40 million sequences at L = 64: the transposed tokens (L x B bytes)
+    pass 2^31, so every 32-bit offset over the whole array would overflow;
+    sampled energies, the last sequences among them, follow the oracle."""
+    L, q, Bn = 64, 21, 40_000_000
+    h, J = synth.planted_dense(L, q, seed=1011, sigma_J=0.05)
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    S = torch.randint(0, q, (Bn, L), generator=gen, dtype=torch.int64, device="cuda").to(torch.int8)
+    E = api.energy(dev(h), dev(J), S)
+    idx = np.concatenate([[0, 1, Bn // 2, Bn - 2, Bn - 1],
+                          np.random.default_rng(13).integers(0, Bn, 40)])
+    sel = torch.from_numpy(idx).cuda()
+    Eg = host(E[sel])
+    Ss = host(S[sel])
+    del S, E
+    torch.cuda.empty_cache()
+    Eo = O.energy(h, J, Ss, q)
+    assert np.all(np.abs(Eg - Eo) <= 1e-4 * np.abs(Eo).max())
+
+
 # ---------------------------------------------------------------- largest served model
 def test_largest_model_scores():
     L, q = 512, 21
