@@ -141,7 +141,8 @@ constexpr int gather_lanes(int q, bool small) { return (gather_v(q) <= 2 && !sma
 // waves and still leaves at least kGNarrowWaves, two per SIMD (L = 256,
 // q = 21, 20 000 chains: 8 waves instead of 10, 33.5 against 39.6 ms per 10
 // sweeps; with one wave per SIMD it lost: L = 100, 10 000 chains, 4 instead
-// of 5 waves, 5.71 against 5.45 ms).
+// of 5 waves, 5.71 against 5.45 ms; 7 instead of 8 waves was mixed, 16 384
+// chains: +2.4% at L = 100, +1.3% at L = 256, -3.9% at L = 512).
 constexpr int kGNarrowWaves = 8;
 constexpr int gather_narrow_lanes(int q, bool small) {
   return (small && gather_v(q) == 8 && gather_qp(q) / 4 < 8) ? gather_qp(q) / 4 : 0;
