@@ -3,6 +3,8 @@
 // two are instantiated in separate sources (sampler.hip, sampler_mh.hip) so
 // that they compile in parallel.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 #include "gather_plan.hpp"
 #include "internal.hpp"
@@ -466,9 +468,51 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
         for (int e = 0; e < 16; ++e)
           if (!tail || r0 + e < jcs) acc += x[e];
       };
-      int r0 = 0;
-      for (; r0 + 16 <= jcs; r0 += 16) group(r0, false);
-      if (r0 < jcs) group(r0, true);
+      if (QP < 24 && QP != 16 && jcs % 16 != 0) {
+        // Rows of 1-3 or 5 quads (q <= 12, q = 17..20) in chunks whose
+        // positions per lane are not a multiple of 16: groups of a
+        // compile-time length over the
+        // positions of this chunk that can hold a site j < L (a multiple of
+        // 4, at most jcs; the rest, past the run in a site's last chunk, are
+        // zero rows, and adding +0 to a sum that started at +0 changes no
+        // bit), with no clamped or skipped reads in the tail group.  Measured
+        // per 10 sweeps: q = 5, L = 400: 23.2 -> 17.4 ms; q = 12, L = 200:
+        // 14.5 -> 11.2; q = 17, L = 150: 15.6 -> 10.9.  Where the positions
+        // are a multiple of 16 (q = 8, L = 60; q = 13, L = 130) this form was
+        // 2-4% slower, so those take the group below; with both forms in the
+        // kernel the compiler scheduled the common group of 16-float rows
+        // (q = 13..16) worse (5% at q = 13, L = 130), and for rows of 6-8
+        // quads (q = 21) the new form itself read 10-13% slower, so those
+        // instantiations keep the group below alone.
+        const int nv = min(jcs, (((L - k * jc + S - 1) / S) + 3) & ~3);
+        auto tgroup = [&](int r1, auto n_c) {
+          constexpr int n = decltype(n_c)::value;
+          uint32_t tk[n / 4];
+#pragma unroll
+          for (int d = 0; d < n / 4; ++d)
+            tk[d] = (kPipeTok && r1 == 0) ? g_tok[d] : tw[min(((m0 + r1) >> 2) + d, m4 - 1) * CPB];
+          f4 x[n];
+#pragma unroll
+          for (int e = 0; e < n; ++e) {
+            const uint32_t so = __umul24((tk[e >> 2] >> (8 * (e & 3))) & 0xFFu, (uint32_t)QP);
+            x[e] = *reinterpret_cast<const f4*>(jb + (S * (r1 + e) + u) * Q * QP + so);
+          }
+#pragma unroll
+          for (int e = 0; e < n; ++e) acc += x[e];
+        };
+        int r1 = 0;
+        for (; r1 + 16 <= nv; r1 += 16) tgroup(r1, std::integral_constant<int, 16>{});
+        if (nv - r1 == 12)
+          tgroup(r1, std::integral_constant<int, 12>{});
+        else if (nv - r1 == 8)
+          tgroup(r1, std::integral_constant<int, 8>{});
+        else if (nv - r1 == 4)
+          tgroup(r1, std::integral_constant<int, 4>{});
+      } else {
+        int r0 = 0;
+        for (; r0 + 16 <= jcs; r0 += 16) group(r0, false);
+        if (r0 < jcs) group(r0, true);
+      }
       if (kPipeTok) {
         // the next chunk-step's first token dwords (same site's next chunk,
         // or the next site's first chunk)
