@@ -39,7 +39,11 @@ hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t 
 // Local fields from scratch: H[c][r] = h[r] + sum_{k != site(r)} J[(k, s_k)][r],
 // summed in FP32 in the order k = 0..L-1.  By the symmetry of J this equals
 // h_j(b) + sum_{k != j} J_jk(b, s_k) for r = (j, b).
-// Grid: x over chains, y over 256-column slices of the row.
+// Grid: x over chains, y over 1024-column slices of the row; a thread owns
+// four consecutive columns and reads them with one 16-byte load per coupling
+// row, through a resource that ends with the row (4-byte aligned loads; past
+// the row end they return 0).  The term of a column's own site is dropped by
+// a select on the sum, so each column's sum is that of the plain loop.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ h,
                                                       const float* __restrict__ J,
@@ -58,15 +62,41 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
     rowbase[k] = k * q + t;
   }
   __syncthreads();
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
-  if (r >= Lq) return;
-  const int site = r / q;
-  float acc = h[r];
-  for (int k = 0; k < L; ++k) {
-    if (k == site) continue;
-    acc += J[(size_t)rowbase[k] * Lq + r];
+  const int r0 = 4 * (blockIdx.y * blockDim.x + threadIdx.x);
+  if (r0 >= Lq) return;
+  int site[4];
+  float acc[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    site[e] = (r0 + e) / q;
+    acc[e] = (r0 + e < Lq) ? h[r0 + e] : 0.0f;
   }
-  H[(size_t)c * Lq + r] = acc;
+  auto row = [&](int k) {
+    const int rb = __builtin_amdgcn_readfirstlane(rowbase[k]);  // uniform
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(J + (size_t)rb * Lq), (short)0, (int)(Lq * sizeof(float)), 0x00020000);
+    return __builtin_amdgcn_raw_buffer_load_b128(rs, r0 * (int)sizeof(float), 0, 0);
+  };
+  auto add = [&](int k, decltype(row(0)) w) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float sum = acc[e] + __uint_as_float(w[e]);
+      acc[e] = (k == site[e]) ? acc[e] : sum;
+    }
+  };
+  // four rows in flight, added in k order
+  int k = 0;
+  for (; k + 4 <= L; k += 4) {
+    const auto w0 = row(k), w1 = row(k + 1), w2 = row(k + 2), w3 = row(k + 3);
+    add(k, w0);
+    add(k + 1, w1);
+    add(k + 2, w2);
+    add(k + 3, w3);
+  }
+  for (; k < L; ++k) add(k, row(k));
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (r0 + e < Lq) H[(size_t)c * Lq + r0 + e] = acc[e];
 }
 
 hipError_t launch_local_fields(const float* h, const float* J, const int8_t* chains, int64_t N,
@@ -74,7 +104,7 @@ hipError_t launch_local_fields(const float* h, const float* J, const int8_t* cha
                                const int32_t* active, const int64_t* count) {
   const int Lq = L * q;
   const int bs = 256;
-  dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, bs));
+  dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, 4 * bs));
   hipLaunchKernelGGL(k_local_fields, grid, dim3(bs), sizeof(int) * L, s, h, J, chains, N, L, q, H,
                      dev_err, active, count);
   return hipGetLastError();
