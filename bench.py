@@ -45,7 +45,7 @@ GATHER_TRAFFIC_SOURCES = ("paper_2501_18456_amd/csrc/gather_kernel.hpp",
                           "paper_2501_18456_amd/csrc/common.hpp")
 # workload -> bytes per launch: the gather kernel's 10-sweep launch and the
 # field kernel's 5-sweep launch of the precision form (L = 256, N = 20 000)
-GATHER_TRAFFIC = {"sha256": "06701792a305ee1257e430065fff4bd1892463099b2dea5b526ea8ea22bf2742",
+GATHER_TRAFFIC = {"sha256": "063d90edf6693cfa8855469e7acf4cb25b741fbc1da548a190d5431018dc7510",
                   "bytes": {"precision": 1.18806e10,           # 1.18754e10 read + 5.2e6 written
                             "precision-fields": 1.98215e+12}}  # 1.4603e+12 read + 5.2185e+11
 
