@@ -39,8 +39,8 @@ hipError_t launch_init_chains(int8_t* chains, int64_t N, int L, int q, uint64_t 
 // Local fields from scratch: H[c][r] = h[r] + sum_{k != site(r)} J[(k, s_k)][r],
 // summed in FP32 in the order k = 0..L-1.  By the symmetry of J this equals
 // h_j(b) + sum_{k != j} J_jk(b, s_k) for r = (j, b).
-// Grid: x over chains, y over 1024-column slices of the row; a thread owns
-// four consecutive columns and reads them with one 16-byte load per coupling
+// Workgroups over (chain, column block): blocks of equal width, at most 1024
+// columns; a thread owns four consecutive columns and reads them with one 16-byte load per coupling
 // row, through a resource that ends with the row (4-byte aligned loads; past
 // the row end they return 0).  The term of a column's own site is dropped by
 // a select on the sum, so each column's sum is that of the plain loop.
@@ -51,9 +51,19 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
                                                       int L, int q, float* __restrict__ H,
                                                       int32_t* dev_err,
                                                       const int32_t* __restrict__ active,
-                                                      const int64_t* __restrict__ count) {
+                                                      const int64_t* __restrict__ count,
+                                                      int64_t g0, int wq) {
   if (active && *active == 0) return;
-  const int64_t c = blockIdx.x;
+  // Workgroups are numbered so that each XCD runs a contiguous range of the
+  // (column block, chain) order, chain fastest: the chains of one column
+  // block walk the sites together on one XCD, and a coupling row segment that
+  // several of them read (the same residue at a site) comes from that XCD's
+  // L2 after the first.  The hardware deals consecutive workgroup ids to the
+  // 8 XCDs in turn; the mapping is a bijection whatever the real placement.
+  const uint32_t nwg = gridDim.x, f = blockIdx.x, xcd = f % 8u, per = nwg / 8u;
+  const int64_t g = g0 + (int64_t)(xcd * per + min(xcd, nwg % 8u) + f / 8u);
+  const int64_t c = g % N;
+  const int yb = (int)(g / N);
   if (count && c >= *count) return;  // whole workgroup, before any barrier
   extern __shared__ int rowbase[];  // L entries: (k*q + s_k)
   const int Lq = L * q;
@@ -62,8 +72,8 @@ __global__ __launch_bounds__(256) void k_local_fields(const float* __restrict__ 
     rowbase[k] = k * q + t;
   }
   __syncthreads();
-  const int r0 = 4 * (blockIdx.y * blockDim.x + threadIdx.x);
-  if (r0 >= Lq) return;
+  const int r0 = 4 * (yb * wq + (int)threadIdx.x);
+  if ((int)threadIdx.x >= wq || r0 >= Lq) return;
   int site[4];
   float acc[4];
 #pragma unroll
@@ -103,11 +113,21 @@ hipError_t launch_local_fields(const float* h, const float* J, const int8_t* cha
                                int L, int q, float* H, int32_t* dev_err, hipStream_t s,
                                const int32_t* active, const int64_t* count) {
   const int Lq = L * q;
-  const int bs = 256;
-  dim3 grid((unsigned)N, (unsigned)ceil_div(Lq, 4 * bs));
-  hipLaunchKernelGGL(k_local_fields, grid, dim3(bs), sizeof(int) * L, s, h, J, chains, N, L, q, H,
-                     dev_err, active, count);
-  return hipGetLastError();
+  // column blocks of equal width, wq quads (at most 256), so that every XCD's
+  // range of workgroups holds the same work (a ragged last block left whole
+  // XCDs with the light blocks: 14% longer at L = 256, q = 21)
+  const int quads = (int)ceil_div(Lq, 4), nyb = (int)ceil_div(quads, 256);
+  const int wq = (int)ceil_div(quads, nyb), bs = (int)ceil_div(wq, 64) * 64;
+  // one launch per 2^22 workgroups (a grid dimension holds fewer than 2^32
+  // work-items)
+  const int64_t nwg = N * nyb, chunk = (int64_t)1 << 22;
+  for (int64_t g0 = 0; g0 < nwg; g0 += chunk) {
+    hipLaunchKernelGGL(k_local_fields, dim3((unsigned)std::min(chunk, nwg - g0)), dim3(bs),
+                       sizeof(int) * L, s, h, J, chains, N, L, q, H, dev_err, active, count, g0, wq);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
