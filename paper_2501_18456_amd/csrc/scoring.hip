@@ -317,82 +317,124 @@ hipError_t launch_mutant_delta(const float* H, const int8_t* wt, int64_t B, int 
 }
 
 // ---------------------------------------------------------------------------
-// APC Frobenius.  k_frob_rows: a workgroup owns block-row i and one chunk of
-// 16 sites j (only j > i are blocks): the q x 16q tile of rows (i, a) is read
-// into LDS with each thread owning columns and all q row loads in flight at
-// once (coalesced over the columns; row stride 16q + 1 floats, odd, so that
-// the column walks below hit distinct banks); 16 threads per block then take
-// the block's row and column means over all states (FP64), the total mean,
-// and sum the squares of the gauged entries with a, b != gap; F_ij = F_ji =
-// the square root.  J is read once.  k_apc_rows: S_i = sum_k F_ik (one wave
-// per row); k_apc_total: S = sum_i S_i; k_apc_out: F_apc = F - S_i S_j / S,
-// diagonals 0.
+// APC Frobenius.  k_frob_blocks: each wave takes 64 / q blocks (i, j), j > i,
+// of one block-row i; lane (block, t) owns row t and column t of its block,
+// both held in registers: the row by 16-byte loads, the column by 4-byte
+// loads that are coalesced over the block's lanes (and hit the cache lines
+// the row loads brought in).  In FP64 the lane forms the row mean r_t and the
+// column mean c_t over all q states; the column means go through LDS, every
+// lane of the block reads all q of them and their mean m, and sums the
+// squares of the gauged entries J_tb - r_t - c_b + m of its row with
+// t, b != gap; one lane per block adds the q row sums in order, and
+// F_ij = F_ji = the square root.  Block-rows i and L - 1 - i share a run of
+// wave tasks (L - 1 blocks between them), so every run is as long.  J is read
+// once, without LDS staging.  k_apc_rows: S_i = sum_k F_ik (one wave per
+// row); k_apc_total: S = sum_i S_i; k_apc_out: F_apc = F - S_i S_j / S,
+// diagonals 0 (the diagonal of F is never read).
 // ---------------------------------------------------------------------------
-constexpr int kFJC = 16;
-
 size_t apc_ws_bytes(int L) { return align256(sizeof(double) * ((size_t)L * L + L + 8)); }
 
-__global__ __launch_bounds__(256) void k_frob_rows(const float* __restrict__ J, int L, int q,
-                                                   int gap, double* __restrict__ F) {
-  extern __shared__ double frob_smem[];  // rmean[16][32], cmean[16][32], then the tile
-  double* rmean = frob_smem;
-  double* cmean = frob_smem + kFJC * 32;
-  float* tile = reinterpret_cast<float*>(frob_smem + 2 * kFJC * 32);  // q x (16 q + 1)
-  const int i = blockIdx.y;
-  const int j0 = blockIdx.x * kFJC;
+// Wave tasks per pair of block-rows (p, L - 1 - p): ceil((L - 1 - p) / bpw)
+// tasks of row p and ceil(p / bpw) of row L - 1 - p, at most this many.
+inline int frob_tasks_per_pair(int L, int q) { return (int)ceil_div(L - 1, 64 / q) + 1; }
+
+// QP4: quads per block row, ceil(q / 4).
+template <int QP4>
+__global__ __launch_bounds__(256) void k_frob_blocks(const float* __restrict__ J, int L, int q,
+                                                     int gap, int tpp, double* __restrict__ F) {
+  constexpr int QB = 4 * QP4;  // columns a lane walks (q rounded up to quads)
+  __shared__ double cmean[4][64];  // per wave: c_t of lane (block, t) at block * q + t
+  __shared__ double rowss[4][64];  // per wave: the lanes' sums of squares
+  const int lane = threadIdx.x % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform: the task is
+  const int task = (int)blockIdx.x * 4 + wv;  // below 2^19 (L <= 1024, tpp <= 1024)
+  const int npair = (L + 1) / 2;
+  if (task >= npair * tpp) return;  // whole wave; only wave barriers below
+  const int p = task / tpp, k = task - (task / tpp) * tpp;
+  const int bpw = 64 / q;
+  const int i0 = p, i1 = L - 1 - p;
+  const int n0 = (int)ceil_div(L - 1 - i0, bpw);  // tasks of row i0
+  int i, jfirst;
+  if (k < n0) {
+    i = i0;
+    jfirst = i0 + 1 + k * bpw;
+  } else {
+    if (i1 == i0) return;  // the middle row of an odd L has no partner
+    i = i1;
+    jfirst = i1 + 1 + (k - n0) * bpw;
+    if (jfirst >= L) return;
+  }
+  const int jb = lane / q, t = lane - jb * q;
+  const bool live = jb < bpw && jfirst + jb < L;
+  const int j = live ? jfirst + jb : i;  // dead lanes read block (i, i): in bounds, unused
   const int Lq = L * q;
-  const int W = kFJC * q + 1;
-  const int jb = threadIdx.x / 16, t = threadIdx.x % 16;  // block of the chunk, thread in it
-  if (j0 == 0 && threadIdx.x == 0) F[(size_t)i * L + i] = 0.0;  // never read as a pair
-  if (j0 + kFJC - 1 <= i) return;  // no j > i in this chunk (whole workgroup)
-  const int nj = min(kFJC, L - j0);
-  const float* src = J + (size_t)i * q * Lq + (size_t)j0 * q;
-  for (int c = threadIdx.x; c < nj * q; c += blockDim.x) {
-    float v[32];
+  // Block-row i as one buffer (q Lq floats, at most 4 MiB).  Row t of block
+  // (i, j) starts at float t Lq + j q; the quads past its q-th float read the
+  // next block (or, past the buffer, zeros) and are cleared.
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(J + (size_t)i * q * Lq), (short)0, (int)((size_t)q * Lq * sizeof(float)), 0x00020000);
+  const int rowoff = (t * Lq + j * q) * (int)sizeof(float);
+  double x[QB];
 #pragma unroll
-    for (int a = 0; a < 32; ++a)
-      if (a < q) v[a] = src[(size_t)a * Lq + c];
+  for (int u = 0; u < QP4; ++u) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, rowoff + 16 * u, 0, 0);
 #pragma unroll
-    for (int a = 0; a < 32; ++a)
-      if (a < q) tile[a * W + c] = v[a];
+    for (int e = 0; e < 4; ++e) x[4 * u + e] = (double)__uint_as_float(v[e]);
   }
-  __syncthreads();
-  const bool mine = jb < nj && j0 + jb > i;
-  const float* blk = tile + jb * q;  // element (a, b) at blk[a * W + b]
-  if (mine) {
-    // row sums over b and column sums over a for rows / columns t, t + 16
-    for (int r = t; r < q; r += 16) {
-      double rs = 0.0, cs = 0.0;
-      for (int k = 0; k < q; ++k) {
-        rs += (double)blk[r * W + k];
-        cs += (double)blk[k * W + r];
-      }
-      rmean[jb * 32 + r] = rs / (double)q;
-      cmean[jb * 32 + r] = cs / (double)q;
-    }
+  float y[QB];
+#pragma unroll
+  for (int a = 0; a < QB; ++a)
+    y[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+        rs, (min(a, q - 1) * Lq + j * q + t) * (int)sizeof(float), 0, 0));
+  // entries past q (compile-time positions in the last quad) become +0, which
+  // leaves every sum below unchanged (a sum that starts at +0 never is -0)
+#pragma unroll
+  for (int b = 4 * (QP4 - 1); b < QB; ++b) {
+    x[b] = (b < q) ? x[b] : 0.0;
+    y[b] = (b < q) ? y[b] : 0.0f;
   }
-  __syncthreads();
-  if (mine) {
-    double all = 0.0;
-    for (int a = 0; a < q; ++a) all += rmean[jb * 32 + a];
-    const double mean_all = all / (double)q;
-    double ss = 0.0;
-    for (int b = t; b < q; b += 16) {
-      if (b == gap) continue;
-      const double cb = cmean[jb * 32 + b];
-      for (int a = 0; a < q; ++a) {
-        if (a == gap) continue;
-        const double z = (double)blk[a * W + b] - rmean[jb * 32 + a] - cb + mean_all;
-        ss += z * z;
-      }
-    }
-    for (int o = 8; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 16);
-    if (t == 0) {
-      const double f = sqrt(ss);
-      const int j = j0 + jb;
-      F[(size_t)i * L + j] = f;
-      F[(size_t)j * L + i] = f;
-    }
+  double rsum = 0.0, csum = 0.0;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    rsum += x[b];
+    csum += (double)y[b];
+  }
+  const double r = rsum / (double)q;
+  double* cm = cmean[wv];
+  cm[lane] = csum / (double)q;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const int base = min(jb, bpw - 1) * q;  // this lane's block in the wave's arrays
+  double cb[QB];
+  double all = 0.0;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    // the read is unconditional (a select around it becomes a branch); past q
+    // it is scaled to +-0
+    cb[b] = cm[base + min(b, q - 1)];
+    if (b >= 4 * (QP4 - 1)) cb[b] *= (b < q) ? 1.0 : 0.0;
+    all += cb[b];
+  }
+  const double m = all / (double)q;
+  double ss = 0.0;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    const double w = (b < q && b != gap) ? 1.0 : 0.0;  // uniform per b
+    const double z = ((x[b] - r) - cb[b]) + m;
+    ss = __builtin_fma(z * w, z, ss);  // +-0 for the skipped columns: ss unchanged
+  }
+  double* rss = rowss[wv];
+  rss[lane] = (t == gap) ? 0.0 : ss;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (live && t == 0) {
+    double tot = 0.0;
+    for (int u = 0; u < q; ++u) tot += rss[base + u];
+    const double f = sqrt(tot);
+    F[(size_t)i * L + j] = f;
+    F[(size_t)j * L + i] = f;
   }
 }
 
@@ -436,12 +478,19 @@ hipError_t launch_apc(const float* J, int L, int q, int gap, float* F, float* Fa
                       hipStream_t s) {
   double* Fd = static_cast<double*>(ws);
   double* S = Fd + (size_t)L * L;
-  const size_t lds = sizeof(double) * 2 * kFJC * 32 + sizeof(float) * (size_t)q * (kFJC * q + 1);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_frob_rows),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_frob_rows, dim3((unsigned)ceil_div(L, kFJC), (unsigned)L), dim3(256), lds, s,
-                     J, L, q, gap, Fd);
+  const int tpp = frob_tasks_per_pair(L, q);
+  const unsigned nwg = (unsigned)ceil_div((int64_t)((L + 1) / 2) * tpp, 4);
+  switch ((q + 3) / 4) {
+#define BMDCA_FROB(QP4)                                                                     \
+  case QP4:                                                                                 \
+    hipLaunchKernelGGL(k_frob_blocks<QP4>, dim3(nwg), dim3(256), 0, s, J, L, q, gap, tpp, Fd); \
+    break;
+    BMDCA_FROB(1) BMDCA_FROB(2) BMDCA_FROB(3) BMDCA_FROB(4)
+    BMDCA_FROB(5) BMDCA_FROB(6) BMDCA_FROB(7) BMDCA_FROB(8)
+#undef BMDCA_FROB
+    default:
+      return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(k_apc_rows, dim3((unsigned)ceil_div(L, 4)), dim3(256), 0, s, Fd, L, S);
   hipLaunchKernelGGL(k_apc_total, dim3(1), dim3(256), 0, s, S, L);
   hipLaunchKernelGGL(k_apc_out, dim3((unsigned)ceil_div((size_t)L * L, (size_t)256)), dim3(256), 0,

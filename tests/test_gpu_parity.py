@@ -320,10 +320,16 @@ def test_single_mutant_scan():
         assert np.all(dE[b].reshape(L, q)[np.arange(L), WT[b]] == 0)
 
 
-@pytest.mark.parametrize("gap", [0, -1])
-def test_apc_frobenius(gap):
-    L, q = 45, 21
-    _, J = synth.planted_sparse(L, q, seed=130, sigma_J=0.5)
+@pytest.mark.parametrize("L,q,gap", [(45, 21, 0), (45, 21, -1), (2, 21, 0), (3, 7, -1),
+                                     (33, 2, 1), (64, 13, 12), (77, 32, 0), (50, 5, 2)])
+def test_apc_frobenius(L, q, gap):
+    """Blocks per wave 64 // q from 2 (q = 32) to 32 (q = 2), rows paired as
+    (i, L - 1 - i) with an odd L's middle row alone; no gap, the first,
+    an inner and the last state as the gap."""
+    if L == 45:
+        _, J = synth.planted_sparse(L, q, seed=130, sigma_J=0.5)
+    else:  # every block nonzero
+        _, J = synth.planted_dense(L, q, seed=130 + L + q, sigma_J=0.3)
     F, Fa = api.apc_frobenius(dev(J), L, q, gap)
     Fo, Fao = O.apc_frobenius(J, L, q, gap)
     sc = np.abs(Fo).max()
