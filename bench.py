@@ -960,9 +960,11 @@ def bench_scoring(args):
     mu_hbm = mu_rows * Lq * 4 + nw * 2 * Lq * 4
     log(f"mutant scans {nw} wild types L={L}: {mu_ms:.2f} ms, rows as read "
         f"{mu_bytes / (mu_ms * 1e-3) / 1e9:.0f} GB/s, distinct rows {mu_hbm / (mu_ms * 1e-3) / 1e9:.0f} GB/s")
+    wsa = api.workspace(B.WS_APC, 0, L, q, 0)
+    api.apc_frobenius(Jg, L, q, 0, ws=wsa)
     t.start()
     for _ in range(args.steps):
-        F, Fa = api.apc_frobenius(Jg, L, q, 0)
+        F, Fa = api.apc_frobenius(Jg, L, q, 0, ws=wsa)
     apc_ms = t.stop_ms() / args.steps
     apc_bytes = Lq * Lq * 4 // 2  # J is symmetric: the blocks j > i are read once
     log(f"APC Frobenius L={L}: {apc_ms:.2f} ms, {apc_bytes / (apc_ms * 1e-3) / 1e9:.0f} GB/s")
