@@ -29,6 +29,41 @@ constexpr int kEThreads = 256;
 constexpr int kESeq = 4;                       // sequences per thread
 constexpr int kESeqBlock = kEThreads * kESeq;  // sequences per workgroup
 
+// Row pitch of the LDS tile in floats: 16 Q plus a pad of 0, 4, 8 or 12
+// (rows stay 16-byte aligned).  A lookup's bank is (P s_i + s_j + const) mod
+// 64 over the 64 four-byte banks; the pad is the one whose largest share of
+// the Q^2 pairs (s_i, s_j) in one bank is smallest, then the smallest sum of
+// squared shares, among the pads that keep as many workgroups per CU (two
+// tiles in 160 KB of LDS).  With P = 16 Q the row offsets take
+// 64 / gcd(16 Q, 64) values only: at q = 21 four, so twenty banks carry twice
+// the pairs of the rest; at q = 8 one, so all rows share the banks of their
+// first 8 floats.
+constexpr int energy_pitch(int Q) {
+  constexpr long long kLdsCU = 160 * 1024, kWgCU = 8;  // 32 waves of a CU in 4-wave groups
+  auto wgs = [](long long bytes) { return kLdsCU / bytes < kWgCU ? kLdsCU / bytes : kWgCU; };
+  const long long wg0 = wgs(2LL * Q * 16 * Q * 4);
+  int best = 16 * Q;
+  long long best_mx = -1, best_sq = 0;
+  for (int pad = 0; pad <= 12; pad += 4) {
+    const int P = 16 * Q + pad;
+    if (wgs(2LL * Q * P * 4) < wg0) continue;
+    int cnt[64] = {};
+    for (int a = 0; a < Q; ++a)
+      for (int b = 0; b < Q; ++b) ++cnt[(P * a + b) % 64];
+    long long mx = 0, sq = 0;
+    for (int k = 0; k < 64; ++k) {
+      mx = cnt[k] > mx ? cnt[k] : mx;
+      sq += (long long)cnt[k] * cnt[k];
+    }
+    if (best_mx < 0 || mx < best_mx || (mx == best_mx && sq < best_sq)) {
+      best = P;
+      best_mx = mx;
+      best_sq = sq;
+    }
+  }
+  return best;
+}
+
 // Row sites of chunk jc that pair with some j > i in the chunk.
 __host__ __device__ inline int energy_rows(int jc, int L) {
   return min(jc * kEJC + kEJC - 1, L - 1);
@@ -58,11 +93,12 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
   if (count && *count < B) B = *count;  // live sequences of a launch sized for B
   if ((int64_t)blockIdx.x * kESeqBlock >= B) return;  // whole workgroup, before any barrier
   constexpr int kW = kEJC * Q;                                 // tile row length (16 Q floats)
+  constexpr int kP = energy_pitch(Q);                          // its pitch in LDS
   constexpr int kRowQ = kW / 4;                                // 16-byte quads per tile row
   constexpr int kQuads = Q * kRowQ;                            // quads per tile
   constexpr int kNQ = (kQuads + kEThreads - 1) / kEThreads;    // tile quads per thread
   typedef float f4 __attribute__((ext_vector_type(4)));
-  __shared__ __attribute__((aligned(16))) float tile[2][Q * kW];
+  __shared__ __attribute__((aligned(16))) float tile[2][Q * kP];
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int64_t t0 = steps * p / parts, t1 = steps * (p + 1) / parts;
@@ -127,7 +163,8 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
 #pragma unroll
     for (int n = 0; n < kNQ; ++n) {
       const int e = tid + kEThreads * n;
-      if (e < kQuads) *reinterpret_cast<f4*>(&tile[buf][4 * e]) = v[n];
+      if (e < kQuads)
+        *reinterpret_cast<f4*>(&tile[buf][(e / kRowQ) * kP + 4 * (e % kRowQ)]) = v[n];
     }
   };
   auto advance = [&](int& ii, int& jj) {
@@ -153,7 +190,7 @@ __global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restr
   auto row_tokens = [&](int(&s)[kESeq], int site) {
     const __amdgpu_buffer_rsrc_t rs = site_rsrc(site);
 #pragma unroll
-    for (int k = 0; k < kESeq; ++k) s[k] = tok_in(rs, k) * kW;
+    for (int k = 0; k < kESeq; ++k) s[k] = tok_in(rs, k) * kP;
   };
   // The lookups of one step (row site si_, chunk cjc, LDS buffer buf): the
   // step's terms summed in FP32 in column order, then added to the FP64 sum.
