@@ -935,7 +935,7 @@ def bench_scoring(args):
         api.energy(hg, Jg, S, out=E, ws=wse)
     en_ms = t.stop_ms() / args.steps
     pairs = Bn * L * (L - 1) / 2
-    blocks = -(-Bn // 1024)
+    blocks = -(-Bn // (2048 if q > 8 else 1024))  # sequences per workgroup
     tiles = sum(min(16 * jc + 15, L - 1) for jc in range(-(-L // 16)))
     lds_bytes = pairs * 4 + blocks * tiles * q * 16 * q * 4  # lookups + staged tiles
     lds_peak = 256 * LDS_BYTES_PER_CLK * 2.4e9

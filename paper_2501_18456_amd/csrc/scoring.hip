@@ -14,20 +14,24 @@ namespace bmdca {
 //
 // The pairs i < j are walked as steps (column chunk jc of kEJC sites, row
 // site i), jc outer: a step needs the q x (kEJC*q) tile of J with rows
-// (i, a) and columns (j, b), j in the chunk.  A workgroup owns 1024
-// sequences (four per thread) and one contiguous range of steps; it stages
+// (i, a) and columns (j, b), j in the chunk.  A workgroup owns 2048 (q > 8)
+// or 1024 sequences (four per thread) and one contiguous range of steps; it stages
 // each tile in LDS once (double-buffered through registers) and every
 // sequence picks J[(i, s_i), (j, s_j)] for its own tokens.  A step's 16
 // terms are summed in FP32 in column order and the step sums in FP64 in step
 // order, one FP64 partial sum per (range, sequence); the finish adds the
 // fields and the partials in range order.
 // The ranges depend on L only, so a sequence's energy does not depend on the
-// rest of the batch.
+// rest of the batch (nor on the workgroup size).
 // ---------------------------------------------------------------------------
 constexpr int kEJC = 16;
-constexpr int kEThreads = 256;
-constexpr int kESeq = 4;                       // sequences per thread
-constexpr int kESeqBlock = kEThreads * kESeq;  // sequences per workgroup
+constexpr int kESeq = 4;  // sequences per thread
+// Threads per workgroup: 512 (2048 sequences) for q > 8, so that each staged
+// tile serves twice the lookups (a workgroup loads its own copy of every
+// tile; at q = 21 the tile stores were about 30% of the LDS traffic): L = 512,
+// q = 21, 1e5 sequences 4.37 -> 3.30 ms, q = 32 -1/3.  For q <= 8 (tiles of
+// at most 8 KB) 256, where 512 measured 3-4% slower.
+constexpr int energy_threads(int Q) { return Q > 8 ? 512 : 256; }
 
 // Row pitch of the LDS tile in floats: 16 Q plus a pad of 0, 4, 8 or 12
 // (rows stay 16-byte aligned).  A lookup's bank is (P s_i + s_j + const) mod
@@ -39,8 +43,9 @@ constexpr int kESeqBlock = kEThreads * kESeq;  // sequences per workgroup
 // the pairs of the rest; at q = 8 one, so all rows share the banks of their
 // first 8 floats.
 constexpr int energy_pitch(int Q) {
-  constexpr long long kLdsCU = 160 * 1024, kWgCU = 8;  // 32 waves of a CU in 4-wave groups
-  auto wgs = [](long long bytes) { return kLdsCU / bytes < kWgCU ? kLdsCU / bytes : kWgCU; };
+  constexpr long long kLdsCU = 160 * 1024;
+  const long long wg_cap = 32 / (energy_threads(Q) / 64);  // 32 waves of a CU
+  auto wgs = [wg_cap](long long bytes) { return kLdsCU / bytes < wg_cap ? kLdsCU / bytes : wg_cap; };
   const long long wg0 = wgs(2LL * Q * 16 * Q * 4);
   int best = 16 * Q;
   long long best_mx = -1, best_sq = 0;
@@ -84,12 +89,14 @@ EnergyPlan plan_energy(int64_t B, int L, int q) {
 }
 
 template <int Q>
-__global__ __launch_bounds__(kEThreads) void k_energy_pairs(const float* __restrict__ J,
+__global__ __launch_bounds__(energy_threads(Q)) void k_energy_pairs(const float* __restrict__ J,
                                                             const int8_t* __restrict__ XT,
                                                             int64_t Bpad, int64_t B, int L,
                                                             int64_t steps, int parts,
                                                             double* __restrict__ part,
                                                             const int64_t* __restrict__ count) {
+  constexpr int kEThreads = energy_threads(Q);
+  constexpr int kESeqBlock = kEThreads * kESeq;  // sequences per workgroup
   if (count && *count < B) B = *count;  // live sequences of a launch sized for B
   if ((int64_t)blockIdx.x * kESeqBlock >= B) return;  // whole workgroup, before any barrier
   constexpr int kW = kEJC * Q;                                 // tile row length (16 Q floats)
@@ -289,8 +296,8 @@ template <int Q>
 static void launch_energy_q(const float* J, const int8_t* XT, int64_t B, int L,
                             const EnergyPlan& plan, double* part, hipStream_t s,
                             const int64_t* count) {
-  const dim3 grid((unsigned)ceil_div(B, kESeqBlock), (unsigned)plan.parts);
-  hipLaunchKernelGGL(k_energy_pairs<Q>, grid, dim3(kEThreads), 0, s, J, XT, plan.Bpad, B, L,
+  const dim3 grid((unsigned)ceil_div(B, energy_threads(Q) * kESeq), (unsigned)plan.parts);
+  hipLaunchKernelGGL(k_energy_pairs<Q>, grid, dim3(energy_threads(Q)), 0, s, J, XT, plan.Bpad, B, L,
                      plan.steps, plan.parts, part, count);
 }
 
