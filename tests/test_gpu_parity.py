@@ -285,10 +285,13 @@ def term_scale(h, J, S, q):
     return np.array(out)
 
 
-# several 1024-sequence blocks with a ragged tail; L below, at and across the
-# 16-site column chunks; q across the template range
+# several sequence blocks (2048 per workgroup for q > 8, 1024 otherwise) with
+# a ragged tail; L below, at and across the 16-site column chunks; q across
+# the template range and every LDS row pad (0: q = 2, 3; 4: q = 16, 32;
+# 8: q = 5, 8, 21; 12: q = 12, 20)
 @pytest.mark.parametrize("L,q,Bn", [(30, 21, 1000), (130, 21, 64), (9, 5, 257), (1, 21, 5),
-                                    (2, 2, 3000), (16, 3, 100), (17, 32, 2100), (100, 21, 2500)])
+                                    (2, 2, 3000), (16, 3, 100), (17, 32, 2100), (100, 21, 2500),
+                                    (40, 12, 4500), (33, 8, 2100), (25, 20, 2049), (18, 16, 700)])
 def test_energy(L, q, Bn):
     h, J = synth.planted_dense(L, q, seed=110 + L, sigma_J=0.3)
     S = synth.random_sequences(Bn, L, q, 111)
