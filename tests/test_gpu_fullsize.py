@@ -256,6 +256,27 @@ def test_rna_gibbs_and_counts():
     assert np.array_equal(host(f2)[r1, r2], O.stats_entries(g, q, r1, r2, None, 0.0))
 
 
+# ---------------------------------------------------------------- launches split in chunks
+def test_local_fields_past_one_launch():
+    """More (chain, column block) workgroups than one launch takes (2^22):
+    4 197 304 chains of an L = 20, q = 2 model (one column block each) are
+    built in two launches; chains at both ends of each launch match the
+    oracle's fields."""
+    L, q = 20, 2
+    N = (1 << 22) + 3000
+    h, J = synth.planted_dense(L, q, seed=1201, sigma_J=0.3)
+    ch = api.init_chains(N, L, q, 1202)
+    H = torch.empty(api.workspace_bytes(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS) // 4,
+                    dtype=torch.float32, device="cuda")
+    api.gibbs(dev(h), dev(J), ch, sweeps=0, seed=0, H_ws=H, sampler="fields")
+    g = np.random.default_rng(1203)
+    picks = [0, 1, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, N - 1] + list(g.integers(0, N, 20))
+    for c in picks:
+        Hg = host(H[c * L * q:(c + 1) * L * q])
+        Ho = O.local_fields(h, J, host(ch[c]), q)
+        assert np.all(np.abs(Hg - Ho) <= 1e-5 * (1 + np.abs(Ho))), c
+
+
 # ---------------------------------------------------------------- batches past 2^31 bytes
 def test_energy_batch_beyond_2gib_of_tokens():
     """40 million sequences at L = 64: the transposed tokens (L x B bytes)
