@@ -939,8 +939,39 @@ def bench_scoring(args):
     tiles = sum(min(16 * jc + 15, L - 1) for jc in range(-(-L // 16)))
     lds_bytes = pairs * 4 + blocks * tiles * q * 16 * q * 4  # lookups + staged tiles
     lds_peak = 256 * LDS_BYTES_PER_CLK * 2.4e9
+    # the rate that random 4-byte LDS lookups of the same address pattern reach
+    # on this device (a probe without tile staging, token loads or step
+    # bookkeeping), at the kernel's tile row pitch: 16 q floats plus the pad
+    # of 0, 4, 8 or 12 whose largest per-bank share of the q^2 (row, column)
+    # pairs is smallest, then the smallest sum of squared shares, among the
+    # pads that keep the workgroups per CU
+    def energy_pitch(qq):
+        thr = 512 if qq > 8 else 256
+        cap = 32 // (thr // 64)
+        wgs = lambda b: min(163840 // b, cap)
+        wg0 = wgs(2 * qq * 16 * qq * 4)
+        best = None
+        for pad in (0, 4, 8, 12):
+            P_ = 16 * qq + pad
+            if wgs(2 * qq * P_ * 4) < wg0:
+                continue
+            cnt = [0] * 64
+            for a in range(qq):
+                for b in range(qq):
+                    cnt[(P_ * a + b) % 64] += 1
+            key = (max(cnt), sum(x * x for x in cnt))
+            if best is None or key < best[0]:
+                best = (key, P_)
+        return best[1]
+    pk.bmdca_probe_lds_lookups.restype = ctypes.c_double
+    pk.bmdca_probe_lds_lookups.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lk_pitch = energy_pitch(q)
+    lk_peak = pk.bmdca_probe_lds_lookups(lk_pitch, 2000, 4096)
+    lk_rate = pairs / (en_ms * 1e-3)
     log(f"energy B={Bn} L={L}: {en_ms:.2f} ms, {Bn / (en_ms * 1e-3):.3e} sequences/s, "
-        f"{pairs / (en_ms * 1e-3):.3e} pair terms/s, LDS {lds_bytes / (en_ms * 1e-3) / 1e12:.1f} TB/s")
+        f"{pairs / (en_ms * 1e-3):.3e} pair terms/s, LDS {lds_bytes / (en_ms * 1e-3) / 1e12:.1f} TB/s; "
+        f"random-lookup probe at pitch {lk_pitch}: {lk_peak:.3e} lookups/s "
+        f"({100 * lk_rate / lk_peak:.0f}% reached)")
     del S, wse, E
     torch.cuda.empty_cache()
     nw = 64
@@ -978,7 +1009,9 @@ def bench_scoring(args):
         "roofline": {"kernel": "k_energy_pairs (energies)", "bound": "lds",
                      "achieved": lds_bytes / (en_ms * 1e-3) / 1e9, "peak": lds_peak / 1e9,
                      "unit": "GB/s", "frac": lds_bytes / (en_ms * 1e-3) / lds_peak,
-                     "traffic": None, "call_ms": en_ms, "alg_bytes_per_call": lds_bytes},
+                     "traffic": None, "call_ms": en_ms, "alg_bytes_per_call": lds_bytes,
+                     "lookups_per_s": lk_rate, "lookup_probe_per_s": lk_peak,
+                     "lookup_probe_frac": lk_rate / lk_peak, "tile_pitch_floats": lk_pitch},
         "extras": {
             "reweight": {"ms": rw_ms, "unordered_pairs_per_s": rw_pairs / (rw_ms * 1e-3),
                          "ops_per_pair": ops_pair, "int_ops_per_s": rw_ops / (rw_ms * 1e-3),

@@ -1,9 +1,20 @@
-// Throughput probe of the 32-bit integer vector ALU on the device (a
-// measurement aid for the benchmark, not part of libbmdca): every lane runs
-// 8 independent chains of three-input bit operations (v_bitop3_b32), or of
-// the pair-count kernel's mix (five bit operations and one popcount-
-// accumulate per word), long enough that issue rate, not latency, bounds
-// it.  Returns 32-bit lane operations per second over the timed launch.
+// Throughput probes of the device (measurement aids for the benchmark, not
+// part of libbmdca).
+//
+// Integer vector ALU: every lane runs 8 independent chains of three-input bit
+// operations (v_bitop3_b32), or of the pair-count kernel's mix (five bit
+// operations and one popcount-accumulate per word), long enough that issue
+// rate, not latency, bounds it.  Returns 32-bit lane operations per second
+// over the timed launch.
+//
+// Random LDS lookups: the energy kernel's access pattern without its tile
+// staging, token loads or step bookkeeping.  512-thread workgroups hold a
+// 21 x P float table; per step every thread adds, for 4 (row, 16-column)
+// sets, the 16 entries table[r P + 21 jj + c_jj] into FP32 sums, r and the
+// c_jj uniform in 0..20 from a hash of the thread (r moves by one each
+// step), so a wave's 64 addresses fall on the banks as uniform random
+// sequences' tokens do; a step's 64 reads are all issued before its adds.
+// Returns 4-byte lookups per second.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -49,7 +60,77 @@ __global__ __launch_bounds__(256) void k_int_valu(uint32_t* out, int iters, uint
   out[blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
+constexpr int kLQ = 21;  // states of the probed lookups
+
+__device__ inline uint32_t probe_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(512) void k_lds_lookups(float* out, int iters, int P) {
+  extern __shared__ float table[];  // kLQ x P
+  for (int e = threadIdx.x; e < kLQ * P; e += blockDim.x) table[e] = (float)(e & 255) * 0.5f;
+  __syncthreads();
+  const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  int r[4];
+  int c[4][16];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r[k] = (int)(probe_hash(id * 4u + k) % kLQ);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) c[k][jj] = (int)(probe_hash(id * 64u + k * 16u + jj + 0x51u) % kLQ);
+  }
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int it = 0; it < iters; ++it) {
+    // all 64 lookups of the step are read before any is added, so the LDS
+    // pipe, not the add chains, sets the pace
+    float v[4][16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k][jj] = table[r[k] * P + jj * kLQ + c[k][jj]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float sf = 0.0f;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) sf += v[k][jj];
+      acc[k] += sf;
+      r[k] = (r[k] + 1 == kLQ) ? 0 : r[k] + 1;
+    }
+  }
+  out[id] = acc[0] + acc[1] + acc[2] + acc[3];
+}
+
 }  // namespace
+
+// Lookups per second of the random-lookup probe with a table row pitch of P
+// floats (P >= 336).  Negative on error.
+extern "C" double bmdca_probe_lds_lookups(int P, int iters, int blocks) {
+  if (P < 16 * kLQ || (size_t)kLQ * P * sizeof(float) > 64 * 1024) return -3.0;
+  float* out = nullptr;
+  if (hipMalloc(&out, sizeof(float) * 512 * (size_t)blocks) != hipSuccess) return -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  const size_t lds = sizeof(float) * kLQ * (size_t)P;
+  auto launch = [&](int n) {
+    hipLaunchKernelGGL(k_lds_lookups, dim3(blocks), dim3(512), lds, 0, out, n, P);
+    return hipGetLastError() == hipSuccess;
+  };
+  float ms = 0.0f;
+  ok = ok && launch(iters / 8);  // warm
+  ok = ok && hipEventRecord(e0, 0) == hipSuccess && launch(iters) &&
+       hipEventRecord(e1, 0) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  if (e0) ok = (hipEventDestroy(e0) == hipSuccess) && ok;
+  if (e1) ok = (hipEventDestroy(e1) == hipSuccess) && ok;
+  ok = (hipFree(out) == hipSuccess) && ok;
+  if (!ok || ms <= 0.0f) return -2.0;
+  return 64.0 * (double)iters * 512.0 * (double)blocks / (ms * 1e-3);
+}
 
 // mix 0: bit operations only; 1: the pair-count mix.  Negative on error.
 extern "C" double bmdca_probe_int_valu(int mix, int iters, int blocks) {
