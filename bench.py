@@ -774,9 +774,20 @@ def bench_precision_epoch(args):
     lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
     lds_gbs = lds_bytes / (g_ms * 1e-3) / 1e9
     lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9
+    # the rate of the row gathers alone in the narrow-chain pattern at q = 21
+    # (10 chains of 6 lanes per wave, one 8-wave workgroup per CU, random rows of
+    # a 16-site chunk) on this device: a probe without staging, draws or barriers
+    import ctypes
+    pk = ctypes.CDLL(os.path.join(ROOT, "paper_2501_18456_amd", "libbmdca_peaks.so"))
+    pk.bmdca_probe_lds_rows.restype = ctypes.c_double
+    pk.bmdca_probe_lds_rows.argtypes = [ctypes.c_int, ctypes.c_int]
+    row_rate = N * L * sweeps * (L - 1) / (g_ms * 1e-3)  # coupling rows gathered per second
+    row_probe = pk.bmdca_probe_lds_rows(20000, cus) if q == 21 else None
     log(f"gather sweep kernel: {g_ms:.2f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms "
         f"re-layout), {visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of "
-        f"{lds_peak:.0f}")
+        f"{lds_peak:.0f}; {row_rate:.3e} row gathers/s"
+        + (f" ({100 * row_rate / row_probe:.0f}% of the {row_probe:.3e}/s that the gathers alone "
+           f"reach in the same pattern)" if row_probe else ""))
     del Wg
     ck = ch_run.clone()
     H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
@@ -833,7 +844,9 @@ def bench_precision_epoch(args):
         "roofline": {"kernel": "k_gibbs_gather (Gibbs sweeps, gather form)", "bound": "lds",
                      "achieved": lds_gbs, "peak": lds_peak, "unit": "GB/s",
                      "frac": lds_gbs / lds_peak, "traffic": gather_traffic("precision"),
-                     "launch_ms": g_ms, "alg_bytes_per_launch": lds_bytes},
+                     "launch_ms": g_ms, "alg_bytes_per_launch": lds_bytes,
+                     "row_gathers_per_s": row_rate, "row_probe_per_s": row_probe,
+                     "row_probe_frac": row_rate / row_probe if row_probe else None},
         "extras": extras,
     }
 

@@ -15,6 +15,15 @@
 // step), so a wave's 64 addresses fall on the banks as uniform random
 // sequences' tokens do; a step's 64 reads are all issued before its adds.
 // Returns 4-byte lookups per second.
+//
+// Row gathers: the gather sampler's pattern (narrow heat-bath chains at
+// q = 21) without staging, draws or barriers.  One 8-wave workgroup per CU
+// (its LDS allocation leaves no room for a second), a chunk of 16 sites x 21
+// rows of 24 floats; 10 chains per wave of 6 lanes, lane v of a chain reading
+// quad v of the row (position, token) with one 16-byte read per position and
+// adding it to its sums, tokens uniform in 0..20 from a hash of (chain,
+// position) and fixed over the iterations (no address arithmetic in the
+// loop).  Returns row reads (one row per chain and position) per second.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -105,7 +114,59 @@ __global__ __launch_bounds__(512) void k_lds_lookups(float* out, int iters, int 
   out[id] = acc[0] + acc[1] + acc[2] + acc[3];
 }
 
+constexpr int kRQ = 21, kRQuads = 6, kRPos = 16;  // states, quads per row, positions
+
+__global__ __launch_bounds__(512) void k_lds_rows(float* out, int iters) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  extern __shared__ f4 chunk[];  // kRPos x kRQ rows of kRQuads quads (more is allocated)
+  for (int e = threadIdx.x; e < kRPos * kRQ * kRQuads; e += blockDim.x)
+    chunk[e] = f4{(float)(e & 63), 1.0f, 2.0f, 3.0f} * 0.001f;
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int chain = lane / kRQuads, v = lane - chain * kRQuads;
+  const bool act = chain < 64 / kRQuads;  // lanes 60..63 idle
+  const uint32_t cg = (blockIdx.x * (blockDim.x / 64) + wave) * (64 / kRQuads) + chain;
+  int idx[kRPos];
+#pragma unroll
+  for (int pos = 0; pos < kRPos; ++pos) {
+    const int t = (int)(probe_hash(cg * kRPos + pos + 0x9Du) % kRQ);
+    idx[pos] = act ? (pos * kRQ + t) * kRQuads + v : 0;
+  }
+  f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int it = 0; it < iters; ++it) {
+    asm volatile("" ::: "memory");  // the reads are repeated, not hoisted out of the loop
+#pragma unroll
+    for (int pos = 0; pos < kRPos; ++pos) acc += chunk[idx[pos]];
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = act ? acc[0] + acc[1] + acc[2] + acc[3] : 0.0f;
+}
+
 }  // namespace
+
+// Row reads per second of the row-gather probe.  Negative on error.
+extern "C" double bmdca_probe_lds_rows(int iters, int blocks) {
+  float* out = nullptr;
+  if (hipMalloc(&out, sizeof(float) * 512 * (size_t)blocks) != hipSuccess) return -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  const size_t lds = 96 * 1024;  // one workgroup per CU, as the sampler runs
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(k_lds_rows),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  auto launch = [&](int n) {
+    hipLaunchKernelGGL(k_lds_rows, dim3(blocks), dim3(512), lds, 0, out, n);
+    return hipGetLastError() == hipSuccess;
+  };
+  float ms = 0.0f;
+  ok = ok && launch(iters / 8);  // warm
+  ok = ok && hipEventRecord(e0, 0) == hipSuccess && launch(iters) &&
+       hipEventRecord(e1, 0) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  if (e0) ok = (hipEventDestroy(e0) == hipSuccess) && ok;
+  if (e1) ok = (hipEventDestroy(e1) == hipSuccess) && ok;
+  ok = (hipFree(out) == hipSuccess) && ok;
+  if (!ok || ms <= 0.0f) return -2.0;
+  return (double)kRPos * (64 / kRQuads) * 8.0 * (double)iters * (double)blocks / (ms * 1e-3);
+}
 
 // Lookups per second of the random-lookup probe with a table row pitch of P
 // floats (P >= 336).  Negative on error.
