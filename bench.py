@@ -264,8 +264,21 @@ def bench_protein(args, emit=True):
     lds_bytes = gather_lds_bytes(N, L, q, sweeps, cus)
     lds_gbs = lds_bytes / (g_ms * 1e-3) / 1e9
     lds_peak = cus * LDS_BYTES_PER_CLK * 2.4e9 / 1e9  # GB/s at 2.4 GHz
+    # the row gathers alone in this launch's pattern (8-lane chains, as many
+    # waves per workgroup as the planner gives these chains: at least 4, 8
+    # chains per wave), measured on this device
+    import ctypes
+    pk = ctypes.CDLL(os.path.join(ROOT, "paper_2501_18456_amd", "libbmdca_peaks.so"))
+    pk.bmdca_probe_lds_rows.restype = ctypes.c_double
+    pk.bmdca_probe_lds_rows.argtypes = [ctypes.c_int] * 4
+    row_rate = N * L * sweeps * (L - 1) / (g_ms * 1e-3)
+    p_waves = max(4, -(-(-(-N // cus)) // 8))
+    row_probe = pk.bmdca_probe_lds_rows(8, p_waves, 20000, cus) if q == 21 else None
     log(f"gather sweep kernel: {g_ms:.3f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms re-layout), "
-        f"{visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of {lds_peak:.0f}")
+        f"{visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of {lds_peak:.0f}; "
+        f"{row_rate:.3e} row gathers/s"
+        + (f" ({100 * row_rate / row_probe:.0f}% of the {row_probe:.3e}/s of the gathers alone "
+           f"with {p_waves} waves)" if row_probe else ""))
 
     ck = chains.clone()
     H = api.workspace(B.WS_GIBBS, N, L, q, B.SAMPLER_FIELDS)
@@ -287,7 +300,9 @@ def bench_protein(args, emit=True):
               "pearson_after": float(pearson.cpu()[0]), "reweight_ms": rw_ms,
               "gather_kernel": {"ms_per_launch": g_ms, "relayout_ms": g_fix,
                                 "site_updates_per_s": visits / (g_ms * 1e-3),
-                                "lds_GBps": lds_gbs, "lds_frac": lds_gbs / lds_peak},
+                                "lds_GBps": lds_gbs, "lds_frac": lds_gbs / lds_peak,
+                                "row_gathers_per_s": row_rate, "row_probe_per_s": row_probe,
+                                "row_probe_frac": row_rate / row_probe if row_probe else None},
               "field_kernel": {"ms_per_launch": k_ms, "site_updates_per_s": visits / (k_ms * 1e-3),
                                "alg_hbm_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS}}
     other = "bf16x2" if args.prec == "fp32" else "fp32"
@@ -780,9 +795,9 @@ def bench_precision_epoch(args):
     import ctypes
     pk = ctypes.CDLL(os.path.join(ROOT, "paper_2501_18456_amd", "libbmdca_peaks.so"))
     pk.bmdca_probe_lds_rows.restype = ctypes.c_double
-    pk.bmdca_probe_lds_rows.argtypes = [ctypes.c_int, ctypes.c_int]
+    pk.bmdca_probe_lds_rows.argtypes = [ctypes.c_int] * 4
     row_rate = N * L * sweeps * (L - 1) / (g_ms * 1e-3)  # coupling rows gathered per second
-    row_probe = pk.bmdca_probe_lds_rows(20000, cus) if q == 21 else None
+    row_probe = pk.bmdca_probe_lds_rows(6, 8, 20000, cus) if q == 21 else None
     log(f"gather sweep kernel: {g_ms:.2f} ms per launch ({sweeps} sweeps; +{g_fix:.3f} ms "
         f"re-layout), {visits / (g_ms * 1e-3):.3e} site-updates/s, LDS {lds_gbs:.0f} GB/s of "
         f"{lds_peak:.0f}; {row_rate:.3e} row gathers/s"

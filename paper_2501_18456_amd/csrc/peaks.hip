@@ -16,14 +16,15 @@
 // sequences' tokens do; a step's 64 reads are all issued before its adds.
 // Returns 4-byte lookups per second.
 //
-// Row gathers: the gather sampler's pattern (narrow heat-bath chains at
-// q = 21) without staging, draws or barriers.  One 8-wave workgroup per CU
-// (its LDS allocation leaves no room for a second), a chunk of 16 sites x 21
-// rows of 24 floats; 10 chains per wave of 6 lanes, lane v of a chain reading
-// quad v of the row (position, token) with one 16-byte read per position and
-// adding it to its sums, tokens uniform in 0..20 from a hash of (chain,
-// position) and fixed over the iterations (no address arithmetic in the
-// loop).  Returns row reads (one row per chain and position) per second.
+// Row gathers: the gather sampler's pattern at q = 21 without staging, draws
+// or barriers.  One workgroup per CU (its LDS allocation leaves no room for a
+// second) of a given number of waves, a chunk of 16 sites x 21 rows of 24
+// floats; chains of 6 lanes (narrow: 10 per wave) or 8 lanes (8 per wave, 2
+// idle), lane v < 6 of a chain reading quad v of the row (position, token)
+// with one 16-byte read per position and adding it to its sums, tokens
+// uniform in 0..20 from a hash of (chain, position) and fixed over the
+// iterations (no address arithmetic in the loop).  Returns row reads (one row
+// per chain and position) per second.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -116,16 +117,17 @@ __global__ __launch_bounds__(512) void k_lds_lookups(float* out, int iters, int 
 
 constexpr int kRQ = 21, kRQuads = 6, kRPos = 16;  // states, quads per row, positions
 
-__global__ __launch_bounds__(512) void k_lds_rows(float* out, int iters) {
+template <int LPC>
+__global__ __launch_bounds__(1024) void k_lds_rows(float* out, int iters) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ f4 chunk[];  // kRPos x kRQ rows of kRQuads quads (more is allocated)
   for (int e = threadIdx.x; e < kRPos * kRQ * kRQuads; e += blockDim.x)
     chunk[e] = f4{(float)(e & 63), 1.0f, 2.0f, 3.0f} * 0.001f;
   __syncthreads();
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int chain = lane / kRQuads, v = lane - chain * kRQuads;
-  const bool act = chain < 64 / kRQuads;  // lanes 60..63 idle
-  const uint32_t cg = (blockIdx.x * (blockDim.x / 64) + wave) * (64 / kRQuads) + chain;
+  const int chain = lane / LPC, v = lane - chain * LPC;
+  const bool act = chain < 64 / LPC && v < kRQuads;  // narrow: lanes 60..63 idle
+  const uint32_t cg = (blockIdx.x * (blockDim.x / 64) + wave) * (64 / LPC) + chain;
   int idx[kRPos];
 #pragma unroll
   for (int pos = 0; pos < kRPos; ++pos) {
@@ -143,17 +145,24 @@ __global__ __launch_bounds__(512) void k_lds_rows(float* out, int iters) {
 
 }  // namespace
 
-// Row reads per second of the row-gather probe.  Negative on error.
-extern "C" double bmdca_probe_lds_rows(int iters, int blocks) {
+// Row reads per second of the row-gather probe with chains of lpc lanes (6
+// or 8) and workgroups of `waves` waves (1..16).  Negative on error.
+extern "C" double bmdca_probe_lds_rows(int lpc, int waves, int iters, int blocks) {
+  if ((lpc != 6 && lpc != 8) || waves < 1 || waves > 16) return -3.0;
   float* out = nullptr;
-  if (hipMalloc(&out, sizeof(float) * 512 * (size_t)blocks) != hipSuccess) return -1.0;
+  if (hipMalloc(&out, sizeof(float) * 64 * waves * (size_t)blocks) != hipSuccess) return -1.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   const size_t lds = 96 * 1024;  // one workgroup per CU, as the sampler runs
-  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(k_lds_rows),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  const void* kern = lpc == 6 ? reinterpret_cast<const void*>(k_lds_rows<6>)
+                              : reinterpret_cast<const void*>(k_lds_rows<8>);
+  ok = ok && hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+                 hipSuccess;
   auto launch = [&](int n) {
-    hipLaunchKernelGGL(k_lds_rows, dim3(blocks), dim3(512), lds, 0, out, n);
+    if (lpc == 6)
+      hipLaunchKernelGGL(k_lds_rows<6>, dim3(blocks), dim3(64 * waves), lds, 0, out, n);
+    else
+      hipLaunchKernelGGL(k_lds_rows<8>, dim3(blocks), dim3(64 * waves), lds, 0, out, n);
     return hipGetLastError() == hipSuccess;
   };
   float ms = 0.0f;
@@ -165,7 +174,7 @@ extern "C" double bmdca_probe_lds_rows(int iters, int blocks) {
   if (e1) ok = (hipEventDestroy(e1) == hipSuccess) && ok;
   ok = (hipFree(out) == hipSuccess) && ok;
   if (!ok || ms <= 0.0f) return -2.0;
-  return (double)kRPos * (64 / kRQuads) * 8.0 * (double)iters * (double)blocks / (ms * 1e-3);
+  return (double)kRPos * (64 / lpc) * waves * (double)iters * (double)blocks / (ms * 1e-3);
 }
 
 // Lookups per second of the random-lookup probe with a table row pitch of P
