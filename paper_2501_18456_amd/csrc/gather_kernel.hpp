@@ -178,7 +178,7 @@ __device__ __forceinline__ int narrow_sum(int x, int base) {
 
 // MAXW: the most waves a workgroup of this instantiation may have (16, or 8
 // for plans of at most 8 waves: twice the registers per lane, 256).
-template <int Q, int IT, int LPC, bool MH, int MAXW>
+template <int Q, int IT, int LPC, bool MH, int MAXW, bool PAIR>
 __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     const float* __restrict__ h, const float* __restrict__ Jt, int8_t* __restrict__ chains,
     int64_t N, int L, int jc, int nchunk, int m4, int ahead, int nload, int slot, int cpb,
@@ -286,7 +286,9 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     }
     if (++sl == nslot) sl = 0;
   };
-  for (int64_t t = 0; t < ahead && t < Tn; ++t) {
+  // chunks in flight before the first step: `ahead` (one barrier per step),
+  // or two (paired steps)
+  for (int64_t t = 0; t < (PAIR ? 2 : ahead) && t < Tn; ++t) {
     if (loader) issue_chunk(pi, pk, psl);
     advance(pi, pk, psl);
   }
@@ -330,22 +332,41 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
     }
   }
   for (int64_t t = 0; t < Tn; ++t) {
-    // chunk t is complete once at most the younger issued chunks (ahead - 1
-    // of them, fewer at the end) are pending
-    const int64_t rest = Tn - 1 - t;
-    const int younger = rest < ahead - 1 ? (int)rest : ahead - 1;
-    compiler_fence();
-    if (younger >= 2)
-      wait_vm_lgkm0<2 * IT>();
-    else if (younger == 1)
-      wait_vm_lgkm0<IT>();
-    else
-      wait_vm_lgkm0<0>();
-    __builtin_amdgcn_s_barrier();
-    compiler_fence();
-    if (t + ahead < Tn) {
-      if (loader) issue_chunk(pi, pk, psl);
-      advance(pi, pk, psl);
+    if constexpr (PAIR) {
+      // even steps: chunks t and t + 1 (issued two steps ago) complete in
+      // every wave after the barrier, and the slots of t - 2 and t - 1 are
+      // free for t + 2 and t + 3; odd steps read chunk t without a barrier
+      // (the loads in flight fill the slots of t + 1 and t + 2)
+      if ((t & 1) == 0) {
+        compiler_fence();
+        wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();
+        compiler_fence();
+        for (int e = 0; e < 2; ++e) {
+          if (t + 2 + e < Tn) {
+            if (loader) issue_chunk(pi, pk, psl);
+            advance(pi, pk, psl);
+          }
+        }
+      }
+    } else {
+      // chunk t is complete once at most the younger issued chunks (ahead - 1
+      // of them, fewer at the end) are pending
+      const int64_t rest = Tn - 1 - t;
+      const int younger = rest < ahead - 1 ? (int)rest : ahead - 1;
+      compiler_fence();
+      if (younger >= 2)
+        wait_vm_lgkm0<2 * IT>();
+      else if (younger == 1)
+        wait_vm_lgkm0<IT>();
+      else
+        wait_vm_lgkm0<0>();
+      __builtin_amdgcn_s_barrier();
+      compiler_fence();
+      if (t + ahead < Tn) {
+        if (loader) issue_chunk(pi, pk, psl);
+        advance(pi, pk, psl);
+      }
     }
     if (MH && k == 0) {
       // proposal and uniform of this visit; lane 0 starts the difference
@@ -659,15 +680,29 @@ hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
   // (heat-bath, 5..7 quads per row) where the planner takes them
   constexpr int LP = gather_lanes(Q, !MH), LN = gather_narrow_lanes(Q, !MH);
   if (gs.lpc != LP && (LN == 0 || gs.lpc != LN)) return hipErrorInvalidValue;
-  decltype(&k_gibbs_gather<Q, 8, LP, MH, MAXW>) kern =
-      gs.items == 31   ? k_gibbs_gather<Q, 31, LP, MH, MAXW>
-      : gs.items == 16 ? k_gibbs_gather<Q, 16, LP, MH, MAXW>
-                       : k_gibbs_gather<Q, 8, LP, MH, MAXW>;
+  if (MH && gs.pair) return hipErrorInvalidValue;  // paired steps: heat-bath plans only
+  // the step schedule is a template parameter: with both in one kernel the
+  // compiler scheduled each of them worse (up to 9% slower)
+  auto pick = [&](auto lanes, auto paired) {
+    constexpr int LL = decltype(lanes)::value;
+    constexpr bool PP = decltype(paired)::value;
+    return gs.items == 31   ? k_gibbs_gather<Q, 31, LL, MH, MAXW, PP>
+           : gs.items == 16 ? k_gibbs_gather<Q, 16, LL, MH, MAXW, PP>
+                            : k_gibbs_gather<Q, 8, LL, MH, MAXW, PP>;
+  };
+  using LPt = std::integral_constant<int, LP>;
+  decltype(&k_gibbs_gather<Q, 8, LP, MH, MAXW, false>) kern = pick(LPt{}, std::false_type{});
+  if constexpr (!MH) {
+    if (gs.pair) kern = pick(LPt{}, std::true_type{});
+  }
   if constexpr (LN > 0) {
-    if (gs.lpc == LN)
-      kern = gs.items == 31   ? k_gibbs_gather<Q, 31, LN, MH, MAXW>
-             : gs.items == 16 ? k_gibbs_gather<Q, 16, LN, MH, MAXW>
-                              : k_gibbs_gather<Q, 8, LN, MH, MAXW>;
+    using LNt = std::integral_constant<int, LN>;
+    if (gs.lpc == LN) {
+      kern = pick(LNt{}, std::false_type{});
+      if constexpr (!MH) {
+        if (gs.pair) kern = pick(LNt{}, std::true_type{});
+      }
+    }
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gs.lds);

@@ -51,6 +51,7 @@ struct GatherShape {
   int slot;       // floats per ring slot (nload * items KB)
   size_t lds;     // dynamic LDS bytes
   unsigned blocks;
+  int pair;       // 1: paired chunk-steps (one barrier per two steps, two chunks in flight)
 };
 
 // Token bytes per chain.
@@ -148,6 +149,17 @@ constexpr int gather_narrow_lanes(int q, bool small) {
   return (small && gather_v(q) == 8 && gather_qp(q) / 4 < 8) ? gather_qp(q) / 4 : 0;
 }
 
+// Paired chunk-steps: the ring of 4 slots is refilled two chunks at a time,
+// one wait and one barrier per two steps, with two chunks in flight instead
+// of three.  Where a workgroup holds at least this many chains the row
+// gathers dominate a step and the halved barriers pay (L = 256, q = 21,
+// 20 000 chains: 33.6 -> 30.2 ms per 10 sweeps; L = 100, 10 000 chains
+// 5.46 -> 5.27; q = 12, L = 200 11.4 -> 10.0; q = 5, L = 400 17.8 -> 16.0);
+// with fewer the staging latency dominates and the third chunk in flight
+// pays more (L = 512, 4096 chains, 16 per workgroup: 114.7 against 130.8).
+// The chains draw the same bits either way.
+constexpr int kGPairChains = 32;
+
 // Chains per workgroup for chains of `lpc` lanes: spread the chains over the
 // CUs (one workgroup per CU at a time) in as few rounds as the largest
 // workgroup that fits allows.
@@ -159,17 +171,19 @@ inline GatherShape gather_plan_lanes(int64_t N, int L, int q, int64_t cus, int c
   const int cpb = (int)std::min<int64_t>(cmax, gp_ceil(N, rounds * cus));
   GatherShape g = gather_shape(L, q, cpb, lpc);
   g.blocks = (unsigned)gp_ceil(N, (int64_t)cpb);
+  g.pair = (g.waves > 0 && g.cpb >= kGPairChains) ? 1 : 0;
   return g;
 }
 
 inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = kGMaxWaves * 8,
                                bool small = true) {
-  const GatherShape g = gather_plan_lanes(N, L, q, cus, cap, gather_lanes(q, small));
+  GatherShape g = gather_plan_lanes(N, L, q, cus, cap, gather_lanes(q, small));
   const int nl = gather_narrow_lanes(q, small);
   if (nl > 0 && g.waves > kGNarrowWaves) {
     const GatherShape n = gather_plan_lanes(N, L, q, cus, cap, nl);
-    if (n.waves >= kGNarrowWaves && n.waves < g.waves && n.blocks <= g.blocks) return n;
+    if (n.waves >= kGNarrowWaves && n.waves < g.waves && n.blocks <= g.blocks) g = n;
   }
+  if (!small) g.pair = 0;  // paired steps are instantiated for the heat-bath draw only
   return g;
 }
 

@@ -46,6 +46,10 @@ static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
   CHECK(g.cpb >= 1 && g.cpb <= CPB && g.cpb <= cap, "cpb %d of %d", g.cpb, CPB);
   CHECK((int64_t)g.blocks * g.cpb >= N && (int64_t)(g.blocks - 1) * g.cpb < N, "blocks %u", g.blocks);
   CHECK(g.ahead == 3, "ahead %d", g.ahead);
+  // paired chunk-steps (two chunks in flight, refilled two at a time) in the
+  // same ring of ahead + 1 = 4 slots, where the workgroup holds enough chains
+  CHECK(g.pair == (small && g.cpb >= kGPairChains ? 1 : 0), "pair %d cpb %d small %d", g.pair,
+        g.cpb, (int)small);
   CHECK(g.items == 8 || g.items == 16 || g.items == 31, "items %d", g.items);
   CHECK((g.ahead - 1) * g.items <= 63, "vmcnt %d", (g.ahead - 1) * g.items);
   CHECK(g.nload >= 1 && g.nload <= g.waves, "nload %d", g.nload);
