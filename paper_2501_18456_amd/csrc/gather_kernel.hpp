@@ -749,8 +749,12 @@ hipError_t launch_gather_form(const float* h, const float* Jt, int8_t* chains, i
   // takes workgroups of at most kGShareChains chains: more, smaller
   // workgroups let the largest models spread onto CUs the others free.
   const int64_t cus = ctl.cu_share > 0 ? std::min<int64_t>(ctl.cu_share, device_cus()) : device_cus();
-  const GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, q, cus, kGShareChains, !MH)
-                                          : gather_plan(N, L, q, cus, kGMaxWaves * 8, !MH);
+  GatherShape gs = ctl.cu_share > 0 ? gather_plan(N, L, q, cus, kGShareChains, !MH)
+                                    : gather_plan(N, L, q, cus, kGMaxWaves * 8, !MH);
+  // On a CU share the other models' launches compete for L2 and the MALL, and
+  // the third chunk in flight pays more than the halved barriers (64 models
+  // trained together: 484.6 ms per epoch with paired steps, 460.7 without)
+  if (ctl.cu_share > 0) gs.pair = 0;
   if (gs.waves == 0 || gs.ahead != 3) return hipErrorInvalidValue;
   const GatherArgs a{h, Jt, chains, N, L, sweeps, seed, sweep_offset, beta, flips_out, dev_err,
                      s, &ctl};

@@ -157,7 +157,8 @@ constexpr int gather_narrow_lanes(int q, bool small) {
 // 5.46 -> 5.27; q = 12, L = 200 11.4 -> 10.0; q = 5, L = 400 17.8 -> 16.0);
 // with fewer the staging latency dominates and the third chunk in flight
 // pays more (L = 512, 4096 chains, 16 per workgroup: 114.7 against 130.8).
-// The chains draw the same bits either way.
+// Launches on a share of the CUs keep one barrier per step (the launch
+// clears the flag).  The chains draw the same bits either way.
 constexpr int kGPairChains = 32;
 
 // Chains per workgroup for chains of `lpc` lanes: spread the chains over the
