@@ -157,9 +157,20 @@ constexpr int gather_narrow_lanes(int q, bool small) {
 // 5.46 -> 5.27; q = 12, L = 200 11.4 -> 10.0; q = 5, L = 400 17.8 -> 16.0);
 // with fewer the staging latency dominates and the third chunk in flight
 // pays more (L = 512, 4096 chains, 16 per workgroup: 114.7 against 130.8).
-// Launches on a share of the CUs keep one barrier per step (the launch
-// clears the flag).  The chains draw the same bits either way.
+// The same holds where the re-laid-out couplings (L^2 q QP 4 bytes) exceed
+// the 256 MB last-level cache and the staging comes from HBM, unless the
+// workgroup holds at least twice as many chains (10 000 chains, 40 per
+// workgroup: L = 400 (323 MB) 71.0 against 79.9 ms, L = 512 (528 MB) 115.3
+// against 130.3; L = 300 (181 MB) 41.0 against 40.6; L = 512, 20 000 chains,
+// 80 per workgroup: 254.9 against 246.2).  Launches on a share of the CUs
+// keep one barrier per step (the launch clears the flag).  The chains draw
+// the same bits either way.
 constexpr int kGPairChains = 32;
+constexpr double kGPairCacheBytes = 256.0 * 1024 * 1024;
+inline int gather_pair(int L, int q, int cpb) {
+  const double jt = (double)L * L * q * gather_qp(q) * sizeof(float);
+  return (cpb >= kGPairChains && (jt <= kGPairCacheBytes || cpb >= 2 * kGPairChains)) ? 1 : 0;
+}
 
 // Chains per workgroup for chains of `lpc` lanes: spread the chains over the
 // CUs (one workgroup per CU at a time) in as few rounds as the largest
@@ -172,7 +183,7 @@ inline GatherShape gather_plan_lanes(int64_t N, int L, int q, int64_t cus, int c
   const int cpb = (int)std::min<int64_t>(cmax, gp_ceil(N, rounds * cus));
   GatherShape g = gather_shape(L, q, cpb, lpc);
   g.blocks = (unsigned)gp_ceil(N, (int64_t)cpb);
-  g.pair = (g.waves > 0 && g.cpb >= kGPairChains) ? 1 : 0;
+  g.pair = g.waves > 0 ? gather_pair(L, q, g.cpb) : 0;
   return g;
 }
 

@@ -48,8 +48,12 @@ static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
   CHECK(g.ahead == 3, "ahead %d", g.ahead);
   // paired chunk-steps (two chunks in flight, refilled two at a time) in the
   // same ring of ahead + 1 = 4 slots, where the workgroup holds enough chains
-  CHECK(g.pair == (small && g.cpb >= kGPairChains ? 1 : 0), "pair %d cpb %d small %d", g.pair,
-        g.cpb, (int)small);
+  {
+    const double jt = (double)L * L * q * QP * 4.0;
+    const bool want_pair = small && g.cpb >= 32 && (jt <= 256.0 * 1024 * 1024 || g.cpb >= 64);
+    CHECK(g.pair == (want_pair ? 1 : 0), "pair %d cpb %d small %d jt %.0f", g.pair, g.cpb,
+          (int)small, jt);
+  }
   CHECK(g.items == 8 || g.items == 16 || g.items == 31, "items %d", g.items);
   CHECK((g.ahead - 1) * g.items <= 63, "vmcnt %d", (g.ahead - 1) * g.items);
   CHECK(g.nload >= 1 && g.nload <= g.waves, "nload %d", g.nload);
