@@ -222,8 +222,10 @@ typedef struct bmdca_chain_stream {
  * fields of the gather form are summed in an order fixed by L, q and the draw
  * (the lanes per chain are a function of q and the draw alone; heat-bath
  * chains with 5..7 quads per row may run narrow, one lane per quad, where a
- * launch has many chains per CU, and draw the same bits), so heat-bath
- * chains are bit-identical to their alone call in any launch.  For
+ * launch has many chains per CU, and draw the same bits; launches with many
+ * chains per workgroup take one barrier per two chunk-steps, which changes no
+ * arithmetic), so heat-bath chains are bit-identical to their alone call in
+ * any launch.  For
  * Metropolis the order also follows the chunk length, which the chains per
  * workgroup bound where their tokens fill the LDS; where two launches differ
  * in it a chain can part from its alone trajectory at a draw within FP32
