@@ -206,12 +206,22 @@ __global__ __launch_bounds__(energy_threads(Q)) void k_energy_pairs(const float*
     float sf[kESeq];
 #pragma unroll
     for (int k = 0; k < kESeq; ++k) sf[k] = 0.0f;
+    // for q <= 8 a step whose columns all pair with the row site skips the
+    // per-column tests (q = 5: 11% shorter; for larger q the tests cost
+    // nothing and the second copy of the loop 1-4%)
+    if (Q <= 8 && cjc * kEJC > si_ && cjc * kEJC + kEJC <= L) {
 #pragma unroll
-    for (int jj = 0; jj < kEJC; ++jj) {
-      const int j = cjc * kEJC + jj;
-      if (j > si_ && j < L) {  // uniform over the workgroup
+      for (int jj = 0; jj < kEJC; ++jj)
 #pragma unroll
         for (int k = 0; k < kESeq; ++k) sf[k] += tb[srow[k] + jj * Q + sj[k][jj]];
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < kEJC; ++jj) {
+        const int j = cjc * kEJC + jj;
+        if (j > si_ && j < L) {  // uniform over the workgroup
+#pragma unroll
+          for (int k = 0; k < kESeq; ++k) sf[k] += tb[srow[k] + jj * Q + sj[k][jj]];
+        }
       }
     }
 #pragma unroll
