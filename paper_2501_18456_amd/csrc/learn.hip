@@ -15,38 +15,44 @@ constexpr int kPearsonThreads = 256;
 
 size_t pearson_red_bytes() { return sizeof(double) * (3 * kPearsonBlocks + 8); }
 
-// Pass 1 (moments == 0): per-block sums of x and y.
-// Pass 2 (moments == 1): per-block sums of dx^2, dy^2, dx*dy about the means.
-// x = f2 - f1_i f1_j (data), y = p2 - p1_i p1_j (model).
+// Pass 0: per-workgroup sums of x and y; pass 1: of dx^2, dy^2, dx*dy about
+// the means.  x = f2 - f1_i f1_j (data), y = p2 - p1_i p1_j (model), over the
+// entries (r1, c) with site(r1) < site(c).  Workgroup (column block b, row
+// chunk g) owns columns 256 b + t (one per thread: its f1 and p1 stay in
+// registers) and rows g, g + G, ...; a row's values are uniform, so the
+// reads of f2 and C are coalesced and nothing is divided per entry but C/N.
 __global__ __launch_bounds__(kPearsonThreads) void k_pearson_pass(
     const double* __restrict__ f1, const double* __restrict__ f2, const double* __restrict__ C,
-    int64_t N, int L, int q, int pass, double* __restrict__ red) {
+    int64_t N, int L, int q, int pass, int nrow_chunks, double* __restrict__ red) {
   __shared__ double sh[16];
   const int Lq = L * q;
-  const size_t total = (size_t)Lq * Lq;
   const double dn = (double)N;
   double mx = 0.0, my = 0.0;
   if (pass == 1) {
     mx = red[3 * kPearsonBlocks + 0];
     my = red[3 * kPearsonBlocks + 1];
   }
+  const int b = blockIdx.x / nrow_chunks, g = blockIdx.x % nrow_chunks;
+  const int c = b * kPearsonThreads + (int)threadIdx.x;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
-    if (r1 / q >= r2 / q) continue;
-    const double x = f2[k] - f1[r1] * f1[r2];
-    const double p1a = C[(size_t)r1 * Lq + r1] / dn;
-    const double p1b = C[(size_t)r2 * Lq + r2] / dn;
-    const double y = C[k] / dn - p1a * p1b;
-    if (pass == 0) {
-      s0 += x;
-      s1 += y;
-    } else {
-      const double dx = x - mx, dy = y - my;
-      s0 += dx * dx;
-      s1 += dy * dy;
-      s2 += dx * dy;
+  if (c < Lq) {
+    const int rmax = (c / q) * q;  // rows of the sites before c's
+    const double f1c = f1[c];
+    const double p1c = C[(size_t)c * Lq + c] / dn;
+    for (int r1 = g; r1 < rmax; r1 += nrow_chunks) {
+      const size_t k = (size_t)r1 * Lq + c;
+      const double x = f2[k] - f1[r1] * f1c;
+      const double p1r = C[(size_t)r1 * Lq + r1] / dn;
+      const double y = C[k] / dn - p1r * p1c;
+      if (pass == 0) {
+        s0 += x;
+        s1 += y;
+      } else {
+        const double dx = x - mx, dy = y - my;
+        s0 += dx * dx;
+        s1 += dy * dy;
+        s2 += dx * dy;
+      }
     }
   }
   const double t0 = block_sum_f64(s0, sh);
@@ -59,17 +65,36 @@ __global__ __launch_bounds__(kPearsonThreads) void k_pearson_pass(
   }
 }
 
-// Sums the block partials in block order.  Pass 0: means into red tail;
-// pass 1: the coefficient into *out.
-__global__ void k_pearson_finish(double* __restrict__ red, int L, int q, int pass,
-                                 double* __restrict__ out, int32_t* dev_err) {
-  if (threadIdx.x != 0) return;
+// Sums the nblk workgroup partials: thread t adds partials t, t + 256, ... in
+// order, then a fixed tree over the 256 threads (one workgroup,
+// deterministic).  Pass 0: means into red's tail; pass 1: the coefficient
+// into *out.
+__global__ __launch_bounds__(256) void k_pearson_finish(double* __restrict__ red, int nblk, int L,
+                                                        int q, int pass, double* __restrict__ out,
+                                                        int32_t* dev_err) {
+  __shared__ double part[3][256];
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = 0; k < kPearsonBlocks; ++k) {
+  for (int k = threadIdx.x; k < nblk; k += 256) {
     a += red[3 * k + 0];
     b += red[3 * k + 1];
     c += red[3 * k + 2];
   }
+  part[0][threadIdx.x] = a;
+  part[1][threadIdx.x] = b;
+  part[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + w];
+      part[1][threadIdx.x] += part[1][threadIdx.x + w];
+      part[2][threadIdx.x] += part[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  a = part[0][0];
+  b = part[1][0];
+  c = part[2][0];
   if (pass == 0) {
     const double n = (double)L * (double)(L - 1) / 2.0 * (double)q * (double)q;
     red[3 * kPearsonBlocks + 0] = a / n;
@@ -83,10 +108,17 @@ __global__ void k_pearson_finish(double* __restrict__ red, int L, int q, int pas
 
 hipError_t launch_pearson(const double* f1, const double* f2, const double* C, int64_t N, int L,
                           int q, double* red, double* out, int32_t* dev_err, hipStream_t s) {
+  // column blocks x row chunks, at most kPearsonBlocks partials
+  const int Lq = L * q;
+  const int ncb = (int)ceil_div(Lq, kPearsonThreads);
+  const int nrc = std::max(1, std::min(kPearsonBlocks / ncb, Lq));
+  const int nblk = ncb * nrc;
+  if (nblk > kPearsonBlocks) return hipErrorInvalidValue;  // Lq > 256 x 1024
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_pearson_pass, dim3(kPearsonBlocks), dim3(kPearsonThreads), 0, s, f1, f2,
-                       C, N, L, q, pass, red);
-    hipLaunchKernelGGL(k_pearson_finish, dim3(1), dim3(64), 0, s, red, L, q, pass, out, dev_err);
+    hipLaunchKernelGGL(k_pearson_pass, dim3(nblk), dim3(kPearsonThreads), 0, s, f1, f2, C, N, L,
+                       q, pass, nrc, red);
+    hipLaunchKernelGGL(k_pearson_finish, dim3(1), dim3(256), 0, s, red, nblk, L, q, pass, out,
+                       dev_err);
   }
   return hipGetLastError();
 }
