@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_frob_blocks(const float* __restrict__ J
   __shared__ double cmean[4][64];  // per wave: c_t of lane (block, t) at block * q + t
   __shared__ double rowss[4][64];  // per wave: the lanes' sums of squares
   const int lane = threadIdx.x % 64;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform: the task is
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform, as is the wave task below
   const int task = (int)blockIdx.x * 4 + wv;  // below 2^19 (L <= 1024, tpp <= 1024)
   const int npair = (L + 1) / 2;
   if (task >= npair * tpp) return;  // whole wave; only wave barriers below
