@@ -132,21 +132,24 @@ __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
                          const uint8_t* __restrict__ mask) {
   if (active && *active == 0) return;
   const int Lq = L * q;
-  const size_t total = (size_t)Lq * Lq;
   const double dn = (double)N;
   bool bad = false;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int r1 = (int)(k / Lq), r2 = (int)(k % Lq);
-    if (r1 / q == r2 / q || (mask && !mask[k])) {  // diagonal block or pruned element
-      J[k] = 0.0f;
-      continue;
+  // rows r1 = blockIdx.x, + gridDim.x, ...; the threads stride over the
+  // columns, and the diagonal block of row r1 is a column range
+  for (int r1 = blockIdx.x; r1 < Lq; r1 += gridDim.x) {
+    const int d0 = (r1 / q) * q;
+    for (int r2 = threadIdx.x; r2 < Lq; r2 += blockDim.x) {
+      const size_t k = (size_t)r1 * Lq + r2;
+      if ((r2 >= d0 && r2 < d0 + q) || (mask && !mask[k])) {  // diagonal block or pruned
+        J[k] = 0.0f;
+        continue;
+      }
+      const double d = f2[k] - C[k] / dn;
+      const double t = lr * d;
+      const float v = (float)((double)J[k] + t);
+      J[k] = v;
+      bad |= !isfinite(v);
     }
-    const double d = f2[k] - C[k] / dn;
-    const double t = lr * d;
-    const float v = (float)((double)J[k] + t);
-    J[k] = v;
-    bad |= !isfinite(v);
   }
   for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < (size_t)Lq;
        r += (size_t)gridDim.x * blockDim.x) {
@@ -162,8 +165,7 @@ __global__ void k_update(float* __restrict__ h, float* __restrict__ J,
 hipError_t launch_update(float* h, float* J, const double* f1, const double* f2, const double* C,
                          int64_t N, int L, int q, double lr, int32_t* dev_err, hipStream_t s,
                          const int32_t* active, const uint8_t* mask) {
-  const size_t total = (size_t)L * q * (size_t)L * q;
-  const unsigned nb = (unsigned)std::min<size_t>(ceil_div(total, 256), 16384);
+  const unsigned nb = (unsigned)std::min(L * q, 16384);  // a row per workgroup (and step)
   hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, s, h, J, f1, f2, C, N, L, q, lr, dev_err,
                      active, mask);
   return hipGetLastError();
