@@ -292,13 +292,34 @@ __global__ void k_energy_finish(const float* __restrict__ h, const int8_t* __res
   if (count && *count < B) B = *count;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
+  // loads in batches of 16 (tokens, then their fields; then partial sums),
+  // subtractions in site order, then in range order
   double acc = 0.0;
-  for (int i = 0; i < L; ++i) {
+  int i = 0;
+  for (; i + 16 <= L; i += 16) {
+    int t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = XT[(size_t)(i + u) * Bpad + b];
+    float hv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) hv[u] = h[(i + u) * q + (t[u] < 0 ? 0 : t[u])];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc -= (double)hv[u];
+  }
+  for (; i < L; ++i) {
     int t = XT[(size_t)i * Bpad + b];
     if (t < 0) t = 0;
     acc -= (double)h[i * q + t];
   }
-  for (int p = 0; p < parts; ++p) acc -= part[(size_t)p * Bpad + b];
+  int p = 0;
+  for (; p + 16 <= parts; p += 16) {
+    double pv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) pv[u] = part[(size_t)(p + u) * Bpad + b];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc -= pv[u];
+  }
+  for (; p < parts; ++p) acc -= part[(size_t)p * Bpad + b];
   E[b] = (float)acc;
 }
 
