@@ -115,6 +115,45 @@ __global__ __launch_bounds__(256) void k_transpose_tokens(const int8_t* __restri
   if (m0 >= M) return;  // whole workgroup (its rows are not read), before the barrier
   const int i0 = blockIdx.y * 64;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  if ((L & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 3) == 0) {
+    // rows of whole, aligned dwords: thread (row 16 k + tid / 16, dword tid % 16) loads
+    // 4 tokens at once; the store side writes dwords of 4 consecutive rows
+    __shared__ uint32_t tw[64][17];
+    const int c = threadIdx.x % 16;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = 16 * k + threadIdx.x / 16;
+      const int64_t m = m0 + r;
+      const int i = i0 + 4 * c;
+      uint32_t w = 0xFFFFFFFFu;  // -1 tokens
+      if (m < M && i < L) {
+        const uint32_t x = *reinterpret_cast<const uint32_t*>(X + m * L + i);
+        w = 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int v = (int)(int8_t)(x >> (8 * e));
+          if (v < 0 || v >= q) {
+            if (dev_err) atomicOr(dev_err, 1);
+            v = -1;
+          }
+          w |= ((uint32_t)v & 0xFFu) << (8 * e);
+        }
+      }
+      tw[r][c] = w;
+    }
+    __syncthreads();
+    // output dword (site i0 + j, sequences m0 + 4 d .. + 3): byte j of each row
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = 16 * k + threadIdx.x / 16, d = threadIdx.x % 16;
+      const int i = i0 + j;
+      uint32_t w = 0u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w |= ((tw[4 * d + e][j >> 2] >> (8 * (j & 3))) & 0xFFu) << (8 * e);
+      if (i < L) *reinterpret_cast<uint32_t*>(XT + (size_t)i * Mpad + m0 + 4 * d) = w;
+    }
+    return;
+  }
   for (int r = ty; r < 64; r += 4) {
     const int64_t m = m0 + r;
     const int i = i0 + tx;
