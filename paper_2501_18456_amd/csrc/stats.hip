@@ -628,14 +628,26 @@ __device__ __forceinline__ double sym_value(const double (*sh)[kFin + 1], int bi
   return sh[a - min(bi, bj) * kFin][b - max(bi, bj) * kFin];
 }
 
+// One workgroup per stored block (bi <= bj): the block is read once and
+// written to (bi, bj) and, transposed through LDS, to (bj, bi).
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ P, int S,
                                                          int Lq, double* __restrict__ C) {
   __shared__ double sh[kFin][kFin + 1];
-  const int bi = blockIdx.y, bj = blockIdx.x;
+  // triangular index t -> (bi, bj), bj (bj + 1) / 2 <= t < (bj + 1) (bj + 2) / 2
+  const int t = blockIdx.x;
+  int bj = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
+  while (bj * (bj + 1) / 2 > t) --bj;
+  const int bi = t - bj * (bj + 1) / 2;
   load_sym_block(P, S, Lq, bi, bj, sh);
   for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
     const int R1 = bi * kFin + e / kFin, R2 = bj * kFin + e % kFin;
     if (R1 < Lq && R2 < Lq) C[(size_t)R1 * Lq + R2] = sym_value(sh, bi, bj, R1, R2);
+  }
+  if (bi == bj) return;
+  for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
+    const int R1 = bj * kFin + e / kFin, R2 = bi * kFin + e % kFin;
+    if (R1 < Lq && R2 < Lq) C[(size_t)R1 * Lq + R2] = sym_value(sh, bj, bi, R1, R2);
   }
 }
 
@@ -643,7 +655,8 @@ hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq,
                                   hipStream_t s) {
   const double* P = reinterpret_cast<const double*>(static_cast<const char*>(ws) + plan.off_part);
   const unsigned nb = (unsigned)ceil_div(Lq, kFin);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(nb, nb), dim3(256), 0, s, P, plan.splits, Lq, C);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, P, plan.splits,
+                     Lq, C);
   return hipGetLastError();
 }
 
