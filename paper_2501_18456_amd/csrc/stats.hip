@@ -686,33 +686,43 @@ __global__ __launch_bounds__(256) void k_stats_epilogue(const double* __restrict
                                                         double* __restrict__ f2) {
   __shared__ double sh[kFin][kFin + 1];
   const int Lq = L * q;
-  const int bi = blockIdx.y, bj = blockIdx.x;
+  // one workgroup per stored block (bi <= bj, triangular index as in
+  // k_reduce_partials): output blocks (bi, bj) and, if distinct, (bj, bi)
+  const int t = blockIdx.x;
+  int bj = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
+  while (bj * (bj + 1) / 2 > t) --bj;
+  const int bi = t - bj * (bj + 1) / 2;
   load_sym_block(P, S, Lq, bi, bj, sh);
   const double meff = *meff_p;
   const double alpha = pc < 0.0 ? 1.0 / meff : pc;
   const double qq = (double)q * (double)q;
-  for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
-    const int r1 = bi * kFin + e / kFin, r2 = bj * kFin + e % kFin;
-    if (r1 >= Lq || r2 >= Lq) continue;
-    double out;
-    if (r1 / q == r2 / q) {
-      if (r1 == r2) {
-        const double f = sym_value(sh, bi, bj, r1, r1) / meff;
-        const double t1 = (1.0 - alpha) * f;
-        const double t2 = alpha / (double)q;
-        out = t1 + t2;
-        f1[r1] = out;
+  auto emit = [&](int b1, int b2) {
+    for (int e = threadIdx.x; e < kFin * kFin; e += blockDim.x) {
+      const int r1 = b1 * kFin + e / kFin, r2 = b2 * kFin + e % kFin;
+      if (r1 >= Lq || r2 >= Lq) continue;
+      double out;
+      if (r1 / q == r2 / q) {
+        if (r1 == r2) {
+          const double f = sym_value(sh, b1, b2, r1, r1) / meff;
+          const double t1 = (1.0 - alpha) * f;
+          const double t2 = alpha / (double)q;
+          out = t1 + t2;
+          f1[r1] = out;
+        } else {
+          out = 0.0;
+        }
       } else {
-        out = 0.0;
+        const double f = sym_value(sh, b1, b2, r1, r2) / meff;
+        const double t1 = (1.0 - alpha) * f;
+        const double t2 = alpha / qq;
+        out = t1 + t2;
       }
-    } else {
-      const double f = sym_value(sh, bi, bj, r1, r2) / meff;
-      const double t1 = (1.0 - alpha) * f;
-      const double t2 = alpha / qq;
-      out = t1 + t2;
+      f2[(size_t)r1 * Lq + r2] = out;
     }
-    f2[(size_t)r1 * Lq + r2] = out;
-  }
+  };
+  emit(bi, bj);
+  if (bi != bj) emit(bj, bi);
 }
 
 hipError_t launch_stats_epilogue(const StatsPlan& plan, const void* ws, int L, int q,
@@ -720,8 +730,8 @@ hipError_t launch_stats_epilogue(const StatsPlan& plan, const void* ws, int L, i
                                  hipStream_t s) {
   const double* P = reinterpret_cast<const double*>(static_cast<const char*>(ws) + plan.off_part);
   const unsigned nb = (unsigned)ceil_div(L * q, kFin);
-  hipLaunchKernelGGL(k_stats_epilogue, dim3(nb, nb), dim3(256), 0, s, P, plan.splits, L, q, meff,
-                     pseudocount, f1, f2);
+  hipLaunchKernelGGL(k_stats_epilogue, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, P, plan.splits, L,
+                     q, meff, pseudocount, f1, f2);
   return hipGetLastError();
 }
 
