@@ -729,10 +729,15 @@ def bench_precision_epoch(args):
                        "peak_tflops": peaks, "error_vs_fp64_oracle": err,
                        "alg_flops_per_call": {p: stats_product_flops(M, Lq, p) for p in peaks}}
 
-    # ---------------- training epochs: FP32 form timed for `value`, then BF16 hi+lo
+    # ---------------- training epochs: FP32 form timed for `value`, then BF16 hi+lo;
+    # chain counts counted directly (the library default), and for the comparison
+    # of the two product forms also from the one-hot product of each precision
     epoch_ms, pear, flipf = {}, {}, {}
-    for prec in ("fp32", "bf16x2"):
-        f1, f2, _ = stats[prec]
+    forms = {"fp32": B.PREC_FP32, "bf16x2": B.PREC_BF16X2,
+             "fp32_product_counts": B.PREC_FP32 | B.COUNTS_PRODUCT,
+             "bf16x2_product_counts": B.PREC_BF16X2 | B.COUNTS_PRODUCT}
+    for form, prec in forms.items():
+        f1, f2, _ = stats[form.split("_")[0]]
         h = api.profile_fields(f1, L, q)
         J = torch.zeros((Lq, Lq), dtype=torch.float32, device="cuda")
         ch = api.init_chains(N, L, q, seed=seed_chain)
@@ -750,13 +755,13 @@ def bench_precision_epoch(args):
             api.train_step(h, J, ch, f1, f2, lr, sweeps, seed_chain, args.warmup + k, prec, wst,
                            pearson, flips, derr)
         torch.cuda.synchronize()
-        epoch_ms[prec] = (time.perf_counter() - t0) * 1e3 / args.steps
-        pear[prec] = float(pearson.item())
-        flipf[prec] = float(flips.item()) / (N * L * sweeps * args.steps)
+        epoch_ms[form] = (time.perf_counter() - t0) * 1e3 / args.steps
+        pear[form] = float(pearson.item())
+        flipf[form] = float(flips.item()) / (N * L * sweeps * args.steps)
         assert int(derr.item()) == 0, "device error flag raised"
-        log(f"epoch {prec}: {epoch_ms[prec]:.2f} ms ({N * L * sweeps / (epoch_ms[prec] * 1e-3):.3e} "
-            f"site-updates/s), flip fraction {flipf[prec]:.3f}, pearson {pear[prec]:.4f}")
-        if prec == "fp32":
+        log(f"epoch {form}: {epoch_ms[form]:.2f} ms ({N * L * sweeps / (epoch_ms[form] * 1e-3):.3e} "
+            f"site-updates/s), flip fraction {flipf[form]:.3f}, pearson {pear[form]:.4f}")
+        if form == "fp32":
             h_run, J_run, ch_run = h, J, ch
         else:
             del h, J, ch
@@ -766,6 +771,8 @@ def bench_precision_epoch(args):
     extras["epoch_ms"] = epoch_ms
     extras["site_updates_per_s"] = {p: N * L * sweeps / (v * 1e-3) for p, v in epoch_ms.items()}
     extras["mixed_speedup_over_fp32"] = epoch_ms["fp32"] / epoch_ms["bf16x2"]
+    extras["mixed_speedup_over_fp32_product_counts"] = (epoch_ms["fp32_product_counts"] /
+                                                       epoch_ms["bf16x2_product_counts"])
     extras["pearson_after"] = pear
     extras["flip_fraction"] = flipf
 

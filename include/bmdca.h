@@ -99,6 +99,14 @@ typedef enum {
                                         without its rule; this is the textbook
                                         rule. */
 
+/* Chain counts of bmdca_train_step (and its grouped and masked forms): by
+ * default they are counted directly, #{n : s_i(n) = a, s_j(n) = b} in
+ * integer histograms; with this bit OR-ed into `prec` they come from the
+ * one-hot product of that precision instead (for comparing the two product
+ * forms).  Both give the same exact integers, so every result is
+ * bit-identical either way. */
+#define BMDCA_COUNTS_PRODUCT 0x200
+
 /* Bits OR-ed into *dev_err. */
 #define BMDCA_DEVERR_TOKEN 1
 #define BMDCA_DEVERR_NONFINITE 2
@@ -282,7 +290,8 @@ int bmdca_energy_noalloc(const float* h, const float* J, const int8_t* seqs, int
  *   1. `sweeps` Gibbs sweeps of the chains at beta = 1, global sweep index
  *      epoch*sweeps + s (as bmdca_gibbs);
  *   2. model marginals from the final chains, p = count / N, with the counts
- *      from the one-hot product of `prec` (exact integers in both forms);
+ *      counted directly (exact integers; with BMDCA_COUNTS_PRODUCT, from the
+ *      one-hot product of `prec`, the same integers);
  *   3. *pearson = Pearson correlation of C^data = f_ij - f_i f_j and
  *      C^model = p_ij - p_i p_j (Eq. 6) over i < j and all a, b, FP64,
  *      two-pass;
@@ -292,7 +301,7 @@ int bmdca_energy_noalloc(const float* h, const float* J, const int8_t* seqs, int
  * h, J     float32, updated in place
  * chains   int8 [N][L] in/out
  * f1, f2   double data frequencies as produced by bmdca_stats
- * prec     bmdca_prec of the count product, OR-ed with BMDCA_SAMPLER_*
+ * prec     bmdca_prec, OR-ed with BMDCA_SAMPLER_* and BMDCA_COUNTS_PRODUCT
  * pearson  double [1] out (device)
  * flips_out optional device uint64, accepted changes added
  * ws       scratch, bmdca_workspace_bytes(BMDCA_WS_TRAIN_STEP, N, L, q, prec)

@@ -17,6 +17,7 @@ PREC_FP32, PREC_BF16X2 = 0, 1
 DEVERR_TOKEN, DEVERR_NONFINITE, DEVERR_INDEX = 1, 2, 4
 SAMPLER_FIELDS, SAMPLER_GATHER, GIBBS_KEEP_FIELDS, SAMPLER_METROPOLIS = 0x10, 0x20, 0x40, 0x80
 GIBBS_KEEP_LAYOUT = 0x100
+COUNTS_PRODUCT = 0x200  # chain counts from the one-hot product (default: counted directly)
 SAMPLER = {"auto": 0, "fields": SAMPLER_FIELDS, "gather": SAMPLER_GATHER,
            "metropolis": SAMPLER_METROPOLIS,
            "metropolis-fields": SAMPLER_METROPOLIS | SAMPLER_FIELDS,

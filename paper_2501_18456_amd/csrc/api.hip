@@ -152,7 +152,8 @@ int check_train(const bmdca_train_problem& p) {
   BMDCA_REQUIRE(p.sweeps >= 0, "sweeps=%d negative", p.sweeps);
   const int pr = p.prec & kPrecMask;
   BMDCA_REQUIRE(pr == BMDCA_PREC_FP32 || pr == BMDCA_PREC_BF16X2, "prec=%d unknown", pr);
-  BMDCA_REQUIRE((p.prec & ~(kPrecMask | kSamplerMask)) == 0, "prec flags 0x%x unknown", p.prec);
+  BMDCA_REQUIRE((p.prec & ~(kPrecMask | kSamplerMask | BMDCA_COUNTS_PRODUCT)) == 0,
+                "prec flags 0x%x unknown", p.prec);
   BMDCA_REQUIRE(pick_gather(p.prec, p.L, p.q) >= 0, "sampler flags 0x%x not usable for L=%d q=%d",
                 p.prec, p.L, p.q);
   if (!std::isfinite(p.lr)) return fail(BMDCA_ENONFINITE, "lr is not finite");
@@ -192,10 +193,16 @@ int enqueue_train(const bmdca_train_problem& p, uint64_t epoch, const DevCtl& ct
                                                (p.prec & BMDCA_SAMPLER_METROPOLIS) != 0),
                            "train_step/sweeps"));
   }
-  BMDCA_TRY(hip_status(launch_onehot_products(p.chains, nullptr, N, L, q, pr, plan.sp, sws,
-                                              p.dev_err, s, ctl.active),
-                       "train_step/counts"));
-  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));
+  if (p.prec & BMDCA_COUNTS_PRODUCT) {
+    BMDCA_TRY(hip_status(launch_onehot_products(p.chains, nullptr, N, L, q, pr, plan.sp, sws,
+                                                p.dev_err, s, ctl.active),
+                         "train_step/counts"));
+    BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, Lq, C, s), "train_step/reduce"));
+  } else {
+    BMDCA_TRY(hip_status(launch_pair_counts(p.chains, N, L, q, plan.sp, sws, C, p.dev_err, s,
+                                            ctl.active),
+                         "train_step/counts"));
+  }
   BMDCA_TRY(hip_status(launch_pearson(p.f1, p.f2, C, N, L, q, red, p.pearson, p.dev_err, s),
                        "train_step/pearson"));
   return hip_status(launch_update(p.h, p.J, p.f1, p.f2, C, N, L, q, p.lr, p.dev_err, s,

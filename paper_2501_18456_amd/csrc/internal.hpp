@@ -82,6 +82,12 @@ hipError_t launch_transpose_tokens(const int8_t* X, int64_t M, int L, int q, int
 hipError_t launch_onehot_products(const int8_t* X, const double* w, int64_t M, int L, int q,
                                   int prec, const StatsPlan& plan, void* ws, int32_t* dev_err,
                                   hipStream_t s, const int32_t* active = nullptr);
+// Chain counts C[(i,a)][(j,b)] = #{n : s_i(n) = a, s_j(n) = b} (unit weights,
+// exact), full symmetric FP64 [Lq][Lq], counted directly in LDS histograms;
+// uses the token region of a plan_stats(N, L, q, .) workspace.  q <= 32.
+hipError_t launch_pair_counts(const int8_t* X, int64_t N, int L, int q, const StatsPlan& plan,
+                              void* ws, double* C, int32_t* dev_err, hipStream_t s,
+                              const int32_t* active = nullptr);
 // Sum of the partial planes into the full symmetric matrix C (FP64).
 hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq, double* C,
                                   hipStream_t s);

@@ -661,6 +661,97 @@ hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq,
 }
 
 // M_eff = sum_m w_m: fixed thread-to-row map, fixed tree.
+// ---------------------------------------------------------------------------
+// Chain counts by direct counting (Eq. 3 with unit weights): C[(i,a)][(j,b)] =
+// #{n : s_i(n) = a, s_j(n) = b}, exact in u32 and written as FP64 to the full
+// symmetric matrix (the diagonal block of site i holds n_i(a) on its
+// diagonal).  Workgroup (jg, i) counts site i against the sites
+// j = kPCG jg .. kPCG jg + kPCG - 1 with i <= j < L, one LDS histogram per j,
+// reading the site-major tokens XT [L][Mpad] four chains per dword.  The bin
+// of (a, b) is a * kPCRow + b over the tokens' low 6 bits: padding and invalid
+// tokens (0xFF) land in row or column 63, which is never written out, and the
+// odd row length spreads a wave's increments over the LDS banks.
+// ---------------------------------------------------------------------------
+constexpr int kPCG = 4;
+constexpr int kPCRow = 65;
+constexpr int kPCBins = 64 * kPCRow;
+
+__global__ __launch_bounds__(256) void k_pair_counts(const int8_t* __restrict__ XT, int64_t Mpad,
+                                                     int L, int q, double* __restrict__ C,
+                                                     const int32_t* __restrict__ active) {
+  __shared__ uint32_t hist[kPCG][kPCBins];
+  if (active && *active == 0) return;
+  const int i = blockIdx.y, j0 = blockIdx.x * kPCG;
+  if (j0 + kPCG - 1 < i) return;  // the whole group lies below the diagonal
+  for (int e = threadIdx.x; e < kPCG * kPCBins; e += 256) (&hist[0][0])[e] = 0u;
+  __syncthreads();
+  const int64_t nd = Mpad / 4;
+  const uint32_t* xi = reinterpret_cast<const uint32_t*>(XT + (size_t)i * Mpad);
+  const uint32_t* xj[kPCG];
+  bool on[kPCG];
+#pragma unroll
+  for (int g = 0; g < kPCG; ++g) {
+    on[g] = j0 + g >= i && j0 + g < L;
+    xj[g] = reinterpret_cast<const uint32_t*>(XT + (size_t)min(j0 + g, L - 1) * Mpad);
+  }
+  // two dwords per thread and iteration, all loads issued before the first
+  // increment (the sites past L or below i load a valid row and skip)
+  for (int64_t d0 = threadIdx.x; d0 < nd; d0 += 512) {
+    const bool two = d0 + 256 < nd;
+    const int64_t d1 = two ? d0 + 256 : d0;
+    uint32_t wi[2], wj[2][kPCG];
+    wi[0] = xi[d0];
+    wi[1] = xi[d1];
+#pragma unroll
+    for (int g = 0; g < kPCG; ++g) {
+      wj[0][g] = xj[g][d0];
+      wj[1][g] = xj[g][d1];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      uint32_t ra[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ra[e] = __builtin_amdgcn_ubfe(wi[u], 8 * e, 6) * kPCRow;
+#pragma unroll
+      for (int g = 0; g < kPCG; ++g) {
+        if (!on[g]) continue;  // uniform
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          atomicAdd(&hist[g][ra[e] + __builtin_amdgcn_ubfe(wj[u][g], 8 * e, 6)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  const int Lq = L * q, qq = q * q;
+#pragma unroll
+  for (int g = 0; g < kPCG; ++g) {
+    if (!on[g]) continue;
+    const int j = j0 + g;
+    for (int e = threadIdx.x; e < qq; e += 256) {
+      const int a = e / q, b = e - a * q;  // rows (i, a), b fastest
+      C[(size_t)(i * q + a) * Lq + j * q + b] = (double)hist[g][a * kPCRow + b];
+    }
+    if (j == i) continue;
+    for (int e = threadIdx.x; e < qq; e += 256) {
+      const int b = e / q, a = e - b * q;  // rows (j, b), a fastest
+      C[(size_t)(j * q + b) * Lq + i * q + a] = (double)hist[g][a * kPCRow + b];
+    }
+  }
+}
+
+hipError_t launch_pair_counts(const int8_t* X, int64_t N, int L, int q, const StatsPlan& plan,
+                              void* ws, double* C, int32_t* dev_err, hipStream_t s,
+                              const int32_t* active) {
+  if (q > 32 || L < 1) return hipErrorInvalidValue;
+  int8_t* XT = reinterpret_cast<int8_t*>(static_cast<char*>(ws) + plan.off_xt);
+  const hipError_t e = launch_transpose_tokens(X, N, L, q, XT, plan.Mpad, dev_err, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pair_counts, dim3((unsigned)ceil_div(L, kPCG), (unsigned)L), dim3(256), 0,
+                     s, XT, plan.Mpad, L, q, C, active);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(1024) void k_meff(const double* __restrict__ w, int64_t M,
                                                double* __restrict__ meff) {
   __shared__ double sh[16];

@@ -420,6 +420,38 @@ def test_train_step_fp32_counts_match_bf16():
     assert outs[0][2][0] == outs[1][2][0]
 
 
+@pytest.mark.parametrize("L,q,N", [(20, 21, 500), (37, 5, 1000), (9, 32, 130), (2, 2, 1),
+                                   (130, 7, 300), (64, 21, 4099)])
+def test_train_step_direct_counts_equal_products(L, q, N):
+    """Chain counts counted directly (the default) and from the one-hot
+    product in both precisions are the same integers, so h, J, chains and the
+    Pearson value agree bit for bit; the shapes take ragged site groups
+    (L % 4 != 0), q = 32, a single chain and chain counts off the 64-row pad.
+    With one chain the model correlations are all zero, so the Pearson value
+    is 0/0 and raises the non-finite flag in every form alike."""
+    rng = np.random.default_rng(L * 1000 + q)
+    chains = rng.integers(0, q, size=(N, L), dtype=np.int8)
+    h = (0.3 * rng.standard_normal((L, q))).astype(np.float32)
+    J = (0.1 * rng.standard_normal((L * q, L * q))).astype(np.float32)
+    J = (J + J.T) / 2
+    Jv = J.reshape(L, q, L, q)
+    for i in range(L):
+        Jv[i, :, i, :] = 0
+    f1 = rng.random(L * q)
+    f2 = rng.random((L * q) ** 2)
+    outs = []
+    for prec in (B.PREC_FP32, B.PREC_FP32 | B.COUNTS_PRODUCT, B.PREC_BF16X2 | B.COUNTS_PRODUCT):
+        hg, Jg, cg = dev(h), dev(J), dev(chains)
+        e = err_flag()
+        pr = api.train_step(hg, Jg, cg, dev(f1), dev(f2), 0.05, 1, 77, 0, prec=prec, dev_err=e)
+        assert int(host(e)[0]) == (B.DEVERR_NONFINITE if N == 1 else 0)
+        outs.append((host(hg), host(Jg), host(cg), host(pr)[0]))
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
+        assert np.array_equal(outs[0][2], o[2])
+        assert outs[0][3] == o[3] or (N == 1 and np.isnan(outs[0][3]) and np.isnan(o[3]))
+
+
 def test_train_step_nonfinite_flag():
     """A huge learning rate overflows the float32 parameters: the device flag is
     raised; nothing faults."""
