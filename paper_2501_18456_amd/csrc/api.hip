@@ -658,10 +658,8 @@ int bmdca_decimate(float* J, uint8_t* mask, const int8_t* chains, int64_t N, int
   char* base = static_cast<char*>(ws);
   void* sws = base + plan.off_stats;
   double* C = reinterpret_cast<double*>(base + plan.off_C);
-  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, BMDCA_PREC_BF16X2, plan.sp,
-                                              sws, dev_err, s),
+  BMDCA_TRY(hip_status(launch_pair_counts(chains, N, L, q, plan.sp, sws, C, dev_err, s),
                        "decimate/counts"));
-  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, L * q, C, s), "decimate/reduce"));
   return hip_status(launch_decimate(J, mask, C, N, L, q, drate, density, n_active,
                                     base + plan.off_dec, s),
                     "decimate/select");
@@ -682,10 +680,8 @@ int bmdca_activate(uint8_t* mask, const int8_t* chains, int64_t N, int32_t L, in
   char* base = static_cast<char*>(ws);
   void* sws = base + plan.off_stats;
   double* C = reinterpret_cast<double*>(base + plan.off_C);
-  BMDCA_TRY(hip_status(launch_onehot_products(chains, nullptr, N, L, q, BMDCA_PREC_BF16X2, plan.sp,
-                                              sws, dev_err, s),
+  BMDCA_TRY(hip_status(launch_pair_counts(chains, N, L, q, plan.sp, sws, C, dev_err, s),
                        "activate/counts"));
-  BMDCA_TRY(hip_status(launch_reduce_partials(plan.sp, sws, L * q, C, s), "activate/reduce"));
   return hip_status(launch_activate(mask, C, f2, N, L, q, factivate, n_active,
                                     base + plan.off_dec, dev_err, s),
                     "activate/select");
