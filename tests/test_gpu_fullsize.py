@@ -256,6 +256,36 @@ def test_rna_gibbs_and_counts():
     assert np.array_equal(host(f2)[r1, r2], O.stats_entries(g, q, r1, r2, None, 0.0))
 
 
+@pytest.mark.parametrize("L,q,N", [(256, 21, 20000), (512, 21, 4096), (400, 5, 10000)])
+def test_direct_chain_counts_full_size(L, q, N):
+    """The epoch's chain counts at full sizes (the precision-form shape, the
+    largest model, the RNA shape): with h = J = 0, zero data frequencies and
+    no sweeps, the update writes J'[r1][r2] = float32(lr (0 - C/N)) for sites
+    i != j, so sampled entries pin C against the oracle's counts of the same
+    chains; the whole h and J equal those of the one-hot product path bit for
+    bit. (The Pearson value is 0/0 here, so no device flag is read.)"""
+    Lq, lr = L * q, 0.05
+    ch0 = O.init_chains(N, L, q, seed=5100 + L)
+    f1 = torch.zeros(Lq, dtype=torch.float64, device="cuda")
+    f2 = torch.zeros(Lq * Lq, dtype=torch.float64, device="cuda")
+    outs = []
+    for prec in (B.PREC_FP32, B.PREC_BF16X2 | B.COUNTS_PRODUCT):
+        hg = torch.zeros((L, q), dtype=torch.float32, device="cuda")
+        Jg = torch.zeros((Lq, Lq), dtype=torch.float32, device="cuda")
+        api.train_step(hg, Jg, dev(ch0), f1, f2, lr, 0, 1, 0, prec=prec)
+        outs.append((hg, Jg))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    r1, r2 = sample_pairs(Lq, 600, L)
+    keep = (r1 // q) != (r2 // q)
+    r1, r2 = r1[keep], r2[keep]
+    p = O.stats_entries(ch0, q, r1, r2, None, 0.0)
+    want = (lr * (0.0 - p)).astype(np.float32)
+    got = host(outs[0][1])[r1, r2]
+    assert np.array_equal(got, want)
+    del outs
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------- launches split in chunks
 def test_local_fields_past_one_launch():
     """More (chain, column block) workgroups than one launch takes (2^22):
