@@ -668,13 +668,16 @@ hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq,
 // diagonal).  Workgroup (jg, i) counts site i against the sites
 // j = kPCG jg .. kPCG jg + kPCG - 1 with i <= j < L, one LDS histogram per j,
 // reading the site-major tokens XT [L][Mpad] four chains per dword.  The bin
-// of (a, b) is a * kPCRow + b over the tokens' low 6 bits: padding and invalid
-// tokens (0xFF) land in row or column 63, which is never written out, and the
-// odd row length spreads a wave's increments over the LDS banks.
+// of (a, b) is a * kPCRow + b with both tokens clamped to 32: padding and
+// invalid tokens (0xFF) land in row or column 32, which is never written out
+// (q <= 32), and the odd row length spreads a wave's increments over the LDS
+// banks.  Histograms of 33 x 33 bins (4.4 KB) leave room for several
+// workgroups per CU (64 x 65 bins over the tokens' low 6 bits, without the
+// clamps, ran 1.2-2.1x longer).
 // ---------------------------------------------------------------------------
 constexpr int kPCG = 4;
-constexpr int kPCRow = 65;
-constexpr int kPCBins = 64 * kPCRow;
+constexpr int kPCRow = 33;
+constexpr int kPCBins = 33 * kPCRow;
 
 __global__ __launch_bounds__(256) void k_pair_counts(const int8_t* __restrict__ XT, int64_t Mpad,
                                                      int L, int q, double* __restrict__ C,
@@ -712,13 +715,13 @@ __global__ __launch_bounds__(256) void k_pair_counts(const int8_t* __restrict__ 
       if (u == 1 && !two) break;
       uint32_t ra[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[e] = __builtin_amdgcn_ubfe(wi[u], 8 * e, 6) * kPCRow;
+      for (int e = 0; e < 4; ++e) ra[e] = min(__builtin_amdgcn_ubfe(wi[u], 8 * e, 8), 32u) * kPCRow;
 #pragma unroll
       for (int g = 0; g < kPCG; ++g) {
         if (!on[g]) continue;  // uniform
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          atomicAdd(&hist[g][ra[e] + __builtin_amdgcn_ubfe(wj[u][g], 8 * e, 6)], 1u);
+          atomicAdd(&hist[g][ra[e] + min(__builtin_amdgcn_ubfe(wj[u][g], 8 * e, 8), 32u)], 1u);
       }
     }
   }
