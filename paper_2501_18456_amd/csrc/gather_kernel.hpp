@@ -680,7 +680,6 @@ hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
   // (heat-bath, 5..7 quads per row) where the planner takes them
   constexpr int LP = gather_lanes(Q, !MH), LN = gather_narrow_lanes(Q, !MH);
   if (gs.lpc != LP && (LN == 0 || gs.lpc != LN)) return hipErrorInvalidValue;
-  if (MH && gs.pair) return hipErrorInvalidValue;  // paired steps: heat-bath plans only
   // the step schedule is a template parameter: with both in one kernel the
   // compiler scheduled each of them worse (up to 9% slower)
   auto pick = [&](auto lanes, auto paired) {
@@ -692,9 +691,7 @@ hipError_t launch_gather_shape(const GatherShape& gs, const GatherArgs& a) {
   };
   using LPt = std::integral_constant<int, LP>;
   decltype(&k_gibbs_gather<Q, 8, LP, MH, MAXW, false>) kern = pick(LPt{}, std::false_type{});
-  if constexpr (!MH) {
-    if (gs.pair) kern = pick(LPt{}, std::true_type{});
-  }
+  if (gs.pair) kern = pick(LPt{}, std::true_type{});
   if constexpr (LN > 0) {
     using LNt = std::integral_constant<int, LN>;
     if (gs.lpc == LN) {

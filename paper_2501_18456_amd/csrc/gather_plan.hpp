@@ -154,7 +154,10 @@ constexpr int gather_narrow_lanes(int q, bool small) {
 // of three.  Where a workgroup holds at least this many chains the row
 // gathers dominate a step and the halved barriers pay (L = 256, q = 21,
 // 20 000 chains: 33.6 -> 30.2 ms per 10 sweeps; L = 100, 10 000 chains
-// 5.46 -> 5.27; q = 12, L = 200 11.4 -> 10.0; q = 5, L = 400 17.8 -> 16.0);
+// 5.46 -> 5.27; q = 12, L = 200 11.4 -> 10.0; q = 5, L = 400 17.8 -> 16.0;
+// Metropolis sweeps, whose staging is most of the step: L = 100 4.30 -> 3.96,
+// L = 256 24.0 -> 21.9, q = 5, L = 400 24.2 -> 22.4, q = 12, L = 200
+// 9.14 -> 8.52);
 // with fewer the staging latency dominates and the third chunk in flight
 // pays more (L = 512, 4096 chains, 16 per workgroup: 114.7 against 130.8).
 // The same holds where the re-laid-out couplings (L^2 q QP 4 bytes) exceed
@@ -195,7 +198,6 @@ inline GatherShape gather_plan(int64_t N, int L, int q, int64_t cus, int cap = k
     const GatherShape n = gather_plan_lanes(N, L, q, cus, cap, nl);
     if (n.waves >= kGNarrowWaves && n.waves < g.waves && n.blocks <= g.blocks) g = n;
   }
-  if (!small) g.pair = 0;  // paired steps are instantiated for the heat-bath draw only
   return g;
 }
 

@@ -50,7 +50,7 @@ static void check(int64_t N, int L, int q, int64_t cus, int cap, bool small) {
   // same ring of ahead + 1 = 4 slots, where the workgroup holds enough chains
   {
     const double jt = (double)L * L * q * QP * 4.0;
-    const bool want_pair = small && g.cpb >= 32 && (jt <= 256.0 * 1024 * 1024 || g.cpb >= 64);
+    const bool want_pair = g.cpb >= 32 && (jt <= 256.0 * 1024 * 1024 || g.cpb >= 64);
     CHECK(g.pair == (want_pair ? 1 : 0), "pair %d cpb %d small %d jt %.0f", g.pair, g.cpb,
           (int)small, jt);
   }
