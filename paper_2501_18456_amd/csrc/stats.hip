@@ -668,26 +668,33 @@ hipError_t launch_reduce_partials(const StatsPlan& plan, const void* ws, int Lq,
 // diagonal).  Workgroup (jg, i) counts site i against the sites
 // j = kPCG jg .. kPCG jg + kPCG - 1 with i <= j < L, one LDS histogram per j,
 // reading the site-major tokens XT [L][Mpad] four chains per dword.  The bin
-// of (a, b) is a * kPCRow + b with both tokens clamped to 32: padding and
-// invalid tokens (0xFF) land in row or column 32, which is never written out
-// (q <= 32), and the odd row length spreads a wave's increments over the LDS
-// banks.  Histograms of 33 x 33 bins (4.4 KB) leave room for several
-// workgroups per CU (64 x 65 bins over the tokens' low 6 bits, without the
-// clamps, ran 1.2-2.1x longer).
+// of (a, b) is a * ROW + b with both tokens clamped to ROW - 1 (33 for q > 8,
+// 9 for q <= 8): padding and invalid tokens (0xFF) land in that row or
+// column, which is never written out, and the odd row length spreads a
+// wave's increments over the LDS banks.  Histograms of 33 x 33 bins (4.4 KB)
+// leave room for several workgroups per CU (64 x 65 bins over the tokens'
+// low 6 bits, without the clamps, ran 1.2-2.1x longer).
 // ---------------------------------------------------------------------------
 constexpr int kPCG = 4;
-constexpr int kPCRow = 33;
-constexpr int kPCBins = 33 * kPCRow;
 
+// ROW: bins per histogram row (tokens clamped to ROW - 1, the trash row and
+// column); NC: copies of each histogram, lane group l / (64 / NC) of a wave
+// adding to copy l * NC / 64, summed when written out.  For q <= 8 a wave's
+// 64 increments fall on at most 64 bins and the same-bin adds serialize, so
+// 8 copies of 9 x 9 bins spread them.
+template <int ROW, int NC>
 __global__ __launch_bounds__(256) void k_pair_counts(const int8_t* __restrict__ XT, int64_t Mpad,
                                                      int L, int q, double* __restrict__ C,
                                                      const int32_t* __restrict__ active) {
-  __shared__ uint32_t hist[kPCG][kPCBins];
+  constexpr int kBins = ROW * ROW;
+  constexpr uint32_t kTrash = ROW - 1;
+  __shared__ uint32_t hist[kPCG][NC * kBins];
   if (active && *active == 0) return;
   const int i = blockIdx.y, j0 = blockIdx.x * kPCG;
   if (j0 + kPCG - 1 < i) return;  // the whole group lies below the diagonal
-  for (int e = threadIdx.x; e < kPCG * kPCBins; e += 256) (&hist[0][0])[e] = 0u;
+  for (int e = threadIdx.x; e < kPCG * NC * kBins; e += 256) (&hist[0][0])[e] = 0u;
   __syncthreads();
+  const uint32_t cbase = (uint32_t)((threadIdx.x % 64) / (64 / NC)) * kBins;
   const int64_t nd = Mpad / 4;
   const uint32_t* xi = reinterpret_cast<const uint32_t*>(XT + (size_t)i * Mpad);
   const uint32_t* xj[kPCG];
@@ -715,30 +722,37 @@ __global__ __launch_bounds__(256) void k_pair_counts(const int8_t* __restrict__ 
       if (u == 1 && !two) break;
       uint32_t ra[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[e] = min(__builtin_amdgcn_ubfe(wi[u], 8 * e, 8), 32u) * kPCRow;
+      for (int e = 0; e < 4; ++e)
+        ra[e] = cbase + min(__builtin_amdgcn_ubfe(wi[u], 8 * e, 8), kTrash) * ROW;
 #pragma unroll
       for (int g = 0; g < kPCG; ++g) {
         if (!on[g]) continue;  // uniform
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          atomicAdd(&hist[g][ra[e] + min(__builtin_amdgcn_ubfe(wj[u][g], 8 * e, 8), 32u)], 1u);
+          atomicAdd(&hist[g][ra[e] + min(__builtin_amdgcn_ubfe(wj[u][g], 8 * e, 8), kTrash)], 1u);
       }
     }
   }
   __syncthreads();
   const int Lq = L * q, qq = q * q;
+  auto count = [&](int g, int a, int b) {
+    uint32_t c = 0u;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) c += hist[g][k * kBins + a * ROW + b];
+    return (double)c;
+  };
 #pragma unroll
   for (int g = 0; g < kPCG; ++g) {
     if (!on[g]) continue;
     const int j = j0 + g;
     for (int e = threadIdx.x; e < qq; e += 256) {
       const int a = e / q, b = e - a * q;  // rows (i, a), b fastest
-      C[(size_t)(i * q + a) * Lq + j * q + b] = (double)hist[g][a * kPCRow + b];
+      C[(size_t)(i * q + a) * Lq + j * q + b] = count(g, a, b);
     }
     if (j == i) continue;
     for (int e = threadIdx.x; e < qq; e += 256) {
       const int b = e / q, a = e - b * q;  // rows (j, b), a fastest
-      C[(size_t)(j * q + b) * Lq + i * q + a] = (double)hist[g][a * kPCRow + b];
+      C[(size_t)(j * q + b) * Lq + i * q + a] = count(g, a, b);
     }
   }
 }
@@ -750,8 +764,12 @@ hipError_t launch_pair_counts(const int8_t* X, int64_t N, int L, int q, const St
   int8_t* XT = reinterpret_cast<int8_t*>(static_cast<char*>(ws) + plan.off_xt);
   const hipError_t e = launch_transpose_tokens(X, N, L, q, XT, plan.Mpad, dev_err, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pair_counts, dim3((unsigned)ceil_div(L, kPCG), (unsigned)L), dim3(256), 0,
-                     s, XT, plan.Mpad, L, q, C, active);
+  const dim3 grid((unsigned)ceil_div(L, kPCG), (unsigned)L);
+  if (q <= 8)
+    hipLaunchKernelGGL((k_pair_counts<9, 8>), grid, dim3(256), 0, s, XT, plan.Mpad, L, q, C, active);
+  else
+    hipLaunchKernelGGL((k_pair_counts<33, 1>), grid, dim3(256), 0, s, XT, plan.Mpad, L, q, C,
+                       active);
   return hipGetLastError();
 }
 
