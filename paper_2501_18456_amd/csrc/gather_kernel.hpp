@@ -342,12 +342,17 @@ __global__ __launch_bounds__(MAXW * 64) void k_gibbs_gather(
         wait_vm_lgkm0<0>();
         __builtin_amdgcn_s_barrier();
         compiler_fence();
+        // the next two chunks' loads go out ahead of the other waves' work
+        // (0.5-1.6% shorter launches; in the one-barrier schedule the same
+        // raise cost up to 1.4%)
+        __builtin_amdgcn_s_setprio(3);
         for (int e = 0; e < 2; ++e) {
           if (t + 2 + e < Tn) {
             if (loader) issue_chunk(pi, pk, psl);
             advance(pi, pk, psl);
           }
         }
+        __builtin_amdgcn_s_setprio(0);
       }
     } else {
       // chunk t is complete once at most the younger issued chunks (ahead - 1
