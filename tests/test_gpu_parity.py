@@ -177,6 +177,21 @@ def test_gibbs_gather_schedules_agree(L, q):
     assert torch.equal(big[:100], small)
 
 
+@pytest.mark.parametrize("L,q", [(256, 21), (100, 21), (200, 12)])
+def test_metropolis_gather_schedules_agree(L, q):
+    """The same for Metropolis sweeps: 100 chains alone (one barrier per
+    chunk-step) and at the head of 20 000 (paired chunk-steps) end in the
+    same states after 4 sweeps; at these shapes both launches take the same
+    chunk length, which the Metropolis summation order also follows."""
+    h, J = synth.planted_dense(L, q, seed=181 + q, sigma_J=0.1)
+    hg, Jg = dev(h), dev(J)
+    big = api.init_chains(20000, L, q, 182)
+    small = big[:100].clone()
+    api.gibbs(hg, Jg, big, sweeps=4, seed=183, sweep_offset=5, sampler="metropolis-gather")
+    api.gibbs(hg, Jg, small, sweeps=4, seed=183, sweep_offset=5, sampler="metropolis-gather")
+    assert torch.equal(big[:100], small)
+
+
 def _sidak_z(n_tests, alpha=0.01):
     from scipy.stats import norm
     a1 = 1 - (1 - alpha) ** (1.0 / n_tests)
